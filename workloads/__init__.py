@@ -1,0 +1,131 @@
+"""Seeded synthetic workloads for the augmented-Lagrangian Stokes multigrid.
+
+This module is the only code shared by the CPU oracle and the GPU path. It
+holds workload *descriptions* and the random numbers they draw (sinker
+centres, Fourier amplitudes, request arrival times); it holds none of the
+method's arithmetic (no basis functions, no viscosity law, no operators).
+
+Workloads follow the multi-sinker benchmark of Section 5.2 (Rudi-Stadler-
+Ghattas setup): unit square/cube, homogeneous Dirichlet walls, n sinkers of
+diameter omega with Gaussian-smoothed edges (parameter delta), contrast
+DR = mu_max/mu_min with mu_max = DR^(1/2), mu_min = DR^(-1/2), forcing
+strength beta. The paper draws the sinker centres "randomly" without a
+distribution or seed; here they are uniform on [0,1)^d from numpy's PCG64
+generator with the seed stored in the workload.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Tuple
+
+import numpy as np
+
+OMEGA = 0.1     # sinker diameter (Section 5.2)
+DELTA = 200.0   # edge smoothing parameter (Section 5.2)
+BETA = 10.0     # forcing strength (Section 5.2)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One Stokes solve: mesh hierarchy, coefficient field and solver knobs."""
+    name: str
+    dim: int              # 2 or 3
+    n_fine: int           # cells per axis on the finest level
+    levels: int           # number of multigrid levels (level 0 = coarsest)
+    n_sinkers: int
+    dr: float             # dynamic ratio mu_max / mu_min
+    gamma: float          # augmented-Lagrangian parameter
+    seed: int             # seed for the sinker centres
+    nu_pre: int = 2       # GMRES-accelerated ASM steps before coarse correction
+    nu_post: int = 2      # ... and after
+    restart: int = 30     # FGMRES restart length
+    rtol: float = 1e-8    # relative residual target ||b - Kx|| <= rtol ||b||
+    maxit: int = 300
+    coef_kind: int = 0    # 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor
+    fourier_seed: Optional[int] = None   # seed of the Fourier velocity (coef_kind 1)
+    fourier_modes: int = 8               # modes per axis (coef_kind 1)
+
+    @property
+    def mu_max(self) -> float:
+        return math.sqrt(self.dr)
+
+    @property
+    def mu_min(self) -> float:
+        return 1.0 / math.sqrt(self.dr)
+
+    def n_level(self, level: int) -> int:
+        """Cells per axis on `level` (0 = coarsest)."""
+        return self.n_fine >> (self.levels - 1 - level)
+
+    def centers(self) -> np.ndarray:
+        """Sinker centres, shape (n_sinkers, dim), uniform on [0,1)^dim."""
+        return sinker_centers(self.n_sinkers, self.dim, self.seed)
+
+    def fourier_amplitudes(self) -> np.ndarray:
+        """Standard-normal amplitudes a[c, m_1..m_d] for the Fourier velocity."""
+        assert self.fourier_seed is not None
+        return fourier_amplitudes(self.dim, self.fourier_modes, self.fourier_seed)
+
+    def unknowns(self) -> Tuple[int, int]:
+        """(interior velocity unknowns, pressure unknowns) on the finest level."""
+        d, n = self.dim, self.n_fine
+        return d * (2 * n - 1) ** d, (d + 1) * n ** d
+
+
+def sinker_centers(n: int, dim: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).random((n, dim))
+
+
+def fourier_amplitudes(dim: int, modes: int, seed: int) -> np.ndarray:
+    shape = (dim,) + (modes,) * dim
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+CONFIGS = {
+    # 2D 16x16, 2 levels, V(2,2), gamma 1e2, 4 sinkers, DR 1e2
+    "c1": Workload("c1_2d_16sq_L2", 2, 16, 2, 4, 1e2, 1e2, 101),
+    # 2D 128x128, 4 levels, 16 sinkers, DR 1e6, gamma 1e3, FGMRES(30) to 1e-8
+    "c2": Workload("c2_2d_128sq_L4", 2, 128, 4, 16, 1e6, 1e3, 201),
+    # 3D 32^3, 3 levels, 24 sinkers, DR 1e8, gamma 1e4
+    "c3": Workload("c3_3d_32cu_L3", 3, 32, 3, 24, 1e8, 1e4, 301),
+    # 3D 48^3, 3 levels, viscoplastic Newton tensor over a 24-sinker base field, DR 1e10
+    "c4": Workload("c4_3d_48cu_L3_tensor", 3, 48, 3, 24, 1e10, 1e4, 401,
+                   coef_kind=1, fourier_seed=402),
+}
+
+
+def small(dim: int, n_fine: int, levels: int, *, n_sinkers: int = 4, dr: float = 1e2,
+          gamma: float = 1e2, seed: int = 7, **kw) -> Workload:
+    """A small workload for tests, same recipe as the named configurations."""
+    name = f"t{dim}d_{n_fine}_L{levels}_g{gamma:g}_dr{dr:g}_s{seed}"
+    return Workload(name, dim, n_fine, levels, n_sinkers, dr, gamma, seed, **kw)
+
+
+def serving_stream(n_requests: int = 200, rate_hz: float = 20.0, seed: int = 501):
+    """Poisson stream of mixed 2D/3D requests: list of (arrival_s, Workload).
+
+    Each request is 2D or 3D with probability 1/2; N is uniform over
+    {32,64,128,256} (2D) or {8,16,32} (3D); the contrast is log-uniform in
+    [1e4, 1e8]; 24 sinkers seeded by 10^6 + i. Coarsest mesh 16^2 in 2D,
+    8^3 in 3D (4^3 for an 8^3 request); gamma 1e3 (2D) / 1e4 (3D).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        dim = 2 if rng.random() < 0.5 else 3
+        if dim == 2:
+            n = int(rng.choice([32, 64, 128, 256]))
+            coarse = 16
+            gamma = 1e3
+        else:
+            n = int(rng.choice([8, 16, 32]))
+            coarse = 8 if n > 8 else 4
+            gamma = 1e4
+        levels = int(round(math.log2(n // coarse))) + 1
+        dr = float(10.0 ** rng.uniform(4.0, 8.0))
+        w = Workload(f"req{i}_{dim}d_{n}", dim, n, levels, 24, dr, gamma, 10 ** 6 + i)
+        out.append((t, w))
+    return out
