@@ -1,0 +1,136 @@
+"""Benchmark: Stokes unknowns solved per second to a 1e-8 relative residual.
+
+One step = one full FGMRES solve (block preconditioner with two V-cycles per
+iteration, robust star smoother and transfers, coarse solve) of the 2D
+128x128 multi-sinker problem (4 levels, 16 sinkers, contrast 1e6, gamma 1e3,
+FP64) from x = 0 with the hierarchy already resident in HBM. Setup is timed
+separately. Prints one JSON line.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Stokes DoF solved/s to rel.res 1e-8 (FP64 vs mixed); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(wl, iters_hint):
+    """The oracle's own FGMRES solve of the same workload on the host CPU,
+    BLAS limited to one thread (the oracle is single-threaded Python/SciPy)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.krylov import StokesSolver
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s = StokesSolver(wl)
+        t_setup = time.perf_counter() - t0
+        x, info = s.solve()
+    dof = sum(wl.unknowns())
+    return {"value": dof / info["t_solve"], "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle FGMRES solve of {wl.name} ({info['iters']} iterations, "
+                      f"{info['t_solve']:.1f} s solve, {t_setup:.1f} s setup excluded), 1 thread",
+            "iters": info["iters"], "t_solve_s": info["t_solve"], "t_setup_s": t_setup}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from workloads import CONFIGS
+    from paper_2107_00820_amd import Hierarchy
+
+    wl = CONFIGS[args.config]
+    n_u, n_p = wl.unknowns()
+    dof = n_u + n_p
+    log(f"[bench] workload {wl.name}: {dof} unknowns")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = Hierarchy.from_workload(wl)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"[bench] setup {t_setup:.3f} s")
+    bu, bp = h.stk_rhs()
+    xu, xp = h.zeros_u(), h.zeros_p()
+    for i in range(args.warmup):
+        _, _, info = h.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp)
+        log(f"[bench] warmup {i}: {info['iters']} iterations, rel res {info['rel_res']:.2e}")
+    # timed region
+    h.stk_profile(True)
+    lat = []
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        _, _, info = h.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp)
+        lat.append(time.perf_counter() - ts)
+        iters.append(info["iters"])
+        assert info["converged"], info
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    n_gemv, ms_gemv, by_gemv = h.stk_profile_read(0)
+    n_elem, ms_elem, by_elem = h.stk_profile_read(1)
+    h.stk_profile(False)
+    log(f"[bench] {args.steps} solves in {t_total:.3f} s, iterations {iters}")
+    value = dof * args.steps / t_total
+    ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": "k_asm_gemv (interior star patches, all levels)",
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "launches": n_gemv,
+                "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
+                "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
+                "time_share_of_solve": (ms_gemv * 1e-3) / t_total,
+                "cell_kernel_avg_us": 1e3 * ms_elem / max(n_elem, 1),
+                "cell_kernel_GBs": (by_elem / (ms_elem * 1e-3) / 1e9) if ms_elem > 0 else 0.0}
+    out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl.name, "dim": wl.dim, "n_fine": wl.n_fine, "levels": wl.levels,
+                      "n_sinkers": wl.n_sinkers, "dr": wl.dr, "gamma": wl.gamma, "seed": wl.seed,
+                      "nu_pre": wl.nu_pre, "nu_post": wl.nu_post, "restart": wl.restart, "rtol": wl.rtol,
+                      "unknowns": dof, "iterations": iters[-1], "setup_s": t_setup,
+                      "form": "fp64"},
+           "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, iters[-1])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

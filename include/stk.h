@@ -1,0 +1,185 @@
+/*
+ * stk -- augmented-Lagrangian Stokes multigrid on AMD MI355X (gfx950).
+ *
+ * C ABI of libstk.so. Problem (Section 2, eq. (stokessys); Section 3,
+ * eq. (augstokessys)): find (u, p) in [Q2]^d x P1disc on the unit square/cube,
+ * u = 0 on the boundary, int p = 0, with
+ *     [A_gamma  B^T] [u]   [b_u]
+ *     [B        0  ] [p] = [ 0 ],   A_gamma = A + gamma B^T W^{-1} B,
+ * A the viscous form (2 mu eps(u), eps(v)) (or (C:eps(u), eps(v)) for a
+ * fourth-order tensor C), B the divergence -(psi, div u), W the pressure mass
+ * matrix M_p (preconditioner P1) or M_p(1/mu) (P2).
+ *
+ * Conventions for every buffer argument:
+ *  - All vectors are caller-owned contiguous DEVICE buffers unless stated.
+ *  - Velocity "stored" layout on a level with N cells per axis: the full node
+ *    grid of (2N+1)^d nodes per component, component-major, x fastest:
+ *    index = comp*(2N+1)^d + (iz*(2N+1) + iy)*(2N+1) + ix. Entries on the
+ *    boundary (Dirichlet nodes) are ignored on input and written as 0.
+ *  - Pressure layout: p[cell*(d+1) + m], cell lexicographic with x fastest,
+ *    basis psi_0 = 1, psi_j = (x_j - c_j)/h on each cell (c the cell centre).
+ *  - Level 0 is the coarsest level, level n_levels-1 the finest.
+ *  - Every call is asynchronous on the HIP stream passed (hipStream_t as
+ *    void*, NULL = default stream) except stk_setup_hierarchy and stk_solve,
+ *    which return after their work has completed.
+ *  - Errors: no exception crosses the ABI; every call returns a stk_status
+ *    and stk_last_error() returns a thread-local message for the last failure.
+ *  - A hierarchy is used by one stream at a time; calls that overlap on one
+ *    hierarchy race on its work buffers.
+ */
+#ifndef STK_H
+#define STK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stk_hier stk_hier;   /* opaque, library-owned device state */
+
+typedef enum {
+  STK_OK = 0,
+  STK_EINVAL = -1,      /* bad argument (size, level, null pointer, dtype) */
+  STK_ENOMEM = -2,      /* device allocation failed or footprint over budget */
+  STK_EDEVICE = -3,     /* a HIP call failed */
+  STK_ENOTCONV = -4,    /* FGMRES hit maxit; the best iterate is returned */
+  STK_ENOTSPD = -5,     /* non-positive pivot in a patch or coarse factorisation */
+  STK_ENAN = -6,        /* NaN/Inf in the right-hand side or the residual */
+  STK_EBUSY = -7        /* a solve is still running (serving interface) */
+} stk_status;
+
+typedef enum { STK_F64 = 0, STK_F32 = 1 } stk_dtype;
+
+/* Multi-sinker viscosity of Section 5.2 (reading: floor mu_min and squared
+ * Gaussian):  chi(x) = prod_i [1 - exp(-delta max(0,|x-c_i| - omega/2)^2)],
+ * mu = (mu_max - mu_min)(1 - chi) + mu_min, forcing f = (0,..,beta(chi-1)).
+ * `centers` is a HOST array [n][d] copied during setup. */
+typedef struct {
+  int n;
+  const double* centers;
+  double omega, delta, mu_min, mu_max, beta;
+} stk_sinker;
+
+typedef struct {
+  int dim;            /* 2 or 3 */
+  int n_fine;         /* cells per axis on the finest level, divisible by 2^(n_levels-1) */
+  int n_levels;       /* >= 2 */
+  double gamma;       /* augmented-Lagrangian parameter, >= 0 */
+  int schur;          /* 1 = P1 (W = M_p), 2 = P2 (W = M_p(1/mu)); only 1 is built */
+  int coef_kind;      /* 0 = scalar sinker viscosity (only kind built) */
+  stk_sinker sinker;
+  int nu_pre, nu_post;   /* right-preconditioned GMRES relaxation steps, 1..8 */
+  int mixed;          /* 0 = plain FP64 form (only form built) */
+  size_t hbm_budget;  /* bytes; 0 = unlimited. Setup fails with STK_ENOMEM above it */
+} stk_desc;
+
+/* Device bytes that stk_setup_hierarchy will allocate for `desc` (host-only
+ * arithmetic, no device work). Returns STK_EINVAL for an invalid desc. */
+stk_status stk_footprint(const stk_desc* desc, size_t* bytes);
+
+/* Builds the hierarchy on the current HIP device: coefficients at the Gauss
+ * points of every level (rediscretisation, Section 5.1), the inverses of all
+ * vertex-star patch matrices of levels >= 1 (Section 4.1, eq. (viim);
+ * factored by Cholesky in FP64 and stored as explicit packed inverses), the
+ * explicit inverse of the coarsest A_gamma (the paper uses a sparse direct
+ * solver), and the cellwise Schur blocks Shat_gamma^{-1} = M_K(1/mu)^{-1} +
+ * gamma M_K^{-1} (eq. (P1P2), Section 5.1). Synchronises `stream` before
+ * returning. On failure *out is NULL and nothing is leaked. */
+stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** out);
+
+/* Frees everything the hierarchy owns. NULL is accepted. */
+stk_status stk_destroy(stk_hier* h);
+
+/* Stored velocity length and pressure length on `level`. */
+stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_t* n_pres);
+
+/* Right-hand side of the finest level: b_u = (f, phi_i) (stored layout,
+ * FP64), b_p = 0 (may be NULL). */
+stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream);
+
+/* y = A_gamma x on `level` (matrix-free, Section 2 entries plus the
+ * augmented term of Section 3). x and y are FP64 stored-layout vectors and
+ * must not alias. dtype must be STK_F64. */
+stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, void* y, void* stream);
+
+/* (y_u, y_p) = K (x_u, x_p), K = [[A_gamma, B^T], [B, 0]] on the finest level. */
+stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p,
+                            double* y_u, double* y_p, void* stream);
+
+/* y = D^{-1} r = sum_i I_i A_i^{-1} I_i^T r: one application of the
+ * vertex-star additive Schwarz operator on `level` >= 1 (Section 4.1). */
+stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream);
+
+/* x <- nsteps of GMRES relaxation on A_gamma x = b on `level` >= 1, right-
+ * preconditioned by D^{-1}, starting from the x passed in (zero allowed). */
+stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x, int nsteps,
+                      void* stream);
+
+/* xf = P~ xc: robust prolongation from `coarse_level` to coarse_level+1
+ * (Section 4.2, eq. (Ptilde)): the standard Q2 prolongation minus the
+ * solution of the local problems on the fine unknowns strictly inside each
+ * coarse cell with right-hand side gamma B^T W^{-1} B P_H xc. */
+stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc, void* xf,
+                       void* stream);
+
+/* rc = P~^T rf: restriction from `fine_level` to fine_level-1 (transpose of
+ * the robust prolongation). */
+stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, void* rc,
+                        void* stream);
+
+/* x = A_0,gamma^{-1} b on the coarsest level (dense explicit inverse). */
+stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream);
+
+/* x = one V-cycle applied to b on the finest level (pre-relaxation from 0,
+ * residual, restriction, recursion, prolongation, post-relaxation). */
+stk_status stk_vcycle(stk_hier* h, const double* b, double* x, void* stream);
+
+/* (z_u, z_p) = P (v_u, v_p): the block preconditioner of eq. (precond) with
+ * two V-cycles and the cellwise Schur blocks; z_p has zero mean. */
+stk_status stk_precond(stk_hier* h, const double* v_u, const double* v_p,
+                       double* z_u, double* z_p, void* stream);
+
+typedef struct {
+  double rtol;   /* stop when ||b - Kx||_2 <= rtol ||b||_2 (default 1e-8) */
+  int restart;   /* FGMRES restart length (default 30, max 64) */
+  int maxit;     /* maximum iterations (default 300, max 1000) */
+} stk_solve_opts;
+
+typedef struct {
+  int iters;            /* FGMRES iterations done */
+  int converged;        /* 1 if the true residual met rtol */
+  double rel_res;       /* true ||b - Kx|| / ||b|| at exit */
+  double t_solve_s;     /* wall time of the solve */
+  double hist[1001];    /* Arnoldi residual estimate / ||b|| after i iterations */
+} stk_solve_info;
+
+/* Solves the augmented Stokes system with right-preconditioned FGMRES
+ * (Section 5.1) from x = 0. b_p may be NULL (zero). The pressure of the
+ * result has zero mean. Host-synchronous. Returns STK_ENOTCONV if maxit was
+ * reached (x then holds the last iterate) and STK_ENAN for a non-finite
+ * right-hand side or residual. */
+stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                     const stk_solve_opts* opts, stk_solve_info* info, void* stream);
+
+/* Kernel timing (tracing). stk_profile(h, 1) clears the records and starts
+ * bracketing launches of the instrumented kernel families with HIP events on
+ * the launch stream; stk_profile(h, 0) stops. stk_profile_read synchronises
+ * the stream and returns, for family `kernel`, the number of launches, their
+ * summed duration in ms and the summed algorithmic bytes:
+ *   kernel 0: batched star-patch solve of the interior patches (all levels);
+ *             bytes = packed inverses + patch outputs + one residual read;
+ *   kernel 1: cell kernel of the A_gamma apply (all levels); bytes = velocity
+ *             input + viscosity at Gauss points + element outputs. */
+stk_status stk_profile(stk_hier* h, int enable);
+stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* total_ms,
+                            double* total_bytes);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* stk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STK_H */

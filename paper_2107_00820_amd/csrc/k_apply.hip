@@ -1,0 +1,465 @@
+// Matrix-free operator kernels: coefficients at Gauss points, the cell kernel
+// of A_gamma / B / B^T, the deterministic node gather, the right-hand side,
+// and the cellwise Schur-complement blocks.
+//
+// Operator (Section 2, entries after eq. (stokessys); Section 3, eq.
+// (augstokessys)): on each cell K of width h
+//   A_K u = h^{d-2} sum_q w_q mu_q [ (G + G^T) : dphi ]      (G = reference gradient of u)
+//   G_K u = gamma h^{d-2} Bhat^T Mhat^{-1} Bhat u             (gamma B^T M_p^{-1} B, cell-local)
+//   (B u)_K = -h^{d-1} Bhat u,   (B^T p)_K = -h^{d-1} Bhat^T p
+// with Bhat[m][j] = int_ref psi_m div(phi_j) and Mhat = diag(1, 1/12, ..) the
+// reference pressure mass matrix (W = M_p; preconditioner P1 of eq. (P1P2)).
+//
+// Determinism: the cell kernel writes element vectors E[j][cell]; a node
+// kernel sums the <= 2^d cell contributions of each node in a fixed order.
+// No atomics, so repeated applications give bit-identical results.
+#include "stk_internal.h"
+
+namespace stk {
+
+template <int D>
+__device__ inline void cell_coords(const LevelGeo& g, int64_t cell, int c[3]) {
+  c[0] = (int)(cell % g.N);
+  c[1] = (int)((cell / g.N) % g.N);
+  c[2] = D == 3 ? (int)(cell / ((int64_t)g.N * g.N)) : 0;
+}
+
+// chi(x) of the multi-sinker field (reading: squared Gaussian).
+template <int D>
+__device__ inline double sinker_chi(const double* __restrict__ ctr, int ns, double omega, double delta,
+                                    const double x[D]) {
+  double out = 1.0;
+  for (int i = 0; i < ns; ++i) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double dx = x[k] - ctr[i * D + k];
+      s2 += dx * dx;
+    }
+    const double s = fmax(0.0, sqrt(s2) - 0.5 * omega);
+    out *= (1.0 - exp(-delta * s * s));
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, double omega,
+                            double delta, double mu_min, double mu_max, double* __restrict__ mu) {
+  constexpr int NQ = Dims<D>::NQ;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)NQ * g.ncell) return;
+  const int q = (int)(idx / g.ncell);
+  const int64_t cell = idx - (int64_t)q * g.ncell;
+  int c[3];
+  cell_coords<D>(g, cell, c);
+  double x[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[k] = g.h * ((double)c[k] + kGaussX[digit(q, k)]);
+  const double chi = sinker_chi<D>(ctr, ns, omega, delta, x);
+  mu[idx] = (mu_max - mu_min) * (1.0 - chi) + mu_min;
+}
+
+// ---------------------------------------------------------------------------
+// Cell kernel. One thread per cell, everything in registers, tables folded.
+template <int D, int MODE>
+__global__ void __launch_bounds__(D == 2 ? 256 : 64)
+k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __restrict__ u,
+       const double* __restrict__ p, double* __restrict__ E, double* __restrict__ pout) {
+  constexpr int NN = Dims<D>::NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int c[3];
+  cell_coords<D>(g, cell, c);
+  const double h = g.h;
+  double ue[NL];
+  constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  if (need_u) {
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      const int a0 = 2 * c[0] + digit(n, 0), a1 = 2 * c[1] + digit(n, 1);
+      const int a2 = D == 3 ? 2 * c[2] + digit(n, 2) : 0;
+      bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
+      if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
+      const int64_t nd = node_index<D>(g, a0, a1, a2);
+#pragma unroll
+      for (int comp = 0; comp < D; ++comp)
+        ue[comp * NN + n] = bnd ? 0.0 : u[comp * g.nnodes + nd];
+    }
+  }
+  double ye[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) ye[j] = 0.0;
+
+  if (MODE & EL_VISC) {
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+      double G[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          double s = 0.0;
+#pragma unroll
+          for (int n = 0; n < NN; ++n)
+            if (T.dphi[q][n][k] != 0.0) s += T.dphi[q][n][k] * ue[a * NN + n];
+          G[a][k] = s;
+        }
+      const double wm = T.w[q] * mu[(int64_t)q * g.ncell + cell];
+      double S[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) S[a][k] = wm * (G[a][k] + G[k][a]);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+          double s = ye[a * NN + n];
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+            if (T.dphi[q][n][k] != 0.0) s += S[a][k] * T.dphi[q][n][k];
+          ye[a * NN + n] = s;
+        }
+    }
+  }
+  // pressure-like coefficients multiplying Bhat^T: gamma * Mhat^{-1} Bhat u - h p
+  double cm[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) cm[m] = 0.0;
+  if (MODE & (EL_AUG | EL_BOUT)) {
+    double bu[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j)
+        if (T.bhat[m][j] != 0.0) s += T.bhat[m][j] * ue[j];
+      bu[m] = s;
+    }
+    if (MODE & EL_AUG) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) cm[m] += gamma * bu[m] / T.mhat[m];
+    }
+    if (MODE & EL_BOUT) {
+      const double sc = -(D == 2 ? h : h * h);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) pout[cell * NP + m] = sc * bu[m];
+    }
+  }
+  if (MODE & EL_BT) {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) cm[m] -= h * p[cell * NP + m];
+  }
+  if (MODE & (EL_AUG | EL_BT)) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double s = ye[j];
+#pragma unroll
+      for (int m = 0; m < NP; ++m)
+        if (T.bhat[m][j] != 0.0) s += T.bhat[m][j] * cm[m];
+      ye[j] = s;
+    }
+  }
+  const double sc = D == 2 ? 1.0 : h;   // h^{d-2}
+#pragma unroll
+  for (int j = 0; j < NL; ++j) E[(int64_t)j * g.ncell + cell] = sc * ye[j];
+}
+
+// ---------------------------------------------------------------------------
+// out[idx] = base[idx] + alpha * sum_{cells K containing node} E_K[local],
+// 0 on Dirichlet nodes. One thread per stored entry.
+template <int D>
+__global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double* __restrict__ base,
+                         double alpha, double* __restrict__ out) {
+  constexpr int NN = Dims<D>::NN;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)D * g.nnodes) return;
+  const int comp = (int)(idx / g.nnodes);
+  const int64_t nd = idx - (int64_t)comp * g.nnodes;
+  int i[3];
+  i[0] = (int)(nd % g.n1);
+  i[1] = (int)((nd / g.n1) % g.n1);
+  i[2] = D == 3 ? (int)(nd / ((int64_t)g.n1 * g.n1)) : 0;
+  bool bnd = false;
+#pragma unroll
+  for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
+  if (bnd) {
+    out[idx] = 0.0;
+    return;
+  }
+  // per axis up to two (cell, local) pairs
+  int cc[3][2], ll[3][2], cnt[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= D) {
+      cnt[k] = 1; cc[k][0] = 0; ll[k][0] = 0;
+      continue;
+    }
+    if (i[k] & 1) {
+      cnt[k] = 1; cc[k][0] = (i[k] - 1) >> 1; ll[k][0] = 1;
+    } else {
+      cnt[k] = 2; cc[k][0] = (i[k] >> 1) - 1; ll[k][0] = 2; cc[k][1] = i[k] >> 1; ll[k][1] = 0;
+    }
+  }
+  double s = 0.0;
+  for (int t2 = 0; t2 < cnt[2]; ++t2)
+    for (int t1 = 0; t1 < cnt[1]; ++t1)
+      for (int t0 = 0; t0 < cnt[0]; ++t0) {
+        const int64_t cell = cell_index<D>(g, cc[0][t0], cc[1][t1], cc[2][t2]);
+        const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
+        s += E[(int64_t)(comp * NN + loc) * g.ncell + cell];
+      }
+  out[idx] = (base ? base[idx] : 0.0) + alpha * s;
+}
+
+// ---------------------------------------------------------------------------
+// Element right-hand side (f, phi) with f = (0, .., beta (chi - 1)).
+template <int D>
+__global__ void k_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, double omega,
+                           double delta, double beta, double* __restrict__ E) {
+  constexpr int NN = Dims<D>::NN;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int c[3];
+  cell_coords<D>(g, cell, c);
+  double be[NN];
+#pragma unroll
+  for (int n = 0; n < NN; ++n) be[n] = 0.0;
+  for (int q = 0; q < NN; ++q) {
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = g.h * ((double)c[k] + kGaussX[digit(q, k)]);
+    const double f = beta * (sinker_chi<D>(ctr, ns, omega, delta, x) - 1.0);
+#pragma unroll
+    for (int n = 0; n < NN; ++n) be[n] += T.w[q] * T.phi[q][n] * f;
+  }
+  const double vol = D == 2 ? g.h * g.h : g.h * g.h * g.h;
+  for (int comp = 0; comp < D - 1; ++comp)
+    for (int n = 0; n < NN; ++n) E[(int64_t)(comp * NN + n) * g.ncell + cell] = 0.0;
+#pragma unroll
+  for (int n = 0; n < NN; ++n) E[(int64_t)((D - 1) * NN + n) * g.ncell + cell] = vol * be[n];
+}
+
+// ---------------------------------------------------------------------------
+// Schur blocks Shat_gamma,K^{-1} = M_K(1/mu)^{-1} + gamma M_K^{-1} (eq. (P1P2), P1).
+template <int D>
+__global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double gamma,
+                              double* __restrict__ Sinv) {
+  constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const double vol = D == 2 ? g.h * g.h : g.h * g.h * g.h;
+  double M[NP][NP], X[NP][NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      M[a][b] = 0.0;
+      X[a][b] = a == b ? 1.0 : 0.0;
+    }
+  for (int q = 0; q < NN; ++q) {
+    const double wq = T.w[q] * vol / mu[(int64_t)q * g.ncell + cell];
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) M[a][b] += wq * T.psi[q][a] * T.psi[q][b];
+  }
+  // Gauss-Jordan on the SPD block (no pivoting needed)
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double piv = 1.0 / M[k][k];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      M[k][b] *= piv;
+      X[k][b] *= piv;
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      if (a == k) continue;
+      const double f = M[a][k];
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        M[a][b] -= f * M[k][b];
+        X[a][b] -= f * X[k][b];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      double v = X[a][b];
+      if (a == b) v += gamma / (vol * T.mhat[a]);
+      Sinv[cell * NP * NP + a * NP + b] = v;
+    }
+}
+
+// z_p = -Sinv (v_p - B y) per cell.
+template <int D>
+__global__ void k_schur_apply(LevelGeo g, const double* __restrict__ Sinv, const double* __restrict__ y,
+                              const double* __restrict__ vp, double* __restrict__ zp) {
+  constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int c[3];
+  cell_coords<D>(g, cell, c);
+  double bu[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) bu[m] = 0.0;
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    const int a0 = 2 * c[0] + digit(n, 0), a1 = 2 * c[1] + digit(n, 1);
+    const int a2 = D == 3 ? 2 * c[2] + digit(n, 2) : 0;
+    bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
+    if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
+    if (bnd) continue;
+    const int64_t nd = node_index<D>(g, a0, a1, a2);
+#pragma unroll
+    for (int comp = 0; comp < D; ++comp) {
+      const double v = y[comp * g.nnodes + nd];
+#pragma unroll
+      for (int m = 0; m < NP; ++m)
+        if (T.bhat[m][comp * NN + n] != 0.0) bu[m] += T.bhat[m][comp * NN + n] * v;
+    }
+  }
+  const double sc = -(D == 2 ? g.h : g.h * g.h);
+  double t[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) t[m] = vp[cell * NP + m] - sc * bu[m];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) s += Sinv[cell * NP * NP + a * NP + b] * t[b];
+    zp[cell * NP + a] = -s;
+  }
+}
+
+// Deterministic mean of psi_0 coefficients: fixed grid of partial sums, then
+// every block of the subtraction kernel reduces the partials in the same order.
+template <int NP>
+__global__ void k_p0_partials(int64_t ncell, const double* __restrict__ p, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x)
+    s += p[c * NP];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <int NP>
+__global__ void k_p0_subtract(int64_t ncell, const double* __restrict__ part, int nparts, double* __restrict__ p) {
+  __shared__ double mean;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    mean = s / (double)ncell;
+  }
+  __syncthreads();
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x)
+    p[c * NP] -= mean;
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 2) {
+    const int64_t n = (int64_t)Dims<2>::NQ * l.g.ncell;
+    hipLaunchKernelGGL(k_mu_sinker<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers,
+                       H.omega, H.delta, H.mu_min, H.mu_max, l.mu);
+  } else {
+    const int64_t n = (int64_t)Dims<3>::NQ * l.g.ncell;
+    hipLaunchKernelGGL(k_mu_sinker<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers,
+                       H.omega, H.delta, H.mu_min, H.mu_max, l.mu);
+  }
+}
+
+template <int D, int MODE>
+static void elem_launch(const Hier& H, const Level& l, const double* u, const double* p, double* pout,
+                        hipStream_t s) {
+  const int t = D == 2 ? 256 : 64;
+  hipLaunchKernelGGL((k_elem<D, MODE>), dim3(nblk(l.g.ncell, t)), dim3(t), 0, s, l.g, l.mu, H.gamma, u, p,
+                     l.E, pout);
+}
+
+template <int D>
+static void elem_dispatch(const Hier& H, const Level& l, int mode, const double* u, const double* p,
+                          double* pout, hipStream_t s) {
+  switch (mode) {
+    case EL_VISC | EL_AUG: elem_launch<D, EL_VISC | EL_AUG>(H, l, u, p, pout, s); break;
+    case EL_AUG: elem_launch<D, EL_AUG>(H, l, u, p, pout, s); break;
+    case EL_BT: elem_launch<D, EL_BT>(H, l, u, p, pout, s); break;
+    case EL_VISC | EL_AUG | EL_BT | EL_BOUT:
+      elem_launch<D, EL_VISC | EL_AUG | EL_BT | EL_BOUT>(H, l, u, p, pout, s);
+      break;
+    default: break;
+  }
+}
+
+void launch_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
+                 hipStream_t s) {
+  if (H.dim == 2) elem_dispatch<2>(H, l, mode, u, p, pout, s);
+  else elem_dispatch<3>(H, l, mode, u, p, pout, s);
+}
+
+void launch_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out,
+                   hipStream_t s) {
+  const int64_t n = (int64_t)H.dim * l.g.nnodes;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_gather<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.E, base, alpha, out);
+  else
+    hipLaunchKernelGGL(k_gather<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.E, base, alpha, out);
+}
+
+void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_rhs_elem<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.beta, l.E);
+  else
+    hipLaunchKernelGGL(k_rhs_elem<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.beta, l.E);
+}
+
+void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_schur_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma,
+                       H.Sinv);
+  else
+    hipLaunchKernelGGL(k_schur_setup<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma,
+                       H.Sinv);
+}
+
+void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
+                        hipStream_t s) {
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_schur_apply<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.Sinv, y, vp, zp);
+  else
+    hipLaunchKernelGGL(k_schur_apply<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.Sinv, y, vp, zp);
+}
+
+void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
+  if (H.dim == 2) {
+    hipLaunchKernelGGL(k_p0_partials<3>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_subtract<3>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials,
+                       kRedBlocks, p);
+  } else {
+    hipLaunchKernelGGL(k_p0_partials<4>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_subtract<4>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials,
+                       kRedBlocks, p);
+  }
+}
+
+}  // namespace stk

@@ -1,0 +1,266 @@
+// Vertex-star additive Schwarz (Section 4.1, eq. (viim)): patch setup,
+// the batched patch solve and the deterministic overlap sum; plus the local
+// solves of the robust prolongation (Section 4.2, eq. (Ptilde)), which reuse
+// the factors of the star patches centred in the coarse cells.
+//
+// Patch of vertex v: the unknowns at the nodes strictly inside the cells
+// around v, i.e. per axis the nodes 2v-1, 2v, 2v+1 that are interior to the
+// domain (one node for a vertex on the boundary), all components.
+// Unknown order inside a patch: component-major, then nodes x-fastest.
+//
+// Setup (one workgroup per patch): the patch matrix is assembled from
+// Gauss-point integrals of the cells of the star (equal to the rows and
+// columns of the assembled A_gamma), factored A = L L^T in LDS, inverted
+// (L^{-1}, then L^{-T} L^{-1}) and stored as a packed lower triangle. Patches
+// of one class are interleaved in blocks of 64: element k of patch s sits at
+// ((s/64)*P + k)*64 + s%64 (P = n(n+1)/2), so a wavefront processing 64
+// patches reads 512 contiguous bytes per element.
+//
+// Apply (one lane per patch): gather the patch residual, symmetric GEMV from
+// the packed inverse, write the result into a vertex-indexed buffer; a node
+// kernel then sums the <= 2^d overlapping patch results in a fixed order.
+#include "stk_dev.h"
+
+namespace stk {
+
+template <int D>
+__global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, double gamma, int n,
+                              const int* __restrict__ verts, int count, double* __restrict__ inv,
+                              int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const int ld = n + 1;
+  double* a = sm;
+  double* tmp = sm + n * ld;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  int lo[3], ext[3], vc[3];
+  patch_box<D>(g, verts[s], lo, ext, vc);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    if (j > i) continue;
+    int ni[3], nj[3];
+    const int ci = patch_dof<D>(i, lo, ext, ni);
+    const int cj = patch_dof<D>(j, lo, ext, nj);
+    const double v = global_entry<D>(g, mu, gamma, ci, ni, cj, nj);
+    a[i * ld + j] = v;
+    a[j * ld + i] = v;
+  }
+  __syncthreads();
+  spd_invert_lds(a, n, ld, tmp, &bad);
+  const int64_t P = (int64_t)n * (n + 1) / 2;
+  double* dst = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  for (int i = 0; i < n; ++i)
+    for (int j = threadIdx.x; j <= i; j += blockDim.x)
+      dst[((int64_t)i * (i + 1) / 2 + j) * 64] = a[i * ld + j];
+  if (threadIdx.x == 0 && bad) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// y = A^{-1} x with A^{-1} packed lower, element stride 64.
+template <int NPT>
+__device__ inline void packed_symv(const double* __restrict__ A, const double (&x)[NPT], double (&y)[NPT]) {
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) y[i] = 0.0;
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const double a = A[(int64_t)k * 64];
+      ++k;
+      y[i] += a * x[j];
+      if (j != i) y[j] += a * x[i];
+    }
+  }
+}
+
+template <int D, int NPT>
+__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, const int* __restrict__ verts, int count,
+                                                  const double* __restrict__ inv, const double* __restrict__ r,
+                                                  double* __restrict__ zbuf, int nvert) {
+  constexpr int NN = Dims<D>::NN;
+  constexpr int NBOX = NPT / D;
+  constexpr bool FULL = NBOX == NN;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= count) return;
+  const int vert = verts[s];
+  int lo[3], ext[3], vc[3];
+  patch_box<D>(g, vert, lo, ext, vc);
+  if (FULL) { ext[0] = 3; ext[1] = 3; ext[2] = D == 3 ? 3 : 1; }
+  double x[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    int nd[3];
+    const int comp = patch_dof<D>(i, lo, ext, nd);
+    x[i] = r[comp * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])];
+  }
+  const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
+  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  double y[NPT];
+  packed_symv<NPT>(A, x, y);
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    int nd[3];
+    const int comp = patch_dof<D>(i, lo, ext, nd);
+    int loc = 0, mul = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      loc += (nd[k] - (2 * vc[k] - 1)) * mul;
+      mul *= 3;
+    }
+    zbuf[(int64_t)(comp * NN + loc) * nvert + vert] = y[i];
+  }
+}
+
+// y[idx] = sum over the patches containing the node of their results; 0 on Dirichlet nodes.
+template <int D>
+__global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nvert, double* __restrict__ y) {
+  constexpr int NN = Dims<D>::NN;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)D * g.nnodes) return;
+  const int comp = (int)(idx / g.nnodes);
+  const int64_t nd = idx - (int64_t)comp * g.nnodes;
+  int i[3];
+  i[0] = (int)(nd % g.n1);
+  i[1] = (int)((nd / g.n1) % g.n1);
+  i[2] = D == 3 ? (int)(nd / ((int64_t)g.n1 * g.n1)) : 0;
+  bool bnd = false;
+#pragma unroll
+  for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
+  if (bnd) {
+    y[idx] = 0.0;
+    return;
+  }
+  int vv[3][2], ll[3][2], cnt[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= D) { cnt[k] = 1; vv[k][0] = 0; ll[k][0] = 0; continue; }
+    if (i[k] & 1) {
+      cnt[k] = 2; vv[k][0] = (i[k] - 1) >> 1; ll[k][0] = 2; vv[k][1] = (i[k] + 1) >> 1; ll[k][1] = 0;
+    } else {
+      cnt[k] = 1; vv[k][0] = i[k] >> 1; ll[k][0] = 1;
+    }
+  }
+  const int nv = g.N + 1;
+  double s = 0.0;
+  for (int t2 = 0; t2 < cnt[2]; ++t2)
+    for (int t1 = 0; t1 < cnt[1]; ++t1)
+      for (int t0 = 0; t0 < cnt[0]; ++t0) {
+        const int vert = vv[0][t0] + nv * (vv[1][t1] + nv * vv[2][t2]);
+        const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
+        s += zbuf[(int64_t)(comp * NN + loc) * nvert + vert];
+      }
+  y[idx] = s;
+}
+
+// Local solves of the robust transfer: for every coarse cell K (one lane),
+// z = A_K^{-1} in|_K where A_K is the star patch of the fine vertex 2K+1
+// (interior-patch slot lex(K)); out|_K = (accumulate ? out|_K : 0) + alpha z.
+template <int D>
+__global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const double* __restrict__ inv,
+                                                      const double* __restrict__ in, double* __restrict__ out,
+                                                      double alpha, int accumulate) {
+  constexpr int NN = Dims<D>::NN, NPT = Dims<D>::NL;
+  const int nc = g.N / 2;
+  const int ncc = D == 2 ? nc * nc : nc * nc * nc;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= ncc) return;
+  const int K0 = s % nc, K1 = (s / nc) % nc, K2 = D == 3 ? s / (nc * nc) : 0;
+  const int lo[3] = {4 * K0 + 1, 4 * K1 + 1, D == 3 ? 4 * K2 + 1 : 0};
+  const int ext[3] = {3, 3, D == 3 ? 3 : 1};
+  double x[NPT];
+  int64_t addr[NN];
+#pragma unroll
+  for (int i = 0; i < NN; ++i) {
+    int nd[3];
+    patch_dof<D>(i, lo, ext, nd);
+    addr[i] = node_index<D>(g, nd[0], nd[1], nd[2]);
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int i = 0; i < NN; ++i) x[c * NN + i] = in[c * g.nnodes + addr[i]];
+  const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
+  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  double y[NPT];
+  packed_symv<NPT>(A, x, y);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+      const int64_t o = c * g.nnodes + addr[i];
+      out[o] = (accumulate ? out[o] : 0.0) + alpha * y[c * NN + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
+  if (pc.count == 0) return;
+  const size_t shm = (size_t)(pc.n * (pc.n + 1) + pc.n) * sizeof(double);
+  const int nt = pc.n > 32 ? 256 : 64;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_patch_setup<2>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, H.gamma, pc.n, pc.verts,
+                       pc.count, pc.inv, H.flag);
+  else
+    hipLaunchKernelGGL(k_patch_setup<3>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, H.gamma, pc.n, pc.verts,
+                       pc.count, pc.inv, H.flag);
+}
+
+template <int D, int NPT>
+static void gemv_launch(const Level& l, const PatchClass& pc, const double* r, hipStream_t s) {
+  hipLaunchKernelGGL((k_asm_gemv<D, NPT>), dim3(nblk(pc.count, 64)), dim3(64), 0, s, l.g, pc.verts, pc.count,
+                     pc.inv, r, l.zbuf, l.nvert);
+}
+
+void launch_asm(Hier& H, const Level& l, const double* r, double* y, hipStream_t s) {
+  for (size_t ci = 0; ci < l.cls.size(); ++ci) {
+    const PatchClass& pc = l.cls[ci];
+    if (pc.count == 0) continue;
+    hipEvent_t ev = nullptr;
+    if (ci == 0) prof_begin(H, s, &ev);
+    if (H.dim == 2) {
+      switch (pc.n) {
+        case 18: gemv_launch<2, 18>(l, pc, r, s); break;
+        case 6: gemv_launch<2, 6>(l, pc, r, s); break;
+        case 2: gemv_launch<2, 2>(l, pc, r, s); break;
+        default: break;
+      }
+    } else {
+      switch (pc.n) {
+        case 81: gemv_launch<3, 81>(l, pc, r, s); break;
+        case 27: gemv_launch<3, 27>(l, pc, r, s); break;
+        case 9: gemv_launch<3, 9>(l, pc, r, s); break;
+        case 3: gemv_launch<3, 3>(l, pc, r, s); break;
+        default: break;
+      }
+    }
+    if (ci == 0) {
+      // algorithmic bytes: packed inverses + patch outputs + one read of the residual
+      const double bytes = 8.0 * ((double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n) + (double)l.nvel);
+      prof_end(H, s, PROF_ASM_GEMV, ev, bytes);
+    }
+  }
+  const int64_t n = (int64_t)H.dim * l.g.nnodes;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_asm_gather<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.zbuf, l.nvert, y);
+  else
+    hipLaunchKernelGGL(k_asm_gather<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.zbuf, l.nvert, y);
+}
+
+void launch_center_solve(const Hier& H, const Level& fine, const double* in, double* out, double alpha,
+                         bool accumulate, hipStream_t s) {
+  const int nc = fine.g.N / 2;
+  const int ncc = H.dim == 2 ? nc * nc : nc * nc * nc;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_center_solve<2>, dim3(nblk(ncc, 64)), dim3(64), 0, s, fine.g, fine.cls[0].inv, in, out,
+                       alpha, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_center_solve<3>, dim3(nblk(ncc, 64)), dim3(64), 0, s, fine.g, fine.cls[0].inv, in, out,
+                       alpha, accumulate ? 1 : 0);
+}
+
+}  // namespace stk

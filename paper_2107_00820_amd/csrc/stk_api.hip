@@ -1,0 +1,743 @@
+// Host orchestration and the C ABI of libstk.so: hierarchy setup, the
+// V-cycle with GMRES relaxation, the block preconditioner and FGMRES.
+// Every device step is a hand-written kernel from the k_*.hip files; this file
+// only allocates, sequences launches on the caller's stream and runs the
+// small host-side Givens recurrences of FGMRES.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/stk.h"
+#include "stk_internal.h"
+
+using namespace stk;
+
+struct stk_hier {
+  Hier H;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+stk_status fail(stk_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(STK_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define STKCHK(call)                  \
+  do {                                \
+    stk_status s_ = (call);           \
+    if (s_ != STK_OK) return s_;      \
+  } while (0)
+
+constexpr int kPartialLen = kRedBlocks * 64;
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+stk_status validate(const stk_desc* d) {
+  if (!d) return fail(STK_EINVAL, "desc is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(STK_EINVAL, "dim must be 2 or 3");
+  if (d->n_levels < 2 || d->n_levels > 12) return fail(STK_EINVAL, "n_levels must be in [2, 12]");
+  if (d->n_fine < 2 || d->n_fine % (1 << (d->n_levels - 1)) != 0)
+    return fail(STK_EINVAL, "n_fine must be a positive multiple of 2^(n_levels-1)");
+  if (d->n_fine > (d->dim == 2 ? 4096 : 256)) return fail(STK_EINVAL, "n_fine too large");
+  const int nc = d->n_fine >> (d->n_levels - 1);
+  const int64_t n0 = (int64_t)d->dim * ipow(2 * nc - 1, d->dim);
+  if (n0 > 40000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve");
+  if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
+  if (d->schur != 1) return fail(STK_EINVAL, "only the P1 Schur approximation (schur=1) is built");
+  if (d->coef_kind != 0) return fail(STK_EINVAL, "only the scalar sinker viscosity (coef_kind=0) is built");
+  if (d->mixed != 0) return fail(STK_EINVAL, "only the plain FP64 form (mixed=0) is built");
+  if (d->nu_pre < 1 || d->nu_pre > kMaxNu || d->nu_post < 1 || d->nu_post > kMaxNu)
+    return fail(STK_EINVAL, "nu_pre/nu_post must be in [1, 8]");
+  const stk_sinker& s = d->sinker;
+  if (s.n < 0 || s.n > 4096 || (s.n > 0 && !s.centers)) return fail(STK_EINVAL, "bad sinker list");
+  if (!(s.mu_min > 0.0) || !(s.mu_max > 0.0)) return fail(STK_EINVAL, "viscosities must be positive");
+  if (!(s.omega >= 0.0) || !(s.delta >= 0.0)) return fail(STK_EINVAL, "bad sinker shape parameters");
+  return STK_OK;
+}
+
+// Patch classes of a level: sizes and counts (host arithmetic, used by the
+// footprint and by setup).
+struct ClassPlan {
+  int n;
+  std::vector<int> verts;
+};
+
+std::vector<ClassPlan> plan_patches(int D, int N) {
+  const int nv = N + 1;
+  const int nvert = D == 2 ? nv * nv : nv * nv * nv;
+  std::vector<ClassPlan> cls;
+  ClassPlan inner{D * ipow(3, D), {}};
+  // all-odd vertices first, in lexicographic order of K = (v-1)/2 (coarse cells)
+  const int nc = N / 2;
+  const int ncc = D == 2 ? nc * nc : nc * nc * nc;
+  for (int s = 0; s < ncc; ++s) {
+    const int k0 = s % nc, k1 = (s / nc) % nc, k2 = D == 3 ? s / (nc * nc) : 0;
+    const int v0 = 2 * k0 + 1, v1 = 2 * k1 + 1, v2 = D == 3 ? 2 * k2 + 1 : 0;
+    inner.verts.push_back(v0 + nv * (v1 + nv * v2));
+  }
+  std::vector<ClassPlan> bnd;
+  for (int vert = 0; vert < nvert; ++vert) {
+    int v[3] = {vert % nv, (vert / nv) % nv, D == 3 ? vert / (nv * nv) : 1};
+    int clipped = 0;
+    bool all_odd = true;
+    for (int k = 0; k < D; ++k) {
+      if (v[k] == 0 || v[k] == N) ++clipped;
+      if ((v[k] & 1) == 0) all_odd = false;
+    }
+    if (clipped == 0) {
+      if (!all_odd) inner.verts.push_back(vert);
+      continue;
+    }
+    const int n = D * ipow(3, D - clipped);
+    auto it = std::find_if(bnd.begin(), bnd.end(), [&](const ClassPlan& c) { return c.n == n; });
+    if (it == bnd.end()) {
+      bnd.push_back(ClassPlan{n, {}});
+      it = bnd.end() - 1;
+    }
+    it->verts.push_back(vert);
+  }
+  cls.push_back(std::move(inner));
+  std::sort(bnd.begin(), bnd.end(), [](const ClassPlan& a, const ClassPlan& b) { return a.n > b.n; });
+  for (auto& c : bnd) cls.push_back(std::move(c));
+  return cls;
+}
+
+int64_t packed_doubles(int n, int count) {
+  const int64_t P = (int64_t)n * (n + 1) / 2;
+  return ((int64_t)(count + 63) / 64) * 64 * P;
+}
+
+// Walks every allocation of a hierarchy; `alloc(bytes, ptr_to_store)`.
+template <class F>
+stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes) {
+  const int D = d->dim;
+  const int NN = ipow(3, D), NL = D * NN, NP = D + 1;
+  H.dim = D;
+  H.L = d->n_levels;
+  H.lv.assign(H.L, Level{});
+  for (int l = 0; l < H.L; ++l) {
+    Level& L = H.lv[l];
+    const int N = d->n_fine >> (H.L - 1 - l);
+    L.g.N = N;
+    L.g.n1 = 2 * N + 1;
+    L.g.nnodes = D == 2 ? (int64_t)L.g.n1 * L.g.n1 : (int64_t)L.g.n1 * L.g.n1 * L.g.n1;
+    L.g.ncell = D == 2 ? (int64_t)N * N : (int64_t)N * N * N;
+    L.g.h = 1.0 / N;
+    L.nvert = D == 2 ? (N + 1) * (N + 1) : (N + 1) * (N + 1) * (N + 1);
+    L.nvel = D * L.g.nnodes;
+    L.npres = NP * L.g.ncell;
+    STKCHK(alloc((size_t)NN * L.g.ncell * 8, (void**)&L.mu));
+    STKCHK(alloc((size_t)NL * L.g.ncell * 8, (void**)&L.E));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.b));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.x));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.r));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.T));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.U));
+    STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.S));
+    STKCHK(alloc((size_t)kSmallLen * 8, (void**)&L.small));
+    if (l >= 1) {
+      STKCHK(alloc((size_t)(kMaxNu + 1) * L.nvel * 8, (void**)&L.V));
+      STKCHK(alloc((size_t)kMaxNu * L.nvel * 8, (void**)&L.Z));
+      STKCHK(alloc((size_t)NL * L.nvert * 8, (void**)&L.zbuf));
+      std::vector<ClassPlan> plan = plan_patches(D, N);
+      L.cls.assign(plan.size(), PatchClass{});
+      for (size_t c = 0; c < plan.size(); ++c) {
+        L.cls[c].n = plan[c].n;
+        L.cls[c].count = (int)plan[c].verts.size();
+        STKCHK(alloc(plan[c].verts.size() * 4, (void**)&L.cls[c].verts));
+        STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 8, (void**)&L.cls[c].inv));
+      }
+    }
+  }
+  const Level& L0 = H.lv[0];
+  H.n0 = (int64_t)D * ipow(2 * L0.g.N - 1, D);
+  STKCHK(alloc((size_t)(H.n0 * H.n0) * 8, (void**)&H.Ainv0));
+  STKCHK(alloc((size_t)(32 * 32 + 2 * 32 * H.n0) * 8, (void**)&H.cwork));
+  const Level& Lf = H.lv[H.L - 1];
+  STKCHK(alloc((size_t)Lf.g.ncell * NP * NP * 8, (void**)&H.Sinv));
+  STKCHK(alloc((size_t)2 * kPartialLen * 8, (void**)&H.partials));
+  STKCHK(alloc(64, (void**)&H.flag));
+  STKCHK(alloc((size_t)std::max(1, d->sinker.n) * D * 8, (void**)&H.centers));
+  // FGMRES storage for the default restart length 30
+  const int m = 30;
+  const int64_t nvec = Lf.nvel + Lf.npres;
+  H.restart_alloc = m;
+  STKCHK(alloc((size_t)(m + 1) * nvec * 8, (void**)&H.fV));
+  STKCHK(alloc((size_t)m * nvec * 8, (void**)&H.fZ));
+  STKCHK(alloc((size_t)nvec * 8, (void**)&H.fw));
+  STKCHK(alloc((size_t)2 * nvec * 8, (void**)&H.fr));
+  STKCHK(alloc((size_t)(m + 1) * m * 8, (void**)&H.fH));
+  STKCHK(alloc((size_t)64 * 8, (void**)&H.fy));
+  STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.pw_u));
+  STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.pw_y));
+  (void)build_classes;
+  return STK_OK;
+}
+
+void free_all(Hier& H) {
+  for (void* p : H.allocs) (void)hipFree(p);
+  H.allocs.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Operators on a level (all asynchronous on H.stream)
+
+void apply_A(Hier& H, int l, const double* x, double* y) {
+  Level& L = H.lv[l];
+  hipEvent_t ev = nullptr;
+  prof_begin(H, H.stream, &ev);
+  launch_elem(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  // algorithmic bytes of the cell kernel: u, viscosity at Gauss points, element outputs
+  {
+    const double nn = H.dim == 2 ? 9.0 : 27.0;   // Gauss points (= nodes) per cell
+    prof_end(H, H.stream, PROF_ELEM, ev, 8.0 * ((double)L.nvel + (double)L.g.ncell * (nn + H.dim * nn)));
+  }
+  launch_gather(H, L, nullptr, 1.0, y, H.stream);
+}
+
+void residual(Hier& H, int l, const double* b, const double* x, double* r) {
+  Level& L = H.lv[l];
+  launch_elem(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  launch_gather(H, L, b, -1.0, r, H.stream);
+}
+
+// rc = P~^T rf (fine level l -> l-1)
+void restrict_robust(Hier& H, int l, const double* rf, double* rc) {
+  Level& F = H.lv[l];
+  Level& C = H.lv[l - 1];
+  launch_center_solve(H, F, rf, F.S, 1.0, false, H.stream);           // S|_K = A_K^{-1} rf|_K
+  launch_elem(H, F, EL_AUG, F.S, nullptr, nullptr, H.stream);          // G S
+  launch_gather(H, F, rf, -1.0, F.U, H.stream);                        // U = rf - G S
+  launch_restrict_std(H, F, C, F.U, rc, H.stream);                     // rc = P_H^T U
+}
+
+// xf = P~ xc (coarse level l-1 -> fine level l)
+void prolong_robust(Hier& H, int l, const double* xc, double* xf) {
+  Level& F = H.lv[l];
+  Level& C = H.lv[l - 1];
+  launch_prolong_std(H, C, F, xc, xf, H.stream);                       // xf = P_H xc
+  launch_elem(H, F, EL_AUG, xf, nullptr, nullptr, H.stream);
+  launch_gather(H, F, nullptr, 1.0, F.U, H.stream);                    // U = G xf
+  launch_center_solve(H, F, F.U, xf, -1.0, true, H.stream);            // xf|_K -= A_K^{-1} U|_K
+}
+
+// nu steps of right-preconditioned GMRES relaxation on A x = b.
+void smooth(Hier& H, int l, const double* b, double* x, int nu, bool x_zero) {
+  Level& L = H.lv[l];
+  const int64_t n = L.nvel;
+  double* part = H.partials;
+  double* normp = H.partials + kPartialLen;
+  launch_fill(L.small, 0.0, kSmallLen, H.stream);
+  const double* r0 = b;
+  if (!x_zero) {
+    residual(H, l, b, x, L.r);
+    r0 = L.r;
+  }
+  launch_dots(r0, n, 1, r0, n, part, H.stream);
+  launch_normalize(part, const_cast<double*>(r0), n, L.V, L.small + kSmallBeta, H.stream);
+  for (int j = 0; j < nu; ++j) {
+    double* Vj = L.V + (int64_t)j * n;
+    double* Zj = L.Z + (int64_t)j * n;
+    double* w = L.V + (int64_t)(j + 1) * n;
+    launch_asm(H, L, Vj, Zj, H.stream);
+    apply_A(H, l, Zj, w);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_dots(L.V, n, j + 1, w, n, part, H.stream);
+      launch_orth_update(L.V, n, j + 1, w, n, part, L.small + kSmallH + j, kMaxNu, normp, H.stream);
+    }
+    launch_normalize(normp, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
+  }
+  launch_ls_solve(L.small, nu, H.stream);
+  launch_combine(L.Z, n, nu, L.small + kSmallY, x, n, x_zero, H.stream);
+}
+
+void coarse_solve(Hier& H, const double* b, double* x) { launch_coarse_apply(H, H.lv[0], b, x, H.stream); }
+
+// One V-cycle on level l: x = V(b).
+void vcycle(Hier& H, int l, const double* b, double* x) {
+  if (l == 0) {
+    coarse_solve(H, b, x);
+    return;
+  }
+  Level& L = H.lv[l];
+  Level& C = H.lv[l - 1];
+  smooth(H, l, b, x, H.nu_pre, true);
+  residual(H, l, b, x, L.r);
+  restrict_robust(H, l, L.r, C.b);
+  vcycle(H, l - 1, C.b, C.x);
+  prolong_robust(H, l, C.x, L.T);
+  launch_axpby(1.0, x, 1.0, L.T, x, L.nvel, H.stream);
+  smooth(H, l, b, x, H.nu_post, false);
+}
+
+// (z_u, z_p) = P (v_u, v_p), eq. (precond) with Ahat^{-1} = one V-cycle.
+void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp) {
+  const int lf = H.L - 1;
+  Level& F = H.lv[lf];
+  vcycle(H, lf, vu, H.pw_y);                                      // y = Ahat^{-1} v_u
+  launch_schur_apply(H, F, H.pw_y, vp, zp, H.stream);             // z_p = -Shat^{-1}(v_p - B y)
+  launch_project_mean(H, F, zp, H.stream);
+  launch_elem(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
+  launch_gather(H, F, nullptr, 1.0, H.pw_u, H.stream);           // B^T z_p
+  vcycle(H, lf, H.pw_u, zu);                                      // Ahat^{-1} B^T z_p
+  launch_axpby(1.0, H.pw_y, -1.0, zu, zu, F.nvel, H.stream);      // z_u = y - that
+}
+
+// y = K x on the finest level; x, y contiguous [u | p].
+void stokes_apply(Hier& H, const double* x, double* y) {
+  Level& F = H.lv[H.L - 1];
+  launch_elem(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x, x + F.nvel, y + F.nvel, H.stream);
+  launch_gather(H, F, nullptr, 1.0, y, H.stream);
+}
+
+stk_status check_level(const Hier& H, int l, int lmin) {
+  if (l < lmin || l >= H.L) return fail(STK_EINVAL, "level out of range");
+  return STK_OK;
+}
+
+stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
+  launch_dots(x, n, 1, x, n, H.partials, H.stream);
+  std::vector<double> part(kRedBlocks);
+  HIPCHK(hipMemcpyAsync(part.data(), H.partials, kRedBlocks * 8, hipMemcpyDeviceToHost, H.stream));
+  HIPCHK(hipStreamSynchronize(H.stream));
+  double s = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) s += part[b];
+  *out = sqrt(s);
+  return STK_OK;
+}
+
+}  // namespace
+
+namespace stk {
+
+void prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev) {
+  *ev = nullptr;
+  if (!H.prof.on) return;
+  Prof& P = H.prof;
+  while (P.pool.size() < P.used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    P.pool.push_back(e);
+  }
+  *ev = P.pool[P.used++];
+  (void)hipEventRecord(*ev, s);
+}
+
+void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes) {
+  if (!H.prof.on || !a) return;
+  Prof& P = H.prof;
+  hipEvent_t b = P.pool[P.used++];
+  (void)hipEventRecord(b, s);
+  P.recs.push_back(Prof::Rec{id, a, b, bytes});
+}
+
+}  // namespace stk
+
+// =========================================================================== C ABI
+extern "C" {
+
+const char* stk_last_error(void) { return g_err.c_str(); }
+
+stk_status stk_footprint(const stk_desc* desc, size_t* bytes) {
+  STKCHK(validate(desc));
+  if (!bytes) return fail(STK_EINVAL, "bytes is NULL");
+  Hier H;
+  size_t total = 0;
+  auto count = [&](size_t b, void** p) -> stk_status {
+    total += (b + 255) / 256 * 256;
+    *p = nullptr;
+    return STK_OK;
+  };
+  STKCHK(plan_allocs(desc, H, count, false));
+  *bytes = total;
+  return STK_OK;
+}
+
+stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** out) {
+  if (!out) return fail(STK_EINVAL, "out is NULL");
+  *out = nullptr;
+  STKCHK(validate(desc));
+  size_t need = 0;
+  STKCHK(stk_footprint(desc, &need));
+  if (desc->hbm_budget && need > desc->hbm_budget)
+    return fail(STK_ENOMEM, "footprint " + std::to_string(need) + " B exceeds budget " +
+                                std::to_string(desc->hbm_budget) + " B");
+  stk_hier* h = new stk_hier();
+  Hier& H = h->H;
+  H.stream = (hipStream_t)stream;
+  H.nu_pre = desc->nu_pre;
+  H.nu_post = desc->nu_post;
+  H.gamma = desc->gamma;
+  H.schur = desc->schur;
+  H.n_sinkers = desc->sinker.n;
+  H.omega = desc->sinker.omega;
+  H.delta = desc->sinker.delta;
+  H.mu_min = desc->sinker.mu_min;
+  H.mu_max = desc->sinker.mu_max;
+  H.beta = desc->sinker.beta;
+  auto dev_alloc = [&](size_t b, void** p) -> stk_status {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(b, 8));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STK_ENOMEM, "hipMalloc of " + std::to_string(b) + " B failed");
+    }
+    H.allocs.push_back(q);
+    H.bytes += b;
+    *p = q;
+    return STK_OK;
+  };
+  stk_status st = plan_allocs(desc, H, dev_alloc, true);
+  if (st != STK_OK) {
+    free_all(H);
+    delete h;
+    return st;
+  }
+  auto bail = [&](stk_status s2) {
+    (void)hipStreamSynchronize(H.stream);
+    free_all(H);
+    delete h;
+    return s2;
+  };
+  const int D = H.dim;
+  hipStream_t s = H.stream;
+  if (desc->sinker.n > 0 &&
+      hipMemcpyAsync(H.centers, desc->sinker.centers, (size_t)desc->sinker.n * D * 8, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return bail(fail(STK_EDEVICE, "copy of sinker centres failed"));
+  launch_fill_int(H.flag, 0, 16, s);
+  for (int l = 0; l < H.L; ++l) {
+    Level& L = H.lv[l];
+    launch_mu_sinker(H, L, s);
+    launch_fill(L.S, 0.0, L.nvel, s);
+    launch_fill(L.x, 0.0, L.nvel, s);
+    if (l >= 1) {
+      std::vector<ClassPlan> plan = plan_patches(D, L.g.N);
+      for (size_t c = 0; c < plan.size(); ++c) {
+        if (hipMemcpyAsync(L.cls[c].verts, plan[c].verts.data(), plan[c].verts.size() * 4, hipMemcpyHostToDevice,
+                           s) != hipSuccess)
+          return bail(fail(STK_EDEVICE, "copy of patch vertex lists failed"));
+        // the host vector must outlive the copy
+        if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(STK_EDEVICE, "sync failed"));
+        launch_patch_setup(H, L, L.cls[c], s);
+      }
+    }
+  }
+  launch_coarse_assemble(H, H.lv[0], H.Ainv0, s);
+  launch_coarse_invert(H, H.Ainv0, H.n0, H.cwork, s);
+  launch_schur_setup(H, H.lv[H.L - 1], s);
+  if (hipGetLastError() != hipSuccess) return bail(fail(STK_EDEVICE, "kernel launch failed during setup"));
+  int flag = 0;
+  if (hipMemcpyAsync(&flag, H.flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(STK_EDEVICE, "setup synchronisation failed"));
+  if (flag) return bail(fail(STK_ENOTSPD, "non-positive pivot in a patch or coarse factorisation"));
+  *out = h;
+  return STK_OK;
+}
+
+stk_status stk_profile(stk_hier* h, int enable) {
+  if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
+  Prof& P = h->H.prof;
+  P.on = enable != 0;
+  P.recs.clear();
+  P.used = 0;
+  return STK_OK;
+}
+
+stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* total_ms, double* total_bytes) {
+  if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
+  if (kernel < 0 || kernel >= PROF_NIDS) return fail(STK_EINVAL, "unknown kernel id");
+  Prof& P = h->H.prof;
+  HIPCHK(hipStreamSynchronize(h->H.stream));
+  int64_t n = 0;
+  double ms = 0.0, by = 0.0;
+  for (const Prof::Rec& r : P.recs) {
+    if (r.id != kernel) continue;
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ++n;
+    ms += t;
+    by += r.bytes;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  if (total_bytes) *total_bytes = by;
+  return STK_OK;
+}
+
+stk_status stk_destroy(stk_hier* h) {
+  if (!h) return STK_OK;
+  (void)hipStreamSynchronize(h->H.stream);
+  for (hipEvent_t e : h->H.prof.pool) (void)hipEventDestroy(e);
+  free_all(h->H);
+  delete h;
+  return STK_OK;
+}
+
+stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_t* n_pres) {
+  if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
+  STKCHK(check_level(h->H, level, 0));
+  if (n_vel_stored) *n_vel_stored = h->H.lv[level].nvel;
+  if (n_pres) *n_pres = h->H.lv[level].npres;
+  return STK_OK;
+}
+
+#define GET_H(h)                                                  \
+  if (!(h)) return fail(STK_EINVAL, "hierarchy is NULL");         \
+  Hier& H = (h)->H;                                               \
+  H.stream = (hipStream_t)stream
+
+stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
+  GET_H(h);
+  if (!b_u) return fail(STK_EINVAL, "b_u is NULL");
+  Level& F = H.lv[H.L - 1];
+  launch_rhs_elem(H, F, H.stream);
+  launch_gather(H, F, nullptr, 1.0, b_u, H.stream);
+  if (b_p) launch_fill(b_p, 0.0, F.npres, H.stream);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, void* y, void* stream) {
+  GET_H(h);
+  STKCHK(check_level(H, level, 0));
+  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  if (!x || !y || x == y) return fail(STK_EINVAL, "x, y must be distinct non-NULL buffers");
+  apply_A(H, level, (const double*)x, (double*)y);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p, double* y_u, double* y_p,
+                            void* stream) {
+  GET_H(h);
+  if (!x_u || !x_p || !y_u || !y_p) return fail(STK_EINVAL, "NULL buffer");
+  Level& F = H.lv[H.L - 1];
+  launch_elem(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x_u, x_p, y_p, H.stream);
+  launch_gather(H, F, nullptr, 1.0, y_u, H.stream);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream) {
+  GET_H(h);
+  STKCHK(check_level(H, level, 1));
+  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  if (!r || !y) return fail(STK_EINVAL, "NULL buffer");
+  launch_asm(H, H.lv[level], (const double*)r, (double*)y, H.stream);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x, int nsteps, void* stream) {
+  GET_H(h);
+  STKCHK(check_level(H, level, 1));
+  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
+  if (nsteps < 1 || nsteps > kMaxNu) return fail(STK_EINVAL, "nsteps must be in [1, 8]");
+  smooth(H, level, (const double*)b, (double*)x, nsteps, false);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc, void* xf, void* stream) {
+  GET_H(h);
+  STKCHK(check_level(H, coarse_level + 1, 1));
+  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  if (!xc || !xf) return fail(STK_EINVAL, "NULL buffer");
+  prolong_robust(H, coarse_level + 1, (const double*)xc, (double*)xf);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, void* rc, void* stream) {
+  GET_H(h);
+  STKCHK(check_level(H, fine_level, 1));
+  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  if (!rf || !rc) return fail(STK_EINVAL, "NULL buffer");
+  restrict_robust(H, fine_level, (const double*)rf, (double*)rc);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream) {
+  GET_H(h);
+  if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
+  coarse_solve(H, b, x);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_vcycle(stk_hier* h, const double* b, double* x, void* stream) {
+  GET_H(h);
+  if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
+  vcycle(H, H.L - 1, b, x);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_precond(stk_hier* h, const double* v_u, const double* v_p, double* z_u, double* z_p,
+                       void* stream) {
+  GET_H(h);
+  if (!v_u || !v_p || !z_u || !z_p) return fail(STK_EINVAL, "NULL buffer");
+  precond(H, v_u, v_p, z_u, z_p);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                     const stk_solve_opts* opts, stk_solve_info* info, void* stream) {
+  GET_H(h);
+  if (!b_u || !x_u || !x_p) return fail(STK_EINVAL, "NULL buffer");
+  double rtol = 1e-8;
+  int m = 30, maxit = 300;
+  if (opts) {
+    rtol = opts->rtol;
+    m = opts->restart;
+    maxit = opts->maxit;
+  }
+  if (!(rtol > 0.0) || m < 1 || m > 64 || maxit < 1 || maxit > 1000)
+    return fail(STK_EINVAL, "bad solve options (rtol > 0, restart 1..64, maxit 1..1000)");
+  Level& F = H.lv[H.L - 1];
+  const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
+  if (m > H.restart_alloc) {
+    // grow the Krylov storage
+    double *nV = nullptr, *nZ = nullptr, *nH = nullptr;
+    HIPCHK(hipMalloc(&nV, (size_t)(m + 1) * nvec * 8));
+    HIPCHK(hipMalloc(&nZ, (size_t)m * nvec * 8));
+    HIPCHK(hipMalloc(&nH, (size_t)(m + 1) * m * 8));
+    H.allocs.push_back(nV);
+    H.allocs.push_back(nZ);
+    H.allocs.push_back(nH);
+    H.fV = nV;
+    H.fZ = nZ;
+    H.fH = nH;
+    H.restart_alloc = m;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = H.stream;
+  double* bvec = H.fr + nvec;          // contiguous copy of b
+  double* xvec = H.fw;                 // iterate x (contiguous)
+  double* rvec = H.fr;                 // residual / scratch
+  double* w = nullptr;
+  HIPCHK(hipMemcpyAsync(bvec, b_u, nu * 8, hipMemcpyDeviceToDevice, s));
+  if (b_p) HIPCHK(hipMemcpyAsync(bvec + nu, b_p, np * 8, hipMemcpyDeviceToDevice, s));
+  else launch_fill(bvec + nu, 0.0, np, s);
+  launch_fill(xvec, 0.0, nvec, s);
+  double bnorm = 0.0;
+  STKCHK(device_norm(H, bvec, nvec, &bnorm));
+  stk_solve_info loc{};
+  stk_solve_info* inf = info ? info : &loc;
+  memset(inf, 0, sizeof(*inf));
+  inf->hist[0] = 1.0;
+  if (!isfinite(bnorm)) return fail(STK_ENAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    launch_fill(x_u, 0.0, nu, s);
+    launch_fill(x_p, 0.0, np, s);
+    inf->converged = 1;
+    HIPCHK(hipStreamSynchronize(s));
+    return STK_OK;
+  }
+  launch_copy(bvec, rvec, nvec, s);
+  double beta = bnorm;
+  int it = 0;
+  bool converged = false;
+  std::vector<double> Hd((size_t)(m + 1) * m), Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double* part = H.partials;
+  double* normp = H.partials + kPartialLen;
+  while (true) {
+    launch_axpby(1.0 / beta, rvec, 0.0, rvec, H.fV, nvec, s);
+    launch_fill(H.fH, 0.0, (int64_t)(m + 1) * m, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = H.fV + (int64_t)j * nvec;
+      double* Zj = H.fZ + (int64_t)j * nvec;
+      w = H.fV + (int64_t)(j + 1) * nvec;
+      precond(H, Vj, Vj + nu, Zj, Zj + nu);
+      stokes_apply(H, Zj, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots(H.fV, nvec, j + 1, w, nvec, part, s);
+        launch_orth_update(H.fV, nvec, j + 1, w, nvec, part, H.fH + j, m, normp, s);
+      }
+      launch_normalize(normp, w, nvec, w, H.fH + (j + 1) * m + j, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(Hd.data(), H.fH, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j + 1; ++i) Hh[i * m + j] = Hd[i * m + j];
+      if (!isfinite(Hh[(j + 1) * m + j])) return fail(STK_ENAN, "non-finite value in the Arnoldi process");
+      for (int i = 0; i < j; ++i) {
+        const double a = Hh[i * m + j], c2 = Hh[(i + 1) * m + j];
+        Hh[i * m + j] = cs[i] * a + sn[i] * c2;
+        Hh[(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      }
+      double c = 1.0, sv = 0.0;
+      const double a = Hh[j * m + j], bb = Hh[(j + 1) * m + j];
+      if (bb != 0.0) {
+        const double r = hypot(a, bb);
+        c = a / r;
+        sv = bb / r;
+      }
+      cs[j] = c;
+      sn[j] = sv;
+      Hh[j * m + j] = c * a + sv * bb;
+      Hh[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sv * g[j];
+      g[j] = c * g[j];
+      ++it;
+      k = j + 1;
+      if (it <= 1000) inf->hist[it] = fabs(g[j + 1]) / bnorm;
+      if (fabs(g[j + 1]) <= rtol * bnorm || it >= maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int t = i + 1; t < k; ++t) sacc -= Hh[i * m + t] * y[t];
+      y[i] = sacc / Hh[i * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(H.fy, y.data(), (size_t)k * 8, hipMemcpyHostToDevice, s));
+    launch_combine(H.fZ, nvec, k, H.fy, xvec, nvec, false, s);
+    // true residual r = b - K x
+    stokes_apply(H, xvec, rvec);
+    launch_axpby(1.0, bvec, -1.0, rvec, rvec, nvec, s);
+    STKCHK(device_norm(H, rvec, nvec, &beta));
+    if (!isfinite(beta)) return fail(STK_ENAN, "non-finite residual");
+    if (beta <= rtol * bnorm) {
+      converged = true;
+      break;
+    }
+    if (it >= maxit) break;
+  }
+  launch_project_mean(H, F, xvec + nu, s);
+  HIPCHK(hipMemcpyAsync(x_u, xvec, nu * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(x_p, xvec + nu, np * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  inf->iters = it;
+  inf->converged = converged ? 1 : 0;
+  inf->rel_res = beta / bnorm;
+  inf->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (!converged) return fail(STK_ENOTCONV, "FGMRES reached maxit");
+  return STK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal declarations shared by the host orchestration and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "stk_ref.h"
+
+namespace stk {
+
+constexpr int kMaxNu = 8;          // relaxation steps per smoothing call
+constexpr int kRedBlocks = 512;    // fixed grid of the deterministic reductions
+constexpr int kRedThreads = 256;
+
+// Modes of the element kernel (bit set).
+enum : int {
+  EL_VISC = 1,   // viscous term (2 mu eps(u), eps(v))
+  EL_AUG = 2,    // augmented term gamma (Pi div u, div v)
+  EL_BT = 4,     // B^T p from the pressure input
+  EL_BOUT = 8    // write (B u) to the pressure output
+};
+
+// One class of vertex-star patches with the same number of unknowns.
+struct PatchClass {
+  int n = 0;              // unknowns per patch
+  int count = 0;          // patches in the class
+  int* verts = nullptr;   // [count] vertex index (lexicographic over (N+1)^d)
+  double* inv = nullptr;  // packed inverses, interleaved in blocks of 64 patches
+};
+
+struct Level {
+  LevelGeo g{};
+  int nvert = 0;               // (N+1)^d
+  int64_t nvel = 0;            // d * nnodes
+  int64_t npres = 0;           // (d+1) * ncell
+  double* mu = nullptr;        // [NQ][ncell] viscosity at Gauss points
+  double* E = nullptr;         // [NL][ncell] element outputs
+  // relaxation and transfer work vectors (stored layout)
+  double *b = nullptr, *x = nullptr, *r = nullptr, *T = nullptr, *U = nullptr, *S = nullptr;
+  double* V = nullptr;         // (kMaxNu+1) * nvel
+  double* Z = nullptr;         // kMaxNu * nvel
+  double* small = nullptr;     // device scalars: H, beta, y
+  std::vector<PatchClass> cls; // [0] = interior patches (all-odd parity class first)
+  double* zbuf = nullptr;      // [d*3^d][nvert] patch outputs
+};
+
+// Optional per-kernel timing with HIP events on the launch stream (used by
+// the benchmark to measure the average launch duration of a kernel family
+// live, over the timed region).
+enum ProfId : int { PROF_ASM_GEMV = 0, PROF_ELEM = 1, PROF_NIDS = 2 };
+struct Prof {
+  bool on = false;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+};
+
+struct Hier {
+  int dim = 2, L = 0, nu_pre = 2, nu_post = 2, schur = 1;
+  double gamma = 0.0;
+  int n_sinkers = 0;
+  double omega = 0.1, delta = 200.0, mu_min = 1.0, mu_max = 1.0, beta = 10.0;
+  double* centers = nullptr;         // device [n][d]
+  std::vector<Level> lv;
+  // coarse level
+  int64_t n0 = 0;
+  double* Ainv0 = nullptr;           // [n0][n0]
+  double* cwork = nullptr;           // GJ panels
+  double* cvec = nullptr;            // compact coarse vectors (2*n0)
+  // finest-level Schur blocks and pressure work
+  double* Sinv = nullptr;            // [ncell][(d+1)^2]
+  double* partials = nullptr;        // kRedBlocks * 64
+  int* flag = nullptr;               // device error flag
+  // FGMRES storage (allocated on first solve)
+  int restart_alloc = 0;
+  double *fV = nullptr, *fZ = nullptr, *fw = nullptr, *fr = nullptr, *fH = nullptr, *fy = nullptr;
+  double *pw_u = nullptr, *pw_y = nullptr;  // preconditioner work (fine velocity)
+  hipStream_t stream = nullptr;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  Prof prof;
+};
+
+// Event bracketing of one launch (no-ops unless H.prof.on).
+void prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev);
+void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes);
+
+// ---- kernel launchers (templated on dimension inside the .hip files) ----
+void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s);
+void launch_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p,
+                 double* pout, hipStream_t s);
+void launch_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out,
+                   hipStream_t s);
+void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s);
+void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s);
+void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
+                        hipStream_t s);
+void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s);
+
+void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
+void launch_asm(Hier& H, const Level& l, const double* r, double* y, hipStream_t s);
+void launch_center_solve(const Hier& H, const Level& fine, const double* in, double* out,
+                         double alpha, bool accumulate, hipStream_t s);
+
+void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc,
+                        double* xf, hipStream_t s);
+void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf,
+                         double* rc, hipStream_t s);
+
+void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_t s);
+int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s);
+void launch_coarse_apply(const Hier& H, const Level& l, const double* b, double* x, hipStream_t s);
+
+// Krylov helpers (vectors of length n)
+void launch_dots(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
+                 hipStream_t s);
+void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n,
+                        const double* partials, double* Hcol, int hstride, double* norm_partials,
+                        hipStream_t s);
+void launch_normalize(const double* norm_partials, double* w, int64_t n, double* dst,
+                      double* hout, hipStream_t s);
+void launch_ls_solve(double* small, int nu, hipStream_t s);
+void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n,
+                    bool x_zero, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
+                  hipStream_t s);
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+void launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
+void launch_fill_int(int* x, int v, int64_t n, hipStream_t s);
+
+// layout of Level::small
+constexpr int kSmallH = 0;                               // H[(kMaxNu+1) x kMaxNu], row i col j at i*kMaxNu+j
+constexpr int kSmallBeta = (kMaxNu + 1) * kMaxNu;        // beta
+constexpr int kSmallY = kSmallBeta + 1;                  // y[kMaxNu]
+constexpr int kSmallLen = kSmallY + kMaxNu + 8;
+
+}  // namespace stk

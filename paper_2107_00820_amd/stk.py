@@ -1,0 +1,253 @@
+"""ctypes binding of libstk.so (argument marshalling only).
+
+Names follow the C ABI in include/stk.h. Buffers are torch tensors on the
+current HIP device (float64, contiguous); every device step runs in the HIP
+kernels of libstk.so. There is no fallback path: if the library is missing
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstk.so")
+
+STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ENOTCONV, STK_ENOTSPD, STK_ENAN, STK_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+STK_F64, STK_F32 = 0, 1
+_NAMES = {0: "STK_OK", -1: "STK_EINVAL", -2: "STK_ENOMEM", -3: "STK_EDEVICE", -4: "STK_ENOTCONV",
+          -5: "STK_ENOTSPD", -6: "STK_ENAN", -7: "STK_EBUSY"}
+
+
+class StkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Sinker(C.Structure):
+    _fields_ = [("n", C.c_int), ("centers", C.POINTER(C.c_double)), ("omega", C.c_double),
+                ("delta", C.c_double), ("mu_min", C.c_double), ("mu_max", C.c_double), ("beta", C.c_double)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_fine", C.c_int), ("n_levels", C.c_int), ("gamma", C.c_double),
+                ("schur", C.c_int), ("coef_kind", C.c_int), ("sinker", Sinker), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_res", C.c_double),
+                ("t_solve_s", C.c_double), ("hist", C.c_double * 1001)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libstk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2107_00820_amd.build` "
+                           "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, i32, i64p, dp = C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)
+    sig = {
+        "stk_footprint": [C.POINTER(Desc), C.POINTER(C.c_size_t)],
+        "stk_setup_hierarchy": [C.POINTER(Desc), vp, C.POINTER(vp)],
+        "stk_destroy": [vp],
+        "stk_sizes": [vp, i32, i64p, i64p],
+        "stk_rhs": [vp, vp, vp, vp],
+        "stk_apply_Agamma": [vp, i32, i32, vp, vp, vp],
+        "stk_apply_stokes": [vp, vp, vp, vp, vp, vp],
+        "stk_asm": [vp, i32, i32, vp, vp, vp],
+        "stk_smooth": [vp, i32, i32, vp, vp, i32, vp],
+        "stk_prolong": [vp, i32, i32, vp, vp, vp],
+        "stk_restrict": [vp, i32, i32, vp, vp, vp],
+        "stk_coarse_solve": [vp, vp, vp, vp],
+        "stk_vcycle": [vp, vp, vp, vp],
+        "stk_precond": [vp, vp, vp, vp, vp, vp],
+        "stk_solve": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp],
+        "stk_profile": [vp, i32],
+        "stk_profile_read": [vp, i32, i64p, dp, dp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.stk_last_error.argtypes = []
+    lib.stk_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int, allow=()):
+    if st != STK_OK and st not in allow:
+        raise StkError(st, load().stk_last_error().decode())
+    return st
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "expected a contiguous float64 GPU tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
+              nu_pre=2, nu_post=2, hbm_budget=0):
+    centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
+    d = Desc()
+    d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
+    d.schur, d.coef_kind, d.mixed = 1, 0, 0
+    d.sinker.n = centers.shape[0]
+    d.sinker.centers = centers.ctypes.data_as(C.POINTER(C.c_double))
+    d.sinker.omega, d.sinker.delta, d.sinker.beta = omega, delta, beta
+    d.sinker.mu_min, d.sinker.mu_max = mu_min, mu_max
+    d.nu_pre, d.nu_post = nu_pre, nu_post
+    d.hbm_budget = int(hbm_budget)
+    d._keep = centers          # keep the host array alive while the desc is used
+    return d
+
+
+def desc_from_workload(wl, hbm_budget=0):
+    from workloads import OMEGA, DELTA, BETA
+    return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
+                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget)
+
+
+def stk_footprint(desc: Desc) -> int:
+    out = C.c_size_t(0)
+    _check(load().stk_footprint(C.byref(desc), C.byref(out)))
+    return out.value
+
+
+class Hierarchy:
+    """A device hierarchy (stk_setup_hierarchy ... stk_destroy)."""
+
+    def __init__(self, desc: Desc):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libstk needs a HIP GPU; none is visible")
+        self.desc = desc
+        self.dim, self.L = desc.dim, desc.n_levels
+        h = C.c_void_p()
+        _check(lib.stk_setup_hierarchy(C.byref(desc), _stream(), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, wl, hbm_budget=0):
+        return cls(desc_from_workload(wl, hbm_budget))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().stk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- sizes and buffers
+    def sizes(self, level: int):
+        nv, npr = C.c_int64(), C.c_int64()
+        _check(load().stk_sizes(self._h, level, C.byref(nv), C.byref(npr)))
+        return nv.value, npr.value
+
+    def zeros_u(self, level: Optional[int] = None):
+        import torch
+        nv, _ = self.sizes(self.L - 1 if level is None else level)
+        return torch.zeros(nv, dtype=torch.float64, device="cuda")
+
+    def zeros_p(self):
+        import torch
+        _, npr = self.sizes(self.L - 1)
+        return torch.zeros(npr, dtype=torch.float64, device="cuda")
+
+    # ---- operations (same names as the C ABI)
+    def stk_rhs(self):
+        bu, bp = self.zeros_u(), self.zeros_p()
+        _check(load().stk_rhs(self._h, _ptr(bu), _ptr(bp), _stream()))
+        return bu, bp
+
+    def stk_apply_Agamma(self, level, x, y=None):
+        y = self.zeros_u(level) if y is None else y
+        _check(load().stk_apply_Agamma(self._h, level, STK_F64, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def stk_apply_stokes(self, xu, xp, yu=None, yp=None):
+        yu = self.zeros_u() if yu is None else yu
+        yp = self.zeros_p() if yp is None else yp
+        _check(load().stk_apply_stokes(self._h, _ptr(xu), _ptr(xp), _ptr(yu), _ptr(yp), _stream()))
+        return yu, yp
+
+    def stk_asm(self, level, r, y=None):
+        y = self.zeros_u(level) if y is None else y
+        _check(load().stk_asm(self._h, level, STK_F64, _ptr(r), _ptr(y), _stream()))
+        return y
+
+    def stk_smooth(self, level, b, x, nsteps):
+        _check(load().stk_smooth(self._h, level, STK_F64, _ptr(b), _ptr(x), nsteps, _stream()))
+        return x
+
+    def stk_prolong(self, coarse_level, xc, xf=None):
+        xf = self.zeros_u(coarse_level + 1) if xf is None else xf
+        _check(load().stk_prolong(self._h, coarse_level, STK_F64, _ptr(xc), _ptr(xf), _stream()))
+        return xf
+
+    def stk_restrict(self, fine_level, rf, rc=None):
+        rc = self.zeros_u(fine_level - 1) if rc is None else rc
+        _check(load().stk_restrict(self._h, fine_level, STK_F64, _ptr(rf), _ptr(rc), _stream()))
+        return rc
+
+    def stk_coarse_solve(self, b, x=None):
+        x = self.zeros_u(0) if x is None else x
+        _check(load().stk_coarse_solve(self._h, _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def stk_vcycle(self, b, x=None):
+        x = self.zeros_u() if x is None else x
+        _check(load().stk_vcycle(self._h, _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def stk_precond(self, vu, vp, zu=None, zp=None):
+        zu = self.zeros_u() if zu is None else zu
+        zp = self.zeros_p() if zp is None else zp
+        _check(load().stk_precond(self._h, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
+        return zu, zp
+
+    def stk_profile(self, enable: bool):
+        _check(load().stk_profile(self._h, 1 if enable else 0))
+
+    def stk_profile_read(self, kernel: int):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        _check(load().stk_profile_read(self._h, kernel, C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
+
+    def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False):
+        xu = self.zeros_u() if xu is None else xu
+        xp = self.zeros_p() if xp is None else xp
+        opts = SolveOpts(rtol, restart, maxit)
+        info = SolveInfo()
+        st = load().stk_solve(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu), _ptr(xp),
+                              C.byref(opts), C.byref(info), _stream())
+        _check(st, allow=(STK_ENOTCONV,) if allow_notconv else ())
+        out = dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
+                   t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
+        return xu, xp, out

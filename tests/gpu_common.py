@@ -1,0 +1,62 @@
+"""Shared helpers of the GPU parity tests: build the oracle and the GPU
+hierarchy for one workload, convert between the oracle's unknown vectors and
+the stored full-grid layout."""
+from __future__ import annotations
+
+import functools
+import sys
+
+import numpy as np
+
+from workloads import CONFIGS, small
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+CASES = {
+    "c1": CONFIGS["c1"],
+    "2d_32_L3": small(2, 32, 3, gamma=1e3, dr=1e6, n_sinkers=16, seed=201),
+    "3d_8_L2": small(3, 8, 2, gamma=1e4, dr=1e8, n_sinkers=24, seed=301),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_for(name: str):
+    from oracle.krylov import StokesSolver
+    return StokesSolver(CASES[name])
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_for(name: str):
+    from paper_2107_00820_amd import Hierarchy
+    return Hierarchy.from_workload(CASES[name])
+
+
+def to_dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rand_u(level, seed):
+    """Random unknown vector of a level and its stored layout (with garbage on
+    Dirichlet nodes, which the library must ignore)."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(level.n_u)
+    s = level.to_stored(u)
+    mask = np.ones(level.n_stored, dtype=bool)
+    mask[level.stored_index()] = False
+    s[mask] = rng.standard_normal(mask.sum()) * 1e3
+    return u, s

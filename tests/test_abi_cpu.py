@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/stk.h declares, validates descriptors and computes the
+HBM footprint without touching a device."""
+import os
+import re
+
+import pytest
+
+from workloads import CONFIGS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    hdr = open(os.path.join(ROOT, "include", "stk.h")).read()
+    return re.findall(r"^\s*(?:stk_status|const char\*)\s+(stk_\w+)\s*\(", hdr, re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2107_00820_amd import stk
+    lib = stk.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_footprint_and_validation():
+    from paper_2107_00820_amd import stk
+    d = stk.desc_from_workload(CONFIGS["c2"])
+    fp = stk.stk_footprint(d)
+    # packed interior inverses alone: 16129 patches of 18x18
+    assert fp > 16129 * 171 * 8
+    assert fp < 2 ** 30
+    d3 = stk.desc_from_workload(CONFIGS["c3"])
+    assert stk.stk_footprint(d3) > 29791 * (81 * 82 // 2) * 8
+    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad.n_fine = 100          # not a multiple of 2^(levels-1)
+    with pytest.raises(stk.StkError) as e:
+        stk.stk_footprint(bad)
+    assert e.value.status == stk.STK_EINVAL
+    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad.sinker.mu_min = -1.0
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(bad)
+    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad.nu_pre = 9
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(bad)
+
+
+def test_setup_rejects_budget_before_touching_the_device():
+    from paper_2107_00820_amd import stk
+    import ctypes
+    d = stk.desc_from_workload(CONFIGS["c1"], hbm_budget=1024)
+    h = ctypes.c_void_p()
+    st = stk.load().stk_setup_hierarchy(ctypes.byref(d), None, ctypes.byref(h))
+    assert st == stk.STK_ENOMEM and not h.value
+    assert b"exceeds budget" in stk.load().stk_last_error()
