@@ -145,6 +145,10 @@ typedef struct {
   double rtol;   /* stop when ||b - Kx||_2 <= rtol ||b||_2 (default 1e-8) */
   int restart;   /* FGMRES restart length (default 30, max 64) */
   int maxit;     /* maximum iterations (default 300, max 1000) */
+  int eager;     /* 0 (default): each Arnoldi step (two V-cycles, Schur blocks,
+                    Stokes apply, Gram-Schmidt) is captured once as a HIP graph
+                    on the library's own stream and replayed; 1: plain launches.
+                    Both give bit-identical results. */
 } stk_solve_opts;
 
 typedef struct {
@@ -156,7 +160,8 @@ typedef struct {
 } stk_solve_info;
 
 /* Solves the augmented Stokes system with right-preconditioned FGMRES
- * (Section 5.1) from x = 0. b_p may be NULL (zero). The pressure of the
+ * (Section 5.1) from x = 0. The work runs on a stream owned by the hierarchy
+ * after `stream` has drained. b_p may be NULL (zero). The pressure of the
  * result has zero mean. Host-synchronous. Returns STK_ENOTCONV if maxit was
  * reached (x then holds the last iterate) and STK_ENAN for a non-finite
  * right-hand side or residual. */

@@ -309,6 +309,30 @@ void stokes_apply(Hier& H, const double* x, double* y) {
   launch_gather(H, F, nullptr, 1.0, y, H.stream);
 }
 
+// One FGMRES Arnoldi step j with restart m: Z_j = P V_j, w = K Z_j,
+// classical Gram-Schmidt twice against V_0..V_j, V_{j+1} = w/||w||, H column j.
+void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec) {
+  double* Vj = H.fV + (int64_t)j * nvec;
+  double* Zj = H.fZ + (int64_t)j * nvec;
+  double* w = H.fV + (int64_t)(j + 1) * nvec;
+  double* part = H.partials;
+  double* normp = H.partials + kPartialLen;
+  precond(H, Vj, Vj + nu, Zj, Zj + nu);
+  stokes_apply(H, Zj, w);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_dots(H.fV, nvec, j + 1, w, nvec, part, H.stream);
+    launch_orth_update(H.fV, nvec, j + 1, w, nvec, part, H.fH + j, m, normp, H.stream);
+  }
+  launch_normalize(normp, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);
+}
+
+void drop_graphs(Hier& H) {
+  for (hipGraphExec_t g : H.steps)
+    if (g) (void)hipGraphExecDestroy(g);
+  H.steps.clear();
+  H.steps_m = 0;
+}
+
 stk_status check_level(const Hier& H, int l, int lmin) {
   if (l < lmin || l >= H.L) return fail(STK_EINVAL, "level out of range");
   return STK_OK;
@@ -414,12 +438,15 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   }
   auto bail = [&](stk_status s2) {
     (void)hipStreamSynchronize(H.stream);
+    if (H.own) (void)hipStreamDestroy(H.own);
     free_all(H);
     delete h;
     return s2;
   };
   const int D = H.dim;
   hipStream_t s = H.stream;
+  if (hipStreamCreateWithFlags(&H.own, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(STK_EDEVICE, "stream creation failed"));
   if (desc->sinker.n > 0 &&
       hipMemcpyAsync(H.centers, desc->sinker.centers, (size_t)desc->sinker.n * D * 8, hipMemcpyHostToDevice, s) !=
           hipSuccess)
@@ -489,6 +516,11 @@ stk_status stk_destroy(stk_hier* h) {
   if (!h) return STK_OK;
   (void)hipStreamSynchronize(h->H.stream);
   for (hipEvent_t e : h->H.prof.pool) (void)hipEventDestroy(e);
+  drop_graphs(h->H);
+  if (h->H.own) {
+    (void)hipStreamSynchronize(h->H.own);
+    (void)hipStreamDestroy(h->H.own);
+  }
   free_all(h->H);
   delete h;
   return STK_OK;
@@ -633,8 +665,15 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     H.fZ = nZ;
     H.fH = nH;
     H.restart_alloc = m;
+    drop_graphs(H);
   }
+  const bool use_graphs = !(opts && opts->eager);
   const auto t0 = std::chrono::steady_clock::now();
+  // all solve work runs on the library's own stream (capturable), ordered
+  // after the caller's stream
+  hipStream_t caller = H.stream;
+  HIPCHK(hipStreamSynchronize(caller));
+  H.stream = H.own;
   hipStream_t s = H.stream;
   double* bvec = H.fr + nvec;          // contiguous copy of b
   double* xvec = H.fw;                 // iterate x (contiguous)
@@ -672,16 +711,31 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      double* Vj = H.fV + (int64_t)j * nvec;
-      double* Zj = H.fZ + (int64_t)j * nvec;
-      w = H.fV + (int64_t)(j + 1) * nvec;
-      precond(H, Vj, Vj + nu, Zj, Zj + nu);
-      stokes_apply(H, Zj, w);
-      for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(H.fV, nvec, j + 1, w, nvec, part, s);
-        launch_orth_update(H.fV, nvec, j + 1, w, nvec, part, H.fH + j, m, normp, s);
+      if (!use_graphs) {
+        arnoldi_step(H, j, m, nu, nvec);
+      } else {
+        if (H.steps_m != m) {
+          drop_graphs(H);
+          H.steps.assign(m, nullptr);
+          H.steps_m = m;
+        }
+        if (!H.steps[j]) {
+          const bool prof_on = H.prof.on;
+          H.prof.on = false;   // no event records inside captured graphs
+          hipGraph_t graph = nullptr;
+          HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          arnoldi_step(H, j, m, nu, nvec);
+          const hipError_t ce = hipStreamEndCapture(s, &graph);
+          H.prof.on = prof_on;
+          if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+          hipGraphExec_t exec = nullptr;
+          const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          if (ie != hipSuccess) return fail(STK_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+          H.steps[j] = exec;
+        }
+        HIPCHK(hipGraphLaunch(H.steps[j], s));
       }
-      launch_normalize(normp, w, nvec, w, H.fH + (j + 1) * m + j, s);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(Hd.data(), H.fH, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -732,6 +786,7 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
   HIPCHK(hipMemcpyAsync(x_u, xvec, nu * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(x_p, xvec + nu, np * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+  H.stream = caller;
   inf->iters = it;
   inf->converged = converged ? 1 : 0;
   inf->rel_res = beta / bnorm;

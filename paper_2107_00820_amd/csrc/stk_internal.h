@@ -87,6 +87,11 @@ struct Hier {
   size_t bytes = 0;
   std::vector<void*> allocs;
   Prof prof;
+  // FGMRES Arnoldi steps captured as HIP graphs (one per step index j) and
+  // replayed on the library's own stream
+  hipStream_t own = nullptr;
+  std::vector<hipGraphExec_t> steps;
+  int steps_m = 0;
 };
 
 // Event bracketing of one launch (no-ops unless H.prof.on).

@@ -40,7 +40,7 @@ class Desc(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int)]
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("eager", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -240,10 +240,11 @@ class Hierarchy:
         _check(load().stk_profile_read(self._h, kernel, C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
 
-    def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False):
+    def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False,
+                  eager=False):
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit)
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0)
         info = SolveInfo()
         st = load().stk_solve(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu), _ptr(xp),
                               C.byref(opts), C.byref(info), _stream())

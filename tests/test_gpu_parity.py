@@ -1,11 +1,13 @@
 """GPU parity: every operation of the hot path through the C ABI against the
 CPU FP64 oracle on the same seeded inputs.
 
-Tolerances: operator applications (A_gamma, K, P_H-based transfers) 1e-12
-relative; patch solves (star smoother, local transfer solves, coarse solve)
-within the conditioning of the patch matrices; compositions (relaxation,
-V-cycle, preconditioner) 1e-10 relative; solves: identical iteration count
-and solutions within 1e-8 relative.
+Tolerances: operator applications (A_gamma, K) 1e-12 relative; patch solves
+(star smoother, local transfer solves, coarse solve) 50 kappa eps64 with
+kappa the largest condition number of the patch (or coarse) matrices, at
+least 1e-12; compositions (relaxation, V-cycle, preconditioner), which chain
+several such solves and small least-squares problems, 50 kappa eps64, at
+least 1e-10; solves: identical iteration count and solutions within 1e-8
+relative.
 """
 import numpy as np
 import pytest
@@ -118,23 +120,25 @@ def test_relaxation_vcycle_precond(name):
     lv = orc.mg.hier[lf]
     b, bs = rand_u(lv, 60)
     x0, x0s = rand_u(lv, 61)
+    tol = max(1e-10, 50 * cond_bound(orc, lf) * np.finfo(float).eps)
+    log(f"  composition tolerance {tol:.1e}")
     x = to_dev(x0s)
     gpu.stk_smooth(lf, to_dev(bs), x, 3)
     ref = gmres_relax(orc.mg.ops[lf].Agamma, orc.mg.smoothers[lf].apply, b, x0, 3)
     e = rel(lv.from_stored(to_host(x)), ref)
     log(f"  relax {e:.2e}")
-    assert e <= 1e-10
+    assert e <= tol
     v = lv.from_stored(to_host(gpu.stk_vcycle(to_dev(bs))))
     e = rel(v, orc.mg.vcycle(b))
     log(f"  vcycle {e:.2e}")
-    assert e <= 1e-10
+    assert e <= tol
     p = np.random.default_rng(62).standard_normal(lv.n_p)
     zu, zp = gpu.stk_precond(to_dev(bs), to_dev(p))
     ref = orc.pc.apply(np.concatenate([b, p]))
     e1 = rel(lv.from_stored(to_host(zu)), ref[:lv.n_u])
     e2 = rel(to_host(zp), ref[lv.n_u:])
     log(f"  precond u {e1:.2e} p {e2:.2e}")
-    assert e1 <= 1e-10 and e2 <= 1e-10
+    assert e1 <= tol and e2 <= tol
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -162,3 +166,25 @@ def test_solve_matches_oracle(name):
     xu2, xp2, info2 = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
     assert info2["iters"] == info["iters"]
     assert np.array_equal(to_host(xu2), to_host(xu)) and np.array_equal(to_host(xp2), to_host(xp))
+
+
+@pytest.mark.parametrize("name", ["c1", "3d_8_L2"])
+def test_graph_replay_matches_eager(name):
+    """Each Arnoldi step is captured once as a HIP graph and replayed; every
+    replay must reproduce the plain-launch solve bit for bit, also with
+    eager work and synchronisations between replays."""
+    log(f"[graph] {name}")
+    import torch
+    gpu = gpu_for(name)
+    wl = CASES[name]
+    bu, bp = gpu.stk_rhs()
+    xe_u, xe_p, ie = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, eager=True)
+    ref_u, ref_p = to_host(xe_u), to_host(xe_p)
+    for rep in range(3):
+        xg_u, xg_p, ig = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+        assert ig["iters"] == ie["iters"]
+        assert np.array_equal(to_host(xg_u), ref_u) and np.array_equal(to_host(xg_p), ref_p), rep
+        # unrelated eager work in between replays
+        y = gpu.stk_vcycle(bu)
+        torch.cuda.synchronize()
+        assert np.isfinite(to_host(y)).all()
