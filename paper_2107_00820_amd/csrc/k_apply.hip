@@ -13,7 +13,7 @@
 // Determinism: the cell kernel writes element vectors E[j][cell]; a node
 // kernel sums the <= 2^d cell contributions of each node in a fixed order.
 // No atomics, so repeated applications give bit-identical results.
-#include "stk_internal.h"
+#include "stk_reduce.h"
 
 namespace stk {
 
@@ -76,16 +76,25 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
   double ue[NL];
   constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
   if (need_u) {
+    // lower-corner node of the cell; the other nodes are at compile-time
+    // offsets (a, b, c) in units of (1, n1, n1^2). Loads are unconditional
+    // (always in bounds); Dirichlet nodes are masked to zero.
+    const int64_t base = node_index<D>(g, 2 * c[0], 2 * c[1], D == 3 ? 2 * c[2] : 0);
+    const bool lo[3] = {c[0] == 0, c[1] == 0, D == 3 && c[2] == 0};
+    const bool hi[3] = {c[0] == g.N - 1, c[1] == g.N - 1, D == 3 && c[2] == g.N - 1};
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      const int a0 = 2 * c[0] + digit(n, 0), a1 = 2 * c[1] + digit(n, 1);
-      const int a2 = D == 3 ? 2 * c[2] + digit(n, 2) : 0;
-      bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
-      if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
-      const int64_t nd = node_index<D>(g, a0, a1, a2);
+      const int d0 = digit(n, 0), d1 = digit(n, 1), d2 = D == 3 ? digit(n, 2) : 0;
+      bool bnd = false;
+      bnd = bnd || (d0 == 0 && lo[0]) || (d0 == 2 && hi[0]);
+      bnd = bnd || (d1 == 0 && lo[1]) || (d1 == 2 && hi[1]);
+      if (D == 3) bnd = bnd || (d2 == 0 && lo[2]) || (d2 == 2 && hi[2]);
+      const int64_t nd = base + d0 + (int64_t)g.n1 * (d1 + (int64_t)g.n1 * d2);
 #pragma unroll
-      for (int comp = 0; comp < D; ++comp)
-        ue[comp * NN + n] = bnd ? 0.0 : u[comp * g.nnodes + nd];
+      for (int comp = 0; comp < D; ++comp) {
+        const double v = u[comp * g.nnodes + nd];
+        ue[comp * NN + n] = bnd ? 0.0 : v;
+      }
     }
   }
   double ye[NL];
@@ -140,7 +149,7 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
     }
     if (MODE & EL_AUG) {
 #pragma unroll
-      for (int m = 0; m < NP; ++m) cm[m] += gamma * bu[m] / T.mhat[m];
+      for (int m = 0; m < NP; ++m) cm[m] += gamma * bu[m] * kInvMhat[m];
     }
     if (MODE & EL_BOUT) {
       const double sc = -(D == 2 ? h : h * h);
@@ -340,8 +349,8 @@ __global__ void k_schur_apply(LevelGeo g, const double* __restrict__ Sinv, const
   }
 }
 
-// Deterministic mean of psi_0 coefficients: fixed grid of partial sums, then
-// every block of the subtraction kernel reduces the partials in the same order.
+// Deterministic mean of the psi_0 coefficients: red_parts(ncell) partial sums,
+// then every block of the subtraction kernel reduces them the same way.
 template <int NP>
 __global__ void k_p0_partials(int64_t ncell, const double* __restrict__ p, double* __restrict__ part) {
   __shared__ double sh[kRedThreads];
@@ -349,22 +358,16 @@ __global__ void k_p0_partials(int64_t ncell, const double* __restrict__ p, doubl
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x)
     s += p[c * NP];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 template <int NP>
 __global__ void k_p0_subtract(int64_t ncell, const double* __restrict__ part, int nparts, double* __restrict__ p) {
   __shared__ double mean;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[i];
-    mean = s / (double)ncell;
+  if (threadIdx.x < 64) {
+    const double s = wave_reduce_parts(part, nparts, 1, 0);
+    if (threadIdx.x == 0) mean = s / (double)ncell;
   }
   __syncthreads();
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
@@ -451,14 +454,13 @@ void launch_schur_apply(const Hier& H, const Level& l, const double* y, const do
 }
 
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
+  const int np = red_parts(l.g.ncell);
   if (H.dim == 2) {
-    hipLaunchKernelGGL(k_p0_partials<3>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
-    hipLaunchKernelGGL(k_p0_subtract<3>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials,
-                       kRedBlocks, p);
+    hipLaunchKernelGGL(k_p0_partials<3>, dim3(np), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_subtract<3>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials, np, p);
   } else {
-    hipLaunchKernelGGL(k_p0_partials<4>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
-    hipLaunchKernelGGL(k_p0_subtract<4>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials,
-                       kRedBlocks, p);
+    hipLaunchKernelGGL(k_p0_partials<4>, dim3(np), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_subtract<4>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials, np, p);
   }
 }
 

@@ -1,28 +1,31 @@
 // Vector kernels of the Krylov methods (relaxation GMRES and outer FGMRES).
-// Reductions are deterministic: a fixed grid of kRedBlocks blocks writes one
-// partial per block, and every consumer sums the partials in block order.
-// Arnoldi uses classical Gram-Schmidt applied twice (dots of all basis
-// vectors against the same w, then one combined update).
-#include "stk_internal.h"
+//
+// Reductions are deterministic: a vector of length n is covered by a fixed
+// grid of red_parts(n) blocks (grid-stride loops, so block b always owns the
+// same indices), each block writes one partial per reduced quantity, and
+// every consumer reduces the partials in a fixed order (64 lanes with strided
+// sums, then a fixed butterfly). Arnoldi uses classical Gram-Schmidt applied
+// twice; the second pass's dot products are formed by the blocks that finish
+// the first pass's update of their own indices, so one CGS2 step takes three
+// kernels plus the normalisation.
+#include "stk_reduce.h"
 
 namespace stk {
 
-__device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+// h[k] = sum_b part[b*nk + k] for k < nk, into LDS, by the block's wavefronts.
+__device__ inline void reduce_parts_to_lds(const double* __restrict__ part, int nparts, int nk, double* h) {
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = wave; k < nk; k += nw) {
+    const double s = wave_reduce_parts(part, nparts, nk, k);
+    if ((threadIdx.x & 63) == 0) h[k] = s;
   }
-  const double r = sh[0];
   __syncthreads();
-  return r;
 }
 
-// partials[b*nk + k] = sum over block b's share of V_k . w
+// part[b*nk + k] = sum over block b's indices of V_k . w
 __global__ void __launch_bounds__(kRedThreads) k_dots(const double* __restrict__ V, int64_t ldv, int nk,
                                                        const double* __restrict__ w, int64_t n,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ part) {
   __shared__ double sh[kRedThreads];
   for (int k0 = 0; k0 < nk; k0 += 8) {
     double acc[8];
@@ -36,28 +39,26 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(const double* __restrict__
     }
     for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
       const double s = block_sum(acc[kk], sh);
-      if (threadIdx.x == 0) partials[blockIdx.x * nk + k0 + kk] = s;
+      if (threadIdx.x == 0) part[blockIdx.x * nk + k0 + kk] = s;
     }
   }
 }
 
-// h_k = sum_b partials[b*nk+k];  w -= sum_k h_k V_k;  Hcol[k*hstride] += h_k
-// (block 0); norm partial of the updated w per block.
+// h = reduce(part_in); Hcol[k*hstride] (+)= h_k (block 0); w -= sum_k h_k V_k on
+// this block's indices; then either the next pass's dot partials
+// (next_dots = 1: part_out[b*nk+k] = V_k . w) or the squared-norm partial
+// (next_dots = 0: part_out[b] = w . w).
 __global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __restrict__ V, int64_t ldv, int nk,
                                                               double* __restrict__ w, int64_t n,
-                                                              const double* __restrict__ partials,
-                                                              double* __restrict__ Hcol, int hstride,
-                                                              double* __restrict__ norm_partials) {
+                                                              const double* __restrict__ part_in,
+                                                              double* __restrict__ Hcol, int hstride, int accumulate,
+                                                              double* __restrict__ part_out, int next_dots) {
   __shared__ double h[64];
   __shared__ double sh[kRedThreads];
-  for (int k = threadIdx.x; k < nk; k += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += partials[b * nk + k];
-    h[k] = s;
-  }
-  __syncthreads();
+  reduce_parts_to_lds(part_in, gridDim.x, nk, h);
   if (blockIdx.x == 0)
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) Hcol[k * hstride] += h[k];
+    for (int k = threadIdx.x; k < nk; k += blockDim.x)
+      Hcol[k * hstride] = (accumulate ? Hcol[k * hstride] : 0.0) + h[k];
   double nrm = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double v = w[i];
@@ -65,20 +66,41 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __res
     w[i] = v;
     nrm += v * v;
   }
-  const double s = block_sum(nrm, sh);
-  if (threadIdx.x == 0) norm_partials[blockIdx.x] = s;
+  if (next_dots) {
+    // second-pass dots over the same indices (each written by this thread above)
+    for (int k0 = 0; k0 < nk; k0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
+      for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+           i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+          if (k0 + kk < nk) acc[kk] += V[(int64_t)(k0 + kk) * ldv + i] * wi;
+      }
+      for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
+        const double s = block_sum(acc[kk], sh);
+        if (threadIdx.x == 0) part_out[blockIdx.x * nk + k0 + kk] = s;
+      }
+    }
+  } else {
+    const double s = block_sum(nrm, sh);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+  }
 }
 
-// nrm = sqrt(sum partials); *hout = nrm (block 0); dst = w / nrm (0 if nrm == 0).
+// nrm = sqrt(sum part); *hout = nrm (block 0); dst = w / nrm (0 if nrm == 0).
 __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restrict__ part, int nparts,
                                                             const double* w, int64_t n, double* dst,
                                                             double* __restrict__ hout) {
   __shared__ double nrm;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[b];
-    nrm = sqrt(s);
-    if (blockIdx.x == 0 && hout) *hout = nrm;
+  if (threadIdx.x < 64) {
+    const double s = wave_reduce_parts(part, nparts, 1, 0);
+    if (threadIdx.x == 0) {
+      nrm = sqrt(s);
+      if (blockIdx.x == 0 && hout) *hout = nrm;
+    }
   }
   __syncthreads();
   const double d = nrm;
@@ -86,12 +108,11 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
     dst[i] = d > 0.0 ? w[i] / d : 0.0;
 }
 
-// Least squares min ||beta e1 - Hbar y|| by Givens rotations (one thread).
-// Columns after an exact breakdown (H[j+1][j] == 0) are dropped.
-__global__ void k_ls_solve(double* __restrict__ small, int nu) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Least squares min ||beta e1 - Hbar y|| by Givens rotations; columns after an
+// exact breakdown (H[j+1][j] == 0) are dropped; entries below the
+// subdiagonal are zero by construction and not read.
+__device__ inline void ls_solve(const double* __restrict__ small, int nu, double* y) {
   const double* Hm = small + kSmallH;
-  double* y = small + kSmallY;
   const double beta = small[kSmallBeta];
   for (int j = 0; j < kMaxNu; ++j) y[j] = 0.0;
   if (!(beta > 0.0)) return;
@@ -102,7 +123,7 @@ __global__ void k_ls_solve(double* __restrict__ small, int nu) {
   double g[kMaxNu + 1];
   for (int i = 0; i <= k; ++i) {
     g[i] = 0.0;
-    for (int j = 0; j < k; ++j) R[i][j] = Hm[i * kMaxNu + j];
+    for (int j = 0; j < k; ++j) R[i][j] = i <= j + 1 ? Hm[i * kMaxNu + j] : 0.0;
   }
   g[0] = beta;
   for (int j = 0; j < k; ++j) {
@@ -127,6 +148,20 @@ __global__ void k_ls_solve(double* __restrict__ small, int nu) {
     for (int t = j + 1; t < k; ++t) s -= R[j][t] * y[t];
     y[j] = s / R[j][j];
   }
+}
+
+// x = (x_zero ? 0 : x) + sum_k y_k Z_k with y solved from the relaxation's
+// Hessenberg system (every block solves the tiny system redundantly).
+__global__ void k_relax_update(const double* __restrict__ Z, int64_t ldz, int nu, const double* __restrict__ small,
+                               double* __restrict__ x, int64_t n, int x_zero) {
+  __shared__ double y[kMaxNu];
+  if (threadIdx.x == 0) ls_solve(small, nu, y);
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = x_zero ? 0.0 : x[i];
+  for (int k = 0; k < nu; ++k) v += y[k] * Z[(int64_t)k * ldz + i];
+  x[i] = v;
 }
 
 __global__ void k_combine(const double* __restrict__ Z, int64_t ldz, int nk, const double* __restrict__ y,
@@ -163,23 +198,25 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 
 void launch_dots(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials);
+  hipLaunchKernelGGL(k_dots, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials);
 }
 
-void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n, const double* partials,
-                        double* Hcol, int hstride, double* norm_partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_orth_update, dim3(kRedBlocks), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials, Hcol,
-                     hstride, norm_partials);
+void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n, const double* part_in,
+                        double* Hcol, int hstride, bool accumulate, double* part_out, bool next_dots,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_orth_update, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, part_in, Hcol,
+                     hstride, accumulate ? 1 : 0, part_out, next_dots ? 1 : 0);
 }
 
 void launch_normalize(const double* norm_partials, double* w, int64_t n, double* dst, double* hout,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, dim3(kRedBlocks), dim3(kRedThreads), 0, s, norm_partials, kRedBlocks, w, n, dst,
-                     hout);
+  hipLaunchKernelGGL(k_normalize, dim3(red_parts(n)), dim3(kRedThreads), 0, s, norm_partials, red_parts(n), w, n,
+                     dst, hout);
 }
 
-void launch_ls_solve(double* small, int nu, hipStream_t s) {
-  hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, s, small, nu);
+void launch_relax_update(const double* Z, int64_t ldz, int nu, const double* small, double* x, int64_t n,
+                         bool x_zero, hipStream_t s) {
+  hipLaunchKernelGGL(k_relax_update, dim3(nblk(n, 256)), dim3(256), 0, s, Z, ldz, nu, small, x, n, x_zero ? 1 : 0);
 }
 
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n, bool x_zero,

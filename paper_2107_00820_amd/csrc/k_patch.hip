@@ -76,14 +76,15 @@ __device__ inline void packed_symv(const double* __restrict__ A, const double (&
   }
 }
 
+// One lane per patch: gather the patch residual, packed symmetric GEMV,
+// write the result into the vertex-indexed buffer.
 template <int D, int NPT>
-__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, const int* __restrict__ verts, int count,
-                                                  const double* __restrict__ inv, const double* __restrict__ r,
-                                                  double* __restrict__ zbuf, int nvert) {
+__device__ inline void asm_patch(const LevelGeo& g, const int* __restrict__ verts, int count,
+                                 const double* __restrict__ inv, const double* __restrict__ r,
+                                 double* __restrict__ zbuf, int nvert, int s) {
   constexpr int NN = Dims<D>::NN;
   constexpr int NBOX = NPT / D;
   constexpr bool FULL = NBOX == NN;
-  const int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= count) return;
   const int vert = verts[s];
   int lo[3], ext[3], vc[3];
@@ -111,6 +112,34 @@ __global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, const int* __restri
       mul *= 3;
     }
     zbuf[(int64_t)(comp * NN + loc) * nvert + vert] = y[i];
+  }
+}
+
+// All patch classes of a level in one launch: block ranges select the class
+// (sizes d*3^d, d*3^(d-1), .., d; interior patches first).
+struct AsmClasses {
+  const int* verts[4];
+  const double* inv[4];
+  int count[4];
+  int first_block[5];
+};
+
+template <int D>
+__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses c, const double* __restrict__ r,
+                                                  double* __restrict__ zbuf, int nvert) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (b < c.first_block[1]) {
+    asm_patch<D, D == 2 ? 18 : 81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane);
+  } else if (b < c.first_block[2]) {
+    const int s = (b - c.first_block[1]) * 64 + lane;
+    asm_patch<D, D == 2 ? 6 : 27>(g, c.verts[1], c.count[1], c.inv[1], r, zbuf, nvert, s);
+  } else if (b < c.first_block[3]) {
+    const int s = (b - c.first_block[2]) * 64 + lane;
+    asm_patch<D, D == 2 ? 2 : 9>(g, c.verts[2], c.count[2], c.inv[2], r, zbuf, nvert, s);
+  } else if (D == 3 && b < c.first_block[4]) {
+    const int s = (b - c.first_block[3]) * 64 + lane;
+    asm_patch<D, 3>(g, c.verts[3], c.count[3], c.inv[3], r, zbuf, nvert, s);
   }
 }
 
@@ -210,40 +239,31 @@ void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hip
                        pc.count, pc.inv, H.flag);
 }
 
-template <int D, int NPT>
-static void gemv_launch(const Level& l, const PatchClass& pc, const double* r, hipStream_t s) {
-  hipLaunchKernelGGL((k_asm_gemv<D, NPT>), dim3(nblk(pc.count, 64)), dim3(64), 0, s, l.g, pc.verts, pc.count,
-                     pc.inv, r, l.zbuf, l.nvert);
-}
-
 void launch_asm(Hier& H, const Level& l, const double* r, double* y, hipStream_t s) {
-  for (size_t ci = 0; ci < l.cls.size(); ++ci) {
-    const PatchClass& pc = l.cls[ci];
-    if (pc.count == 0) continue;
-    hipEvent_t ev = nullptr;
-    if (ci == 0) prof_begin(H, s, &ev);
-    if (H.dim == 2) {
-      switch (pc.n) {
-        case 18: gemv_launch<2, 18>(l, pc, r, s); break;
-        case 6: gemv_launch<2, 6>(l, pc, r, s); break;
-        case 2: gemv_launch<2, 2>(l, pc, r, s); break;
-        default: break;
-      }
-    } else {
-      switch (pc.n) {
-        case 81: gemv_launch<3, 81>(l, pc, r, s); break;
-        case 27: gemv_launch<3, 27>(l, pc, r, s); break;
-        case 9: gemv_launch<3, 9>(l, pc, r, s); break;
-        case 3: gemv_launch<3, 3>(l, pc, r, s); break;
-        default: break;
-      }
-    }
-    if (ci == 0) {
-      // algorithmic bytes: packed inverses + patch outputs + one read of the residual
-      const double bytes = 8.0 * ((double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n) + (double)l.nvel);
-      prof_end(H, s, PROF_ASM_GEMV, ev, bytes);
+  AsmClasses c{};
+  int blocks = 0;
+  double bytes = 8.0 * (double)l.nvel;   // one read of the residual
+  const int ncls = H.dim == 2 ? 3 : 4;
+  for (int ci = 0; ci < 4; ++ci) {
+    c.first_block[ci] = blocks;
+    if (ci < ncls && ci < (int)l.cls.size()) {
+      const PatchClass& pc = l.cls[ci];
+      c.verts[ci] = pc.verts;
+      c.inv[ci] = pc.inv;
+      c.count[ci] = pc.count;
+      blocks += (pc.count + 63) / 64;
+      // algorithmic bytes: packed inverse and patch output of every patch
+      bytes += 8.0 * (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
     }
   }
+  c.first_block[4] = blocks;
+  hipEvent_t ev = nullptr;
+  prof_begin(H, s, &ev);
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_asm_gemv<2>, dim3(blocks), dim3(64), 0, s, l.g, c, r, l.zbuf, l.nvert);
+  else
+    hipLaunchKernelGGL(k_asm_gemv<3>, dim3(blocks), dim3(64), 0, s, l.g, c, r, l.zbuf, l.nvert);
+  prof_end(H, s, PROF_ASM_GEMV, ev, bytes);
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
     hipLaunchKernelGGL(k_asm_gather<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.zbuf, l.nvert, y);

@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "../../include/stk.h"
-#include "stk_internal.h"
+#include "stk_reduce.h"
 
 using namespace stk;
 
@@ -244,30 +244,28 @@ void prolong_robust(Hier& H, int l, const double* xc, double* xf) {
 void smooth(Hier& H, int l, const double* b, double* x, int nu, bool x_zero) {
   Level& L = H.lv[l];
   const int64_t n = L.nvel;
-  double* part = H.partials;
-  double* normp = H.partials + kPartialLen;
-  launch_fill(L.small, 0.0, kSmallLen, H.stream);
+  double* p1 = H.partials;
+  double* p2 = H.partials + kPartialLen;
   const double* r0 = b;
   if (!x_zero) {
     residual(H, l, b, x, L.r);
     r0 = L.r;
   }
-  launch_dots(r0, n, 1, r0, n, part, H.stream);
-  launch_normalize(part, const_cast<double*>(r0), n, L.V, L.small + kSmallBeta, H.stream);
+  launch_dots(r0, n, 1, r0, n, p1, H.stream);
+  launch_normalize(p1, const_cast<double*>(r0), n, L.V, L.small + kSmallBeta, H.stream);
   for (int j = 0; j < nu; ++j) {
     double* Vj = L.V + (int64_t)j * n;
     double* Zj = L.Z + (int64_t)j * n;
     double* w = L.V + (int64_t)(j + 1) * n;
     launch_asm(H, L, Vj, Zj, H.stream);
     apply_A(H, l, Zj, w);
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_dots(L.V, n, j + 1, w, n, part, H.stream);
-      launch_orth_update(L.V, n, j + 1, w, n, part, L.small + kSmallH + j, kMaxNu, normp, H.stream);
-    }
-    launch_normalize(normp, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
+    double* Hcol = L.small + kSmallH + j;
+    launch_dots(L.V, n, j + 1, w, n, p1, H.stream);
+    launch_orth_update(L.V, n, j + 1, w, n, p1, Hcol, kMaxNu, false, p2, true, H.stream);
+    launch_orth_update(L.V, n, j + 1, w, n, p2, Hcol, kMaxNu, true, p1, false, H.stream);
+    launch_normalize(p1, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
   }
-  launch_ls_solve(L.small, nu, H.stream);
-  launch_combine(L.Z, n, nu, L.small + kSmallY, x, n, x_zero, H.stream);
+  launch_relax_update(L.Z, n, nu, L.small, x, n, x_zero, H.stream);
 }
 
 void coarse_solve(Hier& H, const double* b, double* x) { launch_coarse_apply(H, H.lv[0], b, x, H.stream); }
@@ -315,15 +313,14 @@ void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec) {
   double* Vj = H.fV + (int64_t)j * nvec;
   double* Zj = H.fZ + (int64_t)j * nvec;
   double* w = H.fV + (int64_t)(j + 1) * nvec;
-  double* part = H.partials;
-  double* normp = H.partials + kPartialLen;
+  double* p1 = H.partials;
+  double* p2 = H.partials + kPartialLen;
   precond(H, Vj, Vj + nu, Zj, Zj + nu);
   stokes_apply(H, Zj, w);
-  for (int pass = 0; pass < 2; ++pass) {
-    launch_dots(H.fV, nvec, j + 1, w, nvec, part, H.stream);
-    launch_orth_update(H.fV, nvec, j + 1, w, nvec, part, H.fH + j, m, normp, H.stream);
-  }
-  launch_normalize(normp, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);
+  launch_dots(H.fV, nvec, j + 1, w, nvec, p1, H.stream);
+  launch_orth_update(H.fV, nvec, j + 1, w, nvec, p1, H.fH + j, m, false, p2, true, H.stream);
+  launch_orth_update(H.fV, nvec, j + 1, w, nvec, p2, H.fH + j, m, true, p1, false, H.stream);
+  launch_normalize(p1, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);
 }
 
 void drop_graphs(Hier& H) {
@@ -340,11 +337,12 @@ stk_status check_level(const Hier& H, int l, int lmin) {
 
 stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
   launch_dots(x, n, 1, x, n, H.partials, H.stream);
-  std::vector<double> part(kRedBlocks);
-  HIPCHK(hipMemcpyAsync(part.data(), H.partials, kRedBlocks * 8, hipMemcpyDeviceToHost, H.stream));
+  const int np = red_parts(n);
+  std::vector<double> part(np);
+  HIPCHK(hipMemcpyAsync(part.data(), H.partials, np * 8, hipMemcpyDeviceToHost, H.stream));
   HIPCHK(hipStreamSynchronize(H.stream));
   double s = 0.0;
-  for (int b = 0; b < kRedBlocks; ++b) s += part[b];
+  for (int b = 0; b < np; ++b) s += part[b];
   *out = sqrt(s);
   return STK_OK;
 }
@@ -678,7 +676,7 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
   double* bvec = H.fr + nvec;          // contiguous copy of b
   double* xvec = H.fw;                 // iterate x (contiguous)
   double* rvec = H.fr;                 // residual / scratch
-  double* w = nullptr;
+
   HIPCHK(hipMemcpyAsync(bvec, b_u, nu * 8, hipMemcpyDeviceToDevice, s));
   if (b_p) HIPCHK(hipMemcpyAsync(bvec + nu, b_p, np * 8, hipMemcpyDeviceToDevice, s));
   else launch_fill(bvec + nu, 0.0, np, s);
@@ -702,11 +700,8 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
   int it = 0;
   bool converged = false;
   std::vector<double> Hd((size_t)(m + 1) * m), Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  double* part = H.partials;
-  double* normp = H.partials + kPartialLen;
   while (true) {
     launch_axpby(1.0 / beta, rvec, 0.0, rvec, H.fV, nvec, s);
-    launch_fill(H.fH, 0.0, (int64_t)(m + 1) * m, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;

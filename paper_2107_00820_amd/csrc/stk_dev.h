@@ -65,7 +65,7 @@ __device__ inline double cell_entry(const double* __restrict__ mu, int64_t ncell
   }
   double al = 0.0;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) al += T.bhat[m][ci * NN + na] * T.bhat[m][cj * NN + nb] / T.mhat[m];
+  for (int m = 0; m < NP; ++m) al += T.bhat[m][ci * NN + na] * T.bhat[m][cj * NN + nb] * kInvMhat[m];
   const double sc = D == 2 ? 1.0 : h;
   return sc * (s + gamma * al);
 }

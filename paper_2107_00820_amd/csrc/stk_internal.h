@@ -12,6 +12,8 @@
 namespace stk {
 
 constexpr int kMaxNu = 8;          // relaxation steps per smoothing call
+// 1 / Mhat: inverse of the reference pressure mass diag(1, 1/12, ..)
+constexpr double kInvMhat[4] = {1.0, 12.0, 12.0, 12.0};
 constexpr int kRedBlocks = 512;    // fixed grid of the deterministic reductions
 constexpr int kRedThreads = 256;
 
@@ -128,11 +130,12 @@ void launch_coarse_apply(const Hier& H, const Level& l, const double* b, double*
 void launch_dots(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
                  hipStream_t s);
 void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n,
-                        const double* partials, double* Hcol, int hstride, double* norm_partials,
-                        hipStream_t s);
+                        const double* part_in, double* Hcol, int hstride, bool accumulate,
+                        double* part_out, bool next_dots, hipStream_t s);
 void launch_normalize(const double* norm_partials, double* w, int64_t n, double* dst,
                       double* hout, hipStream_t s);
-void launch_ls_solve(double* small, int nu, hipStream_t s);
+void launch_relax_update(const double* Z, int64_t ldz, int nu, const double* small, double* x,
+                         int64_t n, bool x_zero, hipStream_t s);
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n,
                     bool x_zero, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
