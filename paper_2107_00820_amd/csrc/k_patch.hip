@@ -19,9 +19,21 @@
 // Apply (one lane per patch): gather the patch residual, symmetric GEMV from
 // the packed inverse, write the result into a vertex-indexed buffer; a node
 // kernel then sums the <= 2^d overlapping patch results in a fixed order.
+#include <utility>
+
 #include "stk_dev.h"
 
 namespace stk {
+
+template <class F, int... I>
+__device__ __attribute__((always_inline)) inline void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, i>) for i = 0..N-1, expanded at compile time.
+template <int N, class F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <int D>
 __global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, double gamma, int n,
@@ -59,27 +71,114 @@ __global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, double 
 
 // ---------------------------------------------------------------------------
 // y = A^{-1} x with A^{-1} packed lower, element stride 64.
+// Packed symmetric GEMV y = A x over one patch, A's element k at A[k*64].
+// The element loop is generated at compile time (fold expressions over index
+// sequences) so that every index into x and y is a constant and both stay in
+// registers; the unroller is not relied upon for the 3321-element 3D case.
+template <int NPT, int I, int J, class X>
+__device__ __attribute__((always_inline)) inline void symv_elem(const double* __restrict__ A, const X& x, double (&y)[NPT], double xi) {
+  const double a = A[(int64_t)(I * (I + 1) / 2 + J) * 64];
+  if constexpr (J != I) {
+    y[I] += a * x(J);
+    y[J] += a * xi;
+  } else {
+    y[I] += a * xi;
+  }
+}
+
+template <int NPT, int I, class X, int... J>
+__device__ __attribute__((always_inline)) inline void symv_row(const double* __restrict__ A, const X& x, double (&y)[NPT],
+                                std::integer_sequence<int, J...>) {
+  const double xi = x(I);
+  (symv_elem<NPT, I, J>(A, x, y, xi), ...);
+}
+
+template <int NPT, class X, int... I>
+__device__ __attribute__((always_inline)) inline void symv_rows(const double* __restrict__ A, const X& x, double (&y)[NPT],
+                                 std::integer_sequence<int, I...>) {
+  (symv_row<NPT, I>(A, x, y, std::make_integer_sequence<int, I + 1>{}), ...);
+}
+
+// x from registers
 template <int NPT>
-__device__ inline void packed_symv(const double* __restrict__ A, const double (&x)[NPT], double (&y)[NPT]) {
+__device__ __attribute__((always_inline)) inline void packed_symv(const double* __restrict__ A, const double (&x)[NPT], double (&y)[NPT]) {
 #pragma unroll
   for (int i = 0; i < NPT; ++i) y[i] = 0.0;
-  int k = 0;
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const double a = A[(int64_t)k * 64];
-      ++k;
-      y[i] += a * x[j];
-      if (j != i) y[j] += a * x[i];
+  auto xr = [&](int j) { return x[j]; };
+  symv_rows<NPT>(A, xr, y, std::make_integer_sequence<int, NPT>{});
+}
+
+// Row index of packed lower-triangle element e (largest i with i(i+1)/2 <= e).
+constexpr int tri_row(int e) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= e) ++i;
+  return i;
+}
+
+// x staged in LDS (column `lane` of xs[NPT][64]); used for the 81-unknown 3D
+// patches, where x and y together would not fit the register file. Each lane
+// reads only its own column, so no barrier is needed. The 3321 packed
+// elements stream in chunks of CH with the next chunk's loads issued before
+// the current chunk's arithmetic (scheduling barriers keep the compiler from
+// hoisting all loads at once, which would spill).
+template <int NPT, int CH, int C, class X>
+__device__ __attribute__((always_inline)) inline void symv_chunk_load(const double* __restrict__ A, double (&buf)[CH]) {
+  constexpr int NE = NPT * (NPT + 1) / 2;
+  static_for<CH>([&](auto T) {
+    constexpr int e = C * CH + T;
+    if constexpr (e < NE) buf[T] = A[(int64_t)e * 64];
+  });
+}
+
+template <int NPT, int CH, int C, class X>
+__device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x, const double (&buf)[CH],
+                                                                     double (&y)[NPT]) {
+  constexpr int NE = NPT * (NPT + 1) / 2;
+  static_for<CH>([&](auto T) {
+    constexpr int e = C * CH + T;
+    if constexpr (e < NE) {
+      constexpr int i = tri_row(e);
+      constexpr int j = e - i * (i + 1) / 2;
+      if constexpr (j != i) {
+        y[i] += buf[T] * x(j);
+        y[j] += buf[T] * x(i);
+      } else {
+        y[i] += buf[T] * x(i);
+      }
     }
-  }
+  });
+}
+
+template <int NPT>
+__device__ __attribute__((always_inline)) inline void packed_symv_lds(const double* __restrict__ A,
+                                                                      const double* xs, int lane,
+                                                                      double (&y)[NPT]) {
+  constexpr int CH = 16;
+  constexpr int NE = NPT * (NPT + 1) / 2;
+  constexpr int NC = (NE + CH - 1) / CH;
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) y[i] = 0.0;
+  auto xr = [&](int j) { return xs[j * 64 + lane]; };
+  using X = decltype(xr);
+  double b0[CH], b1[CH];
+  symv_chunk_load<NPT, CH, 0, X>(A, b0);
+  static_for<NC>([&](auto C) {
+    constexpr int c = C;
+    if constexpr (c + 1 < NC) {
+      if constexpr ((c & 1) == 0) symv_chunk_load<NPT, CH, c + 1, X>(A, b1);
+      else symv_chunk_load<NPT, CH, c + 1, X>(A, b0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr ((c & 1) == 0) symv_chunk_fma<NPT, CH, c>(xr, b0, y);
+    else symv_chunk_fma<NPT, CH, c>(xr, b1, y);
+    __builtin_amdgcn_sched_barrier(0);
+  });
 }
 
 // One lane per patch: gather the patch residual, packed symmetric GEMV,
 // write the result into the vertex-indexed buffer.
 template <int D, int NPT>
-__device__ inline void asm_patch(const LevelGeo& g, const int* __restrict__ verts, int count,
+__device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& g, const int* __restrict__ verts, int count,
                                  const double* __restrict__ inv, const double* __restrict__ r,
                                  double* __restrict__ zbuf, int nvert, int s) {
   constexpr int NN = Dims<D>::NN;
@@ -115,6 +214,34 @@ __device__ inline void asm_patch(const LevelGeo& g, const int* __restrict__ vert
   }
 }
 
+// Interior (full) patch with x staged in LDS; all unknown indices are
+// compile-time: unknown i = comp*3^d + a + 3b + 9c sits at node 2v-1 + (a,b,c).
+template <int D, int NPT>
+__device__ __attribute__((always_inline)) inline void asm_patch_lds(const LevelGeo& g, const int* __restrict__ verts, int count,
+                                     const double* __restrict__ inv, const double* __restrict__ r,
+                                     double* __restrict__ zbuf, int nvert, int s, double* xs, int lane) {
+  constexpr int NN = Dims<D>::NN;
+  if (s >= count) return;
+  const int vert = verts[s];
+  int lo[3], ext[3], vc[3];
+  patch_box<D>(g, vert, lo, ext, vc);
+  const int64_t base = node_index<D>(g, lo[0], lo[1], lo[2]);
+  const int64_t n1 = g.n1;
+  static_for<NPT>([&](auto I) {
+    constexpr int i = I;
+    constexpr int comp = i / NN, loc = i % NN;
+    xs[i * 64 + lane] = r[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
+  });
+  const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
+  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  double y[NPT];
+  packed_symv_lds<NPT>(A, xs, lane, y);
+  static_for<NPT>([&](auto I) {
+    constexpr int i = I;
+    zbuf[(int64_t)i * nvert + vert] = y[i];
+  });
+}
+
 // All patch classes of a level in one launch: block ranges select the class
 // (sizes d*3^d, d*3^(d-1), .., d; interior patches first).
 struct AsmClasses {
@@ -130,7 +257,12 @@ __global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses c, const
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   if (b < c.first_block[1]) {
-    asm_patch<D, D == 2 ? 18 : 81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane);
+    if (D == 2) {
+      asm_patch<D, 18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane);
+    } else {
+      __shared__ double xs[81 * 64];
+      asm_patch_lds<D, 81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane, xs, lane);
+    }
   } else if (b < c.first_block[2]) {
     const int s = (b - c.first_block[1]) * 64 + lane;
     asm_patch<D, D == 2 ? 6 : 27>(g, c.verts[1], c.count[1], c.inv[1], r, zbuf, nvert, s);
@@ -187,41 +319,46 @@ __global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nv
 // Local solves of the robust transfer: for every coarse cell K (one lane),
 // z = A_K^{-1} in|_K where A_K is the star patch of the fine vertex 2K+1
 // (interior-patch slot lex(K)); out|_K = (accumulate ? out|_K : 0) + alpha z.
-template <int D>
+template <int D, bool ACC>
 __global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const double* __restrict__ inv,
                                                       const double* __restrict__ in, double* __restrict__ out,
-                                                      double alpha, int accumulate) {
+                                                      double alpha) {
   constexpr int NN = Dims<D>::NN, NPT = Dims<D>::NL;
   const int nc = g.N / 2;
   const int ncc = D == 2 ? nc * nc : nc * nc * nc;
   const int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= ncc) return;
   const int K0 = s % nc, K1 = (s / nc) % nc, K2 = D == 3 ? s / (nc * nc) : 0;
-  const int lo[3] = {4 * K0 + 1, 4 * K1 + 1, D == 3 ? 4 * K2 + 1 : 0};
-  const int ext[3] = {3, 3, D == 3 ? 3 : 1};
-  double x[NPT];
-  int64_t addr[NN];
-#pragma unroll
-  for (int i = 0; i < NN; ++i) {
-    int nd[3];
-    patch_dof<D>(i, lo, ext, nd);
-    addr[i] = node_index<D>(g, nd[0], nd[1], nd[2]);
-  }
-#pragma unroll
-  for (int c = 0; c < D; ++c)
-#pragma unroll
-    for (int i = 0; i < NN; ++i) x[c * NN + i] = in[c * g.nnodes + addr[i]];
+  const int64_t base = node_index<D>(g, 4 * K0 + 1, 4 * K1 + 1, D == 3 ? 4 * K2 + 1 : 0);
+  const int64_t n1 = g.n1;
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
   const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
   double y[NPT];
-  packed_symv<NPT>(A, x, y);
-#pragma unroll
-  for (int c = 0; c < D; ++c)
-#pragma unroll
-    for (int i = 0; i < NN; ++i) {
-      const int64_t o = c * g.nnodes + addr[i];
-      out[o] = (accumulate ? out[o] : 0.0) + alpha * y[c * NN + i];
-    }
+  if constexpr (D == 2) {
+    double x[NPT];
+    static_for<NPT>([&](auto I) {
+      constexpr int i = I;
+      constexpr int comp = i / NN, loc = i % NN;
+      x[i] = in[comp * g.nnodes + base + digit(loc, 0) + n1 * digit(loc, 1)];
+    });
+    packed_symv<NPT>(A, x, y);
+  } else {
+    __shared__ double xs[NPT * 64];
+    const int lane = threadIdx.x;
+    static_for<NPT>([&](auto I) {
+      constexpr int i = I;
+      constexpr int comp = i / NN, loc = i % NN;
+      xs[i * 64 + lane] = in[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
+    });
+    packed_symv_lds<NPT>(A, xs, lane, y);
+  }
+  static_for<NPT>([&](auto I) {
+    constexpr int i = I;
+    constexpr int comp = i / NN, loc = i % NN;
+    const int64_t o = comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * (D == 3 ? digit(loc, 2) : 0));
+    if constexpr (ACC) out[o] += alpha * y[i];
+    else out[o] = alpha * y[i];
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -275,12 +412,15 @@ void launch_center_solve(const Hier& H, const Level& fine, const double* in, dou
                          bool accumulate, hipStream_t s) {
   const int nc = fine.g.N / 2;
   const int ncc = H.dim == 2 ? nc * nc : nc * nc * nc;
-  if (H.dim == 2)
-    hipLaunchKernelGGL(k_center_solve<2>, dim3(nblk(ncc, 64)), dim3(64), 0, s, fine.g, fine.cls[0].inv, in, out,
-                       alpha, accumulate ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_center_solve<3>, dim3(nblk(ncc, 64)), dim3(64), 0, s, fine.g, fine.cls[0].inv, in, out,
-                       alpha, accumulate ? 1 : 0);
+  const dim3 grid(nblk(ncc, 64)), blk(64);
+  const double* inv = fine.cls[0].inv;
+  if (H.dim == 2) {
+    if (accumulate) hipLaunchKernelGGL((k_center_solve<2, true>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    else hipLaunchKernelGGL((k_center_solve<2, false>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+  } else {
+    if (accumulate) hipLaunchKernelGGL((k_center_solve<3, true>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    else hipLaunchKernelGGL((k_center_solve<3, false>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+  }
 }
 
 }  // namespace stk
