@@ -10,7 +10,7 @@
 // with Bhat[m][j] = int_ref psi_m div(phi_j) and Mhat = diag(1, 1/12, ..) the
 // reference pressure mass matrix (W = M_p; preconditioner P1 of eq. (P1P2)).
 //
-// Determinism: the cell kernel writes element vectors E[j][cell]; a node
+// Determinism: the cell kernel writes element vectors E[cell][j]; a node
 // kernel sums the <= 2^d cell contributions of each node in a fixed order.
 // No atomics, so repeated applications give bit-identical results.
 #include "stk_reduce.h"
@@ -49,8 +49,8 @@ __global__ void k_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, 
   constexpr int NQ = Dims<D>::NQ;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)NQ * g.ncell) return;
-  const int q = (int)(idx / g.ncell);
-  const int64_t cell = idx - (int64_t)q * g.ncell;
+  const int64_t cell = idx / NQ;
+  const int q = (int)(idx - cell * NQ);
   int c[3];
   cell_coords<D>(g, cell, c);
   double x[D];
@@ -61,119 +61,220 @@ __global__ void k_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, 
 }
 
 // ---------------------------------------------------------------------------
-// Cell kernel. One thread per cell, everything in registers, tables folded.
+// Cell kernel. A wavefront handles CPW = floor(64 / 3^d) cells (7 in 2D, 2 in
+// 3D) with one lane per (cell, Gauss point) in the first phase and one lane
+// per (cell, node) in the second; the cell's velocity and the weighted stress
+// at the Gauss points are exchanged through LDS.
+//   phase 1 (lane = Gauss point q): reference gradient G of u at q by sum
+//     factorisation over the tensor axes; S_q = w_q mu_q (G + G^T) plus the
+//     pressure-like diagonal w_q pi_q, pi_q = sum_m c_m psi_m(q) with
+//     c = gamma Mhat^{-1} Bhat u - h p (the divergence moments Bhat u are
+//     summed over the cell's lanes in a fixed order).
+//   phase 2 (lane = node n): y_n = h^{d-2} sum_q S_q : dphi_n(q), again
+//     sum-factorised; element vectors E[cell][comp * 3^d + n].
+// All table entries are exact compile-time values selected by the lane's
+// digits; no atomics.
+constexpr double kB1[3][3] = {{lag(0, kGaussX[0]), lag(1, kGaussX[0]), lag(2, kGaussX[0])},
+                              {lag(0, kGaussX[1]), lag(1, kGaussX[1]), lag(2, kGaussX[1])},
+                              {lag(0, kGaussX[2]), lag(1, kGaussX[2]), lag(2, kGaussX[2])}};
+constexpr double kD1[3][3] = {{dlag(0, kGaussX[0]), dlag(1, kGaussX[0]), dlag(2, kGaussX[0])},
+                              {dlag(0, kGaussX[1]), dlag(1, kGaussX[1]), dlag(2, kGaussX[1])},
+                              {dlag(0, kGaussX[2]), dlag(1, kGaussX[2]), dlag(2, kGaussX[2])}};
+
+// tab[r][c] with a runtime row r in 0..2 (selects between compile-time constants)
+__device__ inline double sel3(const double (&tab)[3][3], int r, int c) {
+  return r == 0 ? tab[0][c] : (r == 1 ? tab[1][c] : tab[2][c]);
+}
+// tab[r][c] with a runtime column c
+__device__ inline double selc(const double (&tab)[3][3], int r, int c) {
+  return c == 0 ? tab[r][0] : (c == 1 ? tab[r][1] : tab[r][2]);
+}
+
+template <int D>
+struct SymIdx {
+  static constexpr int NS = D * (D + 1) / 2;
+  static constexpr int at(int a, int b) {
+    return a == b ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+  }
+};
+
 template <int D, int MODE>
-__global__ void __launch_bounds__(D == 2 ? 256 : 64)
+__global__ void __launch_bounds__(64)
 k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __restrict__ u,
        const double* __restrict__ p, double* __restrict__ E, double* __restrict__ pout) {
-  constexpr int NN = Dims<D>::NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
-  constexpr const RefTab<D>& T = Ref<D>::T;
-  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (cell >= g.ncell) return;
-  int c[3];
-  cell_coords<D>(g, cell, c);
-  const double h = g.h;
-  double ue[NL];
+  constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
+  constexpr int NS = SymIdx<D>::NS;
+  constexpr int CPW = 64 / NQ;
   constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
-  if (need_u) {
-    // lower-corner node of the cell; the other nodes are at compile-time
-    // offsets (a, b, c) in units of (1, n1, n1^2). Loads are unconditional
-    // (always in bounds); Dirichlet nodes are masked to zero.
-    const int64_t base = node_index<D>(g, 2 * c[0], 2 * c[1], D == 3 ? 2 * c[2] : 0);
-    const bool lo[3] = {c[0] == 0, c[1] == 0, D == 3 && c[2] == 0};
-    const bool hi[3] = {c[0] == g.N - 1, c[1] == g.N - 1, D == 3 && c[2] == g.N - 1};
+  constexpr bool need_c = (MODE & (EL_AUG | EL_BT | EL_BOUT)) != 0;
+  __shared__ double us[CPW][D][NN];
+  __shared__ double ss[CPW][NQ][NS];
+  __shared__ double red[CPW][NQ][NP];
+  __shared__ double cms[CPW][NP];
+  const int lane = threadIdx.x;
+  const int lc = lane / NQ;
+  const int t = lane - lc * NQ;
+  const int64_t cell = (int64_t)blockIdx.x * CPW + lc;
+  const bool valid = lc < CPW && cell < g.ncell;
+  const int t0 = t % 3, t1 = (t / 3) % 3, t2 = D == 3 ? t / 9 : 0;
+  int c[3] = {0, 0, 0};
+  if (valid) {
+    c[0] = (int)(cell % g.N);
+    c[1] = (int)((cell / g.N) % g.N);
+    c[2] = D == 3 ? (int)(cell / ((int64_t)g.N * g.N)) : 0;
+  }
+  const double h = g.h;
+  // ---- stage u: lane t loads node t of its cell (Dirichlet nodes masked)
+  if (need_u && valid) {
+    const int a0 = 2 * c[0] + t0, a1 = 2 * c[1] + t1, a2 = D == 3 ? 2 * c[2] + t2 : 0;
+    bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
+    if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
+    const int64_t nd = node_index<D>(g, a0, a1, a2);
 #pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      const int d0 = digit(n, 0), d1 = digit(n, 1), d2 = D == 3 ? digit(n, 2) : 0;
-      bool bnd = false;
-      bnd = bnd || (d0 == 0 && lo[0]) || (d0 == 2 && hi[0]);
-      bnd = bnd || (d1 == 0 && lo[1]) || (d1 == 2 && hi[1]);
-      if (D == 3) bnd = bnd || (d2 == 0 && lo[2]) || (d2 == 2 && hi[2]);
-      const int64_t nd = base + d0 + (int64_t)g.n1 * (d1 + (int64_t)g.n1 * d2);
+    for (int comp = 0; comp < D; ++comp) {
+      const double v = u[comp * g.nnodes + nd];
+      us[lc][comp][t] = bnd ? 0.0 : v;
+    }
+  }
+  __syncthreads();
+  // ---- phase 1: lane = Gauss point q = (t0, t1, t2)
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  double S[NS];
 #pragma unroll
-      for (int comp = 0; comp < D; ++comp) {
-        const double v = u[comp * g.nnodes + nd];
-        ue[comp * NN + n] = bnd ? 0.0 : v;
+  for (int i = 0; i < NS; ++i) S[i] = 0.0;
+  double wq = 1.0;
+  {
+    wq = kGaussW[t0] * kGaussW[t1] * (D == 3 ? kGaussW[t2] : 1.0);
+  }
+  if (valid && need_u) {
+    double Bx[3], Dx[3], By[3], Dy[3], Bz[3], Dz[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Bx[a] = sel3(kB1, t0, a); Dx[a] = sel3(kD1, t0, a);
+      By[a] = sel3(kB1, t1, a); Dy[a] = sel3(kD1, t1, a);
+      Bz[a] = sel3(kB1, t2, a); Dz[a] = sel3(kD1, t2, a);
+    }
+    double G[D][D];
+#pragma unroll
+    for (int comp = 0; comp < D; ++comp) {
+      if constexpr (D == 3) {
+        double zB[3][3], zD[3][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const double u0 = us[lc][comp][a + 3 * b], u1 = us[lc][comp][a + 3 * b + 9],
+                         u2 = us[lc][comp][a + 3 * b + 18];
+            zB[a][b] = u0 * Bz[0] + u1 * Bz[1] + u2 * Bz[2];
+            zD[a][b] = u0 * Dz[0] + u1 * Dz[1] + u2 * Dz[2];
+          }
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double yBB = zB[a][0] * By[0] + zB[a][1] * By[1] + zB[a][2] * By[2];
+          const double yDB = zB[a][0] * Dy[0] + zB[a][1] * Dy[1] + zB[a][2] * Dy[2];
+          const double yBD = zD[a][0] * By[0] + zD[a][1] * By[1] + zD[a][2] * By[2];
+          g0 += yBB * Dx[a];
+          g1 += yDB * Bx[a];
+          g2 += yBD * Bx[a];
+        }
+        G[comp][0] = g0; G[comp][1] = g1; G[comp][2] = g2;
+      } else {
+        double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double u0 = us[lc][comp][a], u1 = us[lc][comp][a + 3], u2 = us[lc][comp][a + 6];
+          const double yB = u0 * By[0] + u1 * By[1] + u2 * By[2];
+          const double yD = u0 * Dy[0] + u1 * Dy[1] + u2 * Dy[2];
+          g0 += yB * Dx[a];
+          g1 += yD * Bx[a];
+        }
+        G[comp][0] = g0; G[comp][1] = g1;
       }
     }
-  }
-  double ye[NL];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) ye[j] = 0.0;
-
-  if (MODE & EL_VISC) {
-#pragma unroll
-    for (int q = 0; q < NN; ++q) {
-      double G[D][D];
+    if (MODE & EL_VISC) {
+      const double wm = wq * mu[cell * NQ + t];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          double s = 0.0;
+        for (int b = a; b < D; ++b) S[SymIdx<D>::at(a, b)] = wm * (G[a][b] + G[b][a]);
+    }
+    if (MODE & (EL_AUG | EL_BOUT)) {
+      double dv = 0.0;
 #pragma unroll
-          for (int n = 0; n < NN; ++n)
-            if (T.dphi[q][n][k] != 0.0) s += T.dphi[q][n][k] * ue[a * NN + n];
-          G[a][k] = s;
+      for (int a = 0; a < D; ++a) dv += G[a][a];
+      red[lc][t][0] = wq * dv;
+#pragma unroll
+      for (int m = 1; m < NP; ++m) red[lc][t][m] = wq * (kGaussX[m == 1 ? t0 : (m == 2 ? t1 : t2)] - 0.5) * dv;
+    }
+  }
+  if constexpr (need_c) {
+    __syncthreads();
+    if (valid && t == 0) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        double cm = 0.0;
+        if (MODE & (EL_AUG | EL_BOUT)) {
+          double bu = 0.0;
+          for (int q = 0; q < NQ; ++q) bu += red[lc][q][m];
+          if (MODE & EL_AUG) cm += gamma * bu * kInvMhat[m];
+          if (MODE & EL_BOUT) pout[cell * NP + m] = -(D == 2 ? h : h * h) * bu;
         }
-      const double wm = T.w[q] * mu[(int64_t)q * g.ncell + cell];
-      double S[D][D];
+        if (MODE & EL_BT) cm -= h * p[cell * NP + m];
+        cms[lc][m] = cm;
+      }
+    }
+    __syncthreads();
+    if (valid && (MODE & (EL_AUG | EL_BT))) {
+      double pi = cms[lc][0];
+      pi += cms[lc][1] * (kGaussX[t0] - 0.5);
+      pi += cms[lc][2] * (kGaussX[t1] - 0.5);
+      if (D == 3) pi += cms[lc][3] * (kGaussX[t2] - 0.5);
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int k = 0; k < D; ++k) S[a][k] = wm * (G[a][k] + G[k][a]);
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int n = 0; n < NN; ++n) {
-          double s = ye[a * NN + n];
-#pragma unroll
-          for (int k = 0; k < D; ++k)
-            if (T.dphi[q][n][k] != 0.0) s += S[a][k] * T.dphi[q][n][k];
-          ye[a * NN + n] = s;
-        }
+      for (int a = 0; a < D; ++a) S[a] += wq * pi;
     }
   }
-  // pressure-like coefficients multiplying Bhat^T: gamma * Mhat^{-1} Bhat u - h p
-  double cm[NP];
+  if (valid) {
 #pragma unroll
-  for (int m = 0; m < NP; ++m) cm[m] = 0.0;
-  if (MODE & (EL_AUG | EL_BOUT)) {
-    double bu[NP];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) {
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j)
-        if (T.bhat[m][j] != 0.0) s += T.bhat[m][j] * ue[j];
-      bu[m] = s;
-    }
-    if (MODE & EL_AUG) {
-#pragma unroll
-      for (int m = 0; m < NP; ++m) cm[m] += gamma * bu[m] * kInvMhat[m];
-    }
-    if (MODE & EL_BOUT) {
-      const double sc = -(D == 2 ? h : h * h);
-#pragma unroll
-      for (int m = 0; m < NP; ++m) pout[cell * NP + m] = sc * bu[m];
-    }
+    for (int i = 0; i < NS; ++i) ss[lc][t][i] = S[i];
   }
-  if (MODE & EL_BT) {
+  __syncthreads();
+  // ---- phase 2: lane = node n = (t0, t1, t2); y_n = sum_q S_q : dphi_n(q)
+  if (!valid) return;
+  double nBx[3], nDx[3], nBy[3], nDy[3], nBz[3], nDz[3];
 #pragma unroll
-    for (int m = 0; m < NP; ++m) cm[m] -= h * p[cell * NP + m];
-  }
-  if (MODE & (EL_AUG | EL_BT)) {
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      double s = ye[j];
-#pragma unroll
-      for (int m = 0; m < NP; ++m)
-        if (T.bhat[m][j] != 0.0) s += T.bhat[m][j] * cm[m];
-      ye[j] = s;
-    }
+  for (int q = 0; q < 3; ++q) {
+    nBx[q] = selc(kB1, q, t0); nDx[q] = selc(kD1, q, t0);
+    nBy[q] = selc(kB1, q, t1); nDy[q] = selc(kD1, q, t1);
+    nBz[q] = selc(kB1, q, t2); nDz[q] = selc(kD1, q, t2);
   }
   const double sc = D == 2 ? 1.0 : h;   // h^{d-2}
 #pragma unroll
-  for (int j = 0; j < NL; ++j) E[(int64_t)j * g.ncell + cell] = sc * ye[j];
+  for (int comp = 0; comp < D; ++comp) {
+    double ycomp = 0.0;
+#pragma unroll
+    for (int qz = 0; qz < (D == 3 ? 3 : 1); ++qz) {
+      double Y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int qy = 0; qy < 3; ++qy) {
+        double X[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int qx = 0; qx < 3; ++qx) {
+          const int q = qx + 3 * qy + 9 * qz;
+          X[0] += ss[lc][q][SymIdx<D>::at(comp, 0)] * nDx[qx];
+          X[1] += ss[lc][q][SymIdx<D>::at(comp, 1)] * nBx[qx];
+          if (D == 3) X[2] += ss[lc][q][SymIdx<D>::at(comp, D == 3 ? 2 : 0)] * nBx[qx];
+        }
+        Y[0] += X[0] * nBy[qy];
+        Y[1] += X[1] * nDy[qy];
+        if (D == 3) Y[2] += X[2] * nBy[qy];
+      }
+      if (D == 3) ycomp += Y[0] * nBz[qz] + Y[1] * nBz[qz] + Y[2] * nDz[qz];
+      else ycomp += Y[0] + Y[1];
+    }
+    E[cell * NL + comp * NN + t] = sc * ycomp;
+  }
+  (void)T;
 }
 
 // ---------------------------------------------------------------------------
@@ -218,7 +319,7 @@ __global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double*
       for (int t0 = 0; t0 < cnt[0]; ++t0) {
         const int64_t cell = cell_index<D>(g, cc[0][t0], cc[1][t1], cc[2][t2]);
         const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
-        s += E[(int64_t)(comp * NN + loc) * g.ncell + cell];
+        s += E[cell * (D * NN) + comp * NN + loc];
       }
   out[idx] = (base ? base[idx] : 0.0) + alpha * s;
 }
@@ -247,9 +348,9 @@ __global__ void k_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, d
   }
   const double vol = D == 2 ? g.h * g.h : g.h * g.h * g.h;
   for (int comp = 0; comp < D - 1; ++comp)
-    for (int n = 0; n < NN; ++n) E[(int64_t)(comp * NN + n) * g.ncell + cell] = 0.0;
+    for (int n = 0; n < NN; ++n) E[cell * (D * NN) + comp * NN + n] = 0.0;
 #pragma unroll
-  for (int n = 0; n < NN; ++n) E[(int64_t)((D - 1) * NN + n) * g.ncell + cell] = vol * be[n];
+  for (int n = 0; n < NN; ++n) E[cell * (D * NN) + (D - 1) * NN + n] = vol * be[n];
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +372,7 @@ __global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double 
       X[a][b] = a == b ? 1.0 : 0.0;
     }
   for (int q = 0; q < NN; ++q) {
-    const double wq = T.w[q] * vol / mu[(int64_t)q * g.ncell + cell];
+    const double wq = T.w[q] * vol / mu[cell * NN + q];
 #pragma unroll
     for (int a = 0; a < NP; ++a)
 #pragma unroll
@@ -393,8 +494,8 @@ void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s) {
 template <int D, int MODE>
 static void elem_launch(const Hier& H, const Level& l, const double* u, const double* p, double* pout,
                         hipStream_t s) {
-  const int t = D == 2 ? 256 : 64;
-  hipLaunchKernelGGL((k_elem<D, MODE>), dim3(nblk(l.g.ncell, t)), dim3(t), 0, s, l.g, l.mu, H.gamma, u, p,
+  constexpr int CPW = 64 / Dims<D>::NQ;
+  hipLaunchKernelGGL((k_elem<D, MODE>), dim3(nblk(l.g.ncell, CPW)), dim3(64), 0, s, l.g, l.mu, H.gamma, u, p,
                      l.E, pout);
 }
 

@@ -61,7 +61,7 @@ __device__ inline double cell_entry(const double* __restrict__ mu, int64_t ncell
 #pragma unroll
       for (int k = 0; k < D; ++k) gg += T.dphi[q][na][k] * T.dphi[q][nb][k];
     }
-    s += T.w[q] * mu[(int64_t)q * ncell + cell] * gg;
+    s += T.w[q] * mu[cell * NN + q] * gg;
   }
   double al = 0.0;
 #pragma unroll
