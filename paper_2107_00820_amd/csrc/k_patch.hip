@@ -99,15 +99,6 @@ __device__ __attribute__((always_inline)) inline void symv_rows(const double* __
   (symv_row<NPT, I>(A, x, y, std::make_integer_sequence<int, I + 1>{}), ...);
 }
 
-// x from registers
-template <int NPT>
-__device__ __attribute__((always_inline)) inline void packed_symv(const double* __restrict__ A, const double (&x)[NPT], double (&y)[NPT]) {
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) y[i] = 0.0;
-  auto xr = [&](int j) { return x[j]; };
-  symv_rows<NPT>(A, xr, y, std::make_integer_sequence<int, NPT>{});
-}
-
 // Row index of packed lower-triangle element e (largest i with i(i+1)/2 <= e).
 constexpr int tri_row(int e) {
   int i = 0;
@@ -149,17 +140,13 @@ __device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x,
   });
 }
 
-template <int NPT>
-__device__ __attribute__((always_inline)) inline void packed_symv_lds(const double* __restrict__ A,
-                                                                      const double* xs, int lane,
-                                                                      double (&y)[NPT]) {
-  constexpr int CH = 16;
+template <int NPT, int CH, class X>
+__device__ __attribute__((always_inline)) inline void packed_symv_chunked(const double* __restrict__ A, const X& xr,
+                                                                          double (&y)[NPT]) {
   constexpr int NE = NPT * (NPT + 1) / 2;
   constexpr int NC = (NE + CH - 1) / CH;
 #pragma unroll
   for (int i = 0; i < NPT; ++i) y[i] = 0.0;
-  auto xr = [&](int j) { return xs[j * 64 + lane]; };
-  using X = decltype(xr);
   double b0[CH], b1[CH];
   symv_chunk_load<NPT, CH, 0, X>(A, b0);
   static_for<NC>([&](auto C) {
@@ -173,6 +160,24 @@ __device__ __attribute__((always_inline)) inline void packed_symv_lds(const doub
     else symv_chunk_fma<NPT, CH, c>(xr, b1, y);
     __builtin_amdgcn_sched_barrier(0);
   });
+}
+
+template <int NPT>
+__device__ __attribute__((always_inline)) inline void packed_symv_lds(const double* __restrict__ A,
+                                                                      const double* xs, int lane,
+                                                                      double (&y)[NPT]) {
+  auto xr = [&](int j) { return xs[j * 64 + lane]; };
+  packed_symv_chunked<NPT, 16>(A, xr, y);
+}
+
+// x from registers (patches of up to 27 unknowns): four double-buffered chunks
+template <int NPT>
+__device__ __attribute__((always_inline)) inline void packed_symv(const double* __restrict__ A,
+                                                                  const double (&x)[NPT], double (&y)[NPT]) {
+  auto xr = [&](int j) { return x[j]; };
+  constexpr int NE = NPT * (NPT + 1) / 2;
+  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 24;
+  packed_symv_chunked<NPT, CH>(A, xr, y);
 }
 
 // One lane per patch: gather the patch residual, packed symmetric GEMV,
