@@ -71,7 +71,10 @@ typedef struct {
   int coef_kind;      /* 0 = scalar sinker viscosity (only kind built) */
   stk_sinker sinker;
   int nu_pre, nu_post;   /* right-preconditioned GMRES relaxation steps, 1..8 */
-  int mixed;          /* 0 = plain FP64 form (only form built) */
+  int mixed;          /* 0 = FP64 form only; 1 = also keep FP32 copies of the
+                         viscosity tables and packed patch inverses so that
+                         the mixed form (FP32 V-cycles inside FP64 FGMRES) and
+                         the STK_F32 level operations are available */
   size_t hbm_budget;  /* bytes; 0 = unlimited. Setup fails with STK_ENOMEM above it */
 } stk_desc;
 
@@ -100,8 +103,12 @@ stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_
 stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream);
 
 /* y = A_gamma x on `level` (matrix-free, Section 2 entries plus the
- * augmented term of Section 3). x and y are FP64 stored-layout vectors and
- * must not alias. dtype must be STK_F64. */
+ * augmented term of Section 3). x and y are stored-layout vectors that must
+ * not alias. dtype STK_F64: FP64 vectors and arithmetic. dtype STK_F32 (needs
+ * a hierarchy set up with mixed=1): FP32 vectors, FP32 viscosity table and
+ * FP32 arithmetic. The same dtype rule holds for stk_asm, stk_smooth,
+ * stk_prolong, stk_restrict and stk_vcycle; in FP32 the patch solves use the
+ * FP32 copy of the FP64 Cholesky-based inverses. */
 stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, void* y, void* stream);
 
 /* (y_u, y_p) = K (x_u, x_p), K = [[A_gamma, B^T], [B, 0]] on the finest level. */
@@ -133,12 +140,17 @@ stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, 
 stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream);
 
 /* x = one V-cycle applied to b on the finest level (pre-relaxation from 0,
- * residual, restriction, recursion, prolongation, post-relaxation). */
-stk_status stk_vcycle(stk_hier* h, const double* b, double* x, void* stream);
+ * residual, restriction, recursion, prolongation, post-relaxation). The
+ * coarsest solve always uses the FP64 inverse; with STK_F32 its input and
+ * output are rounded to FP32. */
+stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream);
 
 /* (z_u, z_p) = P (v_u, v_p): the block preconditioner of eq. (precond) with
- * two V-cycles and the cellwise Schur blocks; z_p has zero mean. */
-stk_status stk_precond(stk_hier* h, const double* v_u, const double* v_p,
+ * two V-cycles and the cellwise Schur blocks; z_p has zero mean. mixed = 1
+ * (hierarchy set up with mixed=1) runs both V-cycles in FP32 on FP32 copies
+ * of their FP64 inputs; the Schur blocks, the B and B^T applies and the
+ * mean projection stay FP64. */
+stk_status stk_precond(stk_hier* h, int mixed, const double* v_u, const double* v_p,
                        double* z_u, double* z_p, void* stream);
 
 typedef struct {
@@ -149,6 +161,13 @@ typedef struct {
                     Stokes apply, Gram-Schmidt) is captured once as a HIP graph
                     on the library's own stream and replayed; 1: plain launches.
                     Both give bit-identical results. */
+  int mixed;     /* 0 (default): FP64 throughout. 1: the mixed form, where the
+                    preconditioner's V-cycles run in FP32 (see stk_precond)
+                    while the outer FGMRES basis, Hessenberg, orthogonalisation,
+                    Stokes residual and Schur scaling stay FP64; needs a
+                    hierarchy set up with mixed=1. FGMRES tolerates the
+                    inexact, varying preconditioner, so the stopping test on
+                    the FP64 true residual is unchanged. */
 } stk_solve_opts;
 
 typedef struct {

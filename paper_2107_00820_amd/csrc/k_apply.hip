@@ -13,6 +13,8 @@
 // Determinism: the cell kernel writes element vectors E[cell][j]; a node
 // kernel sums the <= 2^d cell contributions of each node in a fixed order.
 // No atomics, so repeated applications give bit-identical results.
+#include <type_traits>
+
 #include "stk_reduce.h"
 
 namespace stk {
@@ -98,19 +100,20 @@ struct SymIdx {
   }
 };
 
-template <int D, int MODE>
+template <int D, int MODE, class R>
 __global__ void __launch_bounds__(64)
-k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __restrict__ u,
-       const double* __restrict__ p, double* __restrict__ E, double* __restrict__ pout) {
+k_elem(LevelGeo g, const R* __restrict__ mu, double gamma_d, const R* __restrict__ u,
+       const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
   constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
   constexpr int NS = SymIdx<D>::NS;
   constexpr int CPW = 64 / NQ;
   constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
   constexpr bool need_c = (MODE & (EL_AUG | EL_BT | EL_BOUT)) != 0;
-  __shared__ double us[CPW][D][NN];
-  __shared__ double ss[CPW][NQ][NS];
-  __shared__ double red[CPW][NQ][NP];
-  __shared__ double cms[CPW][NP];
+  __shared__ R us[CPW][D][NN];
+  __shared__ R ss[CPW][NQ][NS];
+  __shared__ R red[CPW][NQ][NP];
+  __shared__ R cms[CPW][NP];
+  const R gamma = (R)gamma_d;
   const int lane = threadIdx.x;
   const int lc = lane / NQ;
   const int t = lane - lc * NQ;
@@ -123,7 +126,7 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
     c[1] = (int)((cell / g.N) % g.N);
     c[2] = D == 3 ? (int)(cell / ((int64_t)g.N * g.N)) : 0;
   }
-  const double h = g.h;
+  const R h = (R)g.h;
   // ---- stage u: lane t loads node t of its cell (Dirichlet nodes masked)
   if (need_u && valid) {
     const int a0 = 2 * c[0] + t0, a1 = 2 * c[1] + t1, a2 = D == 3 ? 2 * c[2] + t2 : 0;
@@ -132,60 +135,57 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
     const int64_t nd = node_index<D>(g, a0, a1, a2);
 #pragma unroll
     for (int comp = 0; comp < D; ++comp) {
-      const double v = u[comp * g.nnodes + nd];
-      us[lc][comp][t] = bnd ? 0.0 : v;
+      const R v = u[comp * g.nnodes + nd];
+      us[lc][comp][t] = bnd ? (R)0 : v;
     }
   }
   __syncthreads();
   // ---- phase 1: lane = Gauss point q = (t0, t1, t2)
   constexpr const RefTab<D>& T = Ref<D>::T;
-  double S[NS];
+  R S[NS];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) S[i] = 0.0;
-  double wq = 1.0;
-  {
-    wq = kGaussW[t0] * kGaussW[t1] * (D == 3 ? kGaussW[t2] : 1.0);
-  }
+  for (int i = 0; i < NS; ++i) S[i] = (R)0;
+  const R wq = (R)(kGaussW[t0] * kGaussW[t1] * (D == 3 ? kGaussW[t2] : 1.0));
   if (valid && need_u) {
-    double Bx[3], Dx[3], By[3], Dy[3], Bz[3], Dz[3];
+    R Bx[3], Dx[3], By[3], Dy[3], Bz[3], Dz[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      Bx[a] = sel3(kB1, t0, a); Dx[a] = sel3(kD1, t0, a);
-      By[a] = sel3(kB1, t1, a); Dy[a] = sel3(kD1, t1, a);
-      Bz[a] = sel3(kB1, t2, a); Dz[a] = sel3(kD1, t2, a);
+      Bx[a] = (R)sel3(kB1, t0, a); Dx[a] = (R)sel3(kD1, t0, a);
+      By[a] = (R)sel3(kB1, t1, a); Dy[a] = (R)sel3(kD1, t1, a);
+      Bz[a] = (R)sel3(kB1, t2, a); Dz[a] = (R)sel3(kD1, t2, a);
     }
-    double G[D][D];
+    R G[D][D];
 #pragma unroll
     for (int comp = 0; comp < D; ++comp) {
       if constexpr (D == 3) {
-        double zB[3][3], zD[3][3];
+        R zB[3][3], zD[3][3];
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            const double u0 = us[lc][comp][a + 3 * b], u1 = us[lc][comp][a + 3 * b + 9],
-                         u2 = us[lc][comp][a + 3 * b + 18];
+            const R u0 = us[lc][comp][a + 3 * b], u1 = us[lc][comp][a + 3 * b + 9],
+                    u2 = us[lc][comp][a + 3 * b + 18];
             zB[a][b] = u0 * Bz[0] + u1 * Bz[1] + u2 * Bz[2];
             zD[a][b] = u0 * Dz[0] + u1 * Dz[1] + u2 * Dz[2];
           }
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        R g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double yBB = zB[a][0] * By[0] + zB[a][1] * By[1] + zB[a][2] * By[2];
-          const double yDB = zB[a][0] * Dy[0] + zB[a][1] * Dy[1] + zB[a][2] * Dy[2];
-          const double yBD = zD[a][0] * By[0] + zD[a][1] * By[1] + zD[a][2] * By[2];
+          const R yBB = zB[a][0] * By[0] + zB[a][1] * By[1] + zB[a][2] * By[2];
+          const R yDB = zB[a][0] * Dy[0] + zB[a][1] * Dy[1] + zB[a][2] * Dy[2];
+          const R yBD = zD[a][0] * By[0] + zD[a][1] * By[1] + zD[a][2] * By[2];
           g0 += yBB * Dx[a];
           g1 += yDB * Bx[a];
           g2 += yBD * Bx[a];
         }
         G[comp][0] = g0; G[comp][1] = g1; G[comp][2] = g2;
       } else {
-        double g0 = 0.0, g1 = 0.0;
+        R g0 = 0, g1 = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double u0 = us[lc][comp][a], u1 = us[lc][comp][a + 3], u2 = us[lc][comp][a + 6];
-          const double yB = u0 * By[0] + u1 * By[1] + u2 * By[2];
-          const double yD = u0 * Dy[0] + u1 * Dy[1] + u2 * Dy[2];
+          const R u0 = us[lc][comp][a], u1 = us[lc][comp][a + 3], u2 = us[lc][comp][a + 6];
+          const R yB = u0 * By[0] + u1 * By[1] + u2 * By[2];
+          const R yD = u0 * Dy[0] + u1 * Dy[1] + u2 * Dy[2];
           g0 += yB * Dx[a];
           g1 += yD * Bx[a];
         }
@@ -193,19 +193,19 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
       }
     }
     if (MODE & EL_VISC) {
-      const double wm = wq * mu[cell * NQ + t];
+      const R wm = wq * mu[cell * NQ + t];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) S[SymIdx<D>::at(a, b)] = wm * (G[a][b] + G[b][a]);
     }
     if (MODE & (EL_AUG | EL_BOUT)) {
-      double dv = 0.0;
+      R dv = 0;
 #pragma unroll
       for (int a = 0; a < D; ++a) dv += G[a][a];
       red[lc][t][0] = wq * dv;
 #pragma unroll
-      for (int m = 1; m < NP; ++m) red[lc][t][m] = wq * (kGaussX[m == 1 ? t0 : (m == 2 ? t1 : t2)] - 0.5) * dv;
+      for (int m = 1; m < NP; ++m) red[lc][t][m] = wq * (R)(kGaussX[m == 1 ? t0 : (m == 2 ? t1 : t2)] - 0.5) * dv;
     }
   }
   if constexpr (need_c) {
@@ -213,23 +213,23 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
     if (valid && t == 0) {
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        double cm = 0.0;
+        R cm = 0;
         if (MODE & (EL_AUG | EL_BOUT)) {
-          double bu = 0.0;
+          R bu = 0;
           for (int q = 0; q < NQ; ++q) bu += red[lc][q][m];
-          if (MODE & EL_AUG) cm += gamma * bu * kInvMhat[m];
-          if (MODE & EL_BOUT) pout[cell * NP + m] = -(D == 2 ? h : h * h) * bu;
+          if (MODE & EL_AUG) cm += gamma * bu * (R)kInvMhat[m];
+          if (MODE & EL_BOUT) pout[cell * NP + m] = -(D == 2 ? g.h : g.h * g.h) * (double)bu;
         }
-        if (MODE & EL_BT) cm -= h * p[cell * NP + m];
+        if (MODE & EL_BT) cm -= h * (R)p[cell * NP + m];
         cms[lc][m] = cm;
       }
     }
     __syncthreads();
     if (valid && (MODE & (EL_AUG | EL_BT))) {
-      double pi = cms[lc][0];
-      pi += cms[lc][1] * (kGaussX[t0] - 0.5);
-      pi += cms[lc][2] * (kGaussX[t1] - 0.5);
-      if (D == 3) pi += cms[lc][3] * (kGaussX[t2] - 0.5);
+      R pi = cms[lc][0];
+      pi += cms[lc][1] * (R)(kGaussX[t0] - 0.5);
+      pi += cms[lc][2] * (R)(kGaussX[t1] - 0.5);
+      if (D == 3) pi += cms[lc][3] * (R)(kGaussX[t2] - 0.5);
 #pragma unroll
       for (int a = 0; a < D; ++a) S[a] += wq * pi;
     }
@@ -241,23 +241,23 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
   __syncthreads();
   // ---- phase 2: lane = node n = (t0, t1, t2); y_n = sum_q S_q : dphi_n(q)
   if (!valid) return;
-  double nBx[3], nDx[3], nBy[3], nDy[3], nBz[3], nDz[3];
+  R nBx[3], nDx[3], nBy[3], nDy[3], nBz[3], nDz[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    nBx[q] = selc(kB1, q, t0); nDx[q] = selc(kD1, q, t0);
-    nBy[q] = selc(kB1, q, t1); nDy[q] = selc(kD1, q, t1);
-    nBz[q] = selc(kB1, q, t2); nDz[q] = selc(kD1, q, t2);
+    nBx[q] = (R)selc(kB1, q, t0); nDx[q] = (R)selc(kD1, q, t0);
+    nBy[q] = (R)selc(kB1, q, t1); nDy[q] = (R)selc(kD1, q, t1);
+    nBz[q] = (R)selc(kB1, q, t2); nDz[q] = (R)selc(kD1, q, t2);
   }
-  const double sc = D == 2 ? 1.0 : h;   // h^{d-2}
+  const R sc = D == 2 ? (R)1 : h;   // h^{d-2}
 #pragma unroll
   for (int comp = 0; comp < D; ++comp) {
-    double ycomp = 0.0;
+    R ycomp = 0;
 #pragma unroll
     for (int qz = 0; qz < (D == 3 ? 3 : 1); ++qz) {
-      double Y[3] = {0.0, 0.0, 0.0};
+      R Y[3] = {0, 0, 0};
 #pragma unroll
       for (int qy = 0; qy < 3; ++qy) {
-        double X[3] = {0.0, 0.0, 0.0};
+        R X[3] = {0, 0, 0};
 #pragma unroll
         for (int qx = 0; qx < 3; ++qx) {
           const int q = qx + 3 * qy + 9 * qz;
@@ -280,9 +280,10 @@ k_elem(LevelGeo g, const double* __restrict__ mu, double gamma, const double* __
 // ---------------------------------------------------------------------------
 // out[idx] = base[idx] + alpha * sum_{cells K containing node} E_K[local],
 // 0 on Dirichlet nodes. One thread per stored entry.
-template <int D>
-__global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double* __restrict__ base,
-                         double alpha, double* __restrict__ out) {
+template <int D, class R>
+__global__ void k_gather(LevelGeo g, const R* __restrict__ E, const R* __restrict__ base,
+                         double alpha_d, R* __restrict__ out) {
+  const R alpha = (R)alpha_d;
   constexpr int NN = Dims<D>::NN;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)D * g.nnodes) return;
@@ -296,7 +297,7 @@ __global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double*
 #pragma unroll
   for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
   if (bnd) {
-    out[idx] = 0.0;
+    out[idx] = (R)0;
     return;
   }
   // per axis up to two (cell, local) pairs
@@ -313,7 +314,7 @@ __global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double*
       cnt[k] = 2; cc[k][0] = (i[k] >> 1) - 1; ll[k][0] = 2; cc[k][1] = i[k] >> 1; ll[k][1] = 0;
     }
   }
-  double s = 0.0;
+  R s = 0;
   for (int t2 = 0; t2 < cnt[2]; ++t2)
     for (int t1 = 0; t1 < cnt[1]; ++t1)
       for (int t0 = 0; t0 < cnt[0]; ++t0) {
@@ -321,7 +322,7 @@ __global__ void k_gather(LevelGeo g, const double* __restrict__ E, const double*
         const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
         s += E[cell * (D * NN) + comp * NN + loc];
       }
-  out[idx] = (base ? base[idx] : 0.0) + alpha * s;
+  out[idx] = (base ? base[idx] : (R)0) + alpha * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -491,42 +492,56 @@ void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s) {
   }
 }
 
-template <int D, int MODE>
-static void elem_launch(const Hier& H, const Level& l, const double* u, const double* p, double* pout,
-                        hipStream_t s) {
+template <class R>
+static const R* level_mu(const Level& l);
+template <>
+const double* level_mu<double>(const Level& l) { return l.mu; }
+template <>
+const float* level_mu<float>(const Level& l) { return l.mu32; }
+
+template <int D, int MODE, class R>
+static void elem_launch(const Hier& H, const Level& l, const R* u, const double* p, double* pout, hipStream_t s) {
   constexpr int CPW = 64 / Dims<D>::NQ;
-  hipLaunchKernelGGL((k_elem<D, MODE>), dim3(nblk(l.g.ncell, CPW)), dim3(64), 0, s, l.g, l.mu, H.gamma, u, p,
-                     l.E, pout);
+  hipLaunchKernelGGL((k_elem<D, MODE, R>), dim3(nblk(l.g.ncell, CPW)), dim3(64), 0, s, l.g, level_mu<R>(l), H.gamma,
+                     u, p, reinterpret_cast<R*>(l.E), pout);
 }
 
-template <int D>
-static void elem_dispatch(const Hier& H, const Level& l, int mode, const double* u, const double* p,
-                          double* pout, hipStream_t s) {
+template <int D, class R>
+static void elem_dispatch(const Hier& H, const Level& l, int mode, const R* u, const double* p, double* pout,
+                          hipStream_t s) {
   switch (mode) {
-    case EL_VISC | EL_AUG: elem_launch<D, EL_VISC | EL_AUG>(H, l, u, p, pout, s); break;
-    case EL_AUG: elem_launch<D, EL_AUG>(H, l, u, p, pout, s); break;
-    case EL_BT: elem_launch<D, EL_BT>(H, l, u, p, pout, s); break;
-    case EL_VISC | EL_AUG | EL_BT | EL_BOUT:
-      elem_launch<D, EL_VISC | EL_AUG | EL_BT | EL_BOUT>(H, l, u, p, pout, s);
+    case EL_VISC | EL_AUG: elem_launch<D, EL_VISC | EL_AUG, R>(H, l, u, p, pout, s); break;
+    case EL_AUG: elem_launch<D, EL_AUG, R>(H, l, u, p, pout, s); break;
+    default:
+      if constexpr (std::is_same<R, double>::value) {
+        if (mode == EL_BT) elem_launch<D, EL_BT, R>(H, l, u, p, pout, s);
+        else if (mode == (EL_VISC | EL_AUG | EL_BT | EL_BOUT))
+          elem_launch<D, EL_VISC | EL_AUG | EL_BT | EL_BOUT, R>(H, l, u, p, pout, s);
+      }
       break;
-    default: break;
   }
 }
 
-void launch_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
-                 hipStream_t s) {
-  if (H.dim == 2) elem_dispatch<2>(H, l, mode, u, p, pout, s);
-  else elem_dispatch<3>(H, l, mode, u, p, pout, s);
+template <class R>
+void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const double* p, double* pout, hipStream_t s) {
+  if (H.dim == 2) elem_dispatch<2, R>(H, l, mode, u, p, pout, s);
+  else elem_dispatch<3, R>(H, l, mode, u, p, pout, s);
 }
 
-void launch_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out,
-                   hipStream_t s) {
+template <class R>
+void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R* out, hipStream_t s) {
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
+  const R* E = reinterpret_cast<const R*>(l.E);
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_gather<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.E, base, alpha, out);
+    hipLaunchKernelGGL((k_gather<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, E, base, alpha, out);
   else
-    hipLaunchKernelGGL(k_gather<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.E, base, alpha, out);
+    hipLaunchKernelGGL((k_gather<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, E, base, alpha, out);
 }
+
+template void launch_elem<double>(const Hier&, const Level&, int, const double*, const double*, double*, hipStream_t);
+template void launch_elem<float>(const Hier&, const Level&, int, const float*, const double*, double*, hipStream_t);
+template void launch_gather<double>(const Hier&, const Level&, const double*, double, double*, hipStream_t);
+template void launch_gather<float>(const Hier&, const Level&, const float*, double, float*, hipStream_t);
 
 void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
   if (H.dim == 2)

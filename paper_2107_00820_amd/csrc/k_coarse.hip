@@ -146,9 +146,9 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ A, int64
 }
 
 // x = Ainv b on interior unknowns: one wavefront per row.
-template <int D>
+template <int D, class R>
 __global__ void __launch_bounds__(256) k_coarse_gemv(LevelGeo g, const double* __restrict__ Ainv, int64_t n,
-                                                      const double* __restrict__ b, double* __restrict__ x) {
+                                                      const R* __restrict__ b, R* __restrict__ x) {
   const int lane = threadIdx.x & 63;
   const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -156,13 +156,13 @@ __global__ void __launch_bounds__(256) k_coarse_gemv(LevelGeo g, const double* _
   for (int64_t j = lane; j < n; j += 64) {
     int nd[3];
     const int c = interior_dof<D>(g, j, nd);
-    s += Ainv[row * n + j] * b[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])];
+    s += Ainv[row * n + j] * (double)b[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])];
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) {
     int nd[3];
     const int c = interior_dof<D>(g, row, nd);
-    x[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])] = s;
+    x[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])] = (R)s;
   }
 }
 
@@ -191,12 +191,17 @@ int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipS
   return 0;
 }
 
-void launch_coarse_apply(const Hier& H, const Level& l, const double* b, double* x, hipStream_t s) {
-  launch_fill(x, 0.0, (int64_t)H.dim * l.g.nnodes, s);
+// The coarse solve is FP64 in both forms; R only selects the vector storage.
+template <class R>
+void launch_coarse_apply(const Hier& H, const Level& l, const R* b, R* x, hipStream_t s) {
+  launch_fill<R>(x, 0.0, (int64_t)H.dim * l.g.nnodes, s);
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_coarse_gemv<2>, dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
+    hipLaunchKernelGGL((k_coarse_gemv<2, R>), dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
   else
-    hipLaunchKernelGGL(k_coarse_gemv<3>, dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
+    hipLaunchKernelGGL((k_coarse_gemv<3, R>), dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
 }
+
+template void launch_coarse_apply<double>(const Hier&, const Level&, const double*, double*, hipStream_t);
+template void launch_coarse_apply<float>(const Hier&, const Level&, const float*, float*, hipStream_t);
 
 }  // namespace stk

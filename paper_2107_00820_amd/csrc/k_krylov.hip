@@ -22,9 +22,11 @@ __device__ inline void reduce_parts_to_lds(const double* __restrict__ part, int 
   __syncthreads();
 }
 
-// part[b*nk + k] = sum over block b's indices of V_k . w
-__global__ void __launch_bounds__(kRedThreads) k_dots(const double* __restrict__ V, int64_t ldv, int nk,
-                                                       const double* __restrict__ w, int64_t n,
+// part[b*nk + k] = sum over block b's indices of V_k . w (storage type R,
+// accumulation in double)
+template <class R>
+__global__ void __launch_bounds__(kRedThreads) k_dots(const R* __restrict__ V, int64_t ldv, int nk,
+                                                       const R* __restrict__ w, int64_t n,
                                                        double* __restrict__ part) {
   __shared__ double sh[kRedThreads];
   for (int k0 = 0; k0 < nk; k0 += 8) {
@@ -32,10 +34,10 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(const double* __restrict__
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-      const double wi = w[i];
+      const double wi = (double)w[i];
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk)
-        if (k0 + kk < nk) acc[kk] += V[(int64_t)(k0 + kk) * ldv + i] * wi;
+        if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * wi;
     }
     for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
       const double s = block_sum(acc[kk], sh);
@@ -48,8 +50,9 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(const double* __restrict__
 // this block's indices; then either the next pass's dot partials
 // (next_dots = 1: part_out[b*nk+k] = V_k . w) or the squared-norm partial
 // (next_dots = 0: part_out[b] = w . w).
-__global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __restrict__ V, int64_t ldv, int nk,
-                                                              double* __restrict__ w, int64_t n,
+template <class R>
+__global__ void __launch_bounds__(kRedThreads) k_orth_update(const R* __restrict__ V, int64_t ldv, int nk,
+                                                              R* __restrict__ w, int64_t n,
                                                               const double* __restrict__ part_in,
                                                               double* __restrict__ Hcol, int hstride, int accumulate,
                                                               double* __restrict__ part_out, int next_dots) {
@@ -61,10 +64,11 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __res
       Hcol[k * hstride] = (accumulate ? Hcol[k * hstride] : 0.0) + h[k];
   double nrm = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double v = w[i];
-    for (int k = 0; k < nk; ++k) v -= h[k] * V[(int64_t)k * ldv + i];
-    w[i] = v;
-    nrm += v * v;
+    double v = (double)w[i];
+    for (int k = 0; k < nk; ++k) v -= h[k] * (double)V[(int64_t)k * ldv + i];
+    const R vr = (R)v;
+    w[i] = vr;
+    nrm += (double)vr * (double)vr;
   }
   if (next_dots) {
     // second-pass dots over the same indices (each written by this thread above)
@@ -74,10 +78,10 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __res
       for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
       for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
            i += (int64_t)gridDim.x * blockDim.x) {
-        const double wi = w[i];
+        const double wi = (double)w[i];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
-          if (k0 + kk < nk) acc[kk] += V[(int64_t)(k0 + kk) * ldv + i] * wi;
+          if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * wi;
       }
       for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
         const double s = block_sum(acc[kk], sh);
@@ -91,8 +95,9 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const double* __res
 }
 
 // nrm = sqrt(sum part); *hout = nrm (block 0); dst = w / nrm (0 if nrm == 0).
+template <class R>
 __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restrict__ part, int nparts,
-                                                            const double* w, int64_t n, double* dst,
+                                                            const R* w, int64_t n, R* dst,
                                                             double* __restrict__ hout) {
   __shared__ double nrm;
   if (threadIdx.x < 64) {
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
   __syncthreads();
   const double d = nrm;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = d > 0.0 ? w[i] / d : 0.0;
+    dst[i] = (R)(d > 0.0 ? (double)w[i] / d : 0.0);
 }
 
 // Least squares min ||beta e1 - Hbar y|| by Givens rotations; columns after an
@@ -152,16 +157,17 @@ __device__ inline void ls_solve(const double* __restrict__ small, int nu, double
 
 // x = (x_zero ? 0 : x) + sum_k y_k Z_k with y solved from the relaxation's
 // Hessenberg system (every block solves the tiny system redundantly).
-__global__ void k_relax_update(const double* __restrict__ Z, int64_t ldz, int nu, const double* __restrict__ small,
-                               double* __restrict__ x, int64_t n, int x_zero) {
+template <class R>
+__global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, int nu, const double* __restrict__ small,
+                               R* __restrict__ x, int64_t n, int x_zero) {
   __shared__ double y[kMaxNu];
   if (threadIdx.x == 0) ls_solve(small, nu, y);
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double v = x_zero ? 0.0 : x[i];
-  for (int k = 0; k < nu; ++k) v += y[k] * Z[(int64_t)k * ldz + i];
-  x[i] = v;
+  double v = x_zero ? 0.0 : (double)x[i];
+  for (int k = 0; k < nu; ++k) v += y[k] * (double)Z[(int64_t)k * ldz + i];
+  x[i] = (R)v;
 }
 
 __global__ void k_combine(const double* __restrict__ Z, int64_t ldz, int nk, const double* __restrict__ y,
@@ -173,15 +179,22 @@ __global__ void k_combine(const double* __restrict__ Z, int64_t ldz, int nk, con
   x[i] = v;
 }
 
-__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
-                        double* __restrict__ out, int64_t n) {
+template <class R>
+__global__ void k_axpby(double a, const R* x, double b, const R* y, R* out, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a * x[i] + b * y[i];
+  if (i < n) out[i] = (R)(a * (double)x[i] + b * (double)y[i]);
 }
 
-__global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
+template <class A, class B>
+__global__ void k_convert(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] = v;
+  if (i < n) y[i] = (B)x[i];
+}
+
+template <class R>
+__global__ void k_fill(R* __restrict__ x, double v, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (R)v;
 }
 
 __global__ void k_fill_int(int* __restrict__ x, int v, int64_t n) {
@@ -196,27 +209,29 @@ __global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-void launch_dots(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials);
+template <class R>
+void launch_dots(const R* V, int64_t ldv, int nk, const R* w, int64_t n, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials);
 }
 
-void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n, const double* part_in,
-                        double* Hcol, int hstride, bool accumulate, double* part_out, bool next_dots,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_orth_update, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, part_in, Hcol,
-                     hstride, accumulate ? 1 : 0, part_out, next_dots ? 1 : 0);
+template <class R>
+void launch_orth_update(const R* V, int64_t ldv, int nk, R* w, int64_t n, const double* part_in, double* Hcol,
+                        int hstride, bool accumulate, double* part_out, bool next_dots, hipStream_t s) {
+  hipLaunchKernelGGL(k_orth_update<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, part_in,
+                     Hcol, hstride, accumulate ? 1 : 0, part_out, next_dots ? 1 : 0);
 }
 
-void launch_normalize(const double* norm_partials, double* w, int64_t n, double* dst, double* hout,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, dim3(red_parts(n)), dim3(kRedThreads), 0, s, norm_partials, red_parts(n), w, n,
+template <class R>
+void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, double* hout, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, norm_partials, red_parts(n), w, n,
                      dst, hout);
 }
 
-void launch_relax_update(const double* Z, int64_t ldz, int nu, const double* small, double* x, int64_t n,
-                         bool x_zero, hipStream_t s) {
-  hipLaunchKernelGGL(k_relax_update, dim3(nblk(n, 256)), dim3(256), 0, s, Z, ldz, nu, small, x, n, x_zero ? 1 : 0);
+template <class R>
+void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, R* x, int64_t n, bool x_zero,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_relax_update<R>, dim3(nblk(n, 256)), dim3(256), 0, s, Z, ldz, nu, small, x, n,
+                     x_zero ? 1 : 0);
 }
 
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n, bool x_zero,
@@ -224,12 +239,19 @@ void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, doubl
   hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, Z, ldz, nk, y, x, n, x_zero ? 1 : 0);
 }
 
-void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, s, a, x, b, y, out, n);
+template <class R>
+void launch_axpby(double a, const R* x, double b, const R* y, R* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby<R>, dim3(nblk(n, 256)), dim3(256), 0, s, a, x, b, y, out, n);
 }
 
-void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, s, x, v, n);
+template <class R>
+void launch_fill(R* x, double v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<R>, dim3(nblk(n, 256)), dim3(256), 0, s, x, v, n);
+}
+
+template <class A, class B>
+void launch_convert(const A* x, B* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<A, B>), dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n);
 }
 
 void launch_fill_int(int* x, int v, int64_t n, hipStream_t s) {
@@ -239,5 +261,19 @@ void launch_fill_int(int* x, int v, int64_t n, hipStream_t s) {
 void launch_copy(const double* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(nblk(n, 256)), dim3(256), 0, s, x, y, n);
 }
+
+#define STK_INST(R)                                                                                         \
+  template void launch_dots<R>(const R*, int64_t, int, const R*, int64_t, double*, hipStream_t);           \
+  template void launch_orth_update<R>(const R*, int64_t, int, R*, int64_t, const double*, double*, int, bool, \
+                                      double*, bool, hipStream_t);                                          \
+  template void launch_normalize<R>(const double*, R*, int64_t, R*, double*, hipStream_t);                 \
+  template void launch_relax_update<R>(const R*, int64_t, int, const double*, R*, int64_t, bool, hipStream_t); \
+  template void launch_axpby<R>(double, const R*, double, const R*, R*, int64_t, hipStream_t);             \
+  template void launch_fill<R>(R*, double, int64_t, hipStream_t);
+STK_INST(double)
+STK_INST(float)
+#undef STK_INST
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 
 }  // namespace stk

@@ -71,34 +71,9 @@ __global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, double 
 
 // ---------------------------------------------------------------------------
 // y = A^{-1} x with A^{-1} packed lower, element stride 64.
-// Packed symmetric GEMV y = A x over one patch, A's element k at A[k*64].
-// The element loop is generated at compile time (fold expressions over index
-// sequences) so that every index into x and y is a constant and both stay in
-// registers; the unroller is not relied upon for the 3321-element 3D case.
-template <int NPT, int I, int J, class X>
-__device__ __attribute__((always_inline)) inline void symv_elem(const double* __restrict__ A, const X& x, double (&y)[NPT], double xi) {
-  const double a = A[(int64_t)(I * (I + 1) / 2 + J) * 64];
-  if constexpr (J != I) {
-    y[I] += a * x(J);
-    y[J] += a * xi;
-  } else {
-    y[I] += a * xi;
-  }
-}
-
-template <int NPT, int I, class X, int... J>
-__device__ __attribute__((always_inline)) inline void symv_row(const double* __restrict__ A, const X& x, double (&y)[NPT],
-                                std::integer_sequence<int, J...>) {
-  const double xi = x(I);
-  (symv_elem<NPT, I, J>(A, x, y, xi), ...);
-}
-
-template <int NPT, class X, int... I>
-__device__ __attribute__((always_inline)) inline void symv_rows(const double* __restrict__ A, const X& x, double (&y)[NPT],
-                                 std::integer_sequence<int, I...>) {
-  (symv_row<NPT, I>(A, x, y, std::make_integer_sequence<int, I + 1>{}), ...);
-}
-
+// Packed symmetric GEMV y = A x over one patch, A's element k at A[k*64]
+// (lower triangle, row major). The element order is expanded at compile time
+// so that every index into x and y is a constant and both stay in registers.
 // Row index of packed lower-triangle element e (largest i with i(i+1)/2 <= e).
 constexpr int tri_row(int e) {
   int i = 0;
@@ -112,8 +87,8 @@ constexpr int tri_row(int e) {
 // elements stream in chunks of CH with the next chunk's loads issued before
 // the current chunk's arithmetic (scheduling barriers keep the compiler from
 // hoisting all loads at once, which would spill).
-template <int NPT, int CH, int C, class X>
-__device__ __attribute__((always_inline)) inline void symv_chunk_load(const double* __restrict__ A, double (&buf)[CH]) {
+template <int NPT, int CH, int C, class X, class R>
+__device__ __attribute__((always_inline)) inline void symv_chunk_load(const R* __restrict__ A, R (&buf)[CH]) {
   constexpr int NE = NPT * (NPT + 1) / 2;
   static_for<CH>([&](auto T) {
     constexpr int e = C * CH + T;
@@ -121,9 +96,8 @@ __device__ __attribute__((always_inline)) inline void symv_chunk_load(const doub
   });
 }
 
-template <int NPT, int CH, int C, class X>
-__device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x, const double (&buf)[CH],
-                                                                     double (&y)[NPT]) {
+template <int NPT, int CH, int C, class X, class R>
+__device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x, const R (&buf)[CH], R (&y)[NPT]) {
   constexpr int NE = NPT * (NPT + 1) / 2;
   static_for<CH>([&](auto T) {
     constexpr int e = C * CH + T;
@@ -140,14 +114,14 @@ __device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x,
   });
 }
 
-template <int NPT, int CH, class X>
-__device__ __attribute__((always_inline)) inline void packed_symv_chunked(const double* __restrict__ A, const X& xr,
-                                                                          double (&y)[NPT]) {
+template <int NPT, int CH, class X, class R>
+__device__ __attribute__((always_inline)) inline void packed_symv_chunked(const R* __restrict__ A, const X& xr,
+                                                                          R (&y)[NPT]) {
   constexpr int NE = NPT * (NPT + 1) / 2;
   constexpr int NC = (NE + CH - 1) / CH;
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) y[i] = 0.0;
-  double b0[CH], b1[CH];
+  for (int i = 0; i < NPT; ++i) y[i] = (R)0;
+  R b0[CH], b1[CH];
   symv_chunk_load<NPT, CH, 0, X>(A, b0);
   static_for<NC>([&](auto C) {
     constexpr int c = C;
@@ -162,18 +136,17 @@ __device__ __attribute__((always_inline)) inline void packed_symv_chunked(const 
   });
 }
 
-template <int NPT>
-__device__ __attribute__((always_inline)) inline void packed_symv_lds(const double* __restrict__ A,
-                                                                      const double* xs, int lane,
-                                                                      double (&y)[NPT]) {
+template <int NPT, class R>
+__device__ __attribute__((always_inline)) inline void packed_symv_lds(const R* __restrict__ A, const R* xs, int lane,
+                                                                      R (&y)[NPT]) {
   auto xr = [&](int j) { return xs[j * 64 + lane]; };
-  packed_symv_chunked<NPT, 16>(A, xr, y);
+  packed_symv_chunked<NPT, sizeof(R) == 8 ? 16 : 32>(A, xr, y);
 }
 
 // x from registers (patches of up to 27 unknowns): four double-buffered chunks
-template <int NPT>
-__device__ __attribute__((always_inline)) inline void packed_symv(const double* __restrict__ A,
-                                                                  const double (&x)[NPT], double (&y)[NPT]) {
+template <int NPT, class R>
+__device__ __attribute__((always_inline)) inline void packed_symv(const R* __restrict__ A, const R (&x)[NPT],
+                                                                  R (&y)[NPT]) {
   auto xr = [&](int j) { return x[j]; };
   constexpr int NE = NPT * (NPT + 1) / 2;
   constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 24;
@@ -182,10 +155,10 @@ __device__ __attribute__((always_inline)) inline void packed_symv(const double* 
 
 // One lane per patch: gather the patch residual, packed symmetric GEMV,
 // write the result into the vertex-indexed buffer.
-template <int D, int NPT>
+template <int D, int NPT, class R>
 __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& g, const int* __restrict__ verts, int count,
-                                 const double* __restrict__ inv, const double* __restrict__ r,
-                                 double* __restrict__ zbuf, int nvert, int s) {
+                                 const R* __restrict__ inv, const R* __restrict__ r,
+                                 R* __restrict__ zbuf, int nvert, int s) {
   constexpr int NN = Dims<D>::NN;
   constexpr int NBOX = NPT / D;
   constexpr bool FULL = NBOX == NN;
@@ -194,7 +167,7 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
   int lo[3], ext[3], vc[3];
   patch_box<D>(g, vert, lo, ext, vc);
   if (FULL) { ext[0] = 3; ext[1] = 3; ext[2] = D == 3 ? 3 : 1; }
-  double x[NPT];
+  R x[NPT];
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     int nd[3];
@@ -202,8 +175,8 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
     x[i] = r[comp * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])];
   }
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
-  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  double y[NPT];
+  const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  R y[NPT];
   packed_symv<NPT>(A, x, y);
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
@@ -221,10 +194,10 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
 
 // Interior (full) patch with x staged in LDS; all unknown indices are
 // compile-time: unknown i = comp*3^d + a + 3b + 9c sits at node 2v-1 + (a,b,c).
-template <int D, int NPT>
+template <int D, int NPT, class R>
 __device__ __attribute__((always_inline)) inline void asm_patch_lds(const LevelGeo& g, const int* __restrict__ verts, int count,
-                                     const double* __restrict__ inv, const double* __restrict__ r,
-                                     double* __restrict__ zbuf, int nvert, int s, double* xs, int lane) {
+                                     const R* __restrict__ inv, const R* __restrict__ r,
+                                     R* __restrict__ zbuf, int nvert, int s, R* xs, int lane) {
   constexpr int NN = Dims<D>::NN;
   if (s >= count) return;
   const int vert = verts[s];
@@ -238,8 +211,8 @@ __device__ __attribute__((always_inline)) inline void asm_patch_lds(const LevelG
     xs[i * 64 + lane] = r[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
   });
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
-  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  double y[NPT];
+  const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  R y[NPT];
   packed_symv_lds<NPT>(A, xs, lane, y);
   static_for<NPT>([&](auto I) {
     constexpr int i = I;
@@ -249,23 +222,24 @@ __device__ __attribute__((always_inline)) inline void asm_patch_lds(const LevelG
 
 // All patch classes of a level in one launch: block ranges select the class
 // (sizes d*3^d, d*3^(d-1), .., d; interior patches first).
+template <class R>
 struct AsmClasses {
   const int* verts[4];
-  const double* inv[4];
+  const R* inv[4];
   int count[4];
   int first_block[5];
 };
 
-template <int D>
-__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses c, const double* __restrict__ r,
-                                                  double* __restrict__ zbuf, int nvert) {
+template <int D, class R>
+__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r,
+                                                  R* __restrict__ zbuf, int nvert) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   if (b < c.first_block[1]) {
     if (D == 2) {
       asm_patch<D, 18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane);
     } else {
-      __shared__ double xs[81 * 64];
+      __shared__ R xs[81 * 64];
       asm_patch_lds<D, 81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane, xs, lane);
     }
   } else if (b < c.first_block[2]) {
@@ -281,8 +255,8 @@ __global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses c, const
 }
 
 // y[idx] = sum over the patches containing the node of their results; 0 on Dirichlet nodes.
-template <int D>
-__global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nvert, double* __restrict__ y) {
+template <int D, class R>
+__global__ void k_asm_gather(LevelGeo g, const R* __restrict__ zbuf, int nvert, R* __restrict__ y) {
   constexpr int NN = Dims<D>::NN;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)D * g.nnodes) return;
@@ -296,7 +270,7 @@ __global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nv
 #pragma unroll
   for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
   if (bnd) {
-    y[idx] = 0.0;
+    y[idx] = (R)0;
     return;
   }
   int vv[3][2], ll[3][2], cnt[3];
@@ -310,7 +284,7 @@ __global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nv
     }
   }
   const int nv = g.N + 1;
-  double s = 0.0;
+  R s = 0;
   for (int t2 = 0; t2 < cnt[2]; ++t2)
     for (int t1 = 0; t1 < cnt[1]; ++t1)
       for (int t0 = 0; t0 < cnt[0]; ++t0) {
@@ -324,10 +298,11 @@ __global__ void k_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nv
 // Local solves of the robust transfer: for every coarse cell K (one lane),
 // z = A_K^{-1} in|_K where A_K is the star patch of the fine vertex 2K+1
 // (interior-patch slot lex(K)); out|_K = (accumulate ? out|_K : 0) + alpha z.
-template <int D, bool ACC>
-__global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const double* __restrict__ inv,
-                                                      const double* __restrict__ in, double* __restrict__ out,
-                                                      double alpha) {
+template <int D, bool ACC, class R>
+__global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const R* __restrict__ inv,
+                                                      const R* __restrict__ in, R* __restrict__ out,
+                                                      double alpha_d) {
+  const R alpha = (R)alpha_d;
   constexpr int NN = Dims<D>::NN, NPT = Dims<D>::NL;
   const int nc = g.N / 2;
   const int ncc = D == 2 ? nc * nc : nc * nc * nc;
@@ -337,10 +312,10 @@ __global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const double* _
   const int64_t base = node_index<D>(g, 4 * K0 + 1, 4 * K1 + 1, D == 3 ? 4 * K2 + 1 : 0);
   const int64_t n1 = g.n1;
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
-  const double* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  double y[NPT];
+  const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  R y[NPT];
   if constexpr (D == 2) {
-    double x[NPT];
+    R x[NPT];
     static_for<NPT>([&](auto I) {
       constexpr int i = I;
       constexpr int comp = i / NN, loc = i % NN;
@@ -348,7 +323,7 @@ __global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const double* _
     });
     packed_symv<NPT>(A, x, y);
   } else {
-    __shared__ double xs[NPT * 64];
+    __shared__ R xs[NPT * 64];
     const int lane = threadIdx.x;
     static_for<NPT>([&](auto I) {
       constexpr int i = I;
@@ -381,51 +356,68 @@ void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hip
                        pc.count, pc.inv, H.flag);
 }
 
-void launch_asm(Hier& H, const Level& l, const double* r, double* y, hipStream_t s) {
-  AsmClasses c{};
+template <class R>
+static const R* class_inv(const PatchClass& pc);
+template <>
+const double* class_inv<double>(const PatchClass& pc) { return pc.inv; }
+template <>
+const float* class_inv<float>(const PatchClass& pc) { return pc.inv32; }
+
+template <class R>
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
+  AsmClasses<R> c{};
   int blocks = 0;
-  double bytes = 8.0 * (double)l.nvel;   // one read of the residual
+  double bytes = (double)sizeof(R) * (double)l.nvel;   // one read of the residual
   const int ncls = H.dim == 2 ? 3 : 4;
   for (int ci = 0; ci < 4; ++ci) {
     c.first_block[ci] = blocks;
     if (ci < ncls && ci < (int)l.cls.size()) {
       const PatchClass& pc = l.cls[ci];
       c.verts[ci] = pc.verts;
-      c.inv[ci] = pc.inv;
+      c.inv[ci] = class_inv<R>(pc);
       c.count[ci] = pc.count;
       blocks += (pc.count + 63) / 64;
       // algorithmic bytes: packed inverse and patch output of every patch
-      bytes += 8.0 * (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
+      bytes += (double)sizeof(R) * (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
     }
   }
   c.first_block[4] = blocks;
+  R* zbuf = reinterpret_cast<R*>(l.zbuf);
   hipEvent_t ev = nullptr;
   prof_begin(H, s, &ev);
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_asm_gemv<2>, dim3(blocks), dim3(64), 0, s, l.g, c, r, l.zbuf, l.nvert);
+    hipLaunchKernelGGL((k_asm_gemv<2, R>), dim3(blocks), dim3(64), 0, s, l.g, c, r, zbuf, l.nvert);
   else
-    hipLaunchKernelGGL(k_asm_gemv<3>, dim3(blocks), dim3(64), 0, s, l.g, c, r, l.zbuf, l.nvert);
+    hipLaunchKernelGGL((k_asm_gemv<3, R>), dim3(blocks), dim3(64), 0, s, l.g, c, r, zbuf, l.nvert);
   prof_end(H, s, PROF_ASM_GEMV, ev, bytes);
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_asm_gather<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.zbuf, l.nvert, y);
+    hipLaunchKernelGGL((k_asm_gather<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
   else
-    hipLaunchKernelGGL(k_asm_gather<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, l.zbuf, l.nvert, y);
+    hipLaunchKernelGGL((k_asm_gather<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
 }
 
-void launch_center_solve(const Hier& H, const Level& fine, const double* in, double* out, double alpha,
-                         bool accumulate, hipStream_t s) {
+template <class R>
+void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
+                         hipStream_t s) {
   const int nc = fine.g.N / 2;
   const int ncc = H.dim == 2 ? nc * nc : nc * nc * nc;
   const dim3 grid(nblk(ncc, 64)), blk(64);
-  const double* inv = fine.cls[0].inv;
+  const R* inv = class_inv<R>(fine.cls[0]);
   if (H.dim == 2) {
-    if (accumulate) hipLaunchKernelGGL((k_center_solve<2, true>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
-    else hipLaunchKernelGGL((k_center_solve<2, false>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    if (accumulate) hipLaunchKernelGGL((k_center_solve<2, true, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    else hipLaunchKernelGGL((k_center_solve<2, false, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
   } else {
-    if (accumulate) hipLaunchKernelGGL((k_center_solve<3, true>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
-    else hipLaunchKernelGGL((k_center_solve<3, false>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    if (accumulate) hipLaunchKernelGGL((k_center_solve<3, true, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+    else hipLaunchKernelGGL((k_center_solve<3, false, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
   }
 }
+
+template void launch_asm<double>(Hier&, const Level&, const double*, double*, hipStream_t);
+template void launch_asm<float>(Hier&, const Level&, const float*, float*, hipStream_t);
+template void launch_center_solve<double>(const Hier&, const Level&, const double*, double*, double, bool,
+                                          hipStream_t);
+template void launch_center_solve<float>(const Hier&, const Level&, const float*, float*, double, bool,
+                                         hipStream_t);
 
 }  // namespace stk

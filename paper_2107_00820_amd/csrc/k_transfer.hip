@@ -8,8 +8,8 @@
 
 namespace stk {
 
-template <int D>
-__global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict__ xc, double* __restrict__ xf) {
+template <int D, class R>
+__global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const R* __restrict__ xc, R* __restrict__ xf) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)D * gf.nnodes) return;
   const int comp = (int)(idx / gf.nnodes);
@@ -22,7 +22,7 @@ __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict
 #pragma unroll
   for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * gf.N;
   if (bnd) {
-    xf[idx] = 0.0;
+    xf[idx] = (R)0;
     return;
   }
   int cell[3], r[3];
@@ -33,7 +33,7 @@ __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict
     r[k] = i[k] & 3;
     if (cell[k] == gc.N) { cell[k] = gc.N - 1; r[k] = 4; }
   }
-  double s = 0.0;
+  R s = 0;
   for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2) {
     const double w2 = D == 3 ? kProlW[r[2]][a2] : 1.0;
     if (w2 == 0.0) continue;
@@ -49,7 +49,7 @@ __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict
         if (w0 == 0.0) continue;
         const int j0 = 2 * cell[0] + a0;
         if (j0 == 0 || j0 == 2 * gc.N) continue;
-        s += (w0 * w1 * w2) * xc[comp * gc.nnodes + node_index<D>(gc, j0, j1, j2)];
+        s += (R)(w0 * w1 * w2) * xc[comp * gc.nnodes + node_index<D>(gc, j0, j1, j2)];
       }
     }
   }
@@ -84,8 +84,8 @@ __device__ inline int fine_support(int j, int Nc, int nodes[7], double w[7]) {
   return n;
 }
 
-template <int D>
-__global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restrict__ rf, double* __restrict__ rc) {
+template <int D, class R>
+__global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const R* __restrict__ rf, R* __restrict__ rc) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)D * gc.nnodes) return;
   const int comp = (int)(idx / gc.nnodes);
@@ -98,7 +98,7 @@ __global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restric
 #pragma unroll
   for (int k = 0; k < D; ++k) bnd = bnd || j[k] == 0 || j[k] == 2 * gc.N;
   if (bnd) {
-    rc[idx] = 0.0;
+    rc[idx] = (R)0;
     return;
   }
   int fn[3][7], cnt[3];
@@ -108,7 +108,7 @@ __global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restric
     if (k >= D) { cnt[k] = 1; fn[k][0] = 0; fw[k][0] = 1.0; continue; }
     cnt[k] = fine_support(j[k], gc.N, fn[k], fw[k]);
   }
-  double s = 0.0;
+  R s = 0;
   for (int t2 = 0; t2 < cnt[2]; ++t2) {
     const int i2 = fn[2][t2];
     if (D == 3 && (i2 == 0 || i2 == 2 * gf.N)) continue;
@@ -118,7 +118,7 @@ __global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restric
       for (int t0 = 0; t0 < cnt[0]; ++t0) {
         const int i0 = fn[0][t0];
         if (i0 == 0 || i0 == 2 * gf.N) continue;
-        s += (fw[0][t0] * fw[1][t1] * fw[2][t2]) * rf[comp * gf.nnodes + node_index<D>(gf, i0, i1, i2)];
+        s += (R)(fw[0][t0] * fw[1][t1] * fw[2][t2]) * rf[comp * gf.nnodes + node_index<D>(gf, i0, i1, i2)];
       }
     }
   }
@@ -127,22 +127,28 @@ __global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restric
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc, double* xf,
-                        hipStream_t s) {
+template <class R>
+void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const R* xc, R* xf, hipStream_t s) {
   const int64_t n = (int64_t)H.dim * fine.g.nnodes;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_prolong_std<2>, dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
+    hipLaunchKernelGGL((k_prolong_std<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
   else
-    hipLaunchKernelGGL(k_prolong_std<3>, dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
+    hipLaunchKernelGGL((k_prolong_std<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
 }
 
-void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf, double* rc,
-                         hipStream_t s) {
+template <class R>
+void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const R* rf, R* rc, hipStream_t s) {
   const int64_t n = (int64_t)H.dim * coarse.g.nnodes;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_restrict_std<2>, dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
+    hipLaunchKernelGGL((k_restrict_std<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
   else
-    hipLaunchKernelGGL(k_restrict_std<3>, dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
+    hipLaunchKernelGGL((k_restrict_std<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
 }
+
+template void launch_prolong_std<double>(const Hier&, const Level&, const Level&, const double*, double*, hipStream_t);
+template void launch_prolong_std<float>(const Hier&, const Level&, const Level&, const float*, float*, hipStream_t);
+template void launch_restrict_std<double>(const Hier&, const Level&, const Level&, const double*, double*,
+                                          hipStream_t);
+template void launch_restrict_std<float>(const Hier&, const Level&, const Level&, const float*, float*, hipStream_t);
 
 }  // namespace stk

@@ -64,7 +64,7 @@ stk_status validate(const stk_desc* d) {
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
   if (d->schur != 1) return fail(STK_EINVAL, "only the P1 Schur approximation (schur=1) is built");
   if (d->coef_kind != 0) return fail(STK_EINVAL, "only the scalar sinker viscosity (coef_kind=0) is built");
-  if (d->mixed != 0) return fail(STK_EINVAL, "only the plain FP64 form (mixed=0) is built");
+  if (d->mixed != 0 && d->mixed != 1) return fail(STK_EINVAL, "mixed must be 0 (FP64 form) or 1 (mixed form)");
   if (d->nu_pre < 1 || d->nu_pre > kMaxNu || d->nu_post < 1 || d->nu_post > kMaxNu)
     return fail(STK_EINVAL, "nu_pre/nu_post must be in [1, 8]");
   const stk_sinker& s = d->sinker;
@@ -146,6 +146,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     L.nvel = D * L.g.nnodes;
     L.npres = NP * L.g.ncell;
     STKCHK(alloc((size_t)NN * L.g.ncell * 8, (void**)&L.mu));
+    if (d->mixed) STKCHK(alloc((size_t)NN * L.g.ncell * 4, (void**)&L.mu32));
     STKCHK(alloc((size_t)NL * L.g.ncell * 8, (void**)&L.E));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.b));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.x));
@@ -153,6 +154,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.T));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.U));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.S));
+    if (d->mixed) STKCHK(alloc((size_t)L.nvel * 4, (void**)&L.S32));
     STKCHK(alloc((size_t)kSmallLen * 8, (void**)&L.small));
     if (l >= 1) {
       STKCHK(alloc((size_t)(kMaxNu + 1) * L.nvel * 8, (void**)&L.V));
@@ -165,6 +167,8 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
         L.cls[c].count = (int)plan[c].verts.size();
         STKCHK(alloc(plan[c].verts.size() * 4, (void**)&L.cls[c].verts));
         STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 8, (void**)&L.cls[c].inv));
+        if (d->mixed)
+          STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 4, (void**)&L.cls[c].inv32));
       }
     }
   }
@@ -189,6 +193,11 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   STKCHK(alloc((size_t)64 * 8, (void**)&H.fy));
   STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.pw_u));
   STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.pw_y));
+  H.mixed = d->mixed;
+  if (d->mixed) {
+    STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.mb));
+    STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.mx));
+  }
   (void)build_classes;
   return STK_OK;
 }
@@ -199,128 +208,180 @@ void free_all(Hier& H) {
 }
 
 // ---------------------------------------------------------------------------
-// Operators on a level (all asynchronous on H.stream)
+// Operators on a level (all asynchronous on H.stream), templated on the
+// storage type R of the level vectors: double (FP64 form) or float (the
+// V-cycle of the mixed form). Level work buffers are sized for doubles and
+// the FP32 path reuses their memory wherever every use writes the entries it
+// later reads; buffers with entries that must stay zero get FP32 copies.
+template <class R>
+R* rv(double* p) {
+  return reinterpret_cast<R*>(p);
+}
 
-void apply_A(Hier& H, int l, const double* x, double* y) {
+// buffer of the restriction's local solves (zero outside the coarse-cell interiors)
+template <class R>
+R* level_S(Level& L);
+template <>
+double* level_S<double>(Level& L) {
+  return L.S;
+}
+template <>
+float* level_S<float>(Level& L) {
+  return L.S32;
+}
+
+template <class R>
+void apply_A(Hier& H, int l, const R* x, R* y) {
   Level& L = H.lv[l];
   hipEvent_t ev = nullptr;
   prof_begin(H, H.stream, &ev);
-  launch_elem(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
   // algorithmic bytes of the cell kernel: u, viscosity at Gauss points, element outputs
   {
     const double nn = H.dim == 2 ? 9.0 : 27.0;   // Gauss points (= nodes) per cell
-    prof_end(H, H.stream, PROF_ELEM, ev, 8.0 * ((double)L.nvel + (double)L.g.ncell * (nn + H.dim * nn)));
+    prof_end(H, H.stream, PROF_ELEM, ev,
+             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (nn + H.dim * nn)));
   }
-  launch_gather(H, L, nullptr, 1.0, y, H.stream);
+  launch_gather<R>(H, L, nullptr, 1.0, y, H.stream);
 }
 
-void residual(Hier& H, int l, const double* b, const double* x, double* r) {
+template <class R>
+void residual(Hier& H, int l, const R* b, const R* x, R* r) {
   Level& L = H.lv[l];
-  launch_elem(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
-  launch_gather(H, L, b, -1.0, r, H.stream);
+  launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  launch_gather<R>(H, L, b, -1.0, r, H.stream);
 }
 
 // rc = P~^T rf (fine level l -> l-1)
-void restrict_robust(Hier& H, int l, const double* rf, double* rc) {
+template <class R>
+void restrict_robust(Hier& H, int l, const R* rf, R* rc) {
   Level& F = H.lv[l];
   Level& C = H.lv[l - 1];
-  launch_center_solve(H, F, rf, F.S, 1.0, false, H.stream);           // S|_K = A_K^{-1} rf|_K
-  launch_elem(H, F, EL_AUG, F.S, nullptr, nullptr, H.stream);          // G S
-  launch_gather(H, F, rf, -1.0, F.U, H.stream);                        // U = rf - G S
-  launch_restrict_std(H, F, C, F.U, rc, H.stream);                     // rc = P_H^T U
+  R* S = level_S<R>(F);
+  R* U = rv<R>(F.U);
+  launch_center_solve<R>(H, F, rf, S, 1.0, false, H.stream);          // S|_K = A_K^{-1} rf|_K
+  launch_elem<R>(H, F, EL_AUG, S, nullptr, nullptr, H.stream);         // G S
+  launch_gather<R>(H, F, rf, -1.0, U, H.stream);                       // U = rf - G S
+  launch_restrict_std<R>(H, F, C, U, rc, H.stream);                    // rc = P_H^T U
 }
 
 // xf = P~ xc (coarse level l-1 -> fine level l)
-void prolong_robust(Hier& H, int l, const double* xc, double* xf) {
+template <class R>
+void prolong_robust(Hier& H, int l, const R* xc, R* xf) {
   Level& F = H.lv[l];
   Level& C = H.lv[l - 1];
-  launch_prolong_std(H, C, F, xc, xf, H.stream);                       // xf = P_H xc
-  launch_elem(H, F, EL_AUG, xf, nullptr, nullptr, H.stream);
-  launch_gather(H, F, nullptr, 1.0, F.U, H.stream);                    // U = G xf
-  launch_center_solve(H, F, F.U, xf, -1.0, true, H.stream);            // xf|_K -= A_K^{-1} U|_K
+  R* U = rv<R>(F.U);
+  launch_prolong_std<R>(H, C, F, xc, xf, H.stream);                    // xf = P_H xc
+  launch_elem<R>(H, F, EL_AUG, xf, nullptr, nullptr, H.stream);
+  launch_gather<R>(H, F, nullptr, 1.0, U, H.stream);                   // U = G xf
+  launch_center_solve<R>(H, F, U, xf, -1.0, true, H.stream);           // xf|_K -= A_K^{-1} U|_K
 }
 
 // nu steps of right-preconditioned GMRES relaxation on A x = b.
-void smooth(Hier& H, int l, const double* b, double* x, int nu, bool x_zero) {
+template <class R>
+void smooth(Hier& H, int l, const R* b, R* x, int nu, bool x_zero) {
   Level& L = H.lv[l];
   const int64_t n = L.nvel;
   double* p1 = H.partials;
   double* p2 = H.partials + kPartialLen;
-  const double* r0 = b;
+  R* V = rv<R>(L.V);
+  R* Z = rv<R>(L.Z);
+  const R* r0 = b;
   if (!x_zero) {
-    residual(H, l, b, x, L.r);
-    r0 = L.r;
+    residual<R>(H, l, b, x, rv<R>(L.r));
+    r0 = rv<R>(L.r);
   }
-  launch_dots(r0, n, 1, r0, n, p1, H.stream);
-  launch_normalize(p1, const_cast<double*>(r0), n, L.V, L.small + kSmallBeta, H.stream);
+  launch_dots<R>(r0, n, 1, r0, n, p1, H.stream);
+  launch_normalize<R>(p1, const_cast<R*>(r0), n, V, L.small + kSmallBeta, H.stream);
   for (int j = 0; j < nu; ++j) {
-    double* Vj = L.V + (int64_t)j * n;
-    double* Zj = L.Z + (int64_t)j * n;
-    double* w = L.V + (int64_t)(j + 1) * n;
-    launch_asm(H, L, Vj, Zj, H.stream);
-    apply_A(H, l, Zj, w);
+    R* Vj = V + (int64_t)j * n;
+    R* Zj = Z + (int64_t)j * n;
+    R* w = V + (int64_t)(j + 1) * n;
+    launch_asm<R>(H, L, Vj, Zj, H.stream);
+    apply_A<R>(H, l, Zj, w);
     double* Hcol = L.small + kSmallH + j;
-    launch_dots(L.V, n, j + 1, w, n, p1, H.stream);
-    launch_orth_update(L.V, n, j + 1, w, n, p1, Hcol, kMaxNu, false, p2, true, H.stream);
-    launch_orth_update(L.V, n, j + 1, w, n, p2, Hcol, kMaxNu, true, p1, false, H.stream);
-    launch_normalize(p1, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
+    launch_dots<R>(V, n, j + 1, w, n, p1, H.stream);
+    launch_orth_update<R>(V, n, j + 1, w, n, p1, Hcol, kMaxNu, false, p2, true, H.stream);
+    launch_orth_update<R>(V, n, j + 1, w, n, p2, Hcol, kMaxNu, true, p1, false, H.stream);
+    launch_normalize<R>(p1, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
   }
-  launch_relax_update(L.Z, n, nu, L.small, x, n, x_zero, H.stream);
+  launch_relax_update<R>(Z, n, nu, L.small, x, n, x_zero, H.stream);
 }
 
-void coarse_solve(Hier& H, const double* b, double* x) { launch_coarse_apply(H, H.lv[0], b, x, H.stream); }
+template <class R>
+void coarse_solve(Hier& H, const R* b, R* x) {
+  launch_coarse_apply<R>(H, H.lv[0], b, x, H.stream);
+}
 
 // One V-cycle on level l: x = V(b).
-void vcycle(Hier& H, int l, const double* b, double* x) {
+template <class R>
+void vcycle(Hier& H, int l, const R* b, R* x) {
   if (l == 0) {
-    coarse_solve(H, b, x);
+    coarse_solve<R>(H, b, x);
     return;
   }
   Level& L = H.lv[l];
   Level& C = H.lv[l - 1];
-  smooth(H, l, b, x, H.nu_pre, true);
-  residual(H, l, b, x, L.r);
-  restrict_robust(H, l, L.r, C.b);
-  vcycle(H, l - 1, C.b, C.x);
-  prolong_robust(H, l, C.x, L.T);
-  launch_axpby(1.0, x, 1.0, L.T, x, L.nvel, H.stream);
-  smooth(H, l, b, x, H.nu_post, false);
+  smooth<R>(H, l, b, x, H.nu_pre, true);
+  residual<R>(H, l, b, x, rv<R>(L.r));
+  restrict_robust<R>(H, l, rv<R>(L.r), rv<R>(C.b));
+  vcycle<R>(H, l - 1, rv<R>(C.b), rv<R>(C.x));
+  prolong_robust<R>(H, l, rv<R>(C.x), rv<R>(L.T));
+  launch_axpby<R>(1.0, x, 1.0, rv<R>(L.T), x, L.nvel, H.stream);
+  smooth<R>(H, l, b, x, H.nu_post, false);
+}
+
+// Ahat^{-1} applied to an FP64 fine-level vector: one V-cycle in FP64, or in
+// the mixed form one FP32 V-cycle (FP32 applies, transfers and patch solves;
+// FP64 coarse solve and small least-squares problems) between conversions.
+void vcycle_fine(Hier& H, const double* b, double* x, bool mixed) {
+  const int lf = H.L - 1;
+  if (!mixed) {
+    vcycle<double>(H, lf, b, x);
+    return;
+  }
+  const int64_t n = H.lv[lf].nvel;
+  float* b32 = reinterpret_cast<float*>(H.mb);
+  float* x32 = reinterpret_cast<float*>(H.mx);
+  launch_convert<double, float>(b, b32, n, H.stream);
+  vcycle<float>(H, lf, b32, x32);
+  launch_convert<float, double>(x32, x, n, H.stream);
 }
 
 // (z_u, z_p) = P (v_u, v_p), eq. (precond) with Ahat^{-1} = one V-cycle.
-void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp) {
+void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp, bool mixed) {
   const int lf = H.L - 1;
   Level& F = H.lv[lf];
-  vcycle(H, lf, vu, H.pw_y);                                      // y = Ahat^{-1} v_u
+  vcycle_fine(H, vu, H.pw_y, mixed);                              // y = Ahat^{-1} v_u
   launch_schur_apply(H, F, H.pw_y, vp, zp, H.stream);             // z_p = -Shat^{-1}(v_p - B y)
   launch_project_mean(H, F, zp, H.stream);
-  launch_elem(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
-  launch_gather(H, F, nullptr, 1.0, H.pw_u, H.stream);           // B^T z_p
-  vcycle(H, lf, H.pw_u, zu);                                      // Ahat^{-1} B^T z_p
-  launch_axpby(1.0, H.pw_y, -1.0, zu, zu, F.nvel, H.stream);      // z_u = y - that
+  launch_elem<double>(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, H.pw_u, H.stream);   // B^T z_p
+  vcycle_fine(H, H.pw_u, zu, mixed);                              // Ahat^{-1} B^T z_p
+  launch_axpby<double>(1.0, H.pw_y, -1.0, zu, zu, F.nvel, H.stream);  // z_u = y - that
 }
 
 // y = K x on the finest level; x, y contiguous [u | p].
 void stokes_apply(Hier& H, const double* x, double* y) {
   Level& F = H.lv[H.L - 1];
-  launch_elem(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x, x + F.nvel, y + F.nvel, H.stream);
-  launch_gather(H, F, nullptr, 1.0, y, H.stream);
+  launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x, x + F.nvel, y + F.nvel, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, y, H.stream);
 }
 
 // One FGMRES Arnoldi step j with restart m: Z_j = P V_j, w = K Z_j,
 // classical Gram-Schmidt twice against V_0..V_j, V_{j+1} = w/||w||, H column j.
-void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec) {
+void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed) {
   double* Vj = H.fV + (int64_t)j * nvec;
   double* Zj = H.fZ + (int64_t)j * nvec;
   double* w = H.fV + (int64_t)(j + 1) * nvec;
   double* p1 = H.partials;
   double* p2 = H.partials + kPartialLen;
-  precond(H, Vj, Vj + nu, Zj, Zj + nu);
+  precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed);
   stokes_apply(H, Zj, w);
-  launch_dots(H.fV, nvec, j + 1, w, nvec, p1, H.stream);
-  launch_orth_update(H.fV, nvec, j + 1, w, nvec, p1, H.fH + j, m, false, p2, true, H.stream);
-  launch_orth_update(H.fV, nvec, j + 1, w, nvec, p2, H.fH + j, m, true, p1, false, H.stream);
-  launch_normalize(p1, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);
+  launch_dots<double>(H.fV, nvec, j + 1, w, nvec, p1, H.stream);
+  launch_orth_update<double>(H.fV, nvec, j + 1, w, nvec, p1, H.fH + j, m, false, p2, true, H.stream);
+  launch_orth_update<double>(H.fV, nvec, j + 1, w, nvec, p2, H.fH + j, m, true, p1, false, H.stream);
+  launch_normalize<double>(p1, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);
 }
 
 void drop_graphs(Hier& H) {
@@ -330,13 +391,19 @@ void drop_graphs(Hier& H) {
   H.steps_m = 0;
 }
 
+stk_status check_dtype(const Hier& H, int dtype) {
+  if (dtype == STK_F64) return STK_OK;
+  if (dtype == STK_F32 && H.mixed) return STK_OK;
+  return fail(STK_EINVAL, dtype == STK_F32 ? "STK_F32 needs a hierarchy set up with mixed=1" : "unknown dtype");
+}
+
 stk_status check_level(const Hier& H, int l, int lmin) {
   if (l < lmin || l >= H.L) return fail(STK_EINVAL, "level out of range");
   return STK_OK;
 }
 
 stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
-  launch_dots(x, n, 1, x, n, H.partials, H.stream);
+  launch_dots<double>(x, n, 1, x, n, H.partials, H.stream);
   const int np = red_parts(n);
   std::vector<double> part(np);
   HIPCHK(hipMemcpyAsync(part.data(), H.partials, np * 8, hipMemcpyDeviceToHost, H.stream));
@@ -453,8 +520,9 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   for (int l = 0; l < H.L; ++l) {
     Level& L = H.lv[l];
     launch_mu_sinker(H, L, s);
-    launch_fill(L.S, 0.0, L.nvel, s);
-    launch_fill(L.x, 0.0, L.nvel, s);
+    launch_fill<double>(L.S, 0.0, L.nvel, s);
+    if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
+    launch_fill<double>(L.x, 0.0, L.nvel, s);
     if (l >= 1) {
       std::vector<ClassPlan> plan = plan_patches(D, L.g.N);
       for (size_t c = 0; c < plan.size(); ++c) {
@@ -465,6 +533,15 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
         if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(STK_EDEVICE, "sync failed"));
         launch_patch_setup(H, L, L.cls[c], s);
       }
+    }
+  }
+  if (H.mixed) {
+    // FP32 copies for the mixed form, rounded from the FP64 factors
+    for (int l = 0; l < H.L; ++l) {
+      Level& L = H.lv[l];
+      launch_convert<double, float>(L.mu, L.mu32, (int64_t)(D == 2 ? 9 : 27) * L.g.ncell, s);
+      for (PatchClass& pc : L.cls)
+        launch_convert<double, float>(pc.inv, pc.inv32, packed_doubles(pc.n, pc.count), s);
     }
   }
   launch_coarse_assemble(H, H.lv[0], H.Ainv0, s);
@@ -542,8 +619,8 @@ stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
   if (!b_u) return fail(STK_EINVAL, "b_u is NULL");
   Level& F = H.lv[H.L - 1];
   launch_rhs_elem(H, F, H.stream);
-  launch_gather(H, F, nullptr, 1.0, b_u, H.stream);
-  if (b_p) launch_fill(b_p, 0.0, F.npres, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, b_u, H.stream);
+  if (b_p) launch_fill<double>(b_p, 0.0, F.npres, H.stream);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -551,9 +628,10 @@ stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
 stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, void* y, void* stream) {
   GET_H(h);
   STKCHK(check_level(H, level, 0));
-  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  STKCHK(check_dtype(H, dtype));
   if (!x || !y || x == y) return fail(STK_EINVAL, "x, y must be distinct non-NULL buffers");
-  apply_A(H, level, (const double*)x, (double*)y);
+  if (dtype == STK_F64) apply_A<double>(H, level, (const double*)x, (double*)y);
+  else apply_A<float>(H, level, (const float*)x, (float*)y);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -563,8 +641,8 @@ stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p, d
   GET_H(h);
   if (!x_u || !x_p || !y_u || !y_p) return fail(STK_EINVAL, "NULL buffer");
   Level& F = H.lv[H.L - 1];
-  launch_elem(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x_u, x_p, y_p, H.stream);
-  launch_gather(H, F, nullptr, 1.0, y_u, H.stream);
+  launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x_u, x_p, y_p, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, y_u, H.stream);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -572,9 +650,10 @@ stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p, d
 stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream) {
   GET_H(h);
   STKCHK(check_level(H, level, 1));
-  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  STKCHK(check_dtype(H, dtype));
   if (!r || !y) return fail(STK_EINVAL, "NULL buffer");
-  launch_asm(H, H.lv[level], (const double*)r, (double*)y, H.stream);
+  if (dtype == STK_F64) launch_asm<double>(H, H.lv[level], (const double*)r, (double*)y, H.stream);
+  else launch_asm<float>(H, H.lv[level], (const float*)r, (float*)y, H.stream);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -582,10 +661,11 @@ stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, vo
 stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x, int nsteps, void* stream) {
   GET_H(h);
   STKCHK(check_level(H, level, 1));
-  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  STKCHK(check_dtype(H, dtype));
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
   if (nsteps < 1 || nsteps > kMaxNu) return fail(STK_EINVAL, "nsteps must be in [1, 8]");
-  smooth(H, level, (const double*)b, (double*)x, nsteps, false);
+  if (dtype == STK_F64) smooth<double>(H, level, (const double*)b, (double*)x, nsteps, false);
+  else smooth<float>(H, level, (const float*)b, (float*)x, nsteps, false);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -593,9 +673,10 @@ stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x,
 stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc, void* xf, void* stream) {
   GET_H(h);
   STKCHK(check_level(H, coarse_level + 1, 1));
-  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  STKCHK(check_dtype(H, dtype));
   if (!xc || !xf) return fail(STK_EINVAL, "NULL buffer");
-  prolong_robust(H, coarse_level + 1, (const double*)xc, (double*)xf);
+  if (dtype == STK_F64) prolong_robust<double>(H, coarse_level + 1, (const double*)xc, (double*)xf);
+  else prolong_robust<float>(H, coarse_level + 1, (const float*)xc, (float*)xf);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -603,9 +684,10 @@ stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc,
 stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, void* rc, void* stream) {
   GET_H(h);
   STKCHK(check_level(H, fine_level, 1));
-  if (dtype != STK_F64) return fail(STK_EINVAL, "only STK_F64 is built");
+  STKCHK(check_dtype(H, dtype));
   if (!rf || !rc) return fail(STK_EINVAL, "NULL buffer");
-  restrict_robust(H, fine_level, (const double*)rf, (double*)rc);
+  if (dtype == STK_F64) restrict_robust<double>(H, fine_level, (const double*)rf, (double*)rc);
+  else restrict_robust<float>(H, fine_level, (const float*)rf, (float*)rc);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -613,24 +695,27 @@ stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, 
 stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream) {
   GET_H(h);
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
-  coarse_solve(H, b, x);
+  coarse_solve<double>(H, b, x);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
 
-stk_status stk_vcycle(stk_hier* h, const double* b, double* x, void* stream) {
+stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream) {
   GET_H(h);
+  STKCHK(check_dtype(H, dtype));
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
-  vcycle(H, H.L - 1, b, x);
+  if (dtype == STK_F64) vcycle<double>(H, H.L - 1, (const double*)b, (double*)x);
+  else vcycle<float>(H, H.L - 1, (const float*)b, (float*)x);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
 
-stk_status stk_precond(stk_hier* h, const double* v_u, const double* v_p, double* z_u, double* z_p,
+stk_status stk_precond(stk_hier* h, int mixed, const double* v_u, const double* v_p, double* z_u, double* z_p,
                        void* stream) {
   GET_H(h);
   if (!v_u || !v_p || !z_u || !z_p) return fail(STK_EINVAL, "NULL buffer");
-  precond(H, v_u, v_p, z_u, z_p);
+  if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
+  precond(H, v_u, v_p, z_u, z_p, mixed != 0);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -666,6 +751,8 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     drop_graphs(H);
   }
   const bool use_graphs = !(opts && opts->eager);
+  const bool mixed = opts && opts->mixed;
+  if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
   const auto t0 = std::chrono::steady_clock::now();
   // all solve work runs on the library's own stream (capturable), ordered
   // after the caller's stream
@@ -679,8 +766,8 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
 
   HIPCHK(hipMemcpyAsync(bvec, b_u, nu * 8, hipMemcpyDeviceToDevice, s));
   if (b_p) HIPCHK(hipMemcpyAsync(bvec + nu, b_p, np * 8, hipMemcpyDeviceToDevice, s));
-  else launch_fill(bvec + nu, 0.0, np, s);
-  launch_fill(xvec, 0.0, nvec, s);
+  else launch_fill<double>(bvec + nu, 0.0, np, s);
+  launch_fill<double>(xvec, 0.0, nvec, s);
   double bnorm = 0.0;
   STKCHK(device_norm(H, bvec, nvec, &bnorm));
   stk_solve_info loc{};
@@ -689,8 +776,8 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
   inf->hist[0] = 1.0;
   if (!isfinite(bnorm)) return fail(STK_ENAN, "right-hand side is not finite");
   if (bnorm == 0.0) {
-    launch_fill(x_u, 0.0, nu, s);
-    launch_fill(x_p, 0.0, np, s);
+    launch_fill<double>(x_u, 0.0, nu, s);
+    launch_fill<double>(x_p, 0.0, np, s);
     inf->converged = 1;
     HIPCHK(hipStreamSynchronize(s));
     return STK_OK;
@@ -701,25 +788,26 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
   bool converged = false;
   std::vector<double> Hd((size_t)(m + 1) * m), Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   while (true) {
-    launch_axpby(1.0 / beta, rvec, 0.0, rvec, H.fV, nvec, s);
+    launch_axpby<double>(1.0 / beta, rvec, 0.0, rvec, H.fV, nvec, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
       if (!use_graphs) {
-        arnoldi_step(H, j, m, nu, nvec);
+        arnoldi_step(H, j, m, nu, nvec, mixed);
       } else {
-        if (H.steps_m != m) {
+        if (H.steps_m != m || H.steps_mixed != (int)mixed) {
           drop_graphs(H);
           H.steps.assign(m, nullptr);
           H.steps_m = m;
+          H.steps_mixed = (int)mixed;
         }
         if (!H.steps[j]) {
           const bool prof_on = H.prof.on;
           H.prof.on = false;   // no event records inside captured graphs
           hipGraph_t graph = nullptr;
           HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-          arnoldi_step(H, j, m, nu, nvec);
+          arnoldi_step(H, j, m, nu, nvec, mixed);
           const hipError_t ce = hipStreamEndCapture(s, &graph);
           H.prof.on = prof_on;
           if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
@@ -768,7 +856,7 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     launch_combine(H.fZ, nvec, k, H.fy, xvec, nvec, false, s);
     // true residual r = b - K x
     stokes_apply(H, xvec, rvec);
-    launch_axpby(1.0, bvec, -1.0, rvec, rvec, nvec, s);
+    launch_axpby<double>(1.0, bvec, -1.0, rvec, rvec, nvec, s);
     STKCHK(device_norm(H, rvec, nvec, &beta));
     if (!isfinite(beta)) return fail(STK_ENAN, "non-finite residual");
     if (beta <= rtol * bnorm) {

@@ -31,6 +31,7 @@ struct PatchClass {
   int count = 0;          // patches in the class
   int* verts = nullptr;   // [count] vertex index (lexicographic over (N+1)^d)
   double* inv = nullptr;  // packed inverses, interleaved in blocks of 64 patches
+  float* inv32 = nullptr; // FP32 copy (mixed form)
 };
 
 struct Level {
@@ -38,10 +39,15 @@ struct Level {
   int nvert = 0;               // (N+1)^d
   int64_t nvel = 0;            // d * nnodes
   int64_t npres = 0;           // (d+1) * ncell
-  double* mu = nullptr;        // [NQ][ncell] viscosity at Gauss points
+  double* mu = nullptr;        // [ncell][NQ] viscosity at Gauss points
+  float* mu32 = nullptr;       // FP32 copy (mixed form)
   double* E = nullptr;         // [NL][ncell] element outputs
   // relaxation and transfer work vectors (stored layout)
   double *b = nullptr, *x = nullptr, *r = nullptr, *T = nullptr, *U = nullptr, *S = nullptr;
+  // S holds A_K^{-1} r on the coarse-cell interiors and must stay zero on the
+  // coarse-cell boundaries; the FP32 path keeps its own zero-initialised copy
+  // because FP64 writes into S would leave non-zero bytes under FP32 views.
+  float* S32 = nullptr;
   double* V = nullptr;         // (kMaxNu+1) * nvel
   double* Z = nullptr;         // kMaxNu * nvel
   double* small = nullptr;     // device scalars: H, beta, y
@@ -94,6 +100,10 @@ struct Hier {
   hipStream_t own = nullptr;
   std::vector<hipGraphExec_t> steps;
   int steps_m = 0;
+  int steps_mixed = 0;
+  // mixed form: FP32 copies exist; fine-level FP32 V-cycle input/output
+  int mixed = 0;
+  double *mb = nullptr, *mx = nullptr;
 };
 
 // Event bracketing of one launch (no-ops unless H.prof.on).
@@ -102,10 +112,11 @@ void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes);
 
 // ---- kernel launchers (templated on dimension inside the .hip files) ----
 void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s);
-void launch_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p,
-                 double* pout, hipStream_t s);
-void launch_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out,
-                   hipStream_t s);
+template <class R>
+void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const double* p, double* pout,
+                 hipStream_t s);
+template <class R>
+void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R* out, hipStream_t s);
 void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
@@ -113,34 +124,41 @@ void launch_schur_apply(const Hier& H, const Level& l, const double* y, const do
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s);
 
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
-void launch_asm(Hier& H, const Level& l, const double* r, double* y, hipStream_t s);
-void launch_center_solve(const Hier& H, const Level& fine, const double* in, double* out,
-                         double alpha, bool accumulate, hipStream_t s);
+template <class R>
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s);
+template <class R>
+void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
+                         hipStream_t s);
 
-void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc,
-                        double* xf, hipStream_t s);
-void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf,
-                         double* rc, hipStream_t s);
+template <class R>
+void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const R* xc, R* xf, hipStream_t s);
+template <class R>
+void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const R* rf, R* rc, hipStream_t s);
 
 void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_t s);
 int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s);
-void launch_coarse_apply(const Hier& H, const Level& l, const double* b, double* x, hipStream_t s);
+template <class R>
+void launch_coarse_apply(const Hier& H, const Level& l, const R* b, R* x, hipStream_t s);
 
-// Krylov helpers (vectors of length n)
-void launch_dots(const double* V, int64_t ldv, int nk, const double* w, int64_t n, double* partials,
-                 hipStream_t s);
-void launch_orth_update(const double* V, int64_t ldv, int nk, double* w, int64_t n,
-                        const double* part_in, double* Hcol, int hstride, bool accumulate,
-                        double* part_out, bool next_dots, hipStream_t s);
-void launch_normalize(const double* norm_partials, double* w, int64_t n, double* dst,
-                      double* hout, hipStream_t s);
-void launch_relax_update(const double* Z, int64_t ldz, int nu, const double* small, double* x,
-                         int64_t n, bool x_zero, hipStream_t s);
+// Krylov helpers (vectors of length n, storage type R; reductions in double)
+template <class R>
+void launch_dots(const R* V, int64_t ldv, int nk, const R* w, int64_t n, double* partials, hipStream_t s);
+template <class R>
+void launch_orth_update(const R* V, int64_t ldv, int nk, R* w, int64_t n, const double* part_in, double* Hcol,
+                        int hstride, bool accumulate, double* part_out, bool next_dots, hipStream_t s);
+template <class R>
+void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, double* hout, hipStream_t s);
+template <class R>
+void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, R* x, int64_t n, bool x_zero,
+                         hipStream_t s);
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n,
                     bool x_zero, hipStream_t s);
-void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
-                  hipStream_t s);
-void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+template <class R>
+void launch_axpby(double a, const R* x, double b, const R* y, R* out, int64_t n, hipStream_t s);
+template <class R>
+void launch_fill(R* x, double v, int64_t n, hipStream_t s);
+template <class A, class B>
+void launch_convert(const A* x, B* y, int64_t n, hipStream_t s);
 void launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
 void launch_fill_int(int* x, int v, int64_t n, hipStream_t s);
 

@@ -1,8 +1,10 @@
 """ctypes binding of libstk.so (argument marshalling only).
 
 Names follow the C ABI in include/stk.h. Buffers are torch tensors on the
-current HIP device (float64, contiguous); every device step runs in the HIP
-kernels of libstk.so. There is no fallback path: if the library is missing
+current HIP device (contiguous float64; the level operations also take
+float32 tensors on a hierarchy built with mixed=1, and the dtype passed to
+the library follows the tensors); every device step runs in the HIP kernels
+of libstk.so. There is no fallback path: if the library is missing
 or no GPU is present, the calls raise.
 """
 from __future__ import annotations
@@ -40,7 +42,8 @@ class Desc(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("eager", C.c_int)]
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("eager", C.c_int),
+                ("mixed", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -74,8 +77,8 @@ def load(path: str = LIB_PATH):
         "stk_prolong": [vp, i32, i32, vp, vp, vp],
         "stk_restrict": [vp, i32, i32, vp, vp, vp],
         "stk_coarse_solve": [vp, vp, vp, vp],
-        "stk_vcycle": [vp, vp, vp, vp],
-        "stk_precond": [vp, vp, vp, vp, vp, vp],
+        "stk_vcycle": [vp, i32, vp, vp, vp],
+        "stk_precond": [vp, i32, vp, vp, vp, vp, vp],
         "stk_solve": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp],
         "stk_profile": [vp, i32],
         "stk_profile_read": [vp, i32, i64p, dp, dp],
@@ -107,12 +110,23 @@ def _ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _dptr(*ts):
+    """dtype code and pointers for tensors that must share one float dtype."""
+    import torch
+    dt = ts[0].dtype
+    code = {torch.float64: STK_F64, torch.float32: STK_F32}.get(dt)
+    assert code is not None, "expected float64 or float32 tensors"
+    for t in ts:
+        assert t.is_cuda and t.dtype == dt and t.is_contiguous(), "expected contiguous GPU tensors of one dtype"
+    return (code,) + tuple(C.c_void_p(t.data_ptr()) for t in ts)
+
+
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
-              nu_pre=2, nu_post=2, hbm_budget=0):
+              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0):
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
-    d.schur, d.coef_kind, d.mixed = 1, 0, 0
+    d.schur, d.coef_kind, d.mixed = 1, 0, int(mixed)
     d.sinker.n = centers.shape[0]
     d.sinker.centers = centers.ctypes.data_as(C.POINTER(C.c_double))
     d.sinker.omega, d.sinker.delta, d.sinker.beta = omega, delta, beta
@@ -123,10 +137,10 @@ def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, 
     return d
 
 
-def desc_from_workload(wl, hbm_budget=0):
+def desc_from_workload(wl, hbm_budget=0, mixed=0):
     from workloads import OMEGA, DELTA, BETA
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
-                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget)
+                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed)
 
 
 def stk_footprint(desc: Desc) -> int:
@@ -150,8 +164,8 @@ class Hierarchy:
         self._h = h
 
     @classmethod
-    def from_workload(cls, wl, hbm_budget=0):
-        return cls(desc_from_workload(wl, hbm_budget))
+    def from_workload(cls, wl, hbm_budget=0, mixed=0):
+        return cls(desc_from_workload(wl, hbm_budget, mixed))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -170,10 +184,10 @@ class Hierarchy:
         _check(load().stk_sizes(self._h, level, C.byref(nv), C.byref(npr)))
         return nv.value, npr.value
 
-    def zeros_u(self, level: Optional[int] = None):
+    def zeros_u(self, level: Optional[int] = None, dtype=None):
         import torch
         nv, _ = self.sizes(self.L - 1 if level is None else level)
-        return torch.zeros(nv, dtype=torch.float64, device="cuda")
+        return torch.zeros(nv, dtype=torch.float64 if dtype is None else dtype, device="cuda")
 
     def zeros_p(self):
         import torch
@@ -187,8 +201,8 @@ class Hierarchy:
         return bu, bp
 
     def stk_apply_Agamma(self, level, x, y=None):
-        y = self.zeros_u(level) if y is None else y
-        _check(load().stk_apply_Agamma(self._h, level, STK_F64, _ptr(x), _ptr(y), _stream()))
+        y = self.zeros_u(level, x.dtype) if y is None else y
+        _check(load().stk_apply_Agamma(self._h, level, *_dptr(x, y), _stream()))
         return y
 
     def stk_apply_stokes(self, xu, xp, yu=None, yp=None):
@@ -198,22 +212,23 @@ class Hierarchy:
         return yu, yp
 
     def stk_asm(self, level, r, y=None):
-        y = self.zeros_u(level) if y is None else y
-        _check(load().stk_asm(self._h, level, STK_F64, _ptr(r), _ptr(y), _stream()))
+        y = self.zeros_u(level, r.dtype) if y is None else y
+        _check(load().stk_asm(self._h, level, *_dptr(r, y), _stream()))
         return y
 
     def stk_smooth(self, level, b, x, nsteps):
-        _check(load().stk_smooth(self._h, level, STK_F64, _ptr(b), _ptr(x), nsteps, _stream()))
+        code, pb, px = _dptr(b, x)
+        _check(load().stk_smooth(self._h, level, code, pb, px, nsteps, _stream()))
         return x
 
     def stk_prolong(self, coarse_level, xc, xf=None):
-        xf = self.zeros_u(coarse_level + 1) if xf is None else xf
-        _check(load().stk_prolong(self._h, coarse_level, STK_F64, _ptr(xc), _ptr(xf), _stream()))
+        xf = self.zeros_u(coarse_level + 1, xc.dtype) if xf is None else xf
+        _check(load().stk_prolong(self._h, coarse_level, *_dptr(xc, xf), _stream()))
         return xf
 
     def stk_restrict(self, fine_level, rf, rc=None):
-        rc = self.zeros_u(fine_level - 1) if rc is None else rc
-        _check(load().stk_restrict(self._h, fine_level, STK_F64, _ptr(rf), _ptr(rc), _stream()))
+        rc = self.zeros_u(fine_level - 1, rf.dtype) if rc is None else rc
+        _check(load().stk_restrict(self._h, fine_level, *_dptr(rf, rc), _stream()))
         return rc
 
     def stk_coarse_solve(self, b, x=None):
@@ -222,14 +237,14 @@ class Hierarchy:
         return x
 
     def stk_vcycle(self, b, x=None):
-        x = self.zeros_u() if x is None else x
-        _check(load().stk_vcycle(self._h, _ptr(b), _ptr(x), _stream()))
+        x = self.zeros_u(None, b.dtype) if x is None else x
+        _check(load().stk_vcycle(self._h, *_dptr(b, x), _stream()))
         return x
 
-    def stk_precond(self, vu, vp, zu=None, zp=None):
+    def stk_precond(self, vu, vp, zu=None, zp=None, mixed=False):
         zu = self.zeros_u() if zu is None else zu
         zp = self.zeros_p() if zp is None else zp
-        _check(load().stk_precond(self._h, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
+        _check(load().stk_precond(self._h, 1 if mixed else 0, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
         return zu, zp
 
     def stk_profile(self, enable: bool):
@@ -241,10 +256,10 @@ class Hierarchy:
         return n.value, ms.value, by.value
 
     def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False,
-                  eager=False):
+                  eager=False, mixed=False):
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0)
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0)
         info = SolveInfo()
         st = load().stk_solve(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu), _ptr(xp),
                               C.byref(opts), C.byref(info), _stream())

@@ -60,3 +60,20 @@ def rand_u(level, seed):
     mask[level.stored_index()] = False
     s[mask] = rng.standard_normal(mask.sum()) * 1e3
     return u, s
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_mixed_for(name: str):
+    """Hierarchy with the FP32 tables of the mixed form."""
+    from paper_2107_00820_amd import Hierarchy
+    return Hierarchy.from_workload(CASES[name], mixed=1)
+
+
+def to_dev32(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def f32(x):
+    """Round an FP64 array to FP32 and back (the values an FP32 input holds)."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)

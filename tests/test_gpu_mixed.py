@@ -1,0 +1,205 @@
+"""Mixed form: FP32 level operations against the FP64 oracle, and the mixed
+FGMRES solve (FP32 V-cycles inside FP64 FGMRES, Section 5.1's solver with the
+preconditioner's arithmetic lowered).
+
+Bars, derived from the arithmetic:
+- A_gamma apply in FP32 (viscosity table and vectors FP32): error bounded by
+  c eps32 ||sum_K |A_K| |x_K| || with c = 2 n_q d (n_q Gauss points per cell,
+  d components), against the oracle applied to the same FP32-rounded input;
+- star smoother in FP32 (FP32 copy of the FP64 patch inverses): elementwise
+  error bounded by (n_max + 16) eps32 sum_i I_i |A_i^{-1}| |r_i|;
+- robust transfers in FP32: componentwise bound c eps32 X with X the chain
+  of operations on absolute values (see test_f32_transfers);
+- mixed solve: converged with the FP64 true residual below rtol (checked with
+  the oracle's assembled operator) and iteration count within 10 % (+2) of
+  the FP64 form's; FGMRES allows a varying preconditioner, so the lower
+  precision may only cost iterations, never accuracy.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from gpu_common import (CASES, oracle_for, gpu_for, gpu_mixed_for, to_dev, to_dev32, to_host, rel, rand_u,
+                        f32, log)
+
+pytestmark = pytest.mark.gpu
+
+NAMES = list(CASES)
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def element_abs_bound(orc, l, x):
+    """sum_K |A_gamma,K| |x_K| on level l (oracle element matrices)."""
+    from oracle.assembly import element_viscous, element_divergence, element_pressure_mass
+    ops = orc.mg.ops[l]
+    lv = ops.level
+    ed = lv.element_dofs()
+    Ae = element_viscous(lv, ops.coef)
+    Be = element_divergence(lv)
+    We_inv = np.linalg.inv(element_pressure_mass(lv)[0])
+    Ge = ops.gamma * np.einsum("pi,pq,qj->ij", Be, We_inv, Be)
+    Ke = np.abs(Ae + Ge[None])
+    xe = np.where(ed >= 0, np.abs(x)[np.maximum(ed, 0)], 0.0)
+    ye = np.einsum("kij,kj->ki", Ke, xe)
+    out = np.zeros(lv.n_u)
+    keep = ed >= 0
+    np.add.at(out, ed[keep], ye[keep])
+    return out
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_f32_apply_agamma(name):
+    log(f"[f32 apply] {name}")
+    orc, gpu = oracle_for(name), gpu_mixed_for(name)
+    wl = CASES[name]
+    nq = 3 ** wl.dim
+    for l in range(wl.levels):
+        lv = orc.mg.hier[l]
+        u, us = rand_u(lv, 110 + l)
+        y = lv.from_stored(to_host(gpu.stk_apply_Agamma(l, to_dev32(us))).astype(np.float64))
+        u32 = f32(u)
+        ref = orc.mg.ops[l].Agamma @ u32
+        bound = 2 * nq * wl.dim * EPS32 * np.linalg.norm(element_abs_bound(orc, l, u32))
+        err = np.linalg.norm(y - ref)
+        log(f"  level {l}: err {err:.3e} bound {bound:.3e} (rel {rel(y, ref):.2e})")
+        assert err <= bound
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_f32_star_asm(name):
+    log(f"[f32 asm] {name}")
+    orc, gpu = oracle_for(name), gpu_mixed_for(name)
+    wl = CASES[name]
+    for l in range(1, wl.levels):
+        lv = orc.mg.hier[l]
+        r, rs = rand_u(lv, 120 + l)
+        y = lv.from_stored(to_host(gpu.stk_asm(l, to_dev32(rs))).astype(np.float64))
+        r32 = f32(r)
+        sm = orc.mg.smoothers[l]
+        ref = sm.apply(r32)
+        S = np.zeros(lv.n_u)
+        nmax = 0
+        for idx, lu in zip(sm.patches, sm.lus):
+            inv = sla.lu_solve(lu, np.eye(idx.size), check_finite=False)
+            S[idx] += np.abs(inv) @ np.abs(r32[idx])
+            nmax = max(nmax, idx.size)
+        bound = (nmax + 16) * EPS32 * S
+        worst = np.max(np.abs(y - ref) / np.maximum(bound, 1e-300))
+        log(f"  level {l}: worst err/bound {worst:.3f} (rel {rel(y, ref):.2e})")
+        assert worst <= 1.0
+
+
+def element_abs_G(orc, l, x):
+    """sum_K |G_K| |x_K| (G = gamma B^T W^{-1} B) on level l."""
+    from oracle.assembly import element_divergence, element_pressure_mass
+    ops = orc.mg.ops[l]
+    lv = ops.level
+    ed = lv.element_dofs()
+    Be = element_divergence(lv)
+    Ge = np.abs(ops.gamma * np.einsum("pi,pq,qj->ij", Be, np.linalg.inv(element_pressure_mass(lv)[0]), Be))
+    xe = np.where(ed >= 0, np.abs(x)[np.maximum(ed, 0)], 0.0)
+    ye = xe @ Ge.T
+    out = np.zeros(lv.n_u)
+    keep = ed >= 0
+    np.add.at(out, ed[keep], ye[keep])
+    return out
+
+
+def abs_local(T, v):
+    """sum_K E_K^T |A_K^{-1}| E_K v for v >= 0 (coarse-cell interior blocks)."""
+    out = np.zeros_like(v)
+    nmax = 0
+    for idx, lu in zip(T.blocks, T.lus):
+        inv = sla.lu_solve(lu, np.eye(idx.size), check_finite=False)
+        out[idx] = np.abs(inv) @ v[idx]
+        nmax = max(nmax, idx.size)
+    return out, nmax
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_f32_transfers(name):
+    """FP32 robust prolongation and restriction against the FP64 oracle on
+    FP32-rounded inputs. Componentwise bound c eps32 X, with X the same
+    chain of operations applied to absolute values (|P_H|, sum_K |G_K|,
+    |A_K^{-1}|) and c = 2 (n_max + 16) for n_max-unknown local blocks."""
+    log(f"[f32 transfer] {name}")
+    orc, gpu = oracle_for(name), gpu_mixed_for(name)
+    wl = CASES[name]
+    for l in range(1, wl.levels):
+        fine, coarse = orc.mg.hier[l], orc.mg.hier[l - 1]
+        T = orc.mg.transfers[l]
+        absP = abs(T.P)
+        xc, xcs = rand_u(coarse, 140 + l)
+        xc32 = f32(xc)
+        xf = fine.from_stored(to_host(gpu.stk_prolong(l - 1, to_dev32(xcs))).astype(np.float64))
+        ref = T.prolong(xc32)
+        t = absP @ np.abs(xc32)
+        loc, nmax = abs_local(T, element_abs_G(orc, l, t))
+        X = t + loc
+        c = 2 * (nmax + 16)
+        w1 = np.max(np.abs(xf - ref) / np.maximum(c * EPS32 * X, 1e-300))
+        rf, rfs = rand_u(fine, 150 + l)
+        rf32 = f32(rf)
+        rc = coarse.from_stored(to_host(gpu.stk_restrict(l, to_dev32(rfs))).astype(np.float64))
+        ref = T.restrict(rf32)
+        s, _ = abs_local(T, np.abs(rf32))
+        X = absP.T @ (np.abs(rf32) + element_abs_G(orc, l, s))
+        w2 = np.max(np.abs(rc - ref) / np.maximum(c * EPS32 * X, 1e-300))
+        log(f"  level {l}: worst err/bound prolong {w1:.3f} restrict {w2:.3f}")
+        assert w1 <= 1.0 and w2 <= 1.0
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_f32_vcycle_unaffected_by_fp64_work(name):
+    """The FP32 V-cycle gives bit-identical results before and after FP64
+    work on the same hierarchy (the two forms share level buffers, so this
+    guards the buffers whose entries must stay zero)."""
+    log(f"[f32 vcycle state] {name}")
+    orc, gpu = oracle_for(name), gpu_mixed_for(name)
+    lv = orc.mg.hier[-1]
+    b, bs = rand_u(lv, 160)
+    b32 = to_dev32(bs)
+    v1 = to_host(gpu.stk_vcycle(b32))
+    bu, bp = gpu.stk_rhs()
+    gpu.stk_solve(bu, bp)
+    gpu.stk_vcycle(to_dev(bs))
+    v2 = to_host(gpu.stk_vcycle(b32))
+    assert np.isfinite(v1).all()
+    assert np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mixed_solve(name):
+    log(f"[mixed solve] {name}")
+    orc, g64, g32 = oracle_for(name), gpu_for(name), gpu_mixed_for(name)
+    wl = CASES[name]
+    lv = orc.mg.hier[-1]
+    bu, bp = g64.stk_rhs()
+    _, _, i64 = g64.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+    bu, bp = g32.stk_rhs()
+    # FP64 solve first on the mixed hierarchy, then the mixed form
+    g32.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+    xu, xp, info = g32.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, mixed=True)
+    log(f"  iterations fp64 {i64['iters']} mixed {info['iters']}; rel res {info['rel_res']:.2e}")
+    assert info["converged"] and info["rel_res"] <= wl.rtol
+    assert info["iters"] <= int(1.1 * i64["iters"]) + 2
+    x = np.concatenate([lv.from_stored(to_host(xu)), to_host(xp)])
+    b = orc.rhs()
+    assert np.linalg.norm(b - orc.K @ x) <= wl.rtol * np.linalg.norm(b)
+    # mixed and FP64 preconditioners on one hierarchy; graphs re-captured on switch
+    _, _, again = g32.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+    assert again["iters"] == i64["iters"]
+
+
+def test_f32_rejected_without_mixed_tables():
+    import torch
+    from paper_2107_00820_amd.stk import StkError
+    gpu = gpu_for("c1")
+    lv = oracle_for("c1").mg.hier[-1]
+    _, us = rand_u(lv, 1)
+    with pytest.raises(StkError):
+        gpu.stk_apply_Agamma(CASES["c1"].levels - 1, to_dev32(us))
+    bu, bp = gpu.stk_rhs()
+    with pytest.raises(StkError):
+        gpu.stk_solve(bu, bp, mixed=True)
+    torch.cuda.synchronize()
