@@ -62,14 +62,38 @@ typedef struct {
   double omega, delta, mu_min, mu_max, beta;
 } stk_sinker;
 
+/* Viscoplastic Newton tensor (Section 5.3.1; coef_kind = 1). Reading for the
+ * synthetic workload: the base field mu0 is the multi-sinker field of
+ * `sinker`, capped by the yield stress tau_y at the strain rate eps of a
+ * smooth Fourier velocity
+ *   u_c(x) = s sum_{m in {1..modes}^d} amp[c][m_1]..[m_d] / (1 + |m|^2)
+ *            prod_j sin(pi m_j x_j)
+ * (amp is a HOST array [d][modes]^d, C order, copied during setup):
+ *   eps_II = (eps:eps / 2)^(1/2),
+ *   mu_eff = mu_min + min(mu0 - mu_min, tau_y / (2 eps_II)),
+ *   C = 2 mu_eff I - 2 (mu_eff - mu_min) [yielded] n (x) n,  n = eps/|eps|_F,
+ * the exact derivative of tau(eps) = 2 mu_eff(eps_II) eps; yielded means
+ * tau_y / (2 eps_II) < mu0 - mu_min. C is stored per Gauss point as mu_eff
+ * and w = (2 (mu_eff - mu_min) [yielded])^(1/2) n, so C:e = 2 mu_eff e -
+ * (w:e) w. scale <= 0 asks the library to choose s so that the root mean
+ * square of eps_II over the finest level's Gauss points is 1. The Schur
+ * blocks use the scalar mu_eff. */
+typedef struct {
+  int modes;           /* 1..8 */
+  const double* amp;
+  double tau_y;        /* > 0 */
+  double scale;
+} stk_viscoplastic;
+
 typedef struct {
   int dim;            /* 2 or 3 */
   int n_fine;         /* cells per axis on the finest level, divisible by 2^(n_levels-1) */
   int n_levels;       /* >= 2 */
   double gamma;       /* augmented-Lagrangian parameter, >= 0 */
   int schur;          /* 1 = P1 (W = M_p), 2 = P2 (W = M_p(1/mu)); only 1 is built */
-  int coef_kind;      /* 0 = scalar sinker viscosity (only kind built) */
-  stk_sinker sinker;
+  int coef_kind;      /* 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor */
+  stk_sinker sinker;  /* the viscosity (coef_kind 0) or the base field mu0 (1); forcing in both */
+  stk_viscoplastic vp;  /* read for coef_kind 1 only */
   int nu_pre, nu_post;   /* right-preconditioned GMRES relaxation steps, 1..8 */
   int mixed;          /* 0 = FP64 form only; 1 = also keep FP32 copies of the
                          viscosity tables and packed patch inverses so that

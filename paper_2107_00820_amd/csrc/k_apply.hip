@@ -63,6 +63,177 @@ __global__ void k_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, 
 }
 
 // ---------------------------------------------------------------------------
+// Viscoplastic Newton tensor (Section 5.3.1; reading for the synthetic
+// workload): mu0 = sinker field, eps = strain rate of the Fourier velocity
+//   u_c = s sum_m amp[c][m] / (1 + |m|^2) prod_j sin(pi m_j x_j),  m in {1..M}^d,
+// eps_II = (eps:eps/2)^(1/2), mu_eff = mu_min + min(mu0 - mu_min, tau_y/(2 eps_II)),
+// C = 2 mu_eff I - w (x) w with w = (2 (mu_eff - mu_min) [yielded])^(1/2) eps/|eps|_F.
+
+// Gradient G[c][k] = d u_c / d x_k of the unscaled velocity (s = 1) at x,
+// by partial sums over the tensor-product modes (x_{d-1} innermost).
+template <int D>
+__device__ inline void fourier_grad(const double* __restrict__ amp, int M, const double x[D], double G[D][D]) {
+  constexpr double kPi = 3.141592653589793;
+  double sn[3][8], cs[3][8];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      double sv = 0.0, cv = 0.0;
+      if (m < M) sincospi((double)(m + 1) * x[j], &sv, &cv);
+      sn[j][m] = sv;
+      cs[j][m] = kPi * (double)(m + 1) * cv;
+    }
+  for (int c = 0; c < D; ++c) {
+    if constexpr (D == 3) {
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+      for (int m0 = 0; m0 < 8; ++m0) {
+        if (m0 >= M) break;
+        double qss = 0.0, qcs = 0.0, qsc = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 < 8; ++m1) {
+          if (m1 >= M) break;
+          double ps = 0.0, pc = 0.0;
+          const double* a = amp + ((int64_t)(c * M + m0) * M + m1) * M;
+#pragma unroll
+          for (int m2 = 0; m2 < 8; ++m2) {
+            if (m2 >= M) break;
+            const double msq = (double)((m0 + 1) * (m0 + 1) + (m1 + 1) * (m1 + 1) + (m2 + 1) * (m2 + 1));
+            const double av = a[m2] / (1.0 + msq);
+            ps += av * sn[2][m2];
+            pc += av * cs[2][m2];
+          }
+          qss += ps * sn[1][m1];
+          qcs += ps * cs[1][m1];
+          qsc += pc * sn[1][m1];
+        }
+        g0 += qss * cs[0][m0];
+        g1 += qcs * sn[0][m0];
+        g2 += qsc * sn[0][m0];
+      }
+      G[c][0] = g0;
+      G[c][1] = g1;
+      G[c][2] = g2;
+    } else {
+      double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+      for (int m0 = 0; m0 < 8; ++m0) {
+        if (m0 >= M) break;
+        double ps = 0.0, pc = 0.0;
+        const double* a = amp + (int64_t)(c * M + m0) * M;
+#pragma unroll
+        for (int m1 = 0; m1 < 8; ++m1) {
+          if (m1 >= M) break;
+          const double msq = (double)((m0 + 1) * (m0 + 1) + (m1 + 1) * (m1 + 1));
+          const double av = a[m1] / (1.0 + msq);
+          ps += av * sn[1][m1];
+          pc += av * cs[1][m1];
+        }
+        g0 += ps * cs[0][m0];
+        g1 += pc * sn[0][m0];
+      }
+      G[c][0] = g0;
+      G[c][1] = g1;
+    }
+  }
+}
+
+template <int D>
+__device__ inline void gauss_point(const LevelGeo& g, int64_t cell, int q, double x[D]) {
+  int c[3];
+  cell_coords<D>(g, cell, c);
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[k] = g.h * ((double)c[k] + kGaussX[digit(q, k)]);
+}
+
+// eps:eps of the unscaled strain rate (eps = sym G).
+template <int D>
+__device__ inline double strain_sq(const double G[D][D]) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double e = 0.5 * (G[a][b] + G[b][a]);
+      s += e * e;
+    }
+  return s;
+}
+
+// part[b] = sum of eps_II^2 = eps:eps / 2 (s = 1) over block b's Gauss points
+// of the finest level (fixed grid-stride partition).
+template <int D>
+__global__ void __launch_bounds__(kRedThreads) k_eps_partials(LevelGeo g, const double* __restrict__ amp, int M,
+                                                               double* __restrict__ part) {
+  constexpr int NQ = Dims<D>::NQ;
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  const int64_t n = (int64_t)NQ * g.ncell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cell = i / NQ;
+    double x[D], G[D][D];
+    gauss_point<D>(g, cell, (int)(i - cell * NQ), x);
+    fourier_grad<D>(amp, M, x, G);
+    acc += 0.5 * strain_sq<D>(G);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// mu_eff and w at the Gauss points of one level. The velocity scale is
+// `scale` if positive, else 1/sqrt(mean eps_II^2) from the fine-level
+// partial sums (reduced identically by every block).
+template <int D>
+__global__ void __launch_bounds__(kRedThreads)
+k_coef_tensor(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta, double mu_min,
+              double mu_max, const double* __restrict__ amp, int M, double tau_y, double scale,
+              const double* __restrict__ part, int nparts, int64_t nfine_pts, double* __restrict__ mu,
+              double* __restrict__ cw) {
+  constexpr int NQ = Dims<D>::NQ, NS = SymIdx<D>::NS;
+  __shared__ double s_sh;
+  if (threadIdx.x < 64) {
+    double sc = scale;
+    if (!(sc > 0.0)) {
+      const double tot = wave_reduce_parts(part, nparts, 1, 0);
+      sc = 1.0 / sqrt(tot / (double)nfine_pts);
+    }
+    if (threadIdx.x == 0) s_sh = sc;
+  }
+  __syncthreads();
+  const double sc = s_sh;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)NQ * g.ncell) return;
+  const int64_t cell = idx / NQ;
+  const int q = (int)(idx - cell * NQ);
+  double x[D], G[D][D];
+  gauss_point<D>(g, cell, q, x);
+  fourier_grad<D>(amp, M, x, G);
+  double eps[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) eps[a][b] = 0.5 * sc * (G[a][b] + G[b][a]);
+  double ee = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) ee += eps[a][b] * eps[a][b];
+  const double eii = sqrt(0.5 * ee);
+  const double mu0 = (mu_max - mu_min) * (1.0 - sinker_chi<D>(ctr, ns, omega, delta, x)) + mu_min;
+  const double cap = eii > 0.0 ? tau_y / (2.0 * eii) : INFINITY;
+  const bool yielded = cap < mu0 - mu_min;
+  const double meff = mu_min + fmin(mu0 - mu_min, cap);
+  const double nrm = sqrt(ee);
+  const double wscale = (yielded && nrm > 0.0) ? sqrt(2.0 * (meff - mu_min)) / nrm : 0.0;
+  mu[idx] = meff;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) cw[(cell * NS + SymIdx<D>::at(a, b)) * NQ + q] = wscale * eps[a][b];
+}
+
+// ---------------------------------------------------------------------------
 // Cell kernel. A wavefront handles CPW = floor(64 / 3^d) cells (7 in 2D, 2 in
 // 3D) with one lane per (cell, Gauss point) in the first phase and one lane
 // per (cell, node) in the second; the cell's velocity and the weighted stress
@@ -92,17 +263,9 @@ __device__ inline double selc(const double (&tab)[3][3], int r, int c) {
   return c == 0 ? tab[r][0] : (c == 1 ? tab[r][1] : tab[r][2]);
 }
 
-template <int D>
-struct SymIdx {
-  static constexpr int NS = D * (D + 1) / 2;
-  static constexpr int at(int a, int b) {
-    return a == b ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
-  }
-};
-
-template <int D, int MODE, class R>
+template <int D, int MODE, bool TENSOR, class R>
 __global__ void __launch_bounds__(64)
-k_elem(LevelGeo g, const R* __restrict__ mu, double gamma_d, const R* __restrict__ u,
+k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, double gamma_d, const R* __restrict__ u,
        const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
   constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
   constexpr int NS = SymIdx<D>::NS;
@@ -198,6 +361,22 @@ k_elem(LevelGeo g, const R* __restrict__ mu, double gamma_d, const R* __restrict
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) S[SymIdx<D>::at(a, b)] = wm * (G[a][b] + G[b][a]);
+      if constexpr (TENSOR) {
+        // C:eps = 2 mu eps - (w:eps) w, and w:eps = w:G for symmetric w
+        R wv[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wv[k] = cw[(cell * NS + k) * NQ + t];
+        R wg = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          wg += wv[a] * G[a][a];
+#pragma unroll
+          for (int b = a + 1; b < D; ++b) wg += wv[SymIdx<D>::at(a, b)] * (G[a][b] + G[b][a]);
+        }
+        const R f = wq * wg;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) S[k] -= f * wv[k];
+      }
     }
     if (MODE & (EL_AUG | EL_BOUT)) {
       R dv = 0;
@@ -498,12 +677,23 @@ template <>
 const double* level_mu<double>(const Level& l) { return l.mu; }
 template <>
 const float* level_mu<float>(const Level& l) { return l.mu32; }
+template <class R>
+static const R* level_cw(const Level& l);
+template <>
+const double* level_cw<double>(const Level& l) { return l.cw; }
+template <>
+const float* level_cw<float>(const Level& l) { return l.cw32; }
 
 template <int D, int MODE, class R>
 static void elem_launch(const Hier& H, const Level& l, const R* u, const double* p, double* pout, hipStream_t s) {
   constexpr int CPW = 64 / Dims<D>::NQ;
-  hipLaunchKernelGGL((k_elem<D, MODE, R>), dim3(nblk(l.g.ncell, CPW)), dim3(64), 0, s, l.g, level_mu<R>(l), H.gamma,
-                     u, p, reinterpret_cast<R*>(l.E), pout);
+  const dim3 grid(nblk(l.g.ncell, CPW));
+  if ((MODE & EL_VISC) && l.cw)
+    hipLaunchKernelGGL((k_elem<D, MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l),
+                       H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+  else
+    hipLaunchKernelGGL((k_elem<D, MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr,
+                       H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
 }
 
 template <int D, class R>
@@ -520,6 +710,31 @@ static void elem_dispatch(const Hier& H, const Level& l, int mode, const R* u, c
       }
       break;
   }
+}
+
+void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s) {
+  const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * fine.g.ncell;
+  const int np = red_parts(n);
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_eps_partials<2>, dim3(np), dim3(kRedThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
+                       H.partials);
+  else
+    hipLaunchKernelGGL(k_eps_partials<3>, dim3(np), dim3(kRedThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
+                       H.partials);
+}
+
+void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStream_t s) {
+  const int64_t nf = (int64_t)(H.dim == 2 ? 9 : 27) * fine.g.ncell;
+  const int np = red_parts(nf);
+  const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_coef_tensor<2>, dim3(nblk(n, kRedThreads)), dim3(kRedThreads), 0, s, l.g, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
+                       H.vp_scale, H.partials, np, nf, l.mu, l.cw);
+  else
+    hipLaunchKernelGGL(k_coef_tensor<3>, dim3(nblk(n, kRedThreads)), dim3(kRedThreads), 0, s, l.g, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
+                       H.vp_scale, H.partials, np, nf, l.mu, l.cw);
 }
 
 template <class R>

@@ -34,15 +34,15 @@ __device__ inline int interior_dof(const LevelGeo& g, int64_t i, int nd[3]) {
 }
 
 template <int D>
-__global__ void k_coarse_assemble(LevelGeo g, const double* __restrict__ mu, double gamma, int64_t n,
-                                  double* __restrict__ A) {
+__global__ void k_coarse_assemble(LevelGeo g, const double* __restrict__ mu, const double* __restrict__ cw,
+                                  double gamma, int64_t n, double* __restrict__ A) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx / n, j = idx - i * n;
   int ni[3], nj[3];
   const int ci = interior_dof<D>(g, i, ni);
   const int cj = interior_dof<D>(g, j, nj);
-  A[idx] = global_entry<D>(g, mu, gamma, ci, ni, cj, nj);
+  A[idx] = global_entry<D>(g, mu, cw, gamma, ci, ni, cj, nj);
 }
 
 // Pivot block inverse (single workgroup).
@@ -171,9 +171,9 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_t s) {
   const int64_t n = H.n0;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, H.gamma, n, A);
+    hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, n, A);
   else
-    hipLaunchKernelGGL(k_coarse_assemble<3>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, H.gamma, n, A);
+    hipLaunchKernelGGL(k_coarse_assemble<3>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, n, A);
 }
 
 // work needs kGJB*kGJB + 2*n*kGJB doubles.

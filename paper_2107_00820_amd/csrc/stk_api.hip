@@ -63,7 +63,14 @@ stk_status validate(const stk_desc* d) {
   if (n0 > 40000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve");
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
   if (d->schur != 1) return fail(STK_EINVAL, "only the P1 Schur approximation (schur=1) is built");
-  if (d->coef_kind != 0) return fail(STK_EINVAL, "only the scalar sinker viscosity (coef_kind=0) is built");
+  if (d->coef_kind != 0 && d->coef_kind != 1)
+    return fail(STK_EINVAL, "coef_kind must be 0 (sinker viscosity) or 1 (viscoplastic Newton tensor)");
+  if (d->coef_kind == 1) {
+    const stk_viscoplastic& v = d->vp;
+    if (v.modes < 1 || v.modes > 8 || !v.amp) return fail(STK_EINVAL, "vp.modes must be in [1, 8] with vp.amp set");
+    if (!(v.tau_y > 0.0) || !isfinite(v.tau_y)) return fail(STK_EINVAL, "vp.tau_y must be positive");
+    if (!isfinite(v.scale)) return fail(STK_EINVAL, "vp.scale must be finite");
+  }
   if (d->mixed != 0 && d->mixed != 1) return fail(STK_EINVAL, "mixed must be 0 (FP64 form) or 1 (mixed form)");
   if (d->nu_pre < 1 || d->nu_pre > kMaxNu || d->nu_post < 1 || d->nu_post > kMaxNu)
     return fail(STK_EINVAL, "nu_pre/nu_post must be in [1, 8]");
@@ -147,6 +154,11 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     L.npres = NP * L.g.ncell;
     STKCHK(alloc((size_t)NN * L.g.ncell * 8, (void**)&L.mu));
     if (d->mixed) STKCHK(alloc((size_t)NN * L.g.ncell * 4, (void**)&L.mu32));
+    if (d->coef_kind == 1) {
+      const int NS = D * (D + 1) / 2;
+      STKCHK(alloc((size_t)NS * NN * L.g.ncell * 8, (void**)&L.cw));
+      if (d->mixed) STKCHK(alloc((size_t)NS * NN * L.g.ncell * 4, (void**)&L.cw32));
+    }
     STKCHK(alloc((size_t)NL * L.g.ncell * 8, (void**)&L.E));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.b));
     STKCHK(alloc((size_t)L.nvel * 8, (void**)&L.x));
@@ -181,6 +193,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   STKCHK(alloc((size_t)2 * kPartialLen * 8, (void**)&H.partials));
   STKCHK(alloc(64, (void**)&H.flag));
   STKCHK(alloc((size_t)std::max(1, d->sinker.n) * D * 8, (void**)&H.centers));
+  if (d->coef_kind == 1) STKCHK(alloc((size_t)D * ipow(d->vp.modes, D) * 8, (void**)&H.vp_amp));
   // FGMRES storage for the default restart length 30
   const int m = 30;
   const int64_t nvec = Lf.nvel + Lf.npres;
@@ -236,11 +249,12 @@ void apply_A(Hier& H, int l, const R* x, R* y) {
   hipEvent_t ev = nullptr;
   prof_begin(H, H.stream, &ev);
   launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
-  // algorithmic bytes of the cell kernel: u, viscosity at Gauss points, element outputs
+  // algorithmic bytes of the cell kernel: u, coefficients at Gauss points, element outputs
   {
     const double nn = H.dim == 2 ? 9.0 : 27.0;   // Gauss points (= nodes) per cell
+    const double ncoef = L.cw ? 1.0 + H.dim * (H.dim + 1) / 2 : 1.0;   // mu [and w] per Gauss point
     prof_end(H, H.stream, PROF_ELEM, ev,
-             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (nn + H.dim * nn)));
+             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)));
   }
   launch_gather<R>(H, L, nullptr, 1.0, y, H.stream);
 }
@@ -483,6 +497,12 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   H.mu_min = desc->sinker.mu_min;
   H.mu_max = desc->sinker.mu_max;
   H.beta = desc->sinker.beta;
+  H.coef_kind = desc->coef_kind;
+  if (H.coef_kind == 1) {
+    H.vp_modes = desc->vp.modes;
+    H.vp_tau_y = desc->vp.tau_y;
+    H.vp_scale = desc->vp.scale;
+  }
   auto dev_alloc = [&](size_t b, void** p) -> stk_status {
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, std::max<size_t>(b, 8));
@@ -516,10 +536,16 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
       hipMemcpyAsync(H.centers, desc->sinker.centers, (size_t)desc->sinker.n * D * 8, hipMemcpyHostToDevice, s) !=
           hipSuccess)
     return bail(fail(STK_EDEVICE, "copy of sinker centres failed"));
+  if (H.coef_kind == 1 &&
+      hipMemcpyAsync(H.vp_amp, desc->vp.amp, (size_t)D * ipow(H.vp_modes, D) * 8, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return bail(fail(STK_EDEVICE, "copy of the Fourier amplitudes failed"));
   launch_fill_int(H.flag, 0, 16, s);
+  if (H.coef_kind == 1 && !(H.vp_scale > 0.0)) launch_eps_partials(H, H.lv[H.L - 1], s);
   for (int l = 0; l < H.L; ++l) {
     Level& L = H.lv[l];
-    launch_mu_sinker(H, L, s);
+    if (H.coef_kind == 1) launch_coef_tensor(H, L, H.lv[H.L - 1], s);
+    else launch_mu_sinker(H, L, s);
     launch_fill<double>(L.S, 0.0, L.nvel, s);
     if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
     launch_fill<double>(L.x, 0.0, L.nvel, s);
@@ -540,6 +566,8 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
     for (int l = 0; l < H.L; ++l) {
       Level& L = H.lv[l];
       launch_convert<double, float>(L.mu, L.mu32, (int64_t)(D == 2 ? 9 : 27) * L.g.ncell, s);
+      if (L.cw)
+        launch_convert<double, float>(L.cw, L.cw32, (int64_t)(D * (D + 1) / 2) * (D == 2 ? 9 : 27) * L.g.ncell, s);
       for (PatchClass& pc : L.cls)
         launch_convert<double, float>(pc.inv, pc.inv32, packed_doubles(pc.n, pc.count), s);
     }

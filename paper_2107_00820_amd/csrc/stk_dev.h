@@ -49,10 +49,13 @@ __device__ inline int patch_dof(int i, const int lo[3], const int ext[3], int nd
 // Contribution of cell `cell` to the (comp ci, local node na; comp cj, local
 // node nb) entry of A_gamma:  h^{d-2} [ sum_q w_q mu_q (delta_{ci,cj} grad phi_a .
 // grad phi_b + d_{cj} phi_a d_{ci} phi_b) + gamma sum_m Bhat_m,a Bhat_m,b / Mhat_m ].
+// With the tensor law (cw != NULL) each Gauss point also subtracts
+// w_q (w_ci,: . grad phi_a)(w_cj,: . grad phi_b), the (w:eps_i)(w:eps_j) part of
+// (C:eps_j):eps_i.
 template <int D>
-__device__ inline double cell_entry(const double* __restrict__ mu, int64_t ncell, int64_t cell, double h,
-                                    double gamma, int ci, int na, int cj, int nb) {
-  constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP;
+__device__ inline double cell_entry(const double* __restrict__ mu, const double* __restrict__ cw, int64_t ncell,
+                                    int64_t cell, double h, double gamma, int ci, int na, int cj, int nb) {
+  constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP, NS = SymIdx<D>::NS;
   const RefTab<D>& T = ctab<D>();
   double s = 0.0;
   for (int q = 0; q < NN; ++q) {
@@ -62,6 +65,15 @@ __device__ inline double cell_entry(const double* __restrict__ mu, int64_t ncell
       for (int k = 0; k < D; ++k) gg += T.dphi[q][na][k] * T.dphi[q][nb][k];
     }
     s += T.w[q] * mu[cell * NN + q] * gg;
+    if (cw) {
+      double wi = 0.0, wj = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        wi += cw[(cell * NS + SymIdx<D>::at(ci, k)) * NN + q] * T.dphi[q][na][k];
+        wj += cw[(cell * NS + SymIdx<D>::at(cj, k)) * NN + q] * T.dphi[q][nb][k];
+      }
+      s -= T.w[q] * wi * wj;
+    }
   }
   double al = 0.0;
 #pragma unroll
@@ -73,8 +85,8 @@ __device__ inline double cell_entry(const double* __restrict__ mu, int64_t ncell
 // Entry of A_gamma between (ci, node ni) and (cj, node nj): sum over the cells
 // that contain both nodes.
 template <int D>
-__device__ inline double global_entry(const LevelGeo& g, const double* __restrict__ mu, double gamma, int ci,
-                                      const int ni[3], int cj, const int nj[3]) {
+__device__ inline double global_entry(const LevelGeo& g, const double* __restrict__ mu, const double* __restrict__ cw,
+                                      double gamma, int ci, const int ni[3], int cj, const int nj[3]) {
   int clo[3], chi[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -94,7 +106,7 @@ __device__ inline double global_entry(const LevelGeo& g, const double* __restric
         const int64_t cell = cell_index<D>(g, c0, c1, c2);
         const int na = (ni[0] - 2 * c0) + 3 * (ni[1] - 2 * c1) + (D == 3 ? 9 * (ni[2] - 2 * c2) : 0);
         const int nb = (nj[0] - 2 * c0) + 3 * (nj[1] - 2 * c1) + (D == 3 ? 9 * (nj[2] - 2 * c2) : 0);
-        s += cell_entry<D>(mu, g.ncell, cell, g.h, gamma, ci, na, cj, nb);
+        s += cell_entry<D>(mu, cw, g.ncell, cell, g.h, gamma, ci, na, cj, nb);
       }
   return s;
 }

@@ -39,8 +39,12 @@ struct Level {
   int nvert = 0;               // (N+1)^d
   int64_t nvel = 0;            // d * nnodes
   int64_t npres = 0;           // (d+1) * ncell
-  double* mu = nullptr;        // [ncell][NQ] viscosity at Gauss points
+  double* mu = nullptr;        // [ncell][NQ] viscosity (mu_eff for the tensor law) at Gauss points
   float* mu32 = nullptr;       // FP32 copy (mixed form)
+  // tensor law only: w at the Gauss points, C:eps = 2 mu eps - (w:eps) w,
+  // [ncell][d(d+1)/2][NQ] (symmetric storage order of SymIdx)
+  double* cw = nullptr;
+  float* cw32 = nullptr;
   double* E = nullptr;         // [NL][ncell] element outputs
   // relaxation and transfer work vectors (stored layout)
   double *b = nullptr, *x = nullptr, *r = nullptr, *T = nullptr, *U = nullptr, *S = nullptr;
@@ -77,6 +81,11 @@ struct Hier {
   int n_sinkers = 0;
   double omega = 0.1, delta = 200.0, mu_min = 1.0, mu_max = 1.0, beta = 10.0;
   double* centers = nullptr;         // device [n][d]
+  // viscoplastic Newton tensor (coef_kind 1)
+  int coef_kind = 0;
+  int vp_modes = 0;
+  double* vp_amp = nullptr;          // device [d][modes^d]
+  double vp_tau_y = 0.0, vp_scale = 0.0;   // vp_scale <= 0: RMS of eps_II over fine Gauss points = 1
   std::vector<Level> lv;
   // coarse level
   int64_t n0 = 0;
@@ -112,6 +121,10 @@ void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes);
 
 // ---- kernel launchers (templated on dimension inside the .hip files) ----
 void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s);
+// Viscoplastic Newton tensor: partial sums of the unscaled eps_II^2 over the
+// finest level's Gauss points (into H.partials), then mu_eff and w per level.
+void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s);
+void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStream_t s);
 template <class R>
 void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const double* p, double* pout,
                  hipStream_t s);

@@ -41,6 +41,16 @@ struct Dims {
 
 constexpr int digit(int n, int k) { return k == 0 ? n % 3 : (k == 1 ? (n / 3) % 3 : n / 9); }
 
+// Storage index of entry (a, b) of a symmetric d x d tensor: the diagonal
+// first, then (0,1) [, (0,2), (1,2)].
+template <int D>
+struct SymIdx {
+  static constexpr int NS = D * (D + 1) / 2;
+  static constexpr int at(int a, int b) {
+    return a == b ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+  }
+};
+
 // Reference tables for dimension D.
 template <int D>
 struct RefTab {

@@ -35,10 +35,14 @@ class Sinker(C.Structure):
                 ("delta", C.c_double), ("mu_min", C.c_double), ("mu_max", C.c_double), ("beta", C.c_double)]
 
 
+class Viscoplastic(C.Structure):
+    _fields_ = [("modes", C.c_int), ("amp", C.POINTER(C.c_double)), ("tau_y", C.c_double), ("scale", C.c_double)]
+
+
 class Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_fine", C.c_int), ("n_levels", C.c_int), ("gamma", C.c_double),
-                ("schur", C.c_int), ("coef_kind", C.c_int), ("sinker", Sinker), ("nu_pre", C.c_int),
-                ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t)]
+                ("schur", C.c_int), ("coef_kind", C.c_int), ("sinker", Sinker), ("vp", Viscoplastic),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t)]
 
 
 class SolveOpts(C.Structure):
@@ -122,11 +126,21 @@ def _dptr(*ts):
 
 
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
-              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0):
+              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_scale=0.0):
+    """Descriptor; vp_amp (array [d][M]^d) selects the viscoplastic Newton
+    tensor over the sinker base field (coef_kind 1)."""
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
     d.schur, d.coef_kind, d.mixed = 1, 0, int(mixed)
+    if vp_amp is not None:
+        amp = np.ascontiguousarray(np.asarray(vp_amp, dtype=np.float64))
+        assert amp.ndim == dim + 1 and amp.shape[0] == dim and all(s == amp.shape[1] for s in amp.shape[1:])
+        d.coef_kind = 1
+        d.vp.modes = amp.shape[1]
+        d.vp.amp = amp.ctypes.data_as(C.POINTER(C.c_double))
+        d.vp.tau_y, d.vp.scale = float(vp_tau_y), float(vp_scale)
+        d._keep_amp = amp
     d.sinker.n = centers.shape[0]
     d.sinker.centers = centers.ctypes.data_as(C.POINTER(C.c_double))
     d.sinker.omega, d.sinker.delta, d.sinker.beta = omega, delta, beta
@@ -138,9 +152,13 @@ def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, 
 
 
 def desc_from_workload(wl, hbm_budget=0, mixed=0):
+    """Descriptor of a workload. For the viscoplastic workloads the yield
+    stress is 2 mu_max and the velocity scale is left to the library (root
+    mean square of eps_II over the finest Gauss points equal to 1)."""
     from workloads import OMEGA, DELTA, BETA
+    vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max) if wl.coef_kind == 1 else {}
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
-                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed)
+                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, **vp)
 
 
 def stk_footprint(desc: Desc) -> int:

@@ -57,3 +57,31 @@ def test_setup_rejects_budget_before_touching_the_device():
     st = stk.load().stk_setup_hierarchy(ctypes.byref(d), None, ctypes.byref(h))
     assert st == stk.STK_ENOMEM and not h.value
     assert b"exceeds budget" in stk.load().stk_last_error()
+
+
+def test_tensor_and_mixed_descriptors():
+    """The viscoplastic tensor adds mu_eff and w (d(d+1)/2 values) per Gauss
+    point on every level; the mixed form adds FP32 copies. Bad tensor
+    parameters are rejected on the host."""
+    from paper_2107_00820_amd import stk
+    wl = CONFIGS["c4"]
+    d_t = stk.desc_from_workload(wl)
+    assert d_t.coef_kind == 1 and d_t.vp.modes == wl.fourier_modes
+    d_s = stk.desc_from_workload(wl)
+    d_s.coef_kind = 0
+    gauss_pts = sum(27 * (wl.n_level(l) ** 3) for l in range(wl.levels))
+    assert stk.stk_footprint(d_t) - stk.stk_footprint(d_s) >= 6 * 8 * gauss_pts
+    d_m = stk.desc_from_workload(wl, mixed=1)
+    assert stk.stk_footprint(d_m) > stk.stk_footprint(d_t)
+    bad = stk.desc_from_workload(wl)
+    bad.vp.modes = 9
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(bad)
+    bad = stk.desc_from_workload(wl)
+    bad.vp.tau_y = 0.0
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(bad)
+    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad.mixed = 2
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(bad)

@@ -19,12 +19,12 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from gpu_common import (CASES, oracle_for, gpu_for, gpu_mixed_for, to_dev, to_dev32, to_host, rel, rand_u,
+from gpu_common import (CASES, SCALAR_CASES, oracle_for, gpu_for, gpu_mixed_for, to_dev, to_dev32, to_host, rel, rand_u,
                         f32, log)
 
 pytestmark = pytest.mark.gpu
 
-NAMES = list(CASES)
+NAMES = SCALAR_CASES
 EPS32 = float(np.finfo(np.float32).eps)
 
 
