@@ -9,7 +9,12 @@ mixed form (FP32 V-cycles inside FP64 FGMRES); `value` is the faster one and
 `forms` holds both. Setup is timed separately. Prints one JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--form both|fp64|mixed]
-                [--no-cpu-baseline]
+                [--no-cpu-baseline] [--serving N] [--budget-gb G]
+
+--serving N adds a `serving` object: the first N requests of the seeded
+Poisson stream (20 req/s, 2D 32^2..256^2 and 3D 8^3..32^3, contrasts 1e4..1e8)
+through the request loop (admission by HBM footprint, continuous batching),
+with whole-stream DoF/s and p50/p99 request latency.
 """
 from __future__ import annotations
 
@@ -56,6 +61,22 @@ def cpu_baseline(wl, iters_hint):
             "iters": info["iters"], "t_solve_s": info["t_solve"], "t_setup_s": t_setup}
 
 
+def serving_leg(n, budget_gb):
+    from workloads import serving_stream
+    from paper_2107_00820_amd.serve import Server
+    reqs = serving_stream(n)
+    log(f"[bench] serving {n} requests, budget {budget_gb} GB")
+    out = Server(hbm_budget=int(budget_gb * 2 ** 30), max_active=16).run(reqs)
+    res = out.pop("results")
+    out["iterations_mean"] = sum(r.iters for r in res) / max(len(res), 1)
+    out["unknowns_total"] = sum(r.unknowns for r in res if r.converged)
+    out["budget_gb"] = budget_gb
+    out["stream"] = f"serving_stream({n}, 20 Hz, seed 501)"
+    log(f"[bench] serving: {out['completed']}/{n} in {out['makespan_s']:.2f} s, "
+        f"p50 {out['latency_p50_ms']:.1f} ms p99 {out['latency_p99_ms']:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +85,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--form", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0)
+    ap.add_argument("--budget-gb", type=float, default=32.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -152,6 +175,8 @@ def main():
            "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
            "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res},
            "roofline": roofline}
+    if args.serving > 0:
+        out["serving"] = serving_leg(args.serving, args.budget_gb)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, r["iterations"])

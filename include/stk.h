@@ -211,6 +211,34 @@ typedef struct {
 stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
                      const stk_solve_opts* opts, stk_solve_info* info, void* stream);
 
+/* ---- Serving: resumable solves (continuous batching across requests) ----
+ * A solve is split into phases: one FGMRES Arnoldi step (two V-cycles, Schur
+ * blocks, Stokes apply, Gram-Schmidt), the true-residual check at the end of
+ * a cycle, and the final copy-out. Each phase's device work runs on the
+ * hierarchy's own stream and ends with a copy of the few numbers the host
+ * needs (Hessenberg column, norm partials) into pinned memory, so the phases
+ * of different hierarchies overlap on the device. The arithmetic is exactly
+ * that of stk_solve (which is built on the same phases), so a request's
+ * result does not depend on which other requests share the device.
+ *
+ * stk_solve_begin: checks, copies b, sets x = 0 and computes ||b|| (waits
+ * for `stream`'s pending work first; host-synchronous for ||b|| only). The
+ * buffers must stay valid until the solve is done. Returns STK_EBUSY if a
+ * solve is still in progress on h. */
+stk_status stk_solve_begin(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                           const stk_solve_opts* opts, void* stream);
+
+/* Advances each of the n hierarchies with a solve in progress by one phase:
+ * enqueues all n phases first, then waits for each and runs its host part.
+ * Entries that are idle or done are skipped. Returns the first error met
+ * (that solve is then done with that status); `stream` is unused. */
+stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream);
+
+/* STK_EBUSY while the solve runs; otherwise fills info and returns the
+ * solve's status (STK_OK, STK_ENOTCONV, STK_ENAN, ...). STK_EINVAL if no
+ * solve was started. */
+stk_status stk_poll(stk_hier* h, stk_solve_info* info);
+
 /* Kernel timing (tracing). stk_profile(h, 1) clears the records and starts
  * bracketing launches of the instrumented kernel families with HIP events on
  * the launch stream; stk_profile(h, 0) stops. stk_profile_read synchronises

@@ -620,6 +620,8 @@ stk_status stk_destroy(stk_hier* h) {
   (void)hipStreamSynchronize(h->H.stream);
   for (hipEvent_t e : h->H.prof.pool) (void)hipEventDestroy(e);
   drop_graphs(h->H);
+  if (h->H.sev) (void)hipEventDestroy(h->H.sev);
+  if (h->H.hpin) (void)hipHostFree(h->H.hpin);
   if (h->H.own) {
     (void)hipStreamSynchronize(h->H.own);
     (void)hipStreamDestroy(h->H.own);
@@ -748,9 +750,41 @@ stk_status stk_precond(stk_hier* h, int mixed, const double* v_u, const double* 
   return STK_OK;
 }
 
-stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
-                     const stk_solve_opts* opts, stk_solve_info* info, void* stream) {
-  GET_H(h);
+}  // extern "C"
+
+namespace {
+
+// Pinned host layout: Hessenberg copy [(kMaxRestart+1) x kMaxRestart], norm
+// partials [kRedBlocks], y [kMaxRestart].
+constexpr int kMaxRestart = 64;
+constexpr size_t kPinH = 0;
+constexpr size_t kPinPart = (size_t)(kMaxRestart + 1) * kMaxRestart;
+constexpr size_t kPinY = kPinPart + kRedBlocks;
+constexpr size_t kPinLen = kPinY + kMaxRestart;
+
+stk_status ensure_pinned(Hier& H) {
+  if (!H.hpin) {
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, kPinLen * 8, hipHostMallocDefault));
+    H.hpin = static_cast<double*>(p);
+  }
+  if (!H.sev) HIPCHK(hipEventCreateWithFlags(&H.sev, hipEventDisableTiming));
+  return STK_OK;
+}
+
+void sv_done(Hier& H, stk_status st) {
+  Hier::Solve& S = H.sv;
+  S.phase = Hier::SV_DONE;
+  S.status = st;
+  S.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
+}
+
+// Starts a solve: checks, copies b, x = 0, ||b|| (host-synchronous on the
+// hierarchy's stream, ordered after the caller's stream).
+stk_status sv_begin(Hier& H, hipStream_t caller, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                    const stk_solve_opts* opts) {
+  Hier::Solve& S = H.sv;
+  if (S.phase != Hier::SV_IDLE && S.phase != Hier::SV_DONE) return fail(STK_EBUSY, "a solve is in progress");
   if (!b_u || !x_u || !x_p) return fail(STK_EINVAL, "NULL buffer");
   double rtol = 1e-8;
   int m = 30, maxit = 300;
@@ -759,8 +793,11 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     m = opts->restart;
     maxit = opts->maxit;
   }
-  if (!(rtol > 0.0) || m < 1 || m > 64 || maxit < 1 || maxit > 1000)
+  if (!(rtol > 0.0) || m < 1 || m > kMaxRestart || maxit < 1 || maxit > 1000)
     return fail(STK_EINVAL, "bad solve options (rtol > 0, restart 1..64, maxit 1..1000)");
+  const bool mixed = opts && opts->mixed;
+  if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
+  STKCHK(ensure_pinned(H));
   Level& F = H.lv[H.L - 1];
   const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
   if (m > H.restart_alloc) {
@@ -778,132 +815,286 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
     H.restart_alloc = m;
     drop_graphs(H);
   }
-  const bool use_graphs = !(opts && opts->eager);
-  const bool mixed = opts && opts->mixed;
-  if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
-  const auto t0 = std::chrono::steady_clock::now();
-  // all solve work runs on the library's own stream (capturable), ordered
-  // after the caller's stream
-  hipStream_t caller = H.stream;
-  HIPCHK(hipStreamSynchronize(caller));
+  S = Hier::Solve{};
+  S.m = m;
+  S.maxit = maxit;
+  S.rtol = rtol;
+  S.mixed = mixed;
+  S.graphs = !(opts && opts->eager);
+  S.x_u = x_u;
+  S.x_p = x_p;
+  S.Hh.assign((size_t)(m + 1) * m, 0.0);
+  S.cs.assign(m, 0.0);
+  S.sn.assign(m, 0.0);
+  S.g.assign(m + 1, 0.0);
+  S.hist.assign(1, 1.0);
+  S.t0 = std::chrono::steady_clock::now();
+  // order the hierarchy's stream after the caller's work on b
+  HIPCHK(hipEventRecord(H.sev, caller));
+  HIPCHK(hipStreamWaitEvent(H.own, H.sev, 0));
   H.stream = H.own;
-  hipStream_t s = H.stream;
-  double* bvec = H.fr + nvec;          // contiguous copy of b
-  double* xvec = H.fw;                 // iterate x (contiguous)
-  double* rvec = H.fr;                 // residual / scratch
-
+  hipStream_t s = H.own;
+  double* bvec = H.fr + nvec;
+  double* xvec = H.fw;
+  double* rvec = H.fr;
   HIPCHK(hipMemcpyAsync(bvec, b_u, nu * 8, hipMemcpyDeviceToDevice, s));
   if (b_p) HIPCHK(hipMemcpyAsync(bvec + nu, b_p, np * 8, hipMemcpyDeviceToDevice, s));
   else launch_fill<double>(bvec + nu, 0.0, np, s);
   launch_fill<double>(xvec, 0.0, nvec, s);
-  double bnorm = 0.0;
-  STKCHK(device_norm(H, bvec, nvec, &bnorm));
-  stk_solve_info loc{};
-  stk_solve_info* inf = info ? info : &loc;
-  memset(inf, 0, sizeof(*inf));
-  inf->hist[0] = 1.0;
-  if (!isfinite(bnorm)) return fail(STK_ENAN, "right-hand side is not finite");
-  if (bnorm == 0.0) {
+  STKCHK(device_norm(H, bvec, nvec, &S.bnorm));
+  if (!isfinite(S.bnorm)) {
+    sv_done(H, STK_ENAN);
+    return fail(STK_ENAN, "right-hand side is not finite");
+  }
+  if (S.bnorm == 0.0) {
     launch_fill<double>(x_u, 0.0, nu, s);
     launch_fill<double>(x_p, 0.0, np, s);
-    inf->converged = 1;
     HIPCHK(hipStreamSynchronize(s));
+    S.converged = true;
+    sv_done(H, STK_OK);
     return STK_OK;
   }
   launch_copy(bvec, rvec, nvec, s);
-  double beta = bnorm;
-  int it = 0;
-  bool converged = false;
-  std::vector<double> Hd((size_t)(m + 1) * m), Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  while (true) {
-    launch_axpby<double>(1.0 / beta, rvec, 0.0, rvec, H.fV, nvec, s);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      if (!use_graphs) {
-        arnoldi_step(H, j, m, nu, nvec, mixed);
-      } else {
-        if (H.steps_m != m || H.steps_mixed != (int)mixed) {
-          drop_graphs(H);
-          H.steps.assign(m, nullptr);
-          H.steps_m = m;
-          H.steps_mixed = (int)mixed;
-        }
-        if (!H.steps[j]) {
-          const bool prof_on = H.prof.on;
-          H.prof.on = false;   // no event records inside captured graphs
-          hipGraph_t graph = nullptr;
-          HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-          arnoldi_step(H, j, m, nu, nvec, mixed);
-          const hipError_t ce = hipStreamEndCapture(s, &graph);
-          H.prof.on = prof_on;
-          if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-          hipGraphExec_t exec = nullptr;
-          const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(graph);
-          if (ie != hipSuccess) return fail(STK_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-          H.steps[j] = exec;
-        }
-        HIPCHK(hipGraphLaunch(H.steps[j], s));
+  S.beta = S.bnorm;
+  S.g[0] = S.beta;
+  S.j = 0;
+  S.phase = Hier::SV_ARNOLDI;
+  return STK_OK;
+}
+
+// Enqueues the device work of the current phase on the hierarchy's stream.
+stk_status sv_enqueue(Hier& H) {
+  Hier::Solve& S = H.sv;
+  H.stream = H.own;
+  hipStream_t s = H.own;
+  Level& F = H.lv[H.L - 1];
+  const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
+  const int m = S.m;
+  double* bvec = H.fr + nvec;
+  double* xvec = H.fw;
+  double* rvec = H.fr;
+  if (S.phase == Hier::SV_ARNOLDI) {
+    const int j = S.j;
+    if (j == 0) launch_axpby<double>(1.0 / S.beta, rvec, 0.0, rvec, H.fV, nvec, s);
+    if (!S.graphs) {
+      arnoldi_step(H, j, m, nu, nvec, S.mixed);
+    } else {
+      if (H.steps_m != m || H.steps_mixed != (int)S.mixed) {
+        drop_graphs(H);
+        H.steps.assign(m, nullptr);
+        H.steps_m = m;
+        H.steps_mixed = (int)S.mixed;
       }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(Hd.data(), H.fH, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j + 1; ++i) Hh[i * m + j] = Hd[i * m + j];
-      if (!isfinite(Hh[(j + 1) * m + j])) return fail(STK_ENAN, "non-finite value in the Arnoldi process");
-      for (int i = 0; i < j; ++i) {
-        const double a = Hh[i * m + j], c2 = Hh[(i + 1) * m + j];
-        Hh[i * m + j] = cs[i] * a + sn[i] * c2;
-        Hh[(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      if (!H.steps[j]) {
+        const bool prof_on = H.prof.on;
+        H.prof.on = false;   // no event records inside captured graphs
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        arnoldi_step(H, j, m, nu, nvec, S.mixed);
+        const hipError_t ce = hipStreamEndCapture(s, &graph);
+        H.prof.on = prof_on;
+        if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(STK_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        H.steps[j] = exec;
       }
-      double c = 1.0, sv = 0.0;
-      const double a = Hh[j * m + j], bb = Hh[(j + 1) * m + j];
-      if (bb != 0.0) {
-        const double r = hypot(a, bb);
-        c = a / r;
-        sv = bb / r;
-      }
-      cs[j] = c;
-      sn[j] = sv;
-      Hh[j * m + j] = c * a + sv * bb;
-      Hh[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sv * g[j];
-      g[j] = c * g[j];
-      ++it;
-      k = j + 1;
-      if (it <= 1000) inf->hist[it] = fabs(g[j + 1]) / bnorm;
-      if (fabs(g[j + 1]) <= rtol * bnorm || it >= maxit) break;
+      HIPCHK(hipGraphLaunch(H.steps[j], s));
     }
-    for (int i = k - 1; i >= 0; --i) {
-      double sacc = g[i];
-      for (int t = i + 1; t < k; ++t) sacc -= Hh[i * m + t] * y[t];
-      y[i] = sacc / Hh[i * m + i];
-    }
-    HIPCHK(hipMemcpyAsync(H.fy, y.data(), (size_t)k * 8, hipMemcpyHostToDevice, s));
-    launch_combine(H.fZ, nvec, k, H.fy, xvec, nvec, false, s);
-    // true residual r = b - K x
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(H.hpin + kPinH, H.fH, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToHost, s));
+  } else if (S.phase == Hier::SV_RESIDUAL) {
+    HIPCHK(hipMemcpyAsync(H.fy, H.hpin + kPinY, (size_t)S.k * 8, hipMemcpyHostToDevice, s));
+    launch_combine(H.fZ, nvec, S.k, H.fy, xvec, nvec, false, s);
+    // true residual r = b - K x and its norm partials
     stokes_apply(H, xvec, rvec);
     launch_axpby<double>(1.0, bvec, -1.0, rvec, rvec, nvec, s);
-    STKCHK(device_norm(H, rvec, nvec, &beta));
-    if (!isfinite(beta)) return fail(STK_ENAN, "non-finite residual");
-    if (beta <= rtol * bnorm) {
-      converged = true;
-      break;
-    }
-    if (it >= maxit) break;
+    launch_dots<double>(rvec, nvec, 1, rvec, nvec, H.partials, s);
+    HIPCHK(hipMemcpyAsync(H.hpin + kPinPart, H.partials, (size_t)red_parts(nvec) * 8, hipMemcpyDeviceToHost, s));
+  } else if (S.phase == Hier::SV_FINISH) {
+    launch_project_mean(H, F, xvec + nu, s);
+    HIPCHK(hipMemcpyAsync(S.x_u, xvec, nu * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(S.x_p, xvec + nu, np * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    return STK_OK;
   }
-  launch_project_mean(H, F, xvec + nu, s);
-  HIPCHK(hipMemcpyAsync(x_u, xvec, nu * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(x_p, xvec + nu, np * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
-  H.stream = caller;
-  inf->iters = it;
-  inf->converged = converged ? 1 : 0;
-  inf->rel_res = beta / bnorm;
-  inf->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (!converged) return fail(STK_ENOTCONV, "FGMRES reached maxit");
+  HIPCHK(hipEventRecord(H.sev, s));
   return STK_OK;
+}
+
+// Waits for the current phase and runs its host part (Givens rotations,
+// stopping tests), moving to the next phase.
+stk_status sv_advance(Hier& H) {
+  Hier::Solve& S = H.sv;
+  if (S.phase == Hier::SV_IDLE || S.phase == Hier::SV_DONE) return STK_OK;
+  HIPCHK(hipEventSynchronize(H.sev));
+  Level& F = H.lv[H.L - 1];
+  const int64_t nvec = F.nvel + F.npres;
+  const int m = S.m;
+  std::vector<double>& Hh = S.Hh;
+  if (S.phase == Hier::SV_ARNOLDI) {
+    const int j = S.j;
+    const double* Hd = H.hpin + kPinH;
+    for (int i = 0; i <= j + 1; ++i) Hh[i * m + j] = Hd[i * m + j];
+    if (!isfinite(Hh[(j + 1) * m + j])) {
+      sv_done(H, STK_ENAN);
+      return fail(STK_ENAN, "non-finite value in the Arnoldi process");
+    }
+    for (int i = 0; i < j; ++i) {
+      const double a = Hh[i * m + j], c2 = Hh[(i + 1) * m + j];
+      Hh[i * m + j] = S.cs[i] * a + S.sn[i] * c2;
+      Hh[(i + 1) * m + j] = -S.sn[i] * a + S.cs[i] * c2;
+    }
+    double c = 1.0, sv = 0.0;
+    const double a = Hh[j * m + j], bb = Hh[(j + 1) * m + j];
+    if (bb != 0.0) {
+      const double r = hypot(a, bb);
+      c = a / r;
+      sv = bb / r;
+    }
+    S.cs[j] = c;
+    S.sn[j] = sv;
+    Hh[j * m + j] = c * a + sv * bb;
+    Hh[(j + 1) * m + j] = 0.0;
+    S.g[j + 1] = -sv * S.g[j];
+    S.g[j] = c * S.g[j];
+    ++S.it;
+    S.hist.push_back(fabs(S.g[j + 1]) / S.bnorm);
+    if (fabs(S.g[j + 1]) <= S.rtol * S.bnorm || S.it >= S.maxit || j + 1 == m) {
+      // end of the cycle: y from the triangular system, then the true residual
+      const int k = j + 1;
+      double* y = H.hpin + kPinY;
+      for (int i = k - 1; i >= 0; --i) {
+        double sacc = S.g[i];
+        for (int t = i + 1; t < k; ++t) sacc -= Hh[i * m + t] * y[t];
+        y[i] = sacc / Hh[i * m + i];
+      }
+      S.k = k;
+      S.phase = Hier::SV_RESIDUAL;
+    } else {
+      S.j = j + 1;
+    }
+  } else if (S.phase == Hier::SV_RESIDUAL) {
+    const int np = red_parts(nvec);
+    double sacc = 0.0;
+    for (int b = 0; b < np; ++b) sacc += H.hpin[kPinPart + b];
+    S.beta = sqrt(sacc);
+    if (!isfinite(S.beta)) {
+      sv_done(H, STK_ENAN);
+      return fail(STK_ENAN, "non-finite residual");
+    }
+    if (S.beta <= S.rtol * S.bnorm) {
+      S.converged = true;
+      S.phase = Hier::SV_FINISH;
+    } else if (S.it >= S.maxit) {
+      S.phase = Hier::SV_FINISH;
+    } else {
+      std::fill(S.g.begin(), S.g.end(), 0.0);
+      S.g[0] = S.beta;
+      S.j = 0;
+      S.phase = Hier::SV_ARNOLDI;
+    }
+  } else if (S.phase == Hier::SV_FINISH) {
+    sv_done(H, S.converged ? STK_OK : STK_ENOTCONV);
+  }
+  return STK_OK;
+}
+
+void sv_info(const Hier& H, stk_solve_info* inf) {
+  if (!inf) return;
+  const Hier::Solve& S = H.sv;
+  memset(inf, 0, sizeof(*inf));
+  inf->iters = S.it;
+  inf->converged = S.converged ? 1 : 0;
+  inf->rel_res = S.bnorm > 0.0 ? S.beta / S.bnorm : 0.0;
+  inf->t_solve_s = S.t_solve;
+  const size_t nh = std::min<size_t>(S.hist.size(), 1001);
+  for (size_t i = 0; i < nh; ++i) inf->hist[i] = S.hist[i];
+  if (S.hist.empty()) inf->hist[0] = 1.0;
+}
+
+stk_status sv_final(Hier& H) {
+  if (H.sv.status == STK_ENOTCONV) return fail(STK_ENOTCONV, "FGMRES reached maxit");
+  if (H.sv.status == STK_ENAN) return fail(STK_ENAN, "non-finite value in the solve");
+  return (stk_status)H.sv.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                     const stk_solve_opts* opts, stk_solve_info* info, void* stream) {
+  GET_H(h);
+  hipStream_t caller = H.stream;
+  const stk_status st0 = sv_begin(H, caller, b_u, b_p, x_u, x_p, opts);
+  if (st0 != STK_OK) {
+    if (H.sv.phase == Hier::SV_DONE) sv_info(H, info);
+    H.stream = caller;
+    return st0;
+  }
+  while (H.sv.phase != Hier::SV_DONE) {
+    stk_status st = sv_enqueue(H);
+    if (st == STK_OK) st = sv_advance(H);
+    if (st != STK_OK) {
+      if (H.sv.phase != Hier::SV_DONE) sv_done(H, st);
+      (void)hipStreamSynchronize(H.own);
+      sv_info(H, info);
+      H.stream = caller;
+      return st;
+    }
+  }
+  sv_info(H, info);
+  H.stream = caller;
+  return sv_final(H);
+}
+
+stk_status stk_solve_begin(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
+                           const stk_solve_opts* opts, void* stream) {
+  GET_H(h);
+  hipStream_t caller = H.stream;
+  const stk_status st = sv_begin(H, caller, b_u, b_p, x_u, x_p, opts);
+  H.stream = caller;
+  return st;
+}
+
+stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream) {
+  if (n < 0 || (n > 0 && !hs)) return fail(STK_EINVAL, "bad hierarchy list");
+  (void)stream;
+  stk_status first = STK_OK;
+  // enqueue every solve's next phase first so their device work overlaps,
+  // then wait for each and run the host part
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(STK_EINVAL, "NULL hierarchy in the list");
+    Hier& H = hs[i]->H;
+    const int ph = H.sv.phase;
+    if (ph == Hier::SV_IDLE || ph == Hier::SV_DONE) continue;
+    const stk_status st = sv_enqueue(H);
+    if (st != STK_OK) {
+      sv_done(H, st);
+      if (first == STK_OK) first = st;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    Hier& H = hs[i]->H;
+    const stk_status st = sv_advance(H);
+    if (st != STK_OK) {
+      if (H.sv.phase != Hier::SV_DONE) sv_done(H, st);
+      if (first == STK_OK) first = st;
+    }
+  }
+  return first;
+}
+
+stk_status stk_poll(stk_hier* h, stk_solve_info* info) {
+  if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
+  Hier& H = h->H;
+  const int ph = H.sv.phase;
+  if (ph == Hier::SV_IDLE) return fail(STK_EINVAL, "no solve was started");
+  if (ph != Hier::SV_DONE) return STK_EBUSY;
+  sv_info(H, info);
+  return sv_final(H);
 }
 
 }  // extern "C"

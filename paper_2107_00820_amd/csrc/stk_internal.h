@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -113,6 +114,23 @@ struct Hier {
   // mixed form: FP32 copies exist; fine-level FP32 V-cycle input/output
   int mixed = 0;
   double *mb = nullptr, *mx = nullptr;
+  // Resumable FGMRES: the solve advances in phases (Arnoldi step, residual
+  // check after a cycle, final copy-out); each phase's device work is
+  // enqueued on `own`, ends in a copy of the few numbers the host needs into
+  // pinned memory and an event, so several solves can have work in flight.
+  enum Phase : int { SV_IDLE = 0, SV_ARNOLDI = 1, SV_RESIDUAL = 2, SV_FINISH = 3, SV_DONE = 4 };
+  struct Solve {
+    int phase = SV_IDLE;
+    int status = 0;
+    int m = 30, maxit = 300, j = 0, k = 0, it = 0;
+    bool mixed = false, graphs = true, converged = false;
+    double rtol = 1e-8, bnorm = 0.0, beta = 0.0, t_solve = 0.0;
+    double *x_u = nullptr, *x_p = nullptr;
+    std::vector<double> Hh, cs, sn, g, hist;
+    std::chrono::steady_clock::time_point t0;
+  } sv;
+  double* hpin = nullptr;          // pinned host: Hessenberg copy, norm partials, y
+  hipEvent_t sev = nullptr;        // end of the last enqueued phase
 };
 
 // Event bracketing of one launch (no-ops unless H.prof.on).

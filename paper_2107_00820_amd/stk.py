@@ -84,6 +84,9 @@ def load(path: str = LIB_PATH):
         "stk_vcycle": [vp, i32, vp, vp, vp],
         "stk_precond": [vp, i32, vp, vp, vp, vp, vp],
         "stk_solve": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp],
+        "stk_solve_begin": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp],
+        "stk_step_batch": [C.POINTER(vp), i32, vp],
+        "stk_poll": [vp, C.POINTER(SolveInfo)],
         "stk_profile": [vp, i32],
         "stk_profile_read": [vp, i32, i64p, dp, dp],
     }
@@ -159,6 +162,12 @@ def desc_from_workload(wl, hbm_budget=0, mixed=0):
     vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max) if wl.coef_kind == 1 else {}
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
                      OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, **vp)
+
+
+def stk_step_batch(hierarchies) -> int:
+    """One phase of every listed hierarchy's solve (their device work overlaps)."""
+    arr = (C.c_void_p * len(hierarchies))(*[h._h.value for h in hierarchies])
+    return _check(load().stk_step_batch(arr, len(hierarchies), None), allow=(STK_ENOTCONV, STK_ENAN))
 
 
 def stk_footprint(desc: Desc) -> int:
@@ -264,6 +273,29 @@ class Hierarchy:
         zp = self.zeros_p() if zp is None else zp
         _check(load().stk_precond(self._h, 1 if mixed else 0, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
         return zu, zp
+
+    # ---- serving (resumable solves)
+    def stk_solve_begin(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, eager=False,
+                        mixed=False):
+        """Starts a solve; the returned output tensors are filled once
+        stk_poll reports completion."""
+        xu = self.zeros_u() if xu is None else xu
+        xp = self.zeros_p() if xp is None else xp
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0)
+        self._solve_refs = (bu, bp, xu, xp)        # keep the buffers alive while the solve runs
+        _check(load().stk_solve_begin(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu),
+                                      _ptr(xp), C.byref(opts), _stream()))
+        return xu, xp
+
+    def stk_poll(self):
+        """None while running, else the info dict (status included)."""
+        info = SolveInfo()
+        st = load().stk_poll(self._h, C.byref(info))
+        if st == STK_EBUSY:
+            return None
+        _check(st, allow=(STK_ENOTCONV, STK_ENAN))
+        return dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
+                    t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
 
     def stk_profile(self, enable: bool):
         _check(load().stk_profile(self._h, 1 if enable else 0))

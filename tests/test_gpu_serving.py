@@ -1,0 +1,65 @@
+"""Serving loop on the GPU: requests that arrive while others run are
+admitted as memory and slots free up, their solves overlap on the device, and
+every result is bit-identical to the same request solved alone (the
+resumable solve runs the same kernels in the same order on each hierarchy;
+no state is shared between requests)."""
+import numpy as np
+import pytest
+
+from workloads import small
+from gpu_common import log
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    # mixed 2D/3D sizes and contrasts, arriving 5 ms apart (so that they overlap)
+    specs = [
+        (2, 32, 2, 1e3, 1e6, 1),
+        (3, 8, 2, 1e4, 1e8, 2),
+        (2, 64, 3, 1e3, 1e4, 3),
+        (2, 16, 2, 1e3, 1e6, 4),
+        (3, 16, 2, 1e4, 1e5, 5),
+        (2, 32, 2, 1e3, 1e8, 6),
+    ]
+    return [(0.005 * k, small(d, n, L, gamma=g, dr=dr, n_sinkers=24, seed=10 ** 6 + s))
+            for k, (d, n, L, g, dr, s) in enumerate(specs)]
+
+
+def test_mix_equals_alone_and_overlaps():
+    import torch
+    from paper_2107_00820_amd import Hierarchy
+    from paper_2107_00820_amd.serve import Server
+    reqs = _requests()
+    log("[serving] mix of 6 requests")
+    out = Server(hbm_budget=8 << 30, max_active=4, keep_solutions=True).run(reqs)
+    assert out["completed"] == len(reqs), [r.error for r in out["results"]]
+    assert out["peak_active"] >= 2            # solves were in flight together
+    for r in out["results"]:
+        wl = reqs[r.index][1]
+        h = Hierarchy.from_workload(wl)
+        bu, bp = h.stk_rhs()
+        xu, xp, info = h.stk_solve(bu, bp)
+        torch.cuda.synchronize()
+        log(f"  {wl.name}: mix {r.iters} it, alone {info['iters']} it")
+        assert info["iters"] == r.iters
+        assert np.array_equal(xu.cpu().numpy(), r.solution[0])
+        assert np.array_equal(xp.cpu().numpy(), r.solution[1])
+        h.close()
+
+
+def test_admission_respects_budget():
+    """With a budget that holds one request at a time, requests are served
+    one after another and the peak footprint never exceeds the budget; a
+    request larger than the budget is rejected without touching the device."""
+    from paper_2107_00820_amd import desc_from_workload, stk_footprint
+    from paper_2107_00820_amd.serve import Server
+    reqs = _requests()[:3]
+    fps = [stk_footprint(desc_from_workload(w)) for _, w in reqs]
+    budget = max(fps) + 1
+    out = Server(hbm_budget=budget, max_active=4).run(reqs)
+    assert out["completed"] == 3
+    assert out["peak_footprint_bytes"] <= budget
+    big = [(0.0, small(3, 32, 3, gamma=1e4, dr=1e4, n_sinkers=24, seed=9))]
+    out = Server(hbm_budget=budget, max_active=4).run(big)
+    assert out["completed"] == 0 and out["results"][0].error
