@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Stokes DoF solved/s to rel.res 1e-8 (FP64 vs mixed); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+PROF_REPS = 10      # back-to-back repetitions per timed launch (excludes launch gaps)
 
 
 def log(msg):
@@ -59,6 +61,26 @@ def cpu_baseline(wl, iters_hint):
             "sample": f"full oracle FGMRES solve of {wl.name} ({info['iters']} iterations, "
                       f"{info['t_solve']:.1f} s solve, {t_setup:.1f} s setup excluded), 1 thread",
             "iters": info["iters"], "t_solve_s": info["t_solve"], "t_setup_s": t_setup}
+
+
+def measured_traffic(wl, form):
+    """HBM bytes per k_asm_gemv launch from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy
+    kernel factor), or None when there is none or the kernels have changed
+    since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{wl.name}.json")
+    if not os.path.exists(p):
+        return None, "no counter summary for this workload"
+    with open(p) as f:
+        t = json.load(f)
+    from paper_2107_00820_amd.profiling import kernel_source_hash
+    if t.get("source_hash") != kernel_source_hash():
+        return None, "kernels changed since the counters were taken"
+    r = "float" if form == "mixed" else "double"
+    for k, v in t["kernels"].items():
+        if re.search(rf"k_asm_gemv<{wl.dim}, {r}>", k):
+            return v["traffic_bytes_per_launch"], os.path.relpath(p, ROOT)
+    return None, "kernel not in the counter summary"
 
 
 def serving_leg(n, budget_gb):
@@ -139,8 +161,9 @@ def main():
         t_total = time.perf_counter() - t0
         log(f"[bench] {form}: {args.steps} solves in {t_total:.3f} s, iterations {iters}")
         # kernel durations: one more solve with plain launches bracketed by HIP
-        # events on the launch stream (graph replays cannot be bracketed per kernel)
-        h.stk_profile(True)
+        # events on the launch stream (graph replays cannot be bracketed per
+        # kernel); each timed launch is repeated back to back inside its bracket
+        h.stk_profile(True, reps=PROF_REPS)
         h.stk_solve(bu, bp, eager=True, **kw)
         prof = {k: h.stk_profile_read(k) for k in (0, 1)}
         h.stk_profile(False)
@@ -156,9 +179,10 @@ def main():
     n_gemv, ms_gemv, by_gemv = r["prof"][0]
     n_elem, ms_elem, by_elem = r["prof"][1]
     ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
+    traffic, traffic_src = measured_traffic(wl, best)
     roofline = {"bound": "hbm", "kernel": "k_asm_gemv (interior star patches, all levels)",
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "form": best, "launches": n_gemv,
+                "traffic": traffic, "traffic_source": traffic_src, "form": best, "launches": n_gemv,
                 "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
                 "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
                 "time_share_of_solve": (ms_gemv * 1e-3) / (r["t_total"] / args.steps),

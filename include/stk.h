@@ -239,9 +239,12 @@ stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream);
  * solve was started. */
 stk_status stk_poll(stk_hier* h, stk_solve_info* info);
 
-/* Kernel timing (tracing). stk_profile(h, 1) clears the records and starts
- * bracketing launches of the instrumented kernel families with HIP events on
- * the launch stream; stk_profile(h, 0) stops. stk_profile_read synchronises
+/* Kernel timing (tracing). stk_profile(h, r), 1 <= r <= 100, clears the
+ * records and starts bracketing launches of the instrumented kernel families
+ * with HIP events on the launch stream; each instrumented launch is issued r
+ * times back to back inside its bracket (both families are pure functions of
+ * their inputs, so results are unchanged), which keeps event and launch
+ * latency out of the per-launch average. stk_profile(h, 0) stops. stk_profile_read synchronises
  * the stream and returns, for family `kernel`, the number of launches, their
  * summed duration in ms and the summed algorithmic bytes:
  *   kernel 0: batched star-patch solve of the interior patches (all levels);

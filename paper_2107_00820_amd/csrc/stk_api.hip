@@ -247,14 +247,15 @@ template <class R>
 void apply_A(Hier& H, int l, const R* x, R* y) {
   Level& L = H.lv[l];
   hipEvent_t ev = nullptr;
-  prof_begin(H, H.stream, &ev);
-  launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  const int reps = prof_begin(H, H.stream, &ev);
+  // pure function of x -> element buffer: a profiled call may repeat it
+  for (int k = 0; k < reps; ++k) launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
   // algorithmic bytes of the cell kernel: u, coefficients at Gauss points, element outputs
   {
     const double nn = H.dim == 2 ? 9.0 : 27.0;   // Gauss points (= nodes) per cell
     const double ncoef = L.cw ? 1.0 + H.dim * (H.dim + 1) / 2 : 1.0;   // mu [and w] per Gauss point
     prof_end(H, H.stream, PROF_ELEM, ev,
-             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)));
+             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)), reps);
   }
   launch_gather<R>(H, L, nullptr, 1.0, y, H.stream);
 }
@@ -432,25 +433,26 @@ stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
 
 namespace stk {
 
-void prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev) {
+int prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev) {
   *ev = nullptr;
-  if (!H.prof.on) return;
+  if (!H.prof.on) return 1;
   Prof& P = H.prof;
   while (P.pool.size() < P.used + 2) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreate(&e) != hipSuccess) return 1;
     P.pool.push_back(e);
   }
   *ev = P.pool[P.used++];
   (void)hipEventRecord(*ev, s);
+  return P.reps;
 }
 
-void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes) {
+void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes, int reps) {
   if (!H.prof.on || !a) return;
   Prof& P = H.prof;
   hipEvent_t b = P.pool[P.used++];
   (void)hipEventRecord(b, s);
-  P.recs.push_back(Prof::Rec{id, a, b, bytes});
+  P.recs.push_back(Prof::Rec{id, a, b, bytes * reps, reps});
 }
 
 }  // namespace stk
@@ -588,7 +590,9 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
 stk_status stk_profile(stk_hier* h, int enable) {
   if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
   Prof& P = h->H.prof;
+  if (enable < 0 || enable > 100) return fail(STK_EINVAL, "enable must be in [0, 100]");
   P.on = enable != 0;
+  P.reps = enable > 0 ? enable : 1;
   P.recs.clear();
   P.used = 0;
   return STK_OK;
@@ -605,7 +609,7 @@ stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* 
     if (r.id != kernel) continue;
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
-    ++n;
+    n += r.n;
     ms += t;
     by += r.bytes;
   }

@@ -66,10 +66,12 @@ struct Level {
 enum ProfId : int { PROF_ASM_GEMV = 0, PROF_ELEM = 1, PROF_NIDS = 2 };
 struct Prof {
   bool on = false;
+  int reps = 1;            // back-to-back repetitions of a profiled launch
   struct Rec {
     int id;
     hipEvent_t a, b;
-    double bytes;
+    double bytes;          // algorithmic bytes of all repetitions
+    int n;                 // launches between a and b
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -134,8 +136,9 @@ struct Hier {
 };
 
 // Event bracketing of one launch (no-ops unless H.prof.on).
-void prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev);
-void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes);
+// prof_begin returns how many times the caller issues the launch (1 unless profiling).
+int prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev);
+void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes, int reps);
 
 // ---- kernel launchers (templated on dimension inside the .hip files) ----
 void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s);

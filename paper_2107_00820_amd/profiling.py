@@ -1,0 +1,153 @@
+"""Profiling helpers around rocprofv3 (measurement tooling, not on the solve path).
+
+  python -m paper_2107_00820_amd.profiling copy [--mib 1024] [--reps 3]
+      a plain device-to-device copy of known size (the calibration kernel of
+      the HBM traffic counters).
+  python -m paper_2107_00820_amd.profiling stats DIR OUT.md --title T --cmd C
+      summarises the kernel trace CSV that `rocprofv3 --kernel-trace --stats
+      --output-format csv -d DIR` wrote.
+  python -m paper_2107_00820_amd.profiling traffic --fetch D1 --write D2 --copy-fetch D3
+      --copy-write D4 --copy-bytes N --kernel REGEX --out OUT.json --cmd C
+      per-launch FETCH_SIZE / WRITE_SIZE of the kernels matching REGEX (from
+      two `--pmc` runs), with the factor measured on the copy kernel
+      (known bytes / counted bytes), keyed by the exact kernel name and stamped
+      with a hash of the kernel sources so a changed kernel invalidates it.
+
+The counters are in KiB per dispatch summed over the TCC channels.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    """Hash of the kernel and host sources (a change invalidates stored counters)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise SystemExit(f"no {pattern} under {d}")
+    return hits
+
+
+def _short(name: str) -> str:
+    return name.replace("void ", "").split("(")[0].strip()
+
+
+def cmd_copy(args):
+    import torch
+    n = args.mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": args.reps}))
+
+
+def cmd_stats(args):
+    rows = []
+    for p in _find(args.dir, "*kernel_trace.csv"):
+        with open(p) as f:
+            rows += list(csv.DictReader(f))
+    byname = collections.defaultdict(list)
+    for r in rows:
+        byname[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    tot = sum(sum(v) for v in byname.values())
+    out = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+           f"Total kernel time {tot / 1e6:.3f} ms over {len(rows)} dispatches.", "",
+           "| kernel | calls | total us | avg us | share |", "|---|---:|---:|---:|---:|"]
+    for k in sorted(byname, key=lambda k: -sum(byname[k]))[:30]:
+        v = byname[k]
+        out.append(f"| `{k}` | {len(v)} | {sum(v) / 1e3:.1f} | {sum(v) / len(v) / 1e3:.2f} | "
+                   f"{100 * sum(v) / max(tot, 1):.1f}% |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out[:24]))
+
+
+def _counter(d, counter, regex):
+    """{kernel name: [KiB per dispatch]} for one counter."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    for p in _find(d, "*counter_collection.csv"):
+        with open(p) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter or not re.search(regex, r["Kernel_Name"]):
+                    continue
+                acc[_short(r["Kernel_Name"])][r.get("Dispatch_Id") or r.get("Correlation_Id")] += \
+                    float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def cmd_traffic(args):
+    cf = _counter(args.copy_fetch, "FETCH_SIZE", args.copy_regex)
+    cw = _counter(args.copy_write, "WRITE_SIZE", args.copy_regex)
+    # the copy kernel: the dispatches with the largest counts
+    cfv = max((v for vs in cf.values() for v in vs), default=0.0)
+    cwv = max((v for vs in cw.values() for v in vs), default=0.0)
+    if cfv <= 0 or cwv <= 0:
+        raise SystemExit("copy kernel counters not found")
+    f_fetch = args.copy_bytes / (cfv * 1024.0)
+    f_write = args.copy_bytes / (cwv * 1024.0)
+    kf = _counter(args.fetch, "FETCH_SIZE", args.kernel)
+    kw = _counter(args.write, "WRITE_SIZE", args.kernel)
+    kernels = {}
+    for k in sorted(set(kf) | set(kw)):
+        fv, wv = kf.get(k, []), kw.get(k, [])
+        kernels[k] = {
+            "launches_fetch_run": len(fv), "launches_write_run": len(wv),
+            "fetch_bytes_per_launch": (sum(fv) / len(fv)) * 1024.0 * f_fetch if fv else None,
+            "write_bytes_per_launch": (sum(wv) / len(wv)) * 1024.0 * f_write if wv else None,
+        }
+        kernels[k]["traffic_bytes_per_launch"] = (
+            (kernels[k]["fetch_bytes_per_launch"] or 0.0) + (kernels[k]["write_bytes_per_launch"] or 0.0))
+    out = {"command": args.cmd, "workload": args.workload, "source_hash": kernel_source_hash(),
+           "copy_bytes": args.copy_bytes, "copy_fetch_kib": cfv, "copy_write_kib": cwv,
+           "factor_fetch": f_fetch, "factor_write": f_write, "kernels": kernels}
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    a = sub.add_parser("copy")
+    a.add_argument("--mib", type=int, default=1024)
+    a.add_argument("--reps", type=int, default=3)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("out")
+    a.add_argument("--title", default="rocprofv3 kernel summary")
+    a.add_argument("--cmd", default="")
+    a = sub.add_parser("traffic")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
+        a.add_argument(k, required=True)
+    a.add_argument("--copy-bytes", type=float, required=True)
+    a.add_argument("--copy-regex", default="copy|elementwise|Copy")
+    a.add_argument("--kernel", default="k_asm_gemv")
+    a.add_argument("--workload", default="")
+    a.add_argument("--cmd", default="")
+    args = ap.parse_args(argv)
+    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd_name](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -297,8 +297,10 @@ class Hierarchy:
         return dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
                     t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
 
-    def stk_profile(self, enable: bool):
-        _check(load().stk_profile(self._h, 1 if enable else 0))
+    def stk_profile(self, enable, reps: int = 1):
+        """Start (enable) or stop kernel timing; each instrumented launch is
+        repeated `reps` times inside its event bracket."""
+        _check(load().stk_profile(self._h, int(reps) if enable else 0))
 
     def stk_profile_read(self, kernel: int):
         n, ms, by = C.c_int64(), C.c_double(), C.c_double()
