@@ -1,22 +1,32 @@
-// Coarsest level: dense A_0,gamma over the interior unknowns, its explicit
-// inverse by blocked in-place Gauss-Jordan elimination, and the solve as one
-// dense GEMV. The paper solves the coarsest level with a sparse direct solver
-// (Section 5.1); the coarse systems here (<= ~10^4 unknowns) fit HBM as dense
-// matrices, and an explicit inverse turns every coarse solve into one fully
-// parallel, coalesced pass instead of two sequential triangular sweeps.
+// Coarsest level: A_0,gamma over the interior unknowns, its explicit inverse
+// by a blocked symmetric sweep, and the solve as one symmetric tile GEMV.
+// The paper solves the coarsest level with a sparse direct solver (Section
+// 5.1); the coarse systems here (<= ~4*10^4 unknowns) fit HBM as dense
+// symmetric matrices, and an explicit inverse turns every coarse solve into
+// one fully parallel, coalesced pass instead of two sequential triangular
+// sweeps.
 //
-// Block Gauss-Jordan step on pivot block k (P = A_kk, SPD for an SPD matrix):
-//   A_kk <- P^{-1};  A_kj <- P^{-1} A_kj;  A_ik <- -A_ik P^{-1};
-//   A_ij <- A_ij - A_ik P^{-1} A_kj          (i, j outside block k).
-// After all blocks the array holds A^{-1}. With R' = [P^{-1} A_k,: whose pivot
-// columns are replaced by P^{-1}] and C = A_:,k (old), every step is
-//   rows i in k:      A_i,: = R'_{i-k0},:
-//   other rows:       A_ij = (j in k ? 0 : A_ij) - C_i,: R'_:,j
+// Storage: the lower triangle in 64 x 64 tiles, tile (I, J), J <= I, at
+// index I(I+1)/2 + J, row-major inside the tile; diagonal tiles hold both
+// triangles. Unknowns beyond n (padding of the last tile) carry an identity
+// block, which the sweep keeps and the solve ignores.
+//
+// Sweep of pivot block K (symmetric Gauss-Jordan; after all blocks the array
+// holds -A^{-1}): with P = A_KK and C_I = A_IK (old),
+//   A_KK <- -P^{-1};  A_IK <- C_I P^{-1};  A_IJ <- A_IJ - C_I P^{-1} C_J^T,
+// for I, J != K. P stays SPD (a Schur complement of an SPD matrix). The
+// rank-64 updates are 64 x 64 x 64 tile products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64); the pivot inverse is a Cholesky-based inversion
+// in LDS.
 #include "stk_dev.h"
 
 namespace stk {
 
-constexpr int kGJB = 32;   // pivot block width
+constexpr int kT = 64;           // tile width
+constexpr int kTT = kT * kT;
+constexpr int kLd = kT + 1;      // LDS row stride (doubles)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Interior unknown i (component-major over the (2N-1)^d interior nodes) ->
 // (component, node coordinates).
@@ -34,171 +44,289 @@ __device__ inline int interior_dof(const LevelGeo& g, int64_t i, int nd[3]) {
 }
 
 template <int D>
-__global__ void k_coarse_assemble(LevelGeo g, const double* __restrict__ mu, const double* __restrict__ cw,
-                                  double gamma, int64_t n, double* __restrict__ A) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  const int64_t i = idx / n, j = idx - i * n;
-  int ni[3], nj[3];
-  const int ci = interior_dof<D>(g, i, ni);
-  const int cj = interior_dof<D>(g, j, nj);
-  A[idx] = global_entry<D>(g, mu, cw, gamma, ci, ni, cj, nj);
+__device__ inline int64_t interior_stored(const LevelGeo& g, int64_t i) {
+  int nd[3];
+  const int c = interior_dof<D>(g, i, nd);
+  return c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2]);
 }
 
-// Pivot block inverse (single workgroup).
-__global__ void k_gj_pivot(double* __restrict__ A, int64_t n, int64_t k0, int nb, double* __restrict__ Pinv,
-                           int* __restrict__ flag) {
-  __shared__ double a[kGJB * (kGJB + 1)];
-  __shared__ double tmp[kGJB];
-  __shared__ int bad;
-  const int ld = nb + 1;
-  if (threadIdx.x == 0) bad = 0;
-  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-    const int i = t / nb, j = t % nb;
-    a[i * ld + j] = A[(k0 + i) * n + k0 + j];
+// Tile t of the lower triangle -> (I, J).
+__device__ inline void tile_ij(int64_t t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
+  while ((int64_t)i * (i + 1) / 2 > t) --i;
+  I = i;
+  J = (int)(t - (int64_t)i * (i + 1) / 2);
+}
+
+__device__ inline const double* tile_ptr(const double* A, int I, int J) {
+  return A + ((int64_t)I * (I + 1) / 2 + J) * kTT;
+}
+__device__ inline double* tile_ptr(double* A, int I, int J) {
+  return A + ((int64_t)I * (I + 1) / 2 + J) * kTT;
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const double* __restrict__ mu,
+                                                          const double* __restrict__ cw, double gamma, int64_t n,
+                                                          int64_t ntiles, double* __restrict__ A) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= ntiles * kTT) return;
+  const int64_t t = idx / kTT;
+  const int e = (int)(idx - t * kTT);
+  int I, J;
+  tile_ij(t, I, J);
+  const int64_t i = (int64_t)I * kT + e / kT, j = (int64_t)J * kT + e % kT;
+  double v;
+  if (i < n && j < n) {
+    int ni[3], nj[3];
+    const int ci = interior_dof<D>(g, i, ni);
+    const int cj = interior_dof<D>(g, j, nj);
+    v = global_entry<D>(g, mu, cw, gamma, ci, ni, cj, nj);
+  } else {
+    v = i == j ? 1.0 : 0.0;
   }
+  A[idx] = v;
+}
+
+// Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64).
+__global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
+                                                      double* __restrict__ Pinv, int* __restrict__ flag) {
+  __shared__ double a[kT * kLd];
+  __shared__ double tmp[kT];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  const double* T = tile_ptr(A, K, K);
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) a[(e / kT) * kLd + e % kT] = T[e];
   __syncthreads();
-  spd_invert_lds(a, nb, ld, tmp, &bad);
+  spd_invert_lds(a, kT, kLd, tmp, &bad);
   __syncthreads();
-  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-    const int i = t / nb, j = t % nb;
-    Pinv[i * nb + j] = i >= j ? a[i * ld + j] : a[j * ld + i];
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) {
+    const int r = e / kT, c = e % kT;
+    Pinv[e] = r >= c ? a[r * kLd + c] : a[c * kLd + r];
   }
   if (threadIdx.x == 0 && bad) *flag = 1;
 }
 
-// R'[t][j] and C[i][t].
-__global__ void k_gj_panels(const double* __restrict__ A, int64_t n, int64_t k0, int nb,
-                            const double* __restrict__ Pinv, double* __restrict__ R, double* __restrict__ C) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n * nb) return;
-  {
-    const int t = (int)(idx / n);
-    const int64_t j = idx - (int64_t)t * n;
-    double v;
-    if (j >= k0 && j < k0 + nb) {
-      v = Pinv[t * nb + (j - k0)];
-    } else {
-      v = 0.0;
-      for (int s = 0; s < nb; ++s) v += Pinv[t * nb + s] * A[(k0 + s) * n + j];
-    }
-    R[t * n + j] = v;
-  }
-  {
-    const int64_t i = idx / nb;
-    const int t = (int)(idx - i * nb);
-    C[i * nb + t] = A[i * n + k0 + t];
+// Stage block C_I = A_IK (I != K) into LDS as X[r][k] (row stride kLd).
+__device__ inline void stage_panel(const double* __restrict__ A, int I, int K, double* X) {
+  if (I > K) {
+    const double* T = tile_ptr(A, I, K);
+    for (int e = threadIdx.x; e < kTT; e += blockDim.x) X[(e / kT) * kLd + e % kT] = T[e];
+  } else {
+    const double* T = tile_ptr(A, K, I);   // A_IK = (A_KI)^T
+    for (int e = threadIdx.x; e < kTT; e += blockDim.x) X[(e % kT) * kLd + e / kT] = T[e];
   }
 }
 
-// Tiled update: 64x64 outputs per workgroup of 256 threads, 4x4 per thread.
-__global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ A, int64_t n, int64_t k0, int nb,
-                                                    const double* __restrict__ R, const double* __restrict__ C) {
-  __shared__ double Ct[64][kGJB + 1];
-  __shared__ double Rt[kGJB][64 + 1];
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int t = threadIdx.x; t < 64 * nb; t += 256) {
-    const int r = t / nb, c = t % nb;
-    const int64_t gi = i0 + r;
-    Ct[r][c] = gi < n ? C[gi * nb + c] : 0.0;
+__device__ inline void stage_full(const double* __restrict__ T, double* X) {
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) X[(e / kT) * kLd + e % kT] = T[e];
+}
+
+// acc = X Y^T over 64 x 64 x 64 with four wavefronts; wavefront w owns the
+// 32 x 32 quadrant (rows 32(w/2).., cols 32(w%2)..) as 2 x 2 MFMA 16 x 16
+// blocks. Operands (v_mfma_f64_16x16x4f64): lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; result register r of lane l is D[l/16 + 4r][l%16].
+__device__ inline void tile_gemm_xyt(const double* X, const double* Y, d4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kT; k0 += 4) {
+    const int k = k0 + lk;
+    const double a0 = X[(rb + li) * kLd + k], a1 = X[(rb + 16 + li) * kLd + k];
+    const double b0 = Y[(cb + li) * kLd + k], b1 = Y[(cb + 16 + li) * kLd + k];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
-  for (int t = threadIdx.x; t < nb * 64; t += 256) {
-    const int r = t / 64, c = t % 64;
-    const int64_t gj = j0 + c;
-    Rt[r][c] = gj < n ? R[(int64_t)r * n + gj] : 0.0;
+}
+
+// Output element of register r in block (a, b) for this lane: (row, col).
+__device__ inline void acc_rc(int a, int b, int r, int& row, int& col) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  row = 32 * (w >> 1) + 16 * a + (lane >> 4) + 4 * r;
+  col = 32 * (w & 1) + 16 * b + (lane & 15);
+}
+
+// W_I = C_I P^{-1} for every I != K (grid: one workgroup per block row).
+__global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ A, int K,
+                                                      const double* __restrict__ Pinv, double* __restrict__ W) {
+  __shared__ double X[kT * kLd];
+  __shared__ double Y[kT * kLd];
+  const int I = blockIdx.x;
+  if (I == K) return;
+  stage_panel(A, I, K, X);
+  stage_full(Pinv, Y);       // P^{-1} is symmetric, so X P^{-1} = X (P^{-1})^T
+  __syncthreads();
+  d4 acc[2][2];
+  tile_gemm_xyt(X, Y, acc);
+  double* out = W + (int64_t)I * kTT;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_rc(a, b, r, row, col);
+        out[row * kT + col] = acc[a][b][r];
+      }
+}
+
+// A_IJ -= W_I C_J^T for every lower tile with I, J != K.
+__global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
+  __shared__ double X[kT * kLd];
+  __shared__ double Y[kT * kLd];
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  if (I == K || J == K) return;
+  stage_full(W + (int64_t)I * kTT, X);
+  stage_panel(A, J, K, Y);
+  __syncthreads();
+  d4 acc[2][2];
+  tile_gemm_xyt(X, Y, acc);
+  double* T = tile_ptr(A, I, J);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_rc(a, b, r, row, col);
+        T[row * kT + col] -= acc[a][b][r];
+      }
+}
+
+// A_IK <- W_I (tile (I,K) for I > K, tile (K,I) = W_I^T for I < K); A_KK <- -P^{-1}.
+__global__ void __launch_bounds__(256) k_sweep_write(double* __restrict__ A, int K, const double* __restrict__ Pinv,
+                                                      const double* __restrict__ W) {
+  const int I = blockIdx.x;
+  if (I == K) {
+    double* T = tile_ptr(A, K, K);
+    for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = -Pinv[e];
+  } else if (I > K) {
+    double* T = tile_ptr(A, I, K);
+    const double* S = W + (int64_t)I * kTT;
+    for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = S[e];
+  } else {
+    double* T = tile_ptr(A, K, I);
+    const double* S = W + (int64_t)I * kTT;
+    for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = S[(e % kT) * kT + e / kT];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve x = A^{-1} b = -(stored) b.
+// bc[i] = b at interior unknown i (0 in the padding).
+template <int D, class R>
+__global__ void k_coarse_gather(LevelGeo g, int64_t n, int64_t npad, const R* __restrict__ b,
+                                double* __restrict__ bc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  bc[i] = i < n ? (double)b[interior_stored<D>(g, i)] : 0.0;
+}
+
+// One workgroup per stored tile (I, J): part[I][J] = T x_J and, below the
+// diagonal, part[J][I] = T^T x_I (each slot written exactly once).
+__global__ void __launch_bounds__(256) k_coarse_tile_gemv(const double* __restrict__ A, int nb,
+                                                           const double* __restrict__ bc,
+                                                           double* __restrict__ part) {
+  __shared__ double Ts[kT * kLd];
+  __shared__ double xj[kT], xi[kT];
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  const double* T = tile_ptr(A, I, J);
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) Ts[(e / kT) * kLd + e % kT] = T[e];
+  if (threadIdx.x < kT) {
+    xj[threadIdx.x] = bc[(int64_t)J * kT + threadIdx.x];
+    xi[threadIdx.x] = bc[(int64_t)I * kT + threadIdx.x];
   }
   __syncthreads();
-  double acc[4][4];
+  const int q = threadIdx.x & 3, r = threadIdx.x >> 2;   // 4 threads per row / column
+  double u = 0.0, v = 0.0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int t = 0; t < nb; ++t) {
-    double cv[4], rv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) cv[a] = Ct[ty + 16 * a][t];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) rv[b] = Rt[t][tx + 16 * b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += cv[a] * rv[b];
+  for (int k = 0; k < 16; ++k) {
+    const int c = q * 16 + k;
+    u += Ts[r * kLd + c] * xj[c];
+    v += Ts[c * kLd + r] * xi[c];
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t i = i0 + ty + 16 * a;
-    if (i >= n) continue;
-    const bool prow = i >= k0 && i < k0 + nb;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t j = j0 + tx + 16 * b;
-      if (j >= n) continue;
-      if (prow) {
-        A[i * n + j] = R[(i - k0) * n + j];
-      } else {
-        const bool pcol = j >= k0 && j < k0 + nb;
-        const double old = pcol ? 0.0 : A[i * n + j];
-        A[i * n + j] = old - acc[a][b];
-      }
-    }
+  u += __shfl_xor(u, 1, 64);
+  u += __shfl_xor(u, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  if (q == 0) {
+    part[((int64_t)I * nb + J) * kT + r] = u;
+    if (I != J) part[((int64_t)J * nb + I) * kT + r] = v;
   }
 }
 
-// x = Ainv b on interior unknowns: one wavefront per row.
+// x at interior unknown i = -sum_J part[I][J][r] (fixed order); Dirichlet
+// entries are zeroed beforehand.
 template <int D, class R>
-__global__ void __launch_bounds__(256) k_coarse_gemv(LevelGeo g, const double* __restrict__ Ainv, int64_t n,
-                                                      const R* __restrict__ b, R* __restrict__ x) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
+__global__ void k_coarse_reduce(LevelGeo g, int64_t n, int nb, const double* __restrict__ part,
+                                R* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t I = i / kT;
+  const int r = (int)(i - I * kT);
   double s = 0.0;
-  for (int64_t j = lane; j < n; j += 64) {
-    int nd[3];
-    const int c = interior_dof<D>(g, j, nd);
-    s += Ainv[row * n + j] * (double)b[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])];
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) {
-    int nd[3];
-    const int c = interior_dof<D>(g, row, nd);
-    x[c * g.nnodes + node_index<D>(g, nd[0], nd[1], nd[2])] = (R)s;
-  }
+  for (int J = 0; J < nb; ++J) s += part[(I * nb + J) * kT + r];
+  x[interior_stored<D>(g, i)] = (R)(-s);
 }
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+int coarse_tiles(int64_t n) { return (int)((n + kT - 1) / kT); }
+
 void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_t s) {
-  const int64_t n = H.n0;
+  const int64_t nb = coarse_tiles(H.n0);
+  const int64_t ntiles = nb * (nb + 1) / 2;
+  const dim3 grid(nblk(ntiles * kTT, 256));
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, n, A);
+    hipLaunchKernelGGL(k_coarse_assemble<2>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, H.n0, ntiles, A);
   else
-    hipLaunchKernelGGL(k_coarse_assemble<3>, dim3(nblk(n * n, 256)), dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, n, A);
+    hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, H.n0, ntiles, A);
 }
 
-// work needs kGJB*kGJB + 2*n*kGJB doubles.
+// work: P^{-1} (kTT) + W (nb * kTT) doubles.
 int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s) {
+  const int nb = coarse_tiles(n);
+  const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
   double* Pinv = work;
-  double* R = work + kGJB * kGJB;
-  double* C = R + (int64_t)kGJB * n;
-  for (int64_t k0 = 0; k0 < n; k0 += kGJB) {
-    const int nb = (int)((n - k0) < kGJB ? (n - k0) : kGJB);
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, H.flag);
-    hipLaunchKernelGGL(k_gj_panels, dim3(nblk(n * nb, 256)), dim3(256), 0, s, A, n, k0, nb, Pinv, R, C);
-    const unsigned t = nblk(n, 64);
-    hipLaunchKernelGGL(k_gj_update, dim3(t, t), dim3(256), 0, s, A, n, k0, nb, R, C);
+  double* W = work + kTT;
+  for (int K = 0; K < nb; ++K) {
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, H.flag);
+    hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
+    hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, W);
+    hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
   }
   return 0;
 }
 
 // The coarse solve is FP64 in both forms; R only selects the vector storage.
+// H.cvec holds bc (nb*64 doubles), H.cpart the tile partials (nb*nb*64).
 template <class R>
 void launch_coarse_apply(const Hier& H, const Level& l, const R* b, R* x, hipStream_t s) {
+  const int nb = coarse_tiles(H.n0);
+  const int64_t npad = (int64_t)nb * kT, ntiles = (int64_t)nb * (nb + 1) / 2;
   launch_fill<R>(x, 0.0, (int64_t)H.dim * l.g.nnodes, s);
   if (H.dim == 2)
-    hipLaunchKernelGGL((k_coarse_gemv<2, R>), dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
+    hipLaunchKernelGGL((k_coarse_gather<2, R>), dim3(nblk(npad, 256)), dim3(256), 0, s, l.g, H.n0, npad, b, H.cvec);
   else
-    hipLaunchKernelGGL((k_coarse_gemv<3, R>), dim3(nblk(H.n0, 4)), dim3(256), 0, s, l.g, H.Ainv0, H.n0, b, x);
+    hipLaunchKernelGGL((k_coarse_gather<3, R>), dim3(nblk(npad, 256)), dim3(256), 0, s, l.g, H.n0, npad, b, H.cvec);
+  hipLaunchKernelGGL(k_coarse_tile_gemv, dim3((unsigned)ntiles), dim3(256), 0, s, H.Ainv0, nb, H.cvec, H.cpart);
+  if (H.dim == 2)
+    hipLaunchKernelGGL((k_coarse_reduce<2, R>), dim3(nblk(H.n0, 256)), dim3(256), 0, s, l.g, H.n0, nb, H.cpart, x);
+  else
+    hipLaunchKernelGGL((k_coarse_reduce<3, R>), dim3(nblk(H.n0, 256)), dim3(256), 0, s, l.g, H.n0, nb, H.cpart, x);
 }
 
 template void launch_coarse_apply<double>(const Hier&, const Level&, const double*, double*, hipStream_t);

@@ -186,8 +186,13 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   }
   const Level& L0 = H.lv[0];
   H.n0 = (int64_t)D * ipow(2 * L0.g.N - 1, D);
-  STKCHK(alloc((size_t)(H.n0 * H.n0) * 8, (void**)&H.Ainv0));
-  STKCHK(alloc((size_t)(32 * 32 + 2 * 32 * H.n0) * 8, (void**)&H.cwork));
+  {
+    const size_t nb = (size_t)coarse_tiles(H.n0);
+    STKCHK(alloc(nb * (nb + 1) / 2 * 4096 * 8, (void**)&H.Ainv0));
+    STKCHK(alloc((nb + 1) * 4096 * 8, (void**)&H.cwork));
+    STKCHK(alloc(nb * 64 * 8, (void**)&H.cvec));
+    STKCHK(alloc(nb * nb * 64 * 8, (void**)&H.cpart));
+  }
   const Level& Lf = H.lv[H.L - 1];
   STKCHK(alloc((size_t)Lf.g.ncell * NP * NP * 8, (void**)&H.Sinv));
   STKCHK(alloc((size_t)2 * kPartialLen * 8, (void**)&H.partials));

@@ -92,9 +92,10 @@ struct Hier {
   std::vector<Level> lv;
   // coarse level
   int64_t n0 = 0;
-  double* Ainv0 = nullptr;           // [n0][n0]
-  double* cwork = nullptr;           // GJ panels
-  double* cvec = nullptr;            // compact coarse vectors (2*n0)
+  double* Ainv0 = nullptr;           // -A_0^{-1}, lower triangle in 64 x 64 tiles
+  double* cwork = nullptr;           // sweep work: pivot inverse + panel
+  double* cvec = nullptr;            // gathered coarse right-hand side (64 * tiles)
+  double* cpart = nullptr;           // tile GEMV partials (tiles^2 * 64)
   // finest-level Schur blocks and pressure work
   double* Sinv = nullptr;            // [ncell][(d+1)^2]
   double* partials = nullptr;        // kRedBlocks * 64
@@ -169,6 +170,7 @@ void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, c
 template <class R>
 void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const R* rf, R* rc, hipStream_t s);
 
+int coarse_tiles(int64_t n);       // 64-wide tiles per row of the coarse matrix
 void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_t s);
 int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s);
 template <class R>
