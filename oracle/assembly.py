@@ -36,14 +36,17 @@ def basis_strain(level: Level):
     return 0.5 * (grad + np.swapaxes(grad, -1, -2)), grad
 
 
-def element_viscous(level: Level, coef) -> np.ndarray:
-    """Element matrices (n_cells, nl, nl) of a(u, v) = (sigma(u), eps(v))."""
+def element_viscous(level: Level, coef, cells=None) -> np.ndarray:
+    """Element matrices (n_cells, nl, nl) of a(u, v) = (sigma(u), eps(v));
+    only those of `cells` (an index array) if given."""
     d = level.dim
     xi, w, phi, dphi = reference_tables(d)
     eps, _ = basis_strain(level)
     nq, nl = eps.shape[0], eps.shape[1]
     vol = level.h ** d
     x = level.quad_points()
+    if cells is not None:
+        x = x[cells]
     E = eps.reshape(nq, nl, d * d)
     if coef.kind == "scalar":
         mu = coef.mu(x)                                            # (nc, nq)
@@ -51,8 +54,8 @@ def element_viscous(level: Level, coef) -> np.ndarray:
         P = np.einsum("qix,qjx->qij", E, E).reshape(nq, nl * nl)
         Ae = (2.0 * mu * (w * vol)[None, :]) @ P
         return Ae.reshape(-1, nl, nl)
-    C = coef.stress_tensor(x).reshape(level.n_cells, nq, d * d, d * d)
-    Ae = np.zeros((level.n_cells, nl, nl))
+    C = coef.stress_tensor(x).reshape(x.shape[0], nq, d * d, d * d)
+    Ae = np.zeros((x.shape[0], nl, nl))
     for q in range(nq):
         CE = np.einsum("kxy,jy->kxj", C[:, q], E[q])              # C : eps_j
         Ae += (w[q] * vol) * np.einsum("ix,kxj->kij", E[q], CE)
@@ -156,3 +159,54 @@ class Operators:
         """Remove the constant-pressure component so that int p = 0 (Q_h in L^2_0)."""
         m = self.p_mass_const
         return p - (m @ p) / (m @ self.p_const) * self.p_const
+
+
+def stokes_rows(level: Level, coef, gamma: float, u: np.ndarray, p: np.ndarray, vel_rows, pres_cells):
+    """Selected entries of K [u; p], K = [[A_gamma, B^T], [B, 0]] (W = M_p),
+    summed from the element matrices of only the cells those entries touch:
+    the same entries as the assembled operators of `Operators`, for spot
+    checks on meshes too large to assemble. Returns (velocity entries at
+    `vel_rows`, pressure entries of the cells `pres_cells` as (len, d+1))."""
+    vel_rows = np.asarray(vel_rows)
+    pres_cells = np.asarray(pres_cells)
+    ed = level.element_dofs()
+    pd = pressure_dofs(level)
+    cells = np.unique(np.concatenate([np.nonzero(np.isin(ed, vel_rows).any(axis=1))[0], pres_cells]))
+    Ae = element_viscous(level, coef, cells)
+    Be = element_divergence(level)
+    Winv = np.linalg.inv(element_pressure_mass(level)[0])
+    Ke = Ae + gamma * (Be.T @ Winv @ Be)[None]
+    ue = np.where(ed[cells] >= 0, u[np.maximum(ed[cells], 0)], 0.0)
+    pe = p[pd[cells]]
+    ye = np.einsum("kij,kj->ki", Ke, ue) + pe @ Be
+    yv = np.zeros(len(vel_rows))
+    pos = {int(r): i for i, r in enumerate(vel_rows)}
+    for k in range(len(cells)):
+        for loc, dof in enumerate(ed[cells[k]]):
+            i = pos.get(int(dof))
+            if i is not None:
+                yv[i] += ye[k, loc]
+    where = {int(c): k for k, c in enumerate(cells)}
+    yp = np.array([Be @ ue[where[int(c)]] for c in pres_cells]).reshape(len(pres_cells), -1)
+    return yv, yp
+
+
+def rhs_rows(level: Level, coef, vel_rows) -> np.ndarray:
+    """Selected entries of the velocity right-hand side (f, phi_i), from the
+    cells that touch them (same element loads as `Operators.rhs`)."""
+    vel_rows = np.asarray(vel_rows)
+    d = level.dim
+    xi, w, phi, dphi = reference_tables(d)
+    ed = level.element_dofs()
+    cells = np.nonzero(np.isin(ed, vel_rows).any(axis=1))[0]
+    base = coef if coef.kind == "scalar" else coef.base
+    f = base.force(level.quad_points()[cells])
+    be = np.einsum("q,kqc,qn->kcn", w * level.h ** d, f, phi).reshape(len(cells), -1)
+    out = np.zeros(len(vel_rows))
+    pos = {int(r): i for i, r in enumerate(vel_rows)}
+    for k in range(len(cells)):
+        for loc, dof in enumerate(ed[cells[k]]):
+            i = pos.get(int(dof))
+            if i is not None:
+                out[i] += be[k, loc]
+    return out

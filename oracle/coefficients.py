@@ -99,14 +99,19 @@ class FourierVelocity:
             msq = msq + (ms ** 2).reshape(shape)
         A = self.a / (1.0 + msq)[None]                               # (d, M, .., M)
         pts = x.reshape(-1, d)
-        S = np.sin(np.pi * ms[None, None, :] * pts[:, :, None])      # (P, d, M)
-        C = np.cos(np.pi * ms[None, None, :] * pts[:, :, None]) * (np.pi * ms)
-        letters = "mno"[:d]
         out = np.zeros((pts.shape[0], d, d))
-        for k in range(d):
-            facs = [C[:, j, :] if j == k else S[:, j, :] for j in range(d)]
-            spec = "c" + letters + "," + ",".join("p" + l for l in letters) + "->pc"
-            out[:, :, k] = np.einsum(spec, A, *facs, optimize=True)
+        for p0 in range(0, pts.shape[0], 16384):
+            P = pts[p0:p0 + 16384]
+            S = np.sin(np.pi * ms[None, None, :] * P[:, :, None])    # (P, d, M)
+            C = np.cos(np.pi * ms[None, None, :] * P[:, :, None]) * (np.pi * ms)
+            for k in range(d):
+                # factor of axis j: derivative (C) for j == k, value (S) otherwise;
+                # sum over the modes one axis at a time, last axis first
+                facs = [C[:, j, :] if j == k else S[:, j, :] for j in range(d)]
+                Z = np.tensordot(facs[d - 1], A, axes=([1], [d]))     # (P, c, m_0 .. m_{d-2})
+                for j in range(d - 2, -1, -1):
+                    Z = np.einsum("pc...m,pm->pc...", Z, facs[j])
+                out[p0:p0 + 16384, :, k] = Z
         return self.scale * out.reshape(x.shape[:-1] + (d, d))
 
     def strain_rate(self, x):

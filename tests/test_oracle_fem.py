@@ -259,3 +259,29 @@ def test_augmented_block_symmetric_positive_definite(dim, n):
     np.linalg.cholesky(A)
     # constants are the kernel of B^T (velocity vanishes on the boundary)
     assert np.abs(ops.B.T @ ops.p_const).max() < 1e-14
+
+
+@pytest.mark.parametrize("tensor", [False, True])
+def test_local_rows_equal_assembled_operator(tensor):
+    """stokes_rows / rhs_rows (used for spot checks at sizes too large to
+    assemble) give the same entries as the assembled K and right-hand side."""
+    from workloads import small
+    from oracle.krylov import StokesSolver
+    from oracle.assembly import stokes_rows, rhs_rows
+    if tensor:
+        wl = small(3, 4, 2, gamma=1e2, dr=1e6, n_sinkers=4, seed=4, coef_kind=1, fourier_seed=5)
+    else:
+        wl = small(2, 8, 2, gamma=1e3, dr=1e4, n_sinkers=4, seed=3)
+    S = StokesSolver(wl)
+    lv = S.ops.level
+    rng = np.random.default_rng(0)
+    u, p = rng.standard_normal(lv.n_u), rng.standard_normal(lv.n_p)
+    rows = rng.choice(lv.n_u, 30, replace=False)
+    pc = rng.choice(lv.n_cells, 5, replace=False)
+    yv, yp = stokes_rows(lv, S.coef, wl.gamma, u, p, rows, pc)
+    full = S.K @ np.concatenate([u, p])
+    scale = np.max(np.abs(full))
+    assert np.max(np.abs(yv - full[rows])) <= 1e-14 * scale
+    pidx = (pc[:, None] * (lv.dim + 1) + np.arange(lv.dim + 1)).ravel()
+    assert np.max(np.abs(yp.ravel() - full[lv.n_u:][pidx])) <= 1e-14 * scale
+    assert np.allclose(rhs_rows(lv, S.coef, rows), S.ops.rhs()[rows], rtol=1e-14, atol=1e-16)

@@ -218,3 +218,39 @@ def test_newton_tensor_spd_and_scalar_limit():
     # where nothing yields the tensor is 2 mu I
     iso = Mm[~yielded]
     assert np.allclose(iso, 2 * mu_eff[~yielded][:, None, None] * np.eye(6), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fourier_gradient_against_brute_force(dim):
+    """The mode-by-mode contraction of the Fourier velocity gradient equals
+    the plain sum over all modes (written out here term by term) and the
+    central difference of the velocity itself."""
+    M = 3
+    a = np.random.default_rng(5).standard_normal((dim,) + (M,) * dim)
+    vel = FourierVelocity(a, 0.7)
+    x = np.random.default_rng(6).random((5, dim))
+
+    def u(p):
+        out = np.zeros(dim)
+        for m in np.ndindex(*(M,) * dim):
+            mm = np.array(m) + 1
+            prod = np.prod(np.sin(np.pi * mm * p))
+            out += a[(slice(None),) + m] / (1.0 + np.sum(mm ** 2)) * prod
+        return 0.7 * out
+
+    G = vel.grad(x)
+    for i, p in enumerate(x):
+        ref = np.zeros((dim, dim))
+        for m in np.ndindex(*(M,) * dim):
+            mm = np.array(m) + 1
+            for k in range(dim):
+                f = np.prod([np.pi * mm[j] * np.cos(np.pi * mm[j] * p[j]) if j == k else np.sin(np.pi * mm[j] * p[j])
+                             for j in range(dim)])
+                ref[:, k] += 0.7 * a[(slice(None),) + m] / (1.0 + np.sum(mm ** 2)) * f
+        assert np.allclose(G[i], ref, rtol=1e-13, atol=1e-13)
+        h = 1e-6
+        for k in range(dim):
+            e = np.zeros(dim)
+            e[k] = h
+            fd = (u(p + e) - u(p - e)) / (2 * h)
+            assert np.allclose(G[i][:, k], fd, rtol=1e-7, atol=1e-7)
