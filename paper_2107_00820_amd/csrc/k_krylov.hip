@@ -39,9 +39,12 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(const R* __restrict__ V, i
       for (int kk = 0; kk < 8; ++kk)
         if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * wi;
     }
-    for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
-      const double s = block_sum(acc[kk], sh);
-      if (threadIdx.x == 0) part[blockIdx.x * nk + k0 + kk] = s;
+    double tot[8];
+    block_sum_n<8>(acc, nk - k0, sh, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        if (k0 + kk < nk) part[blockIdx.x * nk + k0 + kk] = tot[kk];
     }
   }
 }
@@ -83,9 +86,12 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const R* __restrict
         for (int kk = 0; kk < 8; ++kk)
           if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * wi;
       }
-      for (int kk = 0; kk < 8 && k0 + kk < nk; ++kk) {
-        const double s = block_sum(acc[kk], sh);
-        if (threadIdx.x == 0) part_out[blockIdx.x * nk + k0 + kk] = s;
+      double tot[8];
+      block_sum_n<8>(acc, nk - k0, sh, tot);
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+          if (k0 + kk < nk) part_out[blockIdx.x * nk + k0 + kk] = tot[kk];
       }
     }
   } else {
@@ -113,60 +119,81 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
     dst[i] = (R)(d > 0.0 ? (double)w[i] / d : 0.0);
 }
 
-// Least squares min ||beta e1 - Hbar y|| by Givens rotations; columns after an
-// exact breakdown (H[j+1][j] == 0) are dropped; entries below the
-// subdiagonal are zero by construction and not read.
-__device__ inline void ls_solve(const double* __restrict__ small, int nu, double* y) {
+// Least squares min ||beta e1 - Hbar y|| by Givens rotations over NU columns
+// (compile-time, so every array stays in registers); columns after an exact
+// breakdown (H[j+1][j] == 0) are dropped; entries below the subdiagonal are
+// zero by construction and not read.
+template <int NU>
+__device__ inline void ls_solve(const double* __restrict__ small, double* y) {
   const double* Hm = small + kSmallH;
   const double beta = small[kSmallBeta];
-  for (int j = 0; j < kMaxNu; ++j) y[j] = 0.0;
-  if (!(beta > 0.0)) return;
-  int k = nu;
-  for (int j = 0; j < nu; ++j)
-    if (Hm[(j + 1) * kMaxNu + j] == 0.0) { k = j + 1; break; }
-  double R[kMaxNu + 1][kMaxNu];
-  double g[kMaxNu + 1];
-  for (int i = 0; i <= k; ++i) {
-    g[i] = 0.0;
-    for (int j = 0; j < k; ++j) R[i][j] = i <= j + 1 ? Hm[i * kMaxNu + j] : 0.0;
-  }
-  g[0] = beta;
-  for (int j = 0; j < k; ++j) {
-    const double a = R[j][j], b = R[j + 1][j];
-    double c = 1.0, s = 0.0;
-    if (b != 0.0) {
-      const double r = hypot(a, b);
-      c = a / r;
-      s = b / r;
+  double yr[NU];
+#pragma unroll
+  for (int j = 0; j < NU; ++j) yr[j] = 0.0;
+  if (beta > 0.0) {
+    int k = NU;
+#pragma unroll
+    for (int j = NU - 1; j >= 0; --j)
+      if (Hm[(j + 1) * kMaxNu + j] == 0.0) k = j + 1;
+    double R[NU + 1][NU], g[NU + 1];
+#pragma unroll
+    for (int i = 0; i <= NU; ++i) {
+      g[i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < NU; ++j) R[i][j] = i <= j + 1 ? Hm[i * kMaxNu + j] : 0.0;
     }
-    for (int t = j; t < k; ++t) {
-      const double u = R[j][t], v = R[j + 1][t];
-      R[j][t] = c * u + s * v;
-      R[j + 1][t] = -s * u + c * v;
+    g[0] = beta;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      if (j < k) {
+        const double a = R[j][j], b = R[j + 1][j];
+        double c = 1.0, s = 0.0;
+        if (b != 0.0) {
+          const double r = hypot(a, b);
+          c = a / r;
+          s = b / r;
+        }
+#pragma unroll
+        for (int t = j; t < NU; ++t) {
+          if (t < k) {
+            const double u = R[j][t], v = R[j + 1][t];
+            R[j][t] = c * u + s * v;
+            R[j + 1][t] = -s * u + c * v;
+          }
+        }
+        const double gu = g[j], gv = g[j + 1];
+        g[j] = c * gu + s * gv;
+        g[j + 1] = -s * gu + c * gv;
+      }
     }
-    const double gu = g[j], gv = g[j + 1];
-    g[j] = c * gu + s * gv;
-    g[j + 1] = -s * gu + c * gv;
+#pragma unroll
+    for (int j = NU - 1; j >= 0; --j) {
+      if (j < k) {
+        double s = g[j];
+#pragma unroll
+        for (int t = j + 1; t < NU; ++t)
+          if (t < k) s -= R[j][t] * yr[t];
+        yr[j] = s / R[j][j];
+      }
+    }
   }
-  for (int j = k - 1; j >= 0; --j) {
-    double s = g[j];
-    for (int t = j + 1; t < k; ++t) s -= R[j][t] * y[t];
-    y[j] = s / R[j][j];
-  }
+#pragma unroll
+  for (int j = 0; j < NU; ++j) y[j] = yr[j];
 }
 
 // x = (x_zero ? 0 : x) + sum_k y_k Z_k with y solved from the relaxation's
 // Hessenberg system (every block solves the tiny system redundantly).
-template <class R>
-__global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, int nu, const double* __restrict__ small,
+template <class R, int NU>
+__global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, const double* __restrict__ small,
                                R* __restrict__ x, int64_t n, int x_zero) {
-  __shared__ double y[kMaxNu];
-  if (threadIdx.x == 0) ls_solve(small, nu, y);
+  __shared__ double y[NU];
+  if (threadIdx.x == 0) ls_solve<NU>(small, y);
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double v = x_zero ? 0.0 : (double)x[i];
-  for (int k = 0; k < nu; ++k) v += y[k] * (double)Z[(int64_t)k * ldz + i];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) v += y[k] * (double)Z[(int64_t)k * ldz + i];
   x[i] = (R)v;
 }
 
@@ -230,8 +257,18 @@ void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, doub
 template <class R>
 void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, R* x, int64_t n, bool x_zero,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_relax_update<R>, dim3(nblk(n, 256)), dim3(256), 0, s, Z, ldz, nu, small, x, n,
-                     x_zero ? 1 : 0);
+  const dim3 g(nblk(n, 256)), b(256);
+  const int xz = x_zero ? 1 : 0;
+  switch (nu) {
+    case 1: hipLaunchKernelGGL((k_relax_update<R, 1>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 2: hipLaunchKernelGGL((k_relax_update<R, 2>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 3: hipLaunchKernelGGL((k_relax_update<R, 3>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 4: hipLaunchKernelGGL((k_relax_update<R, 4>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 5: hipLaunchKernelGGL((k_relax_update<R, 5>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 6: hipLaunchKernelGGL((k_relax_update<R, 6>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 7: hipLaunchKernelGGL((k_relax_update<R, 7>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    default: hipLaunchKernelGGL((k_relax_update<R, 8>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+  }
 }
 
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n, bool x_zero,

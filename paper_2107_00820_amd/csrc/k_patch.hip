@@ -137,11 +137,17 @@ __device__ __attribute__((always_inline)) inline void packed_symv_chunked(const 
   });
 }
 
+#ifndef STK_CH_LDS64
+#define STK_CH_LDS64 16
+#endif
+#ifndef STK_CH_LDS32
+#define STK_CH_LDS32 32
+#endif
 template <int NPT, class R>
 __device__ __attribute__((always_inline)) inline void packed_symv_lds(const R* __restrict__ A, const R* xs, int lane,
                                                                       R (&y)[NPT]) {
   auto xr = [&](int j) { return xs[j * 64 + lane]; };
-  packed_symv_chunked<NPT, sizeof(R) == 8 ? 16 : 32>(A, xr, y);
+  packed_symv_chunked<NPT, sizeof(R) == 8 ? STK_CH_LDS64 : STK_CH_LDS32>(A, xr, y);
 }
 
 // x from registers (patches of up to 27 unknowns): four double-buffered chunks

@@ -5,21 +5,54 @@
 
 namespace stk {
 
-// Number of partial sums (one per block) used for a vector of length n.
+// Number of partial sums (one per block) used for a vector of length n: one
+// element per thread up to kRedBlocks blocks (short vectors then finish in
+// one memory round trip), grid-stride beyond.
 inline int red_parts(int64_t n) {
-  const int64_t p = (n + (int64_t)kRedThreads * 8 - 1) / ((int64_t)kRedThreads * 8);
+  const int64_t p = (n + (int64_t)kRedThreads - 1) / (int64_t)kRedThreads;
   return (int)(p < 1 ? 1 : (p > kRedBlocks ? kRedBlocks : p));
 }
+
+// Sum over the block (kRedThreads threads): butterfly within each wavefront,
+// then the wavefront sums in a fixed order. `sh` holds kRedThreads/64 doubles.
+// Every thread gets the result.
 __device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  if ((threadIdx.x & 63) == 0) sh[wave] = v;
   __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r += sh[w];
   return r;
+}
+
+// Block sums of v[0..m) (m <= 8) at once: out[k] valid in every thread.
+// `sh` holds 8 * kRedThreads/64 doubles.
+template <int M>
+__device__ inline void block_sum_n(const double (&v)[M], int m, double* sh, double (&out)[M]) {
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double t[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    t[k] = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t[k] += __shfl_xor(t[k], off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (k < m) sh[wave * M + k] = t[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double r = 0.0;
+    if (k < m)
+      for (int w = 0; w < nw; ++w) r += sh[w * M + k];
+    out[k] = r;
+  }
 }
 
 // Sum of part[b*stride + k] over b < nparts by one full wavefront; every lane

@@ -66,6 +66,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2107_00820_amd.build` "
                            "(or __graft_entry__.build())")
+    # torch first: its HIP runtime must be the one the library binds to, so
+    # that device memory and streams are shared
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64p, dp = C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)
     sig = {
