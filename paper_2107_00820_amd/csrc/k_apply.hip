@@ -457,15 +457,11 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, double ga
 }
 
 // ---------------------------------------------------------------------------
-// out[idx] = base[idx] + alpha * sum_{cells K containing node} E_K[local],
-// 0 on Dirichlet nodes. One thread per stored entry.
+// Sum of the element outputs of the <= 2^d cells containing stored entry idx
+// (fixed order); 0 on Dirichlet nodes (flag set).
 template <int D, class R>
-__global__ void k_gather(LevelGeo g, const R* __restrict__ E, const R* __restrict__ base,
-                         double alpha_d, R* __restrict__ out) {
-  const R alpha = (R)alpha_d;
+__device__ inline R gather_sum(const LevelGeo& g, const R* __restrict__ E, int64_t idx, bool& dirichlet) {
   constexpr int NN = Dims<D>::NN;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)D * g.nnodes) return;
   const int comp = (int)(idx / g.nnodes);
   const int64_t nd = idx - (int64_t)comp * g.nnodes;
   int i[3];
@@ -475,10 +471,8 @@ __global__ void k_gather(LevelGeo g, const R* __restrict__ E, const R* __restric
   bool bnd = false;
 #pragma unroll
   for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
-  if (bnd) {
-    out[idx] = (R)0;
-    return;
-  }
+  dirichlet = bnd;
+  if (bnd) return (R)0;
   // per axis up to two (cell, local) pairs
   int cc[3][2], ll[3][2], cnt[3];
 #pragma unroll
@@ -501,7 +495,61 @@ __global__ void k_gather(LevelGeo g, const R* __restrict__ E, const R* __restric
         const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
         s += E[cell * (D * NN) + comp * NN + loc];
       }
-  out[idx] = (base ? base[idx] : (R)0) + alpha * s;
+  return s;
+}
+
+// out[idx] = base[idx] + alpha * sum_{cells K containing node} E_K[local],
+// 0 on Dirichlet nodes. One thread per stored entry.
+template <int D, class R>
+__global__ void k_gather(LevelGeo g, const R* __restrict__ E, const R* __restrict__ base,
+                         double alpha_d, R* __restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)D * g.nnodes) return;
+  bool dir;
+  const R s = gather_sum<D, R>(g, E, idx, dir);
+  out[idx] = dir ? (R)0 : (base ? base[idx] : (R)0) + (R)alpha_d * s;
+}
+
+// The gather of y = A u fused with the dot products V_k . y (k < nk) over the
+// whole vector of length nvec >= d*nnodes (entries past the velocity block,
+// e.g. a pressure block already written, are read as they are). Block
+// partials part[b*nk + k] on the fixed grid-stride partition of red_parts(nvec).
+template <int D, class R>
+__global__ void __launch_bounds__(kRedThreads)
+k_gather_dots(LevelGeo g, const R* __restrict__ E, R* __restrict__ out, int64_t nvec, const R* __restrict__ V,
+              int64_t ldv, int nk, double* __restrict__ part) {
+  __shared__ double sh[8 * (kRedThreads / 64)];
+  const int64_t nvel = (int64_t)D * g.nnodes;
+  for (int k0 = 0; k0 < nk; k0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvec;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      R wi;
+      if (i < nvel) {
+        if (k0 == 0) {
+          bool dir;
+          wi = gather_sum<D, R>(g, E, i, dir);
+          out[i] = wi;
+        } else {
+          wi = out[i];   // written by this thread in the first chunk
+        }
+      } else {
+        wi = out[i];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * (double)wi;
+    }
+    double tot[8];
+    block_sum_n<8>(acc, nk - k0, sh, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        if (k0 + kk < nk) part[blockIdx.x * nk + k0 + kk] = tot[kk];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -753,6 +801,21 @@ void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R
     hipLaunchKernelGGL((k_gather<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, E, base, alpha, out);
 }
 
+template <class R>
+void launch_gather_dots(const Hier& H, const Level& l, R* out, int64_t nvec, const R* V, int64_t ldv, int nk,
+                        double* part, hipStream_t s) {
+  const R* E = reinterpret_cast<const R*>(l.E);
+  const int np = red_parts(nvec);
+  if (H.dim == 2)
+    hipLaunchKernelGGL((k_gather_dots<2, R>), dim3(np), dim3(kRedThreads), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
+  else
+    hipLaunchKernelGGL((k_gather_dots<3, R>), dim3(np), dim3(kRedThreads), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
+}
+
+template void launch_gather_dots<double>(const Hier&, const Level&, double*, int64_t, const double*, int64_t, int,
+                                         double*, hipStream_t);
+template void launch_gather_dots<float>(const Hier&, const Level&, float*, int64_t, const float*, int64_t, int,
+                                        double*, hipStream_t);
 template void launch_elem<double>(const Hier&, const Level&, int, const double*, const double*, double*, hipStream_t);
 template void launch_elem<float>(const Hier&, const Level&, int, const float*, const double*, double*, hipStream_t);
 template void launch_gather<double>(const Hier&, const Level&, const double*, double, double*, hipStream_t);

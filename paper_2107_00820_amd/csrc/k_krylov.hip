@@ -124,9 +124,11 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
 // breakdown (H[j+1][j] == 0) are dropped; entries below the subdiagonal are
 // zero by construction and not read.
 template <int NU>
-__device__ inline void ls_solve(const double* __restrict__ small, double* y) {
+__device__ inline void ls_solve(const double* __restrict__ small, double hlast, double* y) {
   const double* Hm = small + kSmallH;
   const double beta = small[kSmallBeta];
+  // H[NU][NU-1] from the caller when given (hlast >= 0), else as stored
+  auto Hat = [&](int i, int j) { return (i == NU && j == NU - 1 && hlast >= 0.0) ? hlast : Hm[i * kMaxNu + j]; };
   double yr[NU];
 #pragma unroll
   for (int j = 0; j < NU; ++j) yr[j] = 0.0;
@@ -134,13 +136,13 @@ __device__ inline void ls_solve(const double* __restrict__ small, double* y) {
     int k = NU;
 #pragma unroll
     for (int j = NU - 1; j >= 0; --j)
-      if (Hm[(j + 1) * kMaxNu + j] == 0.0) k = j + 1;
+      if (Hat(j + 1, j) == 0.0) k = j + 1;
     double R[NU + 1][NU], g[NU + 1];
 #pragma unroll
     for (int i = 0; i <= NU; ++i) {
       g[i] = 0.0;
 #pragma unroll
-      for (int j = 0; j < NU; ++j) R[i][j] = i <= j + 1 ? Hm[i * kMaxNu + j] : 0.0;
+      for (int j = 0; j < NU; ++j) R[i][j] = i <= j + 1 ? Hat(i, j) : 0.0;
     }
     g[0] = beta;
 #pragma unroll
@@ -182,12 +184,21 @@ __device__ inline void ls_solve(const double* __restrict__ small, double* y) {
 }
 
 // x = (x_zero ? 0 : x) + sum_k y_k Z_k with y solved from the relaxation's
-// Hessenberg system (every block solves the tiny system redundantly).
+// Hessenberg system (every block solves the tiny system redundantly). The
+// last subdiagonal entry ||w|| is reduced here from the norm partials of the
+// final Gram-Schmidt pass, so the last Arnoldi vector is never normalised.
 template <class R, int NU>
 __global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, const double* __restrict__ small,
-                               R* __restrict__ x, int64_t n, int x_zero) {
+                               const double* __restrict__ norm_part, int nparts, R* __restrict__ x, int64_t n,
+                               int x_zero) {
   __shared__ double y[NU];
-  if (threadIdx.x == 0) ls_solve<NU>(small, y);
+  __shared__ double hl;
+  if (threadIdx.x < 64) {
+    const double s = wave_reduce_parts(norm_part, nparts, 1, 0);
+    if (threadIdx.x == 0) hl = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ls_solve<NU>(small, hl, y);
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -255,19 +266,20 @@ void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, doub
 }
 
 template <class R>
-void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, R* x, int64_t n, bool x_zero,
-                         hipStream_t s) {
+void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, const double* norm_part, R* x,
+                         int64_t n, bool x_zero, hipStream_t s) {
   const dim3 g(nblk(n, 256)), b(256);
   const int xz = x_zero ? 1 : 0;
+  const int np = red_parts(n);
   switch (nu) {
-    case 1: hipLaunchKernelGGL((k_relax_update<R, 1>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 2: hipLaunchKernelGGL((k_relax_update<R, 2>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 3: hipLaunchKernelGGL((k_relax_update<R, 3>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 4: hipLaunchKernelGGL((k_relax_update<R, 4>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 5: hipLaunchKernelGGL((k_relax_update<R, 5>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 6: hipLaunchKernelGGL((k_relax_update<R, 6>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    case 7: hipLaunchKernelGGL((k_relax_update<R, 7>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
-    default: hipLaunchKernelGGL((k_relax_update<R, 8>), g, b, 0, s, Z, ldz, small, x, n, xz); break;
+    case 1: hipLaunchKernelGGL((k_relax_update<R, 1>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 2: hipLaunchKernelGGL((k_relax_update<R, 2>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 3: hipLaunchKernelGGL((k_relax_update<R, 3>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 4: hipLaunchKernelGGL((k_relax_update<R, 4>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 5: hipLaunchKernelGGL((k_relax_update<R, 5>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 6: hipLaunchKernelGGL((k_relax_update<R, 6>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    case 7: hipLaunchKernelGGL((k_relax_update<R, 7>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
+    default: hipLaunchKernelGGL((k_relax_update<R, 8>), g, b, 0, s, Z, ldz, small, norm_part, np, x, n, xz); break;
   }
 }
 
@@ -304,7 +316,8 @@ void launch_copy(const double* x, double* y, int64_t n, hipStream_t s) {
   template void launch_orth_update<R>(const R*, int64_t, int, R*, int64_t, const double*, double*, int, bool, \
                                       double*, bool, hipStream_t);                                          \
   template void launch_normalize<R>(const double*, R*, int64_t, R*, double*, hipStream_t);                 \
-  template void launch_relax_update<R>(const R*, int64_t, int, const double*, R*, int64_t, bool, hipStream_t); \
+  template void launch_relax_update<R>(const R*, int64_t, int, const double*, const double*, R*, int64_t, bool,  \
+                                       hipStream_t);                                                           \
   template void launch_axpby<R>(double, const R*, double, const R*, R*, int64_t, hipStream_t);             \
   template void launch_fill<R>(R*, double, int64_t, hipStream_t);
 STK_INST(double)

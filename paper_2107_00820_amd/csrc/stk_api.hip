@@ -265,6 +265,23 @@ void apply_A(Hier& H, int l, const R* x, R* y) {
   launch_gather<R>(H, L, nullptr, 1.0, y, H.stream);
 }
 
+// y = A_gamma x with the partial dot products V_k . y (k < nk) for the
+// Gram-Schmidt step that follows, on the partition of launch_dots.
+template <class R>
+void apply_A_dots(Hier& H, int l, const R* x, R* y, const R* V, int64_t ldv, int nk, double* part) {
+  Level& L = H.lv[l];
+  hipEvent_t ev = nullptr;
+  const int reps = prof_begin(H, H.stream, &ev);
+  for (int k = 0; k < reps; ++k) launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
+  {
+    const double nn = H.dim == 2 ? 9.0 : 27.0;
+    const double ncoef = L.cw ? 1.0 + H.dim * (H.dim + 1) / 2 : 1.0;
+    prof_end(H, H.stream, PROF_ELEM, ev,
+             (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)), reps);
+  }
+  launch_gather_dots<R>(H, L, y, L.nvel, V, ldv, nk, part, H.stream);
+}
+
 template <class R>
 void residual(Hier& H, int l, const R* b, const R* x, R* r) {
   Level& L = H.lv[l];
@@ -318,14 +335,14 @@ void smooth(Hier& H, int l, const R* b, R* x, int nu, bool x_zero) {
     R* Zj = Z + (int64_t)j * n;
     R* w = V + (int64_t)(j + 1) * n;
     launch_asm<R>(H, L, Vj, Zj, H.stream);
-    apply_A<R>(H, l, Zj, w);
+    apply_A_dots<R>(H, l, Zj, w, V, n, j + 1, p1);
     double* Hcol = L.small + kSmallH + j;
-    launch_dots<R>(V, n, j + 1, w, n, p1, H.stream);
     launch_orth_update<R>(V, n, j + 1, w, n, p1, Hcol, kMaxNu, false, p2, true, H.stream);
     launch_orth_update<R>(V, n, j + 1, w, n, p2, Hcol, kMaxNu, true, p1, false, H.stream);
-    launch_normalize<R>(p1, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
+    // the last Arnoldi vector is not needed: its norm goes straight to the update
+    if (j + 1 < nu) launch_normalize<R>(p1, w, n, w, L.small + kSmallH + (j + 1) * kMaxNu + j, H.stream);
   }
-  launch_relax_update<R>(Z, n, nu, L.small, x, n, x_zero, H.stream);
+  launch_relax_update<R>(Z, n, nu, L.small, p1, x, n, x_zero, H.stream);
 }
 
 template <class R>
@@ -397,8 +414,10 @@ void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed) {
   double* p1 = H.partials;
   double* p2 = H.partials + kPartialLen;
   precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed);
-  stokes_apply(H, Zj, w);
-  launch_dots<double>(H.fV, nvec, j + 1, w, nvec, p1, H.stream);
+  // w = K Z_j with the first Gram-Schmidt pass's dot products
+  Level& F = H.lv[H.L - 1];
+  launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, Zj, Zj + nu, w + nu, H.stream);
+  launch_gather_dots<double>(H, F, w, nvec, H.fV, nvec, j + 1, p1, H.stream);
   launch_orth_update<double>(H.fV, nvec, j + 1, w, nvec, p1, H.fH + j, m, false, p2, true, H.stream);
   launch_orth_update<double>(H.fV, nvec, j + 1, w, nvec, p2, H.fH + j, m, true, p1, false, H.stream);
   launch_normalize<double>(p1, w, nvec, w, H.fH + (j + 1) * m + j, H.stream);

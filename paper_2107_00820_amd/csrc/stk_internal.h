@@ -152,6 +152,11 @@ void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const doub
                  hipStream_t s);
 template <class R>
 void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R* out, hipStream_t s);
+// gather of the element outputs into out[0, d*nnodes) fused with the partial
+// dot products V_k . out over out[0, nvec) (same partition as launch_dots)
+template <class R>
+void launch_gather_dots(const Hier& H, const Level& l, R* out, int64_t nvec, const R* V, int64_t ldv, int nk,
+                        double* part, hipStream_t s);
 void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
@@ -185,8 +190,8 @@ void launch_orth_update(const R* V, int64_t ldv, int nk, R* w, int64_t n, const 
 template <class R>
 void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, double* hout, hipStream_t s);
 template <class R>
-void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, R* x, int64_t n, bool x_zero,
-                         hipStream_t s);
+void launch_relax_update(const R* Z, int64_t ldz, int nu, const double* small, const double* norm_part, R* x,
+                         int64_t n, bool x_zero, hipStream_t s);
 void launch_combine(const double* Z, int64_t ldz, int nk, const double* y, double* x, int64_t n,
                     bool x_zero, hipStream_t s);
 template <class R>
