@@ -90,7 +90,10 @@ typedef struct {
   int n_fine;         /* cells per axis on the finest level, divisible by 2^(n_levels-1) */
   int n_levels;       /* >= 2 */
   double gamma;       /* augmented-Lagrangian parameter, >= 0 */
-  int schur;          /* 1 = P1 (W = M_p), 2 = P2 (W = M_p(1/mu)); only 1 is built */
+  int schur;          /* W in A_gamma and the Schur blocks (eq. (P1P2)):
+                         1 = P1: W = M_p, Shat^{-1} = M_p(1/mu)^{-1} + gamma M_p^{-1};
+                         2 = P2: W = M_p(1/mu), Shat^{-1} = (1 + gamma) M_p(1/mu)^{-1}.
+                         The augmented system has the Stokes solution for either W. */
   int coef_kind;      /* 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor */
   stk_sinker sinker;  /* the viscosity (coef_kind 0) or the base field mu0 (1); forcing in both */
   stk_viscoplastic vp;  /* read for coef_kind 1 only */

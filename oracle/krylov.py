@@ -123,7 +123,9 @@ def fgmres(K, M, b: np.ndarray, rtol: float = 1e-8, restart: int = 30, maxit: in
 class StokesSolver:
     """Everything for one workload: hierarchy, operators, preconditioner, FGMRES."""
 
-    def __init__(self, wl, schur: int = 1, robust: bool = True, coef=None):
+    def __init__(self, wl, schur: int = None, robust: bool = True, coef=None):
+        if schur is None:
+            schur = getattr(wl, "schur", 1)
         from .coefficients import SinkerField, ViscoplasticNewton
         from .fem import Level
         self.wl = wl

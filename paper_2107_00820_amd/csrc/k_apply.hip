@@ -265,8 +265,8 @@ __device__ inline double selc(const double (&tab)[3][3], int r, int c) {
 
 template <int D, int MODE, bool TENSOR, class R>
 __global__ void __launch_bounds__(64)
-k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, double gamma_d, const R* __restrict__ u,
-       const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
+k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* __restrict__ winv, double gamma_d,
+       const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
   constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
   constexpr int NS = SymIdx<D>::NS;
   constexpr int CPW = 64 / NQ;
@@ -390,15 +390,27 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, double ga
   if constexpr (need_c) {
     __syncthreads();
     if (valid && t == 0) {
+      R bu[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        bu[m] = 0;
+        if (MODE & (EL_AUG | EL_BOUT))
+          for (int q = 0; q < NQ; ++q) bu[m] += red[lc][q][m];
+      }
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
         R cm = 0;
-        if (MODE & (EL_AUG | EL_BOUT)) {
-          R bu = 0;
-          for (int q = 0; q < NQ; ++q) bu += red[lc][q][m];
-          if (MODE & EL_AUG) cm += gamma * bu * (R)kInvMhat[m];
-          if (MODE & EL_BOUT) pout[cell * NP + m] = -(D == 2 ? g.h : g.h * g.h) * (double)bu;
+        if (MODE & EL_AUG) {
+          if (winv) {   // W = M_p(1/mu): the cell's inverse weighted mass
+            R t2 = 0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) t2 += winv[cell * NP * NP + m * NP + k] * bu[k];
+            cm += gamma * t2;
+          } else {
+            cm += gamma * bu[m] * (R)kInvMhat[m];
+          }
         }
+        if (MODE & EL_BOUT) pout[cell * NP + m] = -(D == 2 ? g.h : g.h * g.h) * (double)bu[m];
         if (MODE & EL_BT) cm -= h * (R)p[cell * NP + m];
         cms[lc][m] = cm;
       }
@@ -582,9 +594,59 @@ __global__ void k_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, d
 }
 
 // ---------------------------------------------------------------------------
-// Schur blocks Shat_gamma,K^{-1} = M_K(1/mu)^{-1} + gamma M_K^{-1} (eq. (P1P2), P1).
+// Per cell: Winv = (sum_q w_q / mu_q psi psi^T)^{-1} on the reference cell,
+// the inverse weighted pressure mass of W = M_p(1/mu) (eq. (P1P2), P2) without
+// the cell volume (M_K(1/mu) = h^d times this matrix).
 template <int D>
-__global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double gamma,
+__global__ void k_winv_setup(LevelGeo g, const double* __restrict__ mu, double* __restrict__ winv) {
+  constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  double M[NP][NP], X[NP][NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      M[a][b] = 0.0;
+      X[a][b] = a == b ? 1.0 : 0.0;
+    }
+  for (int q = 0; q < NN; ++q) {
+    const double wq = T.w[q] / mu[cell * NN + q];
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) M[a][b] += wq * T.psi[q][a] * T.psi[q][b];
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double piv = 1.0 / M[k][k];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      M[k][b] *= piv;
+      X[k][b] *= piv;
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      if (a == k) continue;
+      const double f = M[a][k];
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        M[a][b] -= f * M[k][b];
+        X[a][b] -= f * X[k][b];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) winv[cell * NP * NP + a * NP + b] = X[a][b];
+}
+
+// Schur blocks (eq. (P1P2)): P1 Shat_gamma,K^{-1} = M_K(1/mu)^{-1} + gamma M_K^{-1};
+// P2 (p2 != 0) Shat_gamma,K^{-1} = (1 + gamma) M_K(1/mu)^{-1}.
+template <int D>
+__global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double gamma, int p2,
                               double* __restrict__ Sinv) {
   constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP;
   constexpr const RefTab<D>& T = Ref<D>::T;
@@ -631,7 +693,8 @@ __global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double 
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       double v = X[a][b];
-      if (a == b) v += gamma / (vol * T.mhat[a]);
+      if (p2) v *= 1.0 + gamma;
+      else if (a == b) v += gamma / (vol * T.mhat[a]);
       Sinv[cell * NP * NP + a * NP + b] = v;
     }
 }
@@ -732,15 +795,23 @@ const double* level_cw<double>(const Level& l) { return l.cw; }
 template <>
 const float* level_cw<float>(const Level& l) { return l.cw32; }
 
+template <class R>
+static const R* level_winv(const Level& l);
+template <>
+const double* level_winv<double>(const Level& l) { return l.winv; }
+template <>
+const float* level_winv<float>(const Level& l) { return l.winv32; }
+
 template <int D, int MODE, class R>
 static void elem_launch(const Hier& H, const Level& l, const R* u, const double* p, double* pout, hipStream_t s) {
   constexpr int CPW = 64 / Dims<D>::NQ;
   const dim3 grid(nblk(l.g.ncell, CPW));
+  const R* wi = level_winv<R>(l);
   if ((MODE & EL_VISC) && l.cw)
-    hipLaunchKernelGGL((k_elem<D, MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l),
+    hipLaunchKernelGGL((k_elem<D, MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l), wi,
                        H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
   else
-    hipLaunchKernelGGL((k_elem<D, MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr,
+    hipLaunchKernelGGL((k_elem<D, MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr, wi,
                        H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
 }
 
@@ -831,12 +902,20 @@ void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
 }
 
 void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
+  const int p2 = H.schur == 2 ? 1 : 0;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_schur_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma,
+    hipLaunchKernelGGL(k_schur_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma, p2,
                        H.Sinv);
   else
-    hipLaunchKernelGGL(k_schur_setup<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma,
+    hipLaunchKernelGGL(k_schur_setup<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma, p2,
                        H.Sinv);
+}
+
+void launch_winv_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_winv_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, l.winv);
+  else
+    hipLaunchKernelGGL(k_winv_setup<3>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, l.winv);
 }
 
 void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,

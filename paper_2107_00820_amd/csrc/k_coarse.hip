@@ -69,7 +69,8 @@ __device__ inline double* tile_ptr(double* A, int I, int J) {
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const double* __restrict__ mu,
-                                                          const double* __restrict__ cw, double gamma, int64_t n,
+                                                          const double* __restrict__ cw,
+                                                          const double* __restrict__ winv, double gamma, int64_t n,
                                                           int64_t ntiles, double* __restrict__ A) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= ntiles * kTT) return;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
     int ni[3], nj[3];
     const int ci = interior_dof<D>(g, i, ni);
     const int cj = interior_dof<D>(g, j, nj);
-    v = global_entry<D>(g, mu, cw, gamma, ci, ni, cj, nj);
+    v = global_entry<D>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
   } else {
     v = i == j ? 1.0 : 0.0;
   }
@@ -291,9 +292,9 @@ void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_
   const int64_t ntiles = nb * (nb + 1) / 2;
   const dim3 grid(nblk(ntiles * kTT, 256));
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_coarse_assemble<2>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, H.n0, ntiles, A);
+    hipLaunchKernelGGL(k_coarse_assemble<2>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);
   else
-    hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, H.gamma, H.n0, ntiles, A);
+    hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);
 }
 
 // work: P^{-1} (kTT) + W (nb * kTT) doubles.

@@ -36,8 +36,8 @@ __device__ __attribute__((always_inline)) inline void static_for(F&& f) {
 }
 
 template <int D>
-__global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, const double* __restrict__ cw, double gamma,
-                              int n,
+__global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, const double* __restrict__ cw,
+                              const double* __restrict__ winv, double gamma, int n,
                               const int* __restrict__ verts, int count, double* __restrict__ inv,
                               int* __restrict__ flag) {
   extern __shared__ double sm[];
@@ -56,7 +56,7 @@ __global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, const d
     int ni[3], nj[3];
     const int ci = patch_dof<D>(i, lo, ext, ni);
     const int cj = patch_dof<D>(j, lo, ext, nj);
-    const double v = global_entry<D>(g, mu, cw, gamma, ci, ni, cj, nj);
+    const double v = global_entry<D>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
     a[i * ld + j] = v;
     a[j * ld + i] = v;
   }
@@ -356,10 +356,10 @@ void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hip
   const size_t shm = (size_t)(pc.n * (pc.n + 1) + pc.n) * sizeof(double);
   const int nt = pc.n > 32 ? 256 : 64;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_patch_setup<2>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, H.gamma, pc.n, pc.verts,
+    hipLaunchKernelGGL(k_patch_setup<2>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, l.winv, H.gamma, pc.n, pc.verts,
                        pc.count, pc.inv, H.flag);
   else
-    hipLaunchKernelGGL(k_patch_setup<3>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, H.gamma, pc.n, pc.verts,
+    hipLaunchKernelGGL(k_patch_setup<3>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, l.winv, H.gamma, pc.n, pc.verts,
                        pc.count, pc.inv, H.flag);
 }
 

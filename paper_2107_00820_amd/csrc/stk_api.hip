@@ -62,7 +62,7 @@ stk_status validate(const stk_desc* d) {
   const int64_t n0 = (int64_t)d->dim * ipow(2 * nc - 1, d->dim);
   if (n0 > 40000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve");
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
-  if (d->schur != 1) return fail(STK_EINVAL, "only the P1 Schur approximation (schur=1) is built");
+  if (d->schur != 1 && d->schur != 2) return fail(STK_EINVAL, "schur must be 1 (W = M_p) or 2 (W = M_p(1/mu))");
   if (d->coef_kind != 0 && d->coef_kind != 1)
     return fail(STK_EINVAL, "coef_kind must be 0 (sinker viscosity) or 1 (viscoplastic Newton tensor)");
   if (d->coef_kind == 1) {
@@ -154,6 +154,10 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     L.npres = NP * L.g.ncell;
     STKCHK(alloc((size_t)NN * L.g.ncell * 8, (void**)&L.mu));
     if (d->mixed) STKCHK(alloc((size_t)NN * L.g.ncell * 4, (void**)&L.mu32));
+    if (d->schur == 2) {
+      STKCHK(alloc((size_t)NP * NP * L.g.ncell * 8, (void**)&L.winv));
+      if (d->mixed) STKCHK(alloc((size_t)NP * NP * L.g.ncell * 4, (void**)&L.winv32));
+    }
     if (d->coef_kind == 1) {
       const int NS = D * (D + 1) / 2;
       STKCHK(alloc((size_t)NS * NN * L.g.ncell * 8, (void**)&L.cw));
@@ -572,6 +576,7 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
     Level& L = H.lv[l];
     if (H.coef_kind == 1) launch_coef_tensor(H, L, H.lv[H.L - 1], s);
     else launch_mu_sinker(H, L, s);
+    if (L.winv) launch_winv_setup(H, L, s);
     launch_fill<double>(L.S, 0.0, L.nvel, s);
     if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
     launch_fill<double>(L.x, 0.0, L.nvel, s);
@@ -594,6 +599,7 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
       launch_convert<double, float>(L.mu, L.mu32, (int64_t)(D == 2 ? 9 : 27) * L.g.ncell, s);
       if (L.cw)
         launch_convert<double, float>(L.cw, L.cw32, (int64_t)(D * (D + 1) / 2) * (D == 2 ? 9 : 27) * L.g.ncell, s);
+      if (L.winv) launch_convert<double, float>(L.winv, L.winv32, (int64_t)(D + 1) * (D + 1) * L.g.ncell, s);
       for (PatchClass& pc : L.cls)
         launch_convert<double, float>(pc.inv, pc.inv32, packed_doubles(pc.n, pc.count), s);
     }

@@ -52,9 +52,12 @@ __device__ inline int patch_dof(int i, const int lo[3], const int ext[3], int nd
 // With the tensor law (cw != NULL) each Gauss point also subtracts
 // w_q (w_ci,: . grad phi_a)(w_cj,: . grad phi_b), the (w:eps_i)(w:eps_j) part of
 // (C:eps_j):eps_i.
+// With W = M_p(1/mu) (winv != NULL) the augmented term uses the cell's
+// inverse weighted mass winv[cell] in place of Mhat^{-1}.
 template <int D>
-__device__ inline double cell_entry(const double* __restrict__ mu, const double* __restrict__ cw, int64_t ncell,
-                                    int64_t cell, double h, double gamma, int ci, int na, int cj, int nb) {
+__device__ inline double cell_entry(const double* __restrict__ mu, const double* __restrict__ cw,
+                                    const double* __restrict__ winv, int64_t ncell, int64_t cell, double h,
+                                    double gamma, int ci, int na, int cj, int nb) {
   constexpr int NN = Dims<D>::NN, NP = Dims<D>::NP, NS = SymIdx<D>::NS;
   const RefTab<D>& T = ctab<D>();
   double s = 0.0;
@@ -76,8 +79,19 @@ __device__ inline double cell_entry(const double* __restrict__ mu, const double*
     }
   }
   double al = 0.0;
+  if (winv) {
+    const double* W = winv + cell * NP * NP;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) al += T.bhat[m][ci * NN + na] * T.bhat[m][cj * NN + nb] * kInvMhat[m];
+    for (int m = 0; m < NP; ++m) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) t += W[m * NP + k] * T.bhat[k][cj * NN + nb];
+      al += T.bhat[m][ci * NN + na] * t;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) al += T.bhat[m][ci * NN + na] * T.bhat[m][cj * NN + nb] * kInvMhat[m];
+  }
   const double sc = D == 2 ? 1.0 : h;
   return sc * (s + gamma * al);
 }
@@ -86,7 +100,8 @@ __device__ inline double cell_entry(const double* __restrict__ mu, const double*
 // that contain both nodes.
 template <int D>
 __device__ inline double global_entry(const LevelGeo& g, const double* __restrict__ mu, const double* __restrict__ cw,
-                                      double gamma, int ci, const int ni[3], int cj, const int nj[3]) {
+                                      const double* __restrict__ winv, double gamma, int ci, const int ni[3], int cj,
+                                      const int nj[3]) {
   int clo[3], chi[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -106,7 +121,7 @@ __device__ inline double global_entry(const LevelGeo& g, const double* __restric
         const int64_t cell = cell_index<D>(g, c0, c1, c2);
         const int na = (ni[0] - 2 * c0) + 3 * (ni[1] - 2 * c1) + (D == 3 ? 9 * (ni[2] - 2 * c2) : 0);
         const int nb = (nj[0] - 2 * c0) + 3 * (nj[1] - 2 * c1) + (D == 3 ? 9 * (nj[2] - 2 * c2) : 0);
-        s += cell_entry<D>(mu, cw, g.ncell, cell, g.h, gamma, ci, na, cj, nb);
+        s += cell_entry<D>(mu, cw, winv, g.ncell, cell, g.h, gamma, ci, na, cj, nb);
       }
   return s;
 }

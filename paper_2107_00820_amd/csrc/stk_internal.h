@@ -46,6 +46,11 @@ struct Level {
   // [ncell][d(d+1)/2][NQ] (symmetric storage order of SymIdx)
   double* cw = nullptr;
   float* cw32 = nullptr;
+  // W = M_p(1/mu) (preconditioner P2 of eq. (P1P2)): per cell the inverse of
+  // the reference weighted pressure mass sum_q w_q / mu_q psi psi^T,
+  // [ncell][(d+1)^2]; NULL for W = M_p
+  double* winv = nullptr;
+  float* winv32 = nullptr;
   double* E = nullptr;         // [NL][ncell] element outputs
   // relaxation and transfer work vectors (stored layout)
   double *b = nullptr, *x = nullptr, *r = nullptr, *T = nullptr, *U = nullptr, *S = nullptr;
@@ -159,6 +164,7 @@ void launch_gather_dots(const Hier& H, const Level& l, R* out, int64_t nvec, con
                         double* part, hipStream_t s);
 void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s);
+void launch_winv_setup(const Hier& H, const Level& l, hipStream_t s);
 void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
                         hipStream_t s);
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s);

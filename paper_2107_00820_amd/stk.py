@@ -132,13 +132,13 @@ def _dptr(*ts):
 
 
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
-              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_scale=0.0):
+              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_scale=0.0, schur=1):
     """Descriptor; vp_amp (array [d][M]^d) selects the viscoplastic Newton
     tensor over the sinker base field (coef_kind 1)."""
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
-    d.schur, d.coef_kind, d.mixed = 1, 0, int(mixed)
+    d.schur, d.coef_kind, d.mixed = int(schur), 0, int(mixed)
     if vp_amp is not None:
         amp = np.ascontiguousarray(np.asarray(vp_amp, dtype=np.float64))
         assert amp.ndim == dim + 1 and amp.shape[0] == dim and all(s == amp.shape[1] for s in amp.shape[1:])
@@ -164,7 +164,7 @@ def desc_from_workload(wl, hbm_budget=0, mixed=0):
     from workloads import OMEGA, DELTA, BETA
     vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max) if wl.coef_kind == 1 else {}
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
-                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, **vp)
+                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, schur=getattr(wl, "schur", 1), **vp)
 
 
 def stk_step_batch(hierarchies) -> int:

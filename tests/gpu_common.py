@@ -22,8 +22,12 @@ CASES = {
     # viscoplastic Newton tensor over a sinker base field (the recipe of the 3D 48^3 workload)
     "2d_16_L2_tensor": small(2, 16, 2, gamma=1e3, dr=1e6, n_sinkers=16, seed=411, coef_kind=1, fourier_seed=412),
     "3d_8_L2_tensor": small(3, 8, 2, gamma=1e4, dr=1e10, n_sinkers=24, seed=401, coef_kind=1, fourier_seed=402),
+    # W = M_p(1/mu) (preconditioner P2)
+    "2d_16_L3_p2": small(2, 16, 3, gamma=1e3, dr=1e6, n_sinkers=16, seed=421, schur=2),
+    "3d_8_L2_p2": small(3, 8, 2, gamma=1e4, dr=1e4, n_sinkers=24, seed=431, schur=2),
 }
 SCALAR_CASES = ["c1", "2d_32_L3", "3d_8_L2"]
+P2_CASES = ["2d_16_L3_p2", "3d_8_L2_p2"]
 
 
 @functools.lru_cache(maxsize=None)

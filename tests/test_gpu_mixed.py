@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from gpu_common import (CASES, SCALAR_CASES, oracle_for, gpu_for, gpu_mixed_for, to_dev, to_dev32, to_host, rel, rand_u,
+from gpu_common import (CASES, SCALAR_CASES, P2_CASES, oracle_for, gpu_for, gpu_mixed_for, to_dev, to_dev32, to_host, rel, rand_u,
                         f32, log)
 
 pytestmark = pytest.mark.gpu
@@ -168,7 +168,7 @@ def test_f32_vcycle_unaffected_by_fp64_work(name):
     assert np.array_equal(v1, v2)
 
 
-@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("name", NAMES + P2_CASES)
 def test_mixed_solve(name):
     log(f"[mixed solve] {name}")
     orc, g64, g32 = oracle_for(name), gpu_for(name), gpu_mixed_for(name)

@@ -45,6 +45,7 @@ class Workload:
     coef_kind: int = 0    # 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor
     fourier_seed: Optional[int] = None   # seed of the Fourier velocity (coef_kind 1)
     fourier_modes: int = 8               # modes per axis (coef_kind 1)
+    schur: int = 1        # W in A_gamma: 1 = M_p (preconditioner P1), 2 = M_p(1/mu) (P2)
 
     @property
     def mu_max(self) -> float:
