@@ -30,12 +30,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def kernel_source_hash() -> str:
-    """Hash of the kernel and host sources (a change invalidates stored counters)."""
+# Sources that define the star-patch GEMV kernel, its data layout and launch.
+GEMV_SOURCES = ("k_patch.hip", "stk_dev.h", "stk_internal.h", "stk_ref.h")
+
+
+def kernel_source_hash(files=GEMV_SOURCES) -> str:
+    """Hash of the sources of the measured kernel (a change invalidates stored counters)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
+    for name in sorted(files):
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
