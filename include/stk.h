@@ -173,11 +173,15 @@ stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* strea
 stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream);
 
 /* (z_u, z_p) = P (v_u, v_p): the block preconditioner of eq. (precond) with
- * two V-cycles and the cellwise Schur blocks; z_p has zero mean. mixed = 1
- * (hierarchy set up with mixed=1) runs both V-cycles in FP32 on FP32 copies
- * of their FP64 inputs; the Schur blocks, the B and B^T applies and the
- * mean projection stay FP64. */
-stk_status stk_precond(stk_hier* h, int mixed, const double* v_u, const double* v_p,
+ * two V-cycles and the cellwise Schur blocks; z_p has zero mean. Flags:
+ * STK_PC_MIXED (hierarchy set up with mixed=1) runs the V-cycles in FP32 on
+ * FP32 copies of their FP64 inputs, the Schur blocks, the B and B^T applies
+ * and the mean projection staying FP64; STK_PC_UPPER applies the block
+ * upper-triangular part instead, z_p = -Shat^{-1} v_p (mean removed),
+ * z_u = Ahat^{-1}(v_u - B^T z_p), one V-cycle (a block-triangular variant of
+ * the kind the paper's introduction cites). */
+enum { STK_PC_MIXED = 1, STK_PC_UPPER = 2 };
+stk_status stk_precond(stk_hier* h, int flags, const double* v_u, const double* v_p,
                        double* z_u, double* z_p, void* stream);
 
 typedef struct {
@@ -195,6 +199,8 @@ typedef struct {
                     hierarchy set up with mixed=1. FGMRES tolerates the
                     inexact, varying preconditioner, so the stopping test on
                     the FP64 true residual is unchanged. */
+  int pc;        /* 0 (default): the preconditioner of eq. (precond); 1: its
+                    block upper-triangular part (see stk_precond) */
 } stk_solve_opts;
 
 typedef struct {

@@ -33,14 +33,26 @@ from .multigrid import Multigrid
 
 
 class BlockPreconditioner:
-    def __init__(self, mg: Multigrid):
+    """Eq. (precond): P = [I, -Ahat^{-1}B^T; 0, I] diag(Ahat^{-1}, -Shat^{-1})
+    [I, 0; -B Ahat^{-1}, I] (kind "full", two V-cycles per application), or
+    its block upper-triangular part P = [Ahat, B^T; 0, -Shat]^{-1} (kind
+    "upper", one V-cycle; the block-triangular family the paper's
+    introduction cites), with Ahat^{-1} = one V-cycle."""
+
+    def __init__(self, mg: Multigrid, kind: str = "full"):
+        assert kind in ("full", "upper")
         self.mg = mg
+        self.kind = kind
         self.ops = mg.ops[-1]
         self.nu = self.ops.level.n_u
 
     def apply(self, v: np.ndarray) -> np.ndarray:
         ops = self.ops
         vu, vp = v[:self.nu], v[self.nu:]
+        if self.kind == "upper":
+            zp = ops.project_mean(-(ops.Shat_inv @ vp))
+            zu = self.mg.vcycle(vu - ops.B.T @ zp)
+            return np.concatenate([zu, zp])
         y = self.mg.vcycle(vu)
         zp = -(ops.Shat_inv @ (vp - ops.B @ y))
         zp = ops.project_mean(zp)
@@ -146,12 +158,13 @@ class StokesSolver:
     def rhs(self) -> np.ndarray:
         return np.concatenate([self.ops.rhs(), np.zeros(self.ops.level.n_p)])
 
-    def solve(self, b=None, rtol=None, maxit=None):
+    def solve(self, b=None, rtol=None, maxit=None, pc: str = "full"):
         wl = self.wl
         if b is None:
             b = self.rhs()
         t0 = time.perf_counter()
-        x, info = fgmres(lambda v: self.K @ v, self.pc.apply, b,
+        apply = self.pc.apply if pc == "full" else BlockPreconditioner(self.mg, pc).apply
+        x, info = fgmres(lambda v: self.K @ v, apply, b,
                          rtol=wl.rtol if rtol is None else rtol, restart=wl.restart,
                          maxit=wl.maxit if maxit is None else maxit)
         nu = self.ops.level.n_u

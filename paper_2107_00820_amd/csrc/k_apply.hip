@@ -699,7 +699,7 @@ __global__ void k_schur_setup(LevelGeo g, const double* __restrict__ mu, double 
     }
 }
 
-// z_p = -Sinv (v_p - B y) per cell.
+// z_p = -Sinv (v_p - B y) per cell (y == NULL: z_p = -Sinv v_p).
 template <int D>
 __global__ void k_schur_apply(LevelGeo g, const double* __restrict__ Sinv, const double* __restrict__ y,
                               const double* __restrict__ vp, double* __restrict__ zp) {
@@ -714,6 +714,7 @@ __global__ void k_schur_apply(LevelGeo g, const double* __restrict__ Sinv, const
   for (int m = 0; m < NP; ++m) bu[m] = 0.0;
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
+    if (!y) break;
     const int a0 = 2 * c[0] + digit(n, 0), a1 = 2 * c[1] + digit(n, 1);
     const int a2 = D == 3 ? 2 * c[2] + digit(n, 2) : 0;
     bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;

@@ -389,10 +389,20 @@ void vcycle_fine(Hier& H, const double* b, double* x, bool mixed) {
   launch_convert<float, double>(x32, x, n, H.stream);
 }
 
-// (z_u, z_p) = P (v_u, v_p), eq. (precond) with Ahat^{-1} = one V-cycle.
-void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp, bool mixed) {
+// (z_u, z_p) = P (v_u, v_p), eq. (precond) with Ahat^{-1} = one V-cycle, or
+// (upper) its block upper-triangular part: z_p = -Shat^{-1} v_p (mean
+// removed), z_u = Ahat^{-1} (v_u - B^T z_p): one V-cycle per application.
+void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp, bool mixed, bool upper) {
   const int lf = H.L - 1;
   Level& F = H.lv[lf];
+  if (upper) {
+    launch_schur_apply(H, F, nullptr, vp, zp, H.stream);             // z_p = -Shat^{-1} v_p
+    launch_project_mean(H, F, zp, H.stream);
+    launch_elem<double>(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
+    launch_gather<double>(H, F, vu, -1.0, H.pw_u, H.stream);         // v_u - B^T z_p
+    vcycle_fine(H, H.pw_u, zu, mixed);
+    return;
+  }
   vcycle_fine(H, vu, H.pw_y, mixed);                              // y = Ahat^{-1} v_u
   launch_schur_apply(H, F, H.pw_y, vp, zp, H.stream);             // z_p = -Shat^{-1}(v_p - B y)
   launch_project_mean(H, F, zp, H.stream);
@@ -411,13 +421,13 @@ void stokes_apply(Hier& H, const double* x, double* y) {
 
 // One FGMRES Arnoldi step j with restart m: Z_j = P V_j, w = K Z_j,
 // classical Gram-Schmidt twice against V_0..V_j, V_{j+1} = w/||w||, H column j.
-void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed) {
+void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed, bool upper) {
   double* Vj = H.fV + (int64_t)j * nvec;
   double* Zj = H.fZ + (int64_t)j * nvec;
   double* w = H.fV + (int64_t)(j + 1) * nvec;
   double* p1 = H.partials;
   double* p2 = H.partials + kPartialLen;
-  precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed);
+  precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed, upper);
   // w = K Z_j with the first Gram-Schmidt pass's dot products
   Level& F = H.lv[H.L - 1];
   launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, Zj, Zj + nu, w + nu, H.stream);
@@ -774,12 +784,14 @@ stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stre
   return STK_OK;
 }
 
-stk_status stk_precond(stk_hier* h, int mixed, const double* v_u, const double* v_p, double* z_u, double* z_p,
+stk_status stk_precond(stk_hier* h, int flags, const double* v_u, const double* v_p, double* z_u, double* z_p,
                        void* stream) {
   GET_H(h);
   if (!v_u || !v_p || !z_u || !z_p) return fail(STK_EINVAL, "NULL buffer");
+  if (flags & ~(STK_PC_MIXED | STK_PC_UPPER)) return fail(STK_EINVAL, "unknown preconditioner flags");
+  const bool mixed = (flags & STK_PC_MIXED) != 0;
   if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
-  precond(H, v_u, v_p, z_u, z_p, mixed != 0);
+  precond(H, v_u, v_p, z_u, z_p, mixed, (flags & STK_PC_UPPER) != 0);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -831,6 +843,8 @@ stk_status sv_begin(Hier& H, hipStream_t caller, const double* b_u, const double
     return fail(STK_EINVAL, "bad solve options (rtol > 0, restart 1..64, maxit 1..1000)");
   const bool mixed = opts && opts->mixed;
   if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
+  if (opts && (opts->pc < 0 || opts->pc > 1)) return fail(STK_EINVAL, "pc must be 0 (full) or 1 (upper)");
+  const bool upper = opts && opts->pc == 1;
   STKCHK(ensure_pinned(H));
   Level& F = H.lv[H.L - 1];
   const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
@@ -854,6 +868,7 @@ stk_status sv_begin(Hier& H, hipStream_t caller, const double* b_u, const double
   S.maxit = maxit;
   S.rtol = rtol;
   S.mixed = mixed;
+  S.upper = upper;
   S.graphs = !(opts && opts->eager);
   S.x_u = x_u;
   S.x_p = x_p;
@@ -910,21 +925,22 @@ stk_status sv_enqueue(Hier& H) {
   if (S.phase == Hier::SV_ARNOLDI) {
     const int j = S.j;
     if (j == 0) launch_axpby<double>(1.0 / S.beta, rvec, 0.0, rvec, H.fV, nvec, s);
+    const int key = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0);
     if (!S.graphs) {
-      arnoldi_step(H, j, m, nu, nvec, S.mixed);
+      arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper);
     } else {
-      if (H.steps_m != m || H.steps_mixed != (int)S.mixed) {
+      if (H.steps_m != m || H.steps_key != key) {
         drop_graphs(H);
         H.steps.assign(m, nullptr);
         H.steps_m = m;
-        H.steps_mixed = (int)S.mixed;
+        H.steps_key = key;
       }
       if (!H.steps[j]) {
         const bool prof_on = H.prof.on;
         H.prof.on = false;   // no event records inside captured graphs
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        arnoldi_step(H, j, m, nu, nvec, S.mixed);
+        arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper);
         const hipError_t ce = hipStreamEndCapture(s, &graph);
         H.prof.on = prof_on;
         if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));

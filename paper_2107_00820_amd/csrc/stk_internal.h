@@ -118,7 +118,7 @@ struct Hier {
   hipStream_t own = nullptr;
   std::vector<hipGraphExec_t> steps;
   int steps_m = 0;
-  int steps_mixed = 0;
+  int steps_key = 0;      // preconditioner variant the graphs were captured for
   // mixed form: FP32 copies exist; fine-level FP32 V-cycle input/output
   int mixed = 0;
   double *mb = nullptr, *mx = nullptr;
@@ -131,7 +131,7 @@ struct Hier {
     int phase = SV_IDLE;
     int status = 0;
     int m = 30, maxit = 300, j = 0, k = 0, it = 0;
-    bool mixed = false, graphs = true, converged = false;
+    bool mixed = false, upper = false, graphs = true, converged = false;
     double rtol = 1e-8, bnorm = 0.0, beta = 0.0, t_solve = 0.0;
     double *x_u = nullptr, *x_p = nullptr;
     std::vector<double> Hh, cs, sn, g, hist;

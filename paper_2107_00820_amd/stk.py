@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libstk.so")
 
 STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ENOTCONV, STK_ENOTSPD, STK_ENAN, STK_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 STK_F64, STK_F32 = 0, 1
+STK_PC_MIXED, STK_PC_UPPER = 1, 2
+_PC = {"full": 0, "upper": 1}
 _NAMES = {0: "STK_OK", -1: "STK_EINVAL", -2: "STK_ENOMEM", -3: "STK_EDEVICE", -4: "STK_ENOTCONV",
           -5: "STK_ENOTSPD", -6: "STK_ENAN", -7: "STK_EBUSY"}
 
@@ -47,7 +49,7 @@ class Desc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("eager", C.c_int),
-                ("mixed", C.c_int)]
+                ("mixed", C.c_int), ("pc", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -271,20 +273,21 @@ class Hierarchy:
         _check(load().stk_vcycle(self._h, *_dptr(b, x), _stream()))
         return x
 
-    def stk_precond(self, vu, vp, zu=None, zp=None, mixed=False):
+    def stk_precond(self, vu, vp, zu=None, zp=None, mixed=False, pc="full"):
         zu = self.zeros_u() if zu is None else zu
         zp = self.zeros_p() if zp is None else zp
-        _check(load().stk_precond(self._h, 1 if mixed else 0, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
+        flags = (STK_PC_MIXED if mixed else 0) | (STK_PC_UPPER if pc == "upper" else 0)
+        _check(load().stk_precond(self._h, flags, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
         return zu, zp
 
     # ---- serving (resumable solves)
     def stk_solve_begin(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, eager=False,
-                        mixed=False):
+                        mixed=False, pc="full"):
         """Starts a solve; the returned output tensors are filled once
         stk_poll reports completion."""
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0)
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc])
         self._solve_refs = (bu, bp, xu, xp)        # keep the buffers alive while the solve runs
         _check(load().stk_solve_begin(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu),
                                       _ptr(xp), C.byref(opts), _stream()))
@@ -311,10 +314,10 @@ class Hierarchy:
         return n.value, ms.value, by.value
 
     def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False,
-                  eager=False, mixed=False):
+                  eager=False, mixed=False, pc="full"):
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0)
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc])
         info = SolveInfo()
         st = load().stk_solve(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu), _ptr(xp),
                               C.byref(opts), C.byref(info), _stream())

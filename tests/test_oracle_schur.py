@@ -112,3 +112,35 @@ def test_exact_block_gives_triangular_spectrum():
     assert np.abs(PK[nu:, :nu]).max() < 1e-9
     Sg = B @ Ainv @ B.T
     assert np.allclose(PK[nu:, nu:], Sinv @ Sg, atol=1e-9)
+
+
+def test_upper_triangular_block_preconditioner():
+    """The upper block-triangular variant with an exact inner solve equals the
+    dense solve of [[A_gamma, B^T], [0, -Shat]] (pressure data chosen so that
+    the mean projection is inactive), and as an FGMRES preconditioner it
+    reaches the direct solution."""
+    from types import SimpleNamespace
+    import scipy.sparse.linalg as spla
+    from oracle.krylov import BlockPreconditioner, StokesSolver
+    from workloads import small
+    gamma = 50.0
+    ops, Z = setup(2, 3, gamma, schur=1)
+    nu, npres = ops.level.n_u, ops.level.n_p
+    A = dense(ops.Agamma)
+    B = dense(ops.B)
+    S = np.linalg.inv(dense(ops.Shat_inv))
+    lu = spla.splu(ops.Agamma.tocsc())
+    fake_mg = SimpleNamespace(ops=[ops], vcycle=lambda r: lu.solve(r))
+    pc = BlockPreconditioner(fake_mg, "upper")
+    rng = np.random.default_rng(3)
+    p0 = ops.project_mean(rng.standard_normal(npres))
+    v = np.concatenate([rng.standard_normal(nu), S @ p0])
+    U = np.block([[A, B.T], [np.zeros((npres, nu)), -S]])
+    assert np.allclose(pc.apply(v), np.linalg.solve(U, v), rtol=1e-9, atol=1e-11)
+    wl = small(2, 8, 2, gamma=1e3, dr=1e4, n_sinkers=4, seed=3)
+    st = StokesSolver(wl)
+    from oracle.direct import solve_direct
+    x_d = solve_direct(st.ops, st.ops.rhs())
+    x, info = st.solve(rtol=1e-11, pc="upper")
+    assert info["converged"]
+    assert np.linalg.norm(x - x_d) <= 1e-8 * np.linalg.norm(x_d)
