@@ -85,12 +85,13 @@ def measured_traffic(wl, form):
     return None, "kernel not in the counter summary"
 
 
-def serving_leg(n, budget_gb):
+def serving_leg(n, budget_gb, pc="full"):
     from workloads import serving_stream
     from paper_2107_00820_amd.serve import Server
     reqs = serving_stream(n)
-    log(f"[bench] serving {n} requests, budget {budget_gb} GB")
-    out = Server(hbm_budget=int(budget_gb * 2 ** 30), max_active=16).run(reqs)
+    log(f"[bench] serving {n} requests, budget {budget_gb} GB, preconditioner {pc}")
+    out = Server(hbm_budget=int(budget_gb * 2 ** 30), max_active=16, pc=pc).run(reqs)
+    out["pc"] = pc
     res = out.pop("results")
     out["iterations_mean"] = sum(r.iters for r in res) / max(len(res), 1)
     out["unknowns_total"] = sum(r.unknowns for r in res if r.converged)
@@ -113,6 +114,7 @@ def main():
                     help="skip the block upper-triangular preconditioner variant")
     ap.add_argument("--serving", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--serving-pc", default="full", choices=["full", "upper"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -210,7 +212,7 @@ def main():
            "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res},
            "roofline": roofline}
     if args.serving > 0:
-        out["serving"] = serving_leg(args.serving, args.budget_gb)
+        out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, r["iterations"])

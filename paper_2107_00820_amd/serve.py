@@ -64,7 +64,8 @@ class Server:
     """Admission by footprint, resident per-request state, per-phase stepping."""
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 16, setup_workers: int = 2,
-                 mixed: bool = False, keep_solutions: bool = False, rtol: float = 1e-8, eager: bool = True):
+                 mixed: bool = False, keep_solutions: bool = False, rtol: float = 1e-8, eager: bool = True,
+                 pc: str = "full"):
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.setup_workers = int(setup_workers)
@@ -72,6 +73,7 @@ class Server:
         self.keep = bool(keep_solutions)
         self.rtol = rtol
         self.eager = bool(eager)
+        self.pc = pc
 
     def _setup(self, wl):
         import torch
@@ -134,7 +136,8 @@ class Server:
                         used -= r.footprint
                         continue
                     bu, bp = h.stk_rhs()
-                    xu, xp = h.stk_solve_begin(bu, bp, rtol=self.rtol, mixed=self.mixed, eager=self.eager)
+                    xu, xp = h.stk_solve_begin(bu, bp, rtol=self.rtol, mixed=self.mixed, eager=self.eager,
+                                               pc=self.pc)
                     r.started = now()
                     active.append((i, h, xu, xp))
                 peak_active = max(peak_active, len(active))
