@@ -91,7 +91,9 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
   A[idx] = v;
 }
 
-// Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64).
+// Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64) through its Cholesky
+// factor (accurate to about kappa eps; Gauss-Jordan without pivoting loses
+// more on the ill-conditioned coarse blocks).
 __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
                                                       double* __restrict__ Pinv, int* __restrict__ flag) {
   __shared__ double a[kT * kLd];
@@ -181,18 +183,41 @@ __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ 
       }
 }
 
-// A_IJ -= W_I C_J^T for every lower tile with I, J != K.
+// A_IJ -= W_I C_J^T for every lower tile with I, J != K. The MFMA operands
+// are read straight from global memory (W_I and C_J are shared by a whole
+// block row / column and stay in L2), so there is no LDS staging or barrier.
 __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
-  __shared__ double X[kT * kLd];
-  __shared__ double Y[kT * kLd];
   int I, J;
   tile_ij(blockIdx.x, I, J);
   if (I == K || J == K) return;
-  stage_full(W + (int64_t)I * kTT, X);
-  stage_panel(A, J, K, Y);
-  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const double* X = W + (int64_t)I * kTT;                  // X[r][k] at r*64 + k
+  const bool below = J > K;                                 // C_J = A_JK (tile (J,K)) or (A_KJ)^T (tile (K,J))
+  const double* Ct = below ? tile_ptr(A, J, K) : tile_ptr(A, K, J);
   d4 acc[2][2];
-  tile_gemm_xyt(X, Y, acc);
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < kT; k0 += 4) {
+    const int k = k0 + lk;
+    const double a0 = X[(rb + li) * kT + k], a1 = X[(rb + 16 + li) * kT + k];
+    double b0, b1;
+    if (below) {
+      b0 = Ct[(cb + li) * kT + k];
+      b1 = Ct[(cb + 16 + li) * kT + k];
+    } else {
+      b0 = Ct[k * kT + cb + li];
+      b1 = Ct[k * kT + cb + 16 + li];
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
   double* T = tile_ptr(A, I, J);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -304,7 +329,9 @@ int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipS
   double* Pinv = work;
   double* W = work + kTT;
   for (int K = 0; K < nb; ++K) {
-    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, H.flag);
+    // one wavefront: the inversion is a chain of small dependent steps, so
+    // barriers across more waves cost more than the extra lanes give
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(64), 0, s, A, K, Pinv, H.flag);
     hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
     hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, W);
     hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
