@@ -10,7 +10,7 @@ mixed form (FP32 V-cycles inside FP64 FGMRES); `value` is the faster one and
 of the preconditioner (one V-cycle per iteration; not used for `value`).
 Setup is timed separately. Prints one JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--form both|fp64|mixed]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config sinker_2d_128sq_L4] [--form both|fp64|mixed]
                 [--no-cpu-baseline] [--serving N] [--budget-gb G]
 
 --serving N adds a `serving` object: the first N requests of the seeded
@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="sinker_2d_128sq_L4")
     ap.add_argument("--form", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",

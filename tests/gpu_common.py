@@ -16,7 +16,7 @@ def log(msg: str):
 
 
 CASES = {
-    "c1": CONFIGS["c1"],
+    "sinker_2d_16sq_L2": CONFIGS["sinker_2d_16sq_L2"],
     "2d_32_L3": small(2, 32, 3, gamma=1e3, dr=1e6, n_sinkers=16, seed=201),
     "3d_8_L2": small(3, 8, 2, gamma=1e4, dr=1e8, n_sinkers=24, seed=301),
     # viscoplastic Newton tensor over a sinker base field (the recipe of the 3D 48^3 workload)
@@ -26,7 +26,7 @@ CASES = {
     "2d_16_L3_p2": small(2, 16, 3, gamma=1e3, dr=1e6, n_sinkers=16, seed=421, schur=2),
     "3d_8_L2_p2": small(3, 8, 2, gamma=1e4, dr=1e4, n_sinkers=24, seed=431, schur=2),
 }
-SCALAR_CASES = ["c1", "2d_32_L3", "3d_8_L2"]
+SCALAR_CASES = ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2"]
 P2_CASES = ["2d_16_L3_p2", "3d_8_L2_p2"]
 
 

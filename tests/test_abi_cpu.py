@@ -27,23 +27,23 @@ def test_library_exports_every_declared_symbol():
 
 def test_footprint_and_validation():
     from paper_2107_00820_amd import stk
-    d = stk.desc_from_workload(CONFIGS["c2"])
+    d = stk.desc_from_workload(CONFIGS["sinker_2d_128sq_L4"])
     fp = stk.stk_footprint(d)
     # packed interior inverses alone: 16129 patches of 18x18
     assert fp > 16129 * 171 * 8
     assert fp < 2 ** 30
-    d3 = stk.desc_from_workload(CONFIGS["c3"])
+    d3 = stk.desc_from_workload(CONFIGS["sinker_3d_32cu_L3"])
     assert stk.stk_footprint(d3) > 29791 * (81 * 82 // 2) * 8
-    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad = stk.desc_from_workload(CONFIGS["sinker_2d_128sq_L4"])
     bad.n_fine = 100          # not a multiple of 2^(levels-1)
     with pytest.raises(stk.StkError) as e:
         stk.stk_footprint(bad)
     assert e.value.status == stk.STK_EINVAL
-    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad = stk.desc_from_workload(CONFIGS["sinker_2d_128sq_L4"])
     bad.sinker.mu_min = -1.0
     with pytest.raises(stk.StkError):
         stk.stk_footprint(bad)
-    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad = stk.desc_from_workload(CONFIGS["sinker_2d_128sq_L4"])
     bad.nu_pre = 9
     with pytest.raises(stk.StkError):
         stk.stk_footprint(bad)
@@ -52,7 +52,7 @@ def test_footprint_and_validation():
 def test_setup_rejects_budget_before_touching_the_device():
     from paper_2107_00820_amd import stk
     import ctypes
-    d = stk.desc_from_workload(CONFIGS["c1"], hbm_budget=1024)
+    d = stk.desc_from_workload(CONFIGS["sinker_2d_16sq_L2"], hbm_budget=1024)
     h = ctypes.c_void_p()
     st = stk.load().stk_setup_hierarchy(ctypes.byref(d), None, ctypes.byref(h))
     assert st == stk.STK_ENOMEM and not h.value
@@ -64,7 +64,7 @@ def test_tensor_and_mixed_descriptors():
     point on every level; the mixed form adds FP32 copies. Bad tensor
     parameters are rejected on the host."""
     from paper_2107_00820_amd import stk
-    wl = CONFIGS["c4"]
+    wl = CONFIGS["viscoplastic_3d_48cu_L3"]
     d_t = stk.desc_from_workload(wl)
     assert d_t.coef_kind == 1 and d_t.vp.modes == wl.fourier_modes
     d_s = stk.desc_from_workload(wl)
@@ -81,7 +81,7 @@ def test_tensor_and_mixed_descriptors():
     bad.vp.tau_y = 0.0
     with pytest.raises(stk.StkError):
         stk.stk_footprint(bad)
-    bad = stk.desc_from_workload(CONFIGS["c2"])
+    bad = stk.desc_from_workload(CONFIGS["sinker_2d_128sq_L4"])
     bad.mixed = 2
     with pytest.raises(stk.StkError):
         stk.stk_footprint(bad)

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def pair():
     from oracle.krylov import StokesSolver
     from paper_2107_00820_amd import Hierarchy
-    wl = CONFIGS["c2"]
+    wl = CONFIGS["sinker_2d_128sq_L4"]
     log("[fullsize] oracle setup c2")
     orc = StokesSolver(wl)
     log("[fullsize] gpu setup c2")

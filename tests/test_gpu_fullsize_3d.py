@@ -27,7 +27,7 @@ def _coef(wl, lv):
     return ViscoplasticNewton.from_workload(wl, lv.quad_points())
 
 
-@pytest.mark.parametrize("name", ["c3", "c4"])
+@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3"])
 def test_fullsize_sampled(name):
     import torch
     from oracle.fem import Level

@@ -203,11 +203,11 @@ def test_mixed_solve(name):
 def test_f32_rejected_without_mixed_tables():
     import torch
     from paper_2107_00820_amd.stk import StkError
-    gpu = gpu_for("c1")
-    lv = oracle_for("c1").mg.hier[-1]
+    gpu = gpu_for("sinker_2d_16sq_L2")
+    lv = oracle_for("sinker_2d_16sq_L2").mg.hier[-1]
     _, us = rand_u(lv, 1)
     with pytest.raises(StkError):
-        gpu.stk_apply_Agamma(CASES["c1"].levels - 1, to_dev32(us))
+        gpu.stk_apply_Agamma(CASES["sinker_2d_16sq_L2"].levels - 1, to_dev32(us))
     bu, bp = gpu.stk_rhs()
     with pytest.raises(StkError):
         gpu.stk_solve(bu, bp, mixed=True)

@@ -176,7 +176,7 @@ def test_solve_matches_oracle(name):
     assert np.array_equal(to_host(xu2), to_host(xu)) and np.array_equal(to_host(xp2), to_host(xp))
 
 
-@pytest.mark.parametrize("name", ["c1", "2d_32_L3", "3d_8_L2", "3d_8_L2_tensor"])
+@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2", "3d_8_L2_tensor"])
 def test_solve_upper_matches_oracle(name):
     """FGMRES with the block upper-triangular preconditioner: same iteration
     count as the oracle's, solution within 1e-8, true residual checked with
@@ -196,7 +196,7 @@ def test_solve_upper_matches_oracle(name):
     assert np.linalg.norm(b - orc.K @ x) <= wl.rtol * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("name", ["c1", "3d_8_L2"])
+@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "3d_8_L2"])
 def test_graph_replay_matches_eager(name):
     """Each Arnoldi step is captured once as a HIP graph and replayed; every
     replay must reproduce the plain-launch solve bit for bit, also with

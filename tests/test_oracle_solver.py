@@ -27,8 +27,8 @@ def test_fgmres_routine_on_small_system():
     assert info["rel_res"] <= 1e-12
 
 
-@pytest.mark.parametrize("wl", [CONFIGS["c1"], small(3, 4, 2, gamma=1e3, dr=1e4, n_sinkers=3)],
-                         ids=["c1", "3d_4cu"])
+@pytest.mark.parametrize("wl", [CONFIGS["sinker_2d_16sq_L2"], small(3, 4, 2, gamma=1e3, dr=1e4, n_sinkers=3)],
+                         ids=["sinker_2d_16sq_L2", "3d_4cu"])
 def test_fgmres_solution_matches_direct(wl):
     s = StokesSolver(wl)
     x, info = s.solve()
@@ -172,7 +172,7 @@ def test_manufactured_solution_rates():
 
 # --------------------------------------------------------------------------- viscoplastic tensor
 def _vp(dim=3):
-    wl = CONFIGS["c4"]
+    wl = CONFIGS["viscoplastic_3d_48cu_L3"]
     lv = Level(dim, 4)
     base = SinkerField(np.random.default_rng(0).random((4, dim)), 1e-5, 1e5, omega=0.3)
     vel = FourierVelocity(np.random.default_rng(1).standard_normal((dim,) + (3,) * dim), 1.0)

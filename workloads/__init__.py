@@ -85,13 +85,13 @@ def fourier_amplitudes(dim: int, modes: int, seed: int) -> np.ndarray:
 
 CONFIGS = {
     # 2D 16x16, 2 levels, V(2,2), gamma 1e2, 4 sinkers, DR 1e2
-    "c1": Workload("c1_2d_16sq_L2", 2, 16, 2, 4, 1e2, 1e2, 101),
+    "sinker_2d_16sq_L2": Workload("sinker_2d_16sq_L2", 2, 16, 2, 4, 1e2, 1e2, 101),
     # 2D 128x128, 4 levels, 16 sinkers, DR 1e6, gamma 1e3, FGMRES(30) to 1e-8
-    "c2": Workload("c2_2d_128sq_L4", 2, 128, 4, 16, 1e6, 1e3, 201),
+    "sinker_2d_128sq_L4": Workload("sinker_2d_128sq_L4", 2, 128, 4, 16, 1e6, 1e3, 201),
     # 3D 32^3, 3 levels, 24 sinkers, DR 1e8, gamma 1e4
-    "c3": Workload("c3_3d_32cu_L3", 3, 32, 3, 24, 1e8, 1e4, 301),
+    "sinker_3d_32cu_L3": Workload("sinker_3d_32cu_L3", 3, 32, 3, 24, 1e8, 1e4, 301),
     # 3D 48^3, 3 levels, viscoplastic Newton tensor over a 24-sinker base field, DR 1e10
-    "c4": Workload("c4_3d_48cu_L3_tensor", 3, 48, 3, 24, 1e10, 1e4, 401,
+    "viscoplastic_3d_48cu_L3": Workload("viscoplastic_3d_48cu_L3", 3, 48, 3, 24, 1e10, 1e4, 401,
                    coef_kind=1, fourier_seed=402),
 }
 
