@@ -92,8 +92,7 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
 }
 
 // Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64) through its Cholesky
-// factor (accurate to about kappa eps; Gauss-Jordan without pivoting loses
-// more on the ill-conditioned coarse blocks).
+// factor (accurate to about kappa eps).
 __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
                                                       double* __restrict__ Pinv, int* __restrict__ flag) {
   __shared__ double a[kT * kLd];
@@ -261,36 +260,67 @@ __global__ void k_coarse_gather(LevelGeo g, int64_t n, int64_t npad, const R* __
 }
 
 // One workgroup per stored tile (I, J): part[I][J] = T x_J and, below the
-// diagonal, part[J][I] = T^T x_I (each slot written exactly once).
+// diagonal, part[J][I] = T^T x_I (each slot written exactly once). Thread
+// (tr, tc) = (t / 16, t % 16) holds the 4 x 4 block rows 4tr.., columns
+// 4tc.. in registers (a wavefront reads 16 full rows, 512 contiguous bytes
+// each); row sums are reduced across the 16 threads of a row band, column
+// sums across the 4 bands of a wavefront and then the 4 wavefronts, all in a
+// fixed order.
 __global__ void __launch_bounds__(256) k_coarse_tile_gemv(const double* __restrict__ A, int nb,
                                                            const double* __restrict__ bc,
                                                            double* __restrict__ part) {
-  __shared__ double Ts[kT * kLd];
-  __shared__ double xj[kT], xi[kT];
+  __shared__ double vs[4][kT];
   int I, J;
   tile_ij(blockIdx.x, I, J);
   const double* T = tile_ptr(A, I, J);
-  for (int e = threadIdx.x; e < kTT; e += blockDim.x) Ts[(e / kT) * kLd + e % kT] = T[e];
-  if (threadIdx.x < kT) {
-    xj[threadIdx.x] = bc[(int64_t)J * kT + threadIdx.x];
-    xi[threadIdx.x] = bc[(int64_t)I * kT + threadIdx.x];
-  }
-  __syncthreads();
-  const int q = threadIdx.x & 3, r = threadIdx.x >> 2;   // 4 threads per row / column
-  double u = 0.0, v = 0.0;
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15, wave = t >> 6;
+  const double* xj = bc + (int64_t)J * kT;
+  const double* xi = bc + (int64_t)I * kT;
+  double m[4][4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int c = q * 16 + k;
-    u += Ts[r * kLd + c] * xj[c];
-    v += Ts[c * kLd + r] * xi[c];
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) m[a][b] = T[(4 * tr + a) * kT + 4 * tc + b];
+  double xc[4], xr[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) xc[b] = xj[4 * tc + b];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) xr[a] = xi[4 * tr + a];
+  double u[4], v[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    u[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) u[a] += m[a][b] * xc[b];
   }
-  u += __shfl_xor(u, 1, 64);
-  u += __shfl_xor(u, 2, 64);
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  if (q == 0) {
-    part[((int64_t)I * nb + J) * kT + r] = u;
-    if (I != J) part[((int64_t)J * nb + I) * kT + r] = v;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    v[b] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[b] += m[a][b] * xr[a];
+  }
+  // rows: sum over the 16 lanes tc of this row band (lanes 16*band .. +15)
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) u[a] += __shfl_xor(u[a], off, 64);
+  if (tc == 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) part[((int64_t)I * nb + J) * kT + 4 * tr + a] = u[a];
+  }
+  if (I != J) {
+    // columns: the 4 row bands of this wavefront (lane bits 4, 5), then the 4 wavefronts
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      v[b] += __shfl_xor(v[b], 16, 64);
+      v[b] += __shfl_xor(v[b], 32, 64);
+    }
+    if ((t & 48) == 0) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) vs[wave][4 * tc + b] = v[b];
+    }
+    __syncthreads();
+    if (t < kT) part[((int64_t)J * nb + I) * kT + t] = (vs[0][t] + vs[1][t]) + (vs[2][t] + vs[3][t]);
   }
 }
 
@@ -329,9 +359,7 @@ int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipS
   double* Pinv = work;
   double* W = work + kTT;
   for (int K = 0; K < nb; ++K) {
-    // one wavefront: the inversion is a chain of small dependent steps, so
-    // barriers across more waves cost more than the extra lanes give
-    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(64), 0, s, A, K, Pinv, H.flag);
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, H.flag);
     hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
     hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, W);
     hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
