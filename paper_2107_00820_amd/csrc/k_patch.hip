@@ -16,9 +16,11 @@
 // ((s/64)*P + k)*64 + s%64 (P = n(n+1)/2), so a wavefront processing 64
 // patches reads 512 contiguous bytes per element.
 //
-// Apply (one lane per patch): gather the patch residual, symmetric GEMV from
-// the packed inverse, write the result into a vertex-indexed buffer; a node
-// kernel then sums the <= 2^d overlapping patch results in a fixed order.
+// Apply: gather the patch residual, symmetric GEMV from the packed inverse,
+// write the result into a vertex-indexed buffer; a node kernel then sums the
+// <= 2^d overlapping patch results in a fixed order. One lane per patch,
+// except the 81-unknown 3D interior patches, whose GEMV four wavefronts
+// share (split_symv81).
 #include <utility>
 
 #include "stk_dev.h"
@@ -82,59 +84,98 @@ constexpr int tri_row(int e) {
   return i;
 }
 
-// x staged in LDS (column `lane` of xs[NPT][64]); used for the 81-unknown 3D
-// patches, where x and y together would not fit the register file. Each lane
-// reads only its own column, so no barrier is needed. The 3321 packed
-// elements stream in chunks of CH with the next chunk's loads issued before
-// the current chunk's arithmetic (scheduling barriers keep the compiler from
-// hoisting all loads at once, which would spill).
-template <int NPT, int CH, int C, class X, class R>
+// A piece of the packed lower triangle: the elements (i, j), j <= i, with
+// row_lo <= i < row_hi and col_lo <= j < col_hi, enumerated row by row. A
+// piece is either a triangle (col range = row range) or a block left of the
+// diagonal (col_hi <= row_lo). The result rows it touches are kept in ny
+// slots: slot(i) = i - row_lo for a triangle; for a block the column rows
+// first (i - col_lo), then the rows (col_hi - col_lo + i - row_lo).
+template <int RL, int RH, int CL, int CH>
+struct TriPiece {
+  static_assert((CL == RL && CH == RH) || CH <= RL, "triangle or block below the diagonal");
+  static constexpr bool tri = CL == RL && CH == RH;
+  static constexpr int ny = tri ? RH - RL : (CH - CL) + (RH - RL);
+  static constexpr int slot(int i) { return tri ? i - RL : (i < CH ? i - CL : (CH - CL) + (i - RL)); }
+  static constexpr int row_len(int i) {
+    const int b = i + 1 < CH ? i + 1 : CH;
+    return b > CL ? b - CL : 0;
+  }
+  static constexpr int count() {
+    int n = 0;
+    for (int i = RL; i < RH; ++i) n += row_len(i);
+    return n;
+  }
+  // packed index i(i+1)/2 + j of the t-th element
+  static constexpr int elem(int t) {
+    int i = RL;
+    while (t >= row_len(i)) t -= row_len(i++);
+    return i * (i + 1) / 2 + CL + t;
+  }
+};
+template <int NPT>
+using FullTri = TriPiece<0, NPT, 0, NPT>;
+
+// The elements of the piece stream in chunks of CH with the next chunk's
+// loads issued before the current chunk's arithmetic (scheduling barriers
+// keep the compiler from hoisting all loads at once, which would spill).
+template <class PC, int CH, int C, class R>
 __device__ __attribute__((always_inline)) inline void symv_chunk_load(const R* __restrict__ A, R (&buf)[CH]) {
-  constexpr int NE = NPT * (NPT + 1) / 2;
   static_for<CH>([&](auto T) {
-    constexpr int e = C * CH + T;
-    if constexpr (e < NE) buf[T] = A[(int64_t)e * 64];
+    constexpr int t = C * CH + T;
+    if constexpr (t < PC::count()) {
+      constexpr int e = PC::elem(t);   // folded at compile time
+      buf[T] = A[(int64_t)e * 64];
+    }
   });
 }
 
-template <int NPT, int CH, int C, class X, class R>
-__device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x, const R (&buf)[CH], R (&y)[NPT]) {
-  constexpr int NE = NPT * (NPT + 1) / 2;
+template <class PC, int CH, int C, class X, class R>
+__device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x, const R (&buf)[CH],
+                                                                     R (&y)[PC::ny]) {
   static_for<CH>([&](auto T) {
-    constexpr int e = C * CH + T;
-    if constexpr (e < NE) {
+    constexpr int t = C * CH + T;
+    if constexpr (t < PC::count()) {
+      constexpr int e = PC::elem(t);
       constexpr int i = tri_row(e);
       constexpr int j = e - i * (i + 1) / 2;
       if constexpr (j != i) {
-        y[i] += buf[T] * x(j);
-        y[j] += buf[T] * x(i);
+        y[PC::slot(i)] += buf[T] * x(j);
+        y[PC::slot(j)] += buf[T] * x(i);
       } else {
-        y[i] += buf[T] * x(i);
+        y[PC::slot(i)] += buf[T] * x(i);
       }
     }
   });
 }
 
-template <int NPT, int CH, class X, class R>
-__device__ __attribute__((always_inline)) inline void packed_symv_chunked(const R* __restrict__ A, const X& xr,
-                                                                          R (&y)[NPT]) {
-  constexpr int NE = NPT * (NPT + 1) / 2;
-  constexpr int NC = (NE + CH - 1) / CH;
+// y = (piece PC of A) x over the piece's result slots, counting each
+// off-diagonal element for both (i, j) and (j, i).
+template <int CH, class PC, class X, class R>
+__device__ __attribute__((always_inline)) inline void piece_symv(const R* __restrict__ A, const X& xr,
+                                                                 R (&y)[PC::ny]) {
+  constexpr int NC = (PC::count() + CH - 1) / CH;
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) y[i] = (R)0;
+  for (int i = 0; i < PC::ny; ++i) y[i] = (R)0;
   R b0[CH], b1[CH];
-  symv_chunk_load<NPT, CH, 0, X>(A, b0);
+  symv_chunk_load<PC, CH, 0>(A, b0);
   static_for<NC>([&](auto C) {
     constexpr int c = C;
     if constexpr (c + 1 < NC) {
-      if constexpr ((c & 1) == 0) symv_chunk_load<NPT, CH, c + 1, X>(A, b1);
-      else symv_chunk_load<NPT, CH, c + 1, X>(A, b0);
+      if constexpr ((c & 1) == 0) symv_chunk_load<PC, CH, c + 1>(A, b1);
+      else symv_chunk_load<PC, CH, c + 1>(A, b0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr ((c & 1) == 0) symv_chunk_fma<NPT, CH, c>(xr, b0, y);
-    else symv_chunk_fma<NPT, CH, c>(xr, b1, y);
+    if constexpr ((c & 1) == 0) symv_chunk_fma<PC, CH, c>(xr, b0, y);
+    else symv_chunk_fma<PC, CH, c>(xr, b1, y);
     __builtin_amdgcn_sched_barrier(0);
   });
+}
+
+// Whole packed triangle: y = A x.
+template <int NPT, int CH, class X, class R>
+__device__ __attribute__((always_inline)) inline void packed_symv_chunked(const R* __restrict__ A, const X& xr,
+                                                                          R (&y)[NPT]) {
+  piece_symv<CH, FullTri<NPT>>(A, xr, y);
 }
 
 #ifndef STK_CH_LDS64
@@ -143,11 +184,61 @@ __device__ __attribute__((always_inline)) inline void packed_symv_chunked(const 
 #ifndef STK_CH_LDS32
 #define STK_CH_LDS32 32
 #endif
-template <int NPT, class R>
-__device__ __attribute__((always_inline)) inline void packed_symv_lds(const R* __restrict__ A, const R* xs, int lane,
-                                                                      R (&y)[NPT]) {
+
+// 81-unknown (3D interior) patch solve by the four wavefronts of a 256-thread
+// workgroup that share one 64-patch x tile in LDS (xs[81][64], column = lane).
+// The 3321 packed elements split into four pieces of 820..861: the leading
+// 40x40 triangle (touches y[0,40)), the 41x40 block below it in two column
+// halves (y[0,20) + y[40,81), y[20,40) + y[40,81)) and the trailing 41x41
+// triangle (y[40,81)). Each wavefront keeps only the rows its piece touches
+// (at most 61) and the partial results meet in the x tile once every
+// wavefront is done with it, summed in a fixed order:
+//   y[0,20) = y0 + y1,  y[20,40) = y0 + y2,  y[40,81) = (y1 + y2) + y3.
+// store(integral_constant i, value) receives each final y[i] once.
+// Every thread of the workgroup must call this (it holds barriers).
+using Q81_0 = TriPiece<0, 40, 0, 40>;    // slots: rows 0..39
+using Q81_1 = TriPiece<40, 81, 0, 20>;   // slots: rows 0..19, then 40..80
+using Q81_2 = TriPiece<40, 81, 20, 40>;  // slots: rows 20..39, then 40..80
+using Q81_3 = TriPiece<40, 81, 40, 81>;  // slots: rows 40..80
+static_assert(Q81_0::count() + Q81_1::count() + Q81_2::count() + Q81_3::count() == 81 * 82 / 2, "pieces");
+static_assert(Q81_1::ny == 61 && Q81_2::ny == 61, "slots");
+
+template <class PC, int CH, class X, class R>
+__device__ __attribute__((always_inline)) inline void piece_into(const R* __restrict__ A, const X& xr, R (&yc)[61]) {
+  R y[PC::ny];
+  piece_symv<CH, PC>(A, xr, y);
+  static_for<PC::ny>([&](auto I) { yc[I] = y[I]; });
+}
+
+template <class R, class Store>
+__device__ __attribute__((always_inline)) inline void split_symv81(const R* __restrict__ A, R* xs, int lane, int w,
+                                                                   Store&& store) {
+  constexpr int CHK = sizeof(R) == 8 ? STK_CH_LDS64 : STK_CH_LDS32;
   auto xr = [&](int j) { return xs[j * 64 + lane]; };
-  packed_symv_chunked<NPT, sizeof(R) == 8 ? STK_CH_LDS64 : STK_CH_LDS32>(A, xr, y);
+  R yc[61];
+  if (w == 0) piece_into<Q81_0, CHK>(A, xr, yc);
+  else if (w == 1) piece_into<Q81_1, CHK>(A, xr, yc);
+  else if (w == 2) piece_into<Q81_2, CHK>(A, xr, yc);
+  else piece_into<Q81_3, CHK>(A, xr, yc);
+  __syncthreads();   // every wavefront is done reading x
+  if (w == 1) {
+    static_for<20>([&](auto I) { xs[I * 64 + lane] = yc[I]; });
+    static_for<41>([&](auto I) { xs[(40 + I) * 64 + lane] = yc[20 + I]; });
+  } else if (w == 2) {
+    static_for<20>([&](auto I) { xs[(20 + I) * 64 + lane] = yc[I]; });
+  }
+  __syncthreads();
+  if (w == 0) {
+    static_for<40>([&](auto I) { store(I, yc[I] + xs[I * 64 + lane]); });
+  } else if (w == 2) {
+    static_for<41>([&](auto I) { xs[(40 + I) * 64 + lane] += yc[20 + I]; });
+  }
+  __syncthreads();
+  if (w == 3) {
+    static_for<41>([&](auto I) {
+      store(std::integral_constant<int, 40 + I>{}, xs[(40 + I) * 64 + lane] + yc[I]);
+    });
+  }
 }
 
 // x from registers (patches of up to 27 unknowns): four double-buffered chunks
@@ -156,7 +247,7 @@ __device__ __attribute__((always_inline)) inline void packed_symv(const R* __res
                                                                   R (&y)[NPT]) {
   auto xr = [&](int j) { return x[j]; };
   constexpr int NE = NPT * (NPT + 1) / 2;
-  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 24;
+  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 16;
   packed_symv_chunked<NPT, CH>(A, xr, y);
 }
 
@@ -199,31 +290,38 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
   }
 }
 
-// Interior (full) patch with x staged in LDS; all unknown indices are
-// compile-time: unknown i = comp*3^d + a + 3b + 9c sits at node 2v-1 + (a,b,c).
-template <int D, int NPT, class R>
-__device__ __attribute__((always_inline)) inline void asm_patch_lds(const LevelGeo& g, const int* __restrict__ verts, int count,
-                                     const R* __restrict__ inv, const R* __restrict__ r,
-                                     R* __restrict__ zbuf, int nvert, int s, R* xs, int lane) {
-  constexpr int NN = Dims<D>::NN;
-  if (s >= count) return;
-  const int vert = verts[s];
+// 3D interior (full) patches, 64 per 256-thread workgroup: the residual
+// restricted to each patch is staged in LDS by all four wavefronts, then
+// split_symv81 solves. All unknown indices are compile-time: unknown
+// i = comp*27 + a + 3b + 9c sits at node 2v-1 + (a,b,c). Lanes past the
+// class count take part in the barriers with a clamped vertex and store
+// nothing (the inverse storage is padded to whole blocks of 64 patches).
+template <class R>
+__device__ __attribute__((always_inline)) inline void asm_patch81(const LevelGeo& g, const int* __restrict__ verts,
+                                                                  int count, const R* __restrict__ inv,
+                                                                  const R* __restrict__ r, R* __restrict__ zbuf,
+                                                                  int nvert, int blk, R* xs, int tid) {
+  constexpr int NN = 27, NPT = 81;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int s = blk * 64 + lane;
+  const bool valid = s < count;
+  const int vert = verts[valid ? s : count - 1];
   int lo[3], ext[3], vc[3];
-  patch_box<D>(g, vert, lo, ext, vc);
-  const int64_t base = node_index<D>(g, lo[0], lo[1], lo[2]);
+  patch_box<3>(g, vert, lo, ext, vc);
+  const int64_t base = node_index<3>(g, lo[0], lo[1], lo[2]);
   const int64_t n1 = g.n1;
   static_for<NPT>([&](auto I) {
     constexpr int i = I;
     constexpr int comp = i / NN, loc = i % NN;
-    xs[i * 64 + lane] = r[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
+    if (w == (i & 3))
+      xs[i * 64 + lane] = r[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
   });
+  __syncthreads();
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
-  const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  R y[NPT];
-  packed_symv_lds<NPT>(A, xs, lane, y);
-  static_for<NPT>([&](auto I) {
-    constexpr int i = I;
-    zbuf[(int64_t)i * nvert + vert] = y[i];
+  const R* A = inv + ((int64_t)blk * P) * 64 + lane;
+  split_symv81(A, xs, lane, w, [&](auto I, R v) {
+    if (valid) zbuf[(int64_t)I * nvert + vert] = v;
   });
 }
 
@@ -237,26 +335,33 @@ struct AsmClasses {
   int first_block[5];
 };
 
+// Workgroups of 64 threads in 2D (one lane per patch); of 256 in 3D, where
+// an interior workgroup covers 64 patches (split_symv81) and a boundary one
+// 256 patches (one lane each).
+template <int D>
+constexpr int asm_threads() { return D == 2 ? 64 : 256; }
+
 template <int D, class R>
-__global__ void __launch_bounds__(64) k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r,
-                                                  R* __restrict__ zbuf, int nvert) {
+__global__ void __launch_bounds__(asm_threads<D>()) __attribute__((amdgpu_waves_per_eu(2))) k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r,
+                                                               R* __restrict__ zbuf, int nvert) {
+  constexpr int NT = asm_threads<D>();
   const int b = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
   if (b < c.first_block[1]) {
-    if (D == 2) {
-      asm_patch<D, 18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane);
+    if constexpr (D == 2) {
+      asm_patch<D, 18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + t);
     } else {
       __shared__ R xs[81 * 64];
-      asm_patch_lds<D, 81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + lane, xs, lane);
+      asm_patch81(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b, xs, t);
     }
   } else if (b < c.first_block[2]) {
-    const int s = (b - c.first_block[1]) * 64 + lane;
+    const int s = (b - c.first_block[1]) * NT + t;
     asm_patch<D, D == 2 ? 6 : 27>(g, c.verts[1], c.count[1], c.inv[1], r, zbuf, nvert, s);
   } else if (b < c.first_block[3]) {
-    const int s = (b - c.first_block[2]) * 64 + lane;
+    const int s = (b - c.first_block[2]) * NT + t;
     asm_patch<D, D == 2 ? 2 : 9>(g, c.verts[2], c.count[2], c.inv[2], r, zbuf, nvert, s);
   } else if (D == 3 && b < c.first_block[4]) {
-    const int s = (b - c.first_block[3]) * 64 + lane;
+    const int s = (b - c.first_block[3]) * NT + t;
     asm_patch<D, 3>(g, c.verts[3], c.count[3], c.inv[3], r, zbuf, nvert, s);
   }
 }
@@ -302,50 +407,58 @@ __global__ void k_asm_gather(LevelGeo g, const R* __restrict__ zbuf, int nvert, 
   y[idx] = s;
 }
 
-// Local solves of the robust transfer: for every coarse cell K (one lane),
-// z = A_K^{-1} in|_K where A_K is the star patch of the fine vertex 2K+1
+// Local solves of the robust transfer: for every coarse cell K, z =
+// A_K^{-1} in|_K where A_K is the star patch of the fine vertex 2K+1
 // (interior-patch slot lex(K)); out|_K = (accumulate ? out|_K : 0) + alpha z.
+// 2D: one lane per cell, 64-thread workgroups. 3D: 64 cells per 256-thread
+// workgroup through split_symv81; lanes past the cell count take part in
+// the barriers with a clamped cell and store nothing.
+template <int D>
+constexpr int center_threads() { return D == 2 ? 64 : 256; }
+
 template <int D, bool ACC, class R>
-__global__ void __launch_bounds__(64) k_center_solve(LevelGeo g, const R* __restrict__ inv,
-                                                      const R* __restrict__ in, R* __restrict__ out,
-                                                      double alpha_d) {
+__global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g, const R* __restrict__ inv,
+                                                                      const R* __restrict__ in, R* __restrict__ out,
+                                                                      double alpha_d) {
   const R alpha = (R)alpha_d;
   constexpr int NN = Dims<D>::NN, NPT = Dims<D>::NL;
   const int nc = g.N / 2;
   const int ncc = D == 2 ? nc * nc : nc * nc * nc;
-  const int s = blockIdx.x * 64 + threadIdx.x;
-  if (s >= ncc) return;
-  const int K0 = s % nc, K1 = (s / nc) % nc, K2 = D == 3 ? s / (nc * nc) : 0;
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 64 + lane;
+  const bool valid = s < ncc;
+  if (D == 2 && !valid) return;
+  const int sc = valid ? s : ncc - 1;
+  const int K0 = sc % nc, K1 = (sc / nc) % nc, K2 = D == 3 ? sc / (nc * nc) : 0;
   const int64_t base = node_index<D>(g, 4 * K0 + 1, 4 * K1 + 1, D == 3 ? 4 * K2 + 1 : 0);
   const int64_t n1 = g.n1;
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
-  const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  R y[NPT];
-  if constexpr (D == 2) {
-    R x[NPT];
-    static_for<NPT>([&](auto I) {
-      constexpr int i = I;
-      constexpr int comp = i / NN, loc = i % NN;
-      x[i] = in[comp * g.nnodes + base + digit(loc, 0) + n1 * digit(loc, 1)];
-    });
-    packed_symv<NPT>(A, x, y);
-  } else {
-    __shared__ R xs[NPT * 64];
-    const int lane = threadIdx.x;
-    static_for<NPT>([&](auto I) {
-      constexpr int i = I;
-      constexpr int comp = i / NN, loc = i % NN;
-      xs[i * 64 + lane] = in[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
-    });
-    packed_symv_lds<NPT>(A, xs, lane, y);
-  }
-  static_for<NPT>([&](auto I) {
+  const R* A = inv + ((int64_t)blockIdx.x * P) * 64 + lane;
+  auto offset = [&](auto I) {
     constexpr int i = I;
     constexpr int comp = i / NN, loc = i % NN;
-    const int64_t o = comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * (D == 3 ? digit(loc, 2) : 0));
-    if constexpr (ACC) out[o] += alpha * y[i];
-    else out[o] = alpha * y[i];
-  });
+    return comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * (D == 3 ? digit(loc, 2) : 0));
+  };
+  auto store = [&](auto I, R v) {
+    if (!valid) return;
+    const int64_t o = offset(I);
+    if constexpr (ACC) out[o] += alpha * v;
+    else out[o] = alpha * v;
+  };
+  if constexpr (D == 2) {
+    R x[NPT], y[NPT];
+    static_for<NPT>([&](auto I) { x[I] = in[offset(I)]; });
+    packed_symv<NPT>(A, x, y);
+    static_for<NPT>([&](auto I) { store(I, y[I]); });
+  } else {
+    __shared__ R xs[NPT * 64];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    static_for<NPT>([&](auto I) {
+      if (w == (I & 3)) xs[I * 64 + lane] = in[offset(I)];
+    });
+    __syncthreads();
+    split_symv81(A, xs, lane, w, store);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -383,7 +496,8 @@ void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
       c.verts[ci] = pc.verts;
       c.inv[ci] = class_inv<R>(pc);
       c.count[ci] = pc.count;
-      blocks += (pc.count + 63) / 64;
+      const int per = (H.dim == 2 || ci == 0) ? 64 : 256;   // patches per workgroup
+      blocks += (pc.count + per - 1) / per;
       // algorithmic bytes: packed inverse and patch output of every patch
       bytes += (double)sizeof(R) * (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
     }
@@ -396,9 +510,9 @@ void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
   // call may repeat it back to back to time it without launch gaps
   for (int k = 0; k < reps; ++k) {
     if (H.dim == 2)
-      hipLaunchKernelGGL((k_asm_gemv<2, R>), dim3(blocks), dim3(64), 0, s, l.g, c, r, zbuf, l.nvert);
+      hipLaunchKernelGGL((k_asm_gemv<2, R>), dim3(blocks), dim3(asm_threads<2>()), 0, s, l.g, c, r, zbuf, l.nvert);
     else
-      hipLaunchKernelGGL((k_asm_gemv<3, R>), dim3(blocks), dim3(64), 0, s, l.g, c, r, zbuf, l.nvert);
+      hipLaunchKernelGGL((k_asm_gemv<3, R>), dim3(blocks), dim3(asm_threads<3>()), 0, s, l.g, c, r, zbuf, l.nvert);
   }
   prof_end(H, s, PROF_ASM_GEMV, ev, bytes, reps);
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
@@ -413,7 +527,7 @@ void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, 
                          hipStream_t s) {
   const int nc = fine.g.N / 2;
   const int ncc = H.dim == 2 ? nc * nc : nc * nc * nc;
-  const dim3 grid(nblk(ncc, 64)), blk(64);
+  const dim3 grid(nblk(ncc, 64)), blk(H.dim == 2 ? center_threads<2>() : center_threads<3>());
   const R* inv = class_inv<R>(fine.cls[0]);
   if (H.dim == 2) {
     if (accumulate) hipLaunchKernelGGL((k_center_solve<2, true, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
