@@ -247,7 +247,7 @@ __device__ __attribute__((always_inline)) inline void packed_symv(const R* __res
                                                                   R (&y)[NPT]) {
   auto xr = [&](int j) { return x[j]; };
   constexpr int NE = NPT * (NPT + 1) / 2;
-  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 16;
+  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 12;
   packed_symv_chunked<NPT, CH>(A, xr, y);
 }
 
@@ -276,6 +276,10 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
   const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
   R y[NPT];
   packed_symv<NPT>(A, x, y);
+  // the scatter recomputes its indices rather than keeping the gather's
+  // (which would hold NPT index triples in registers across the GEMV)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(lo[k]), "+v"(ext[k]), "+v"(vc[k]));
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     int nd[3];
