@@ -469,6 +469,286 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* 
 }
 
 // ---------------------------------------------------------------------------
+// 3D cell kernel with the tensor-product contractions shared across lanes.
+// A wavefront handles 7 cells with 9 lanes each (lane 63 idle); in every
+// stage a lane owns one pencil of 3 points along the axis being contracted,
+// so each 1D contraction is done once per cell instead of once per Gauss
+// point. Stages exchange their pencils through LDS:
+//   gradient:   x (lane = (y,z)) -> y (lane = (qx,z)) -> z (lane = (qx,qy)),
+//               leaving lane (qx,qy) with G at its 3 points (qx,qy,0..2);
+//   pointwise:  S_q = w_q mu_q (G + G^T) [- w_q (w:G) w] + w_q pi_q I, the
+//               divergence moments summed over the cell's 9 lanes in a fixed
+//               order (every lane of the cell forms the same sum);
+//   transpose:  z (lane = (qx,qy)) -> y (lane = (qx,nz)) -> x (lane = (ny,nz)),
+//               leaving lane (ny,nz) with y at nodes (0..2,ny,nz).
+// About 1,900 FMAs per cell each way, instead of 7,300 when every Gauss point
+// forms its own gradient. Same outputs as k_elem up to rounding order.
+constexpr int kE3Cells = 7;
+
+// [cell slot][27]: slot 7 belongs to the idle lane 63. The divergence
+// moments share storage with the x-stage pencils (neither is live while the
+// other is).
+template <class R>
+struct E3Smem {
+  R u[kE3Cells + 1][3][27];
+  union {
+    R x[kE3Cells + 1][2][27];
+    R red[kE3Cells + 1][9][4];
+  };
+  R y[kE3Cells + 1][3][27];
+};
+
+__device__ constexpr int i3(int a, int b, int c) { return a + 3 * b + 9 * c; }
+
+template <int MODE, bool TENSOR, class R>
+__global__ void __launch_bounds__(64)
+k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* __restrict__ winv, double gamma_d,
+        const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
+  constexpr int NQ = 27, NL = 81, NP = 4, NS = 6;
+  constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  constexpr bool need_c = (MODE & (EL_AUG | EL_BT | EL_BOUT)) != 0;
+  __shared__ E3Smem<R> sm;
+  const R gamma = (R)gamma_d;
+  const int lane = threadIdx.x;
+  const int lc = lane / 9;                 // cell slot 0..7 (7 = idle lane)
+  const int pa = lane - 9 * lc;            // pencil: (pa % 3, pa / 3)
+  const int p0 = pa % 3, p1 = pa / 3;
+  const int64_t cell = (int64_t)blockIdx.x * kE3Cells + lc;
+  const bool valid = lc < kE3Cells && cell < g.ncell;
+  int c[3] = {0, 0, 0};
+  if (valid) {
+    c[0] = (int)(cell % g.N);
+    c[1] = (int)((cell / g.N) % g.N);
+    c[2] = (int)(cell / ((int64_t)g.N * g.N));
+  }
+  // ---- stage u: lane (y,z) = (p0,p1) loads the x-pencil of each component
+  if (need_u) {
+    const int a1 = 2 * c[1] + p0, a2 = 2 * c[2] + p1;
+    const bool bnd12 = a1 == 0 || a1 == 2 * g.N || a2 == 0 || a2 == 2 * g.N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int a0 = 2 * c[0] + a;
+      const bool bnd = bnd12 || a0 == 0 || a0 == 2 * g.N;
+      const int64_t nd = node_index<3>(g, a0, a1, a2);
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        R v = (R)0;
+        if (valid && !bnd) v = u[comp * g.nnodes + nd];
+        sm.u[lc][comp][i3(a, p0, p1)] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- gradient at the lane's Gauss points (qx,qy) = (p0,p1), qz = 0..2
+  R G[3][3][3];   // [qz][comp][k]
+#pragma unroll
+  for (int qz = 0; qz < 3; ++qz)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) G[qz][a][b] = (R)0;
+  if (need_u) {
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      // x: lane (y,z) = (p0,p1)
+      {
+        const R u0 = sm.u[lc][comp][i3(0, p0, p1)], u1 = sm.u[lc][comp][i3(1, p0, p1)],
+                u2 = sm.u[lc][comp][i3(2, p0, p1)];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          sm.x[lc][0][i3(q, p0, p1)] = u0 * (R)kB1[q][0] + u1 * (R)kB1[q][1] + u2 * (R)kB1[q][2];
+          sm.x[lc][1][i3(q, p0, p1)] = u0 * (R)kD1[q][0] + u1 * (R)kD1[q][1] + u2 * (R)kD1[q][2];
+        }
+      }
+      __syncthreads();
+      // y: lane (qx,z) = (p0,p1); outputs B_y B_x u, D_y B_x u, B_y D_x u
+      {
+        R xb[3], xd[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          xb[b] = sm.x[lc][0][i3(p0, b, p1)];
+          xd[b] = sm.x[lc][1][i3(p0, b, p1)];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          sm.y[lc][0][i3(p0, q, p1)] = xb[0] * (R)kB1[q][0] + xb[1] * (R)kB1[q][1] + xb[2] * (R)kB1[q][2];
+          sm.y[lc][1][i3(p0, q, p1)] = xb[0] * (R)kD1[q][0] + xb[1] * (R)kD1[q][1] + xb[2] * (R)kD1[q][2];
+          sm.y[lc][2][i3(p0, q, p1)] = xd[0] * (R)kB1[q][0] + xd[1] * (R)kB1[q][1] + xd[2] * (R)kB1[q][2];
+        }
+      }
+      __syncthreads();
+      // z: lane (qx,qy) = (p0,p1)
+      {
+        R ybb[3], ybd[3], ydb[3];
+#pragma unroll
+        for (int z = 0; z < 3; ++z) {
+          ybb[z] = sm.y[lc][0][i3(p0, p1, z)];
+          ybd[z] = sm.y[lc][1][i3(p0, p1, z)];
+          ydb[z] = sm.y[lc][2][i3(p0, p1, z)];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          G[q][comp][0] = ydb[0] * (R)kB1[q][0] + ydb[1] * (R)kB1[q][1] + ydb[2] * (R)kB1[q][2];
+          G[q][comp][1] = ybd[0] * (R)kB1[q][0] + ybd[1] * (R)kB1[q][1] + ybd[2] * (R)kB1[q][2];
+          G[q][comp][2] = ybb[0] * (R)kD1[q][0] + ybb[1] * (R)kD1[q][1] + ybb[2] * (R)kD1[q][2];
+        }
+      }
+      // the next component's x stage overwrites sm.x only after this
+      // component's y stage has read it (barrier above); its y stage
+      // overwrites sm.y after the barrier that follows its x stage
+    }
+  }
+  // ---- pointwise stress at (p0, p1, qz)
+  auto sel = [](int i, double a, double b, double c) { return (R)(i == 0 ? a : (i == 1 ? b : c)); };
+  const R wxy = sel(p0, kGaussW[0], kGaussW[1], kGaussW[2]) * sel(p1, kGaussW[0], kGaussW[1], kGaussW[2]);
+  const R gx = sel(p0, kGaussX[0] - 0.5, kGaussX[1] - 0.5, kGaussX[2] - 0.5);
+  const R gy = sel(p1, kGaussX[0] - 0.5, kGaussX[1] - 0.5, kGaussX[2] - 0.5);
+  R S[3][NS];
+#pragma unroll
+  for (int qz = 0; qz < 3; ++qz) {
+    const R wq = wxy * (R)kGaussW[qz];
+    const int q = i3(p0, p1, qz);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) S[qz][k] = (R)0;
+    if ((MODE & EL_VISC) && valid) {
+      const R wm = wq * mu[cell * NQ + q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) S[qz][SymIdx<3>::at(a, b)] = wm * (G[qz][a][b] + G[qz][b][a]);
+      if constexpr (TENSOR) {
+        R wv[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wv[k] = cw[(cell * NS + k) * NQ + q];
+        R wg = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          wg += wv[a] * G[qz][a][a];
+#pragma unroll
+          for (int b = a + 1; b < 3; ++b) wg += wv[SymIdx<3>::at(a, b)] * (G[qz][a][b] + G[qz][b][a]);
+        }
+        const R f = wq * wg;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) S[qz][k] -= f * wv[k];
+      }
+    }
+  }
+  if constexpr (need_c) {
+    if (MODE & (EL_AUG | EL_BOUT)) {
+      R part[NP] = {0, 0, 0, 0};
+#pragma unroll
+      for (int qz = 0; qz < 3; ++qz) {
+        const R wd = wxy * (R)kGaussW[qz] * (G[qz][0][0] + G[qz][1][1] + G[qz][2][2]);
+        part[0] += wd;
+        part[1] += wd * gx;
+        part[2] += wd * gy;
+        part[3] += wd * (R)(kGaussX[qz] - 0.5);
+      }
+#pragma unroll
+      for (int m = 0; m < NP; ++m) sm.red[lc][pa][m] = part[m];
+    }
+    __syncthreads();
+    R bu[NP] = {0, 0, 0, 0};
+    if (MODE & (EL_AUG | EL_BOUT)) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bu[m] += sm.red[lc][k][m];
+    }
+    R cm[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      cm[m] = 0;
+      if (MODE & EL_AUG) {
+        if (winv) {   // W = M_p(1/mu): the cell's inverse weighted mass
+          R t2 = 0;
+          if (valid) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) t2 += winv[cell * NP * NP + m * NP + k] * bu[k];
+          }
+          cm[m] += gamma * t2;
+        } else {
+          cm[m] += gamma * bu[m] * (R)kInvMhat[m];
+        }
+      }
+      if ((MODE & EL_BOUT) && valid && pa == 0) pout[cell * NP + m] = -(g.h * g.h) * (double)bu[m];
+      if ((MODE & EL_BT) && valid) cm[m] -= (R)g.h * (R)p[cell * NP + m];
+    }
+    if (MODE & (EL_AUG | EL_BT)) {
+#pragma unroll
+      for (int qz = 0; qz < 3; ++qz) {
+        const R wq = wxy * (R)kGaussW[qz];
+        const R pi = cm[0] + cm[1] * gx + cm[2] * gy + cm[3] * (R)(kGaussX[qz] - 0.5);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) S[qz][a] += wq * pi;
+      }
+    }
+  }
+  if constexpr (!need_c) __syncthreads();   // the z stages below overwrite sm.y
+  // ---- transpose contractions, one component at a time
+  const R h = (R)g.h;   // h^{d-2}
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    // z: lane (qx,qy) = (p0,p1) -> (qx,qy,nz)
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      R t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        t0 += S[q][SymIdx<3>::at(comp, 0)] * (R)kB1[q][n];
+        t1 += S[q][SymIdx<3>::at(comp, 1)] * (R)kB1[q][n];
+        t2 += S[q][SymIdx<3>::at(comp, 2)] * (R)kD1[q][n];
+      }
+      sm.y[lc][0][i3(p0, p1, n)] = t0;
+      sm.y[lc][1][i3(p0, p1, n)] = t1;
+      sm.y[lc][2][i3(p0, p1, n)] = t2;
+    }
+    __syncthreads();
+    // y: lane (qx,nz) = (p0,p1) -> (qx,ny,nz); outputs D_x-bound and B_x-bound parts
+    {
+      R t0[3], t1[3], t2[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        t0[q] = sm.y[lc][0][i3(p0, q, p1)];
+        t1[q] = sm.y[lc][1][i3(p0, q, p1)];
+        t2[q] = sm.y[lc][2][i3(p0, q, p1)];
+      }
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        R w0 = 0, w12 = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          w0 += t0[q] * (R)kB1[q][n];
+          w12 += t1[q] * (R)kD1[q][n] + t2[q] * (R)kB1[q][n];
+        }
+        sm.x[lc][0][i3(p0, n, p1)] = w0;
+        sm.x[lc][1][i3(p0, n, p1)] = w12;
+      }
+    }
+    __syncthreads();
+    // x: lane (ny,nz) = (p0,p1) -> nodes (0..2, ny, nz)
+    {
+      R w0[3], w12[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        w0[q] = sm.x[lc][0][i3(q, p0, p1)];
+        w12[q] = sm.x[lc][1][i3(q, p0, p1)];
+      }
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        R yv = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) yv += w0[q] * (R)kD1[q][n] + w12[q] * (R)kB1[q][n];
+        if (valid) E[cell * NL + comp * 27 + i3(n, p0, p1)] = h * yv;
+      }
+    }
+    // the next component's z stage overwrites sm.y after this component's
+    // y stage read it (barrier above) and sm.x after this x stage (the
+    // barrier that follows the next z stage)
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Sum of the element outputs of the <= 2^d cells containing stored entry idx
 // (fixed order); 0 on Dirichlet nodes (flag set).
 template <int D, class R>
@@ -805,15 +1085,25 @@ const float* level_winv<float>(const Level& l) { return l.winv32; }
 
 template <int D, int MODE, class R>
 static void elem_launch(const Hier& H, const Level& l, const R* u, const double* p, double* pout, hipStream_t s) {
-  constexpr int CPW = 64 / Dims<D>::NQ;
-  const dim3 grid(nblk(l.g.ncell, CPW));
   const R* wi = level_winv<R>(l);
-  if ((MODE & EL_VISC) && l.cw)
-    hipLaunchKernelGGL((k_elem<D, MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l), wi,
-                       H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
-  else
-    hipLaunchKernelGGL((k_elem<D, MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr, wi,
-                       H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+  if constexpr (D == 3) {
+    const dim3 grid(nblk(l.g.ncell, kE3Cells));
+    if ((MODE & EL_VISC) && l.cw)
+      hipLaunchKernelGGL((k_elem3<MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l), wi,
+                         H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+    else
+      hipLaunchKernelGGL((k_elem3<MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr,
+                         wi, H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+  } else {
+    constexpr int CPW = 64 / Dims<D>::NQ;
+    const dim3 grid(nblk(l.g.ncell, CPW));
+    if ((MODE & EL_VISC) && l.cw)
+      hipLaunchKernelGGL((k_elem<D, MODE, true, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l), wi,
+                         H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+    else
+      hipLaunchKernelGGL((k_elem<D, MODE, false, R>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), (const R*)nullptr,
+                         wi, H.gamma, u, p, reinterpret_cast<R*>(l.E), pout);
+  }
 }
 
 template <int D, class R>

@@ -324,18 +324,30 @@ __global__ void __launch_bounds__(256) k_coarse_tile_gemv(const double* __restri
   }
 }
 
-// x at interior unknown i = -sum_J part[I][J][r] (fixed order); Dirichlet
-// entries are zeroed beforehand.
+// x at interior unknown i = -sum_J part[I][J][r]: one workgroup per row
+// tile I; wavefront w sums the partials J = w, w + 16, .. in order, and the
+// 16 wavefront sums are added in order w = 0..15 (a fixed order independent
+// of timing). Dirichlet entries are zeroed beforehand.
+constexpr int kReduceWaves = 16;
+
 template <int D, class R>
-__global__ void k_coarse_reduce(LevelGeo g, int64_t n, int nb, const double* __restrict__ part,
-                                R* __restrict__ x) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t I = i / kT;
-  const int r = (int)(i - I * kT);
+__global__ void __launch_bounds__(kReduceWaves * kT) k_coarse_reduce(LevelGeo g, int64_t n, int nb,
+                                                                     const double* __restrict__ part,
+                                                                     R* __restrict__ x) {
+  __shared__ double sh[kReduceWaves][kT];
+  const int I = blockIdx.x;
+  const int r = threadIdx.x % kT, w = threadIdx.x / kT;
   double s = 0.0;
-  for (int J = 0; J < nb; ++J) s += part[(I * nb + J) * kT + r];
-  x[interior_stored<D>(g, i)] = (R)(-s);
+  for (int J = w; J < nb; J += kReduceWaves) s += part[((int64_t)I * nb + J) * kT + r];
+  sh[w][r] = s;
+  __syncthreads();
+  const int64_t i = (int64_t)I * kT + r;
+  if (w == 0 && i < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kReduceWaves; ++k) t += sh[k][r];
+    x[interior_stored<D>(g, i)] = (R)(-t);
+  }
 }
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -379,10 +391,11 @@ void launch_coarse_apply(const Hier& H, const Level& l, const R* b, R* x, hipStr
   else
     hipLaunchKernelGGL((k_coarse_gather<3, R>), dim3(nblk(npad, 256)), dim3(256), 0, s, l.g, H.n0, npad, b, H.cvec);
   hipLaunchKernelGGL(k_coarse_tile_gemv, dim3((unsigned)ntiles), dim3(256), 0, s, H.Ainv0, nb, H.cvec, H.cpart);
+  const dim3 rgrid((unsigned)nb), rblk(kReduceWaves * kT);
   if (H.dim == 2)
-    hipLaunchKernelGGL((k_coarse_reduce<2, R>), dim3(nblk(H.n0, 256)), dim3(256), 0, s, l.g, H.n0, nb, H.cpart, x);
+    hipLaunchKernelGGL((k_coarse_reduce<2, R>), rgrid, rblk, 0, s, l.g, H.n0, nb, H.cpart, x);
   else
-    hipLaunchKernelGGL((k_coarse_reduce<3, R>), dim3(nblk(H.n0, 256)), dim3(256), 0, s, l.g, H.n0, nb, H.cpart, x);
+    hipLaunchKernelGGL((k_coarse_reduce<3, R>), rgrid, rblk, 0, s, l.g, H.n0, nb, H.cpart, x);
 }
 
 template void launch_coarse_apply<double>(const Hier&, const Level&, const double*, double*, hipStream_t);

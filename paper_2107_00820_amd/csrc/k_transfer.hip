@@ -3,7 +3,8 @@
 // the fine nodes). Per axis a fine node i lies in coarse cell floor(i/4) at
 // offset r = i mod 4 quarters; the 1D weights l_a(r/4) are exact binary
 // fractions (1, 3/8, 3/4, -1/8, ...), so P_H itself introduces no rounding
-// beyond the sums. Both kernels are node-parallel gathers (no atomics).
+// beyond the sums. Both are node-parallel gathers (no atomics); the transpose
+// runs one axis at a time.
 #include "stk_internal.h"
 
 namespace stk {
@@ -56,7 +57,7 @@ __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const R* __restrict__ xc
   xf[idx] = s;
 }
 
-// Transpose: coarse node j gathers from the fine nodes where its basis
+// Transpose: coarse node j collects from the fine nodes where its basis
 // function is nonzero. Per axis: j even (= 2C) -> fine 4C + t, t = -3..3 with
 // weights l2((4+t)/4) for t < 0 and l0(t/4) for t >= 0; j odd (= 2C+1) ->
 // fine 4C + t, t = 1..3 with weights l1(t/4).
@@ -84,45 +85,55 @@ __device__ inline int fine_support(int j, int Nc, int nodes[7], double w[7]) {
   return n;
 }
 
-template <int D, class R>
-__global__ void k_restrict_std(LevelGeo gf, LevelGeo gc, const R* __restrict__ rf, R* __restrict__ rc) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)D * gc.nnodes) return;
-  const int comp = (int)(idx / gc.nnodes);
-  const int64_t nd = idx - (int64_t)comp * gc.nnodes;
-  int j[3];
-  j[0] = (int)(nd % gc.n1);
-  j[1] = (int)((nd / gc.n1) % gc.n1);
-  j[2] = D == 3 ? (int)(nd / ((int64_t)gc.n1 * gc.n1)) : 0;
-  bool bnd = false;
-#pragma unroll
-  for (int k = 0; k < D; ++k) bnd = bnd || j[k] == 0 || j[k] == 2 * gc.N;
-  if (bnd) {
-    rc[idx] = (R)0;
-    return;
-  }
-  int fn[3][7], cnt[3];
-  double fw[3][7];
+// P_H^T as d one-dimensional passes (the weights are a tensor product): pass
+// AX maps extents (.., n1f along AX, ..) to (.., n1c along AX, ..) with the
+// axes before AX already coarse. Each output gathers the <= 5 nonzero fine
+// weights of its coarse node along AX; fine nodes on the Dirichlet boundary of
+// that axis are skipped, so that over all passes a fine node contributes only
+// if it is interior (the same set as the direct d-dimensional sum). The last
+// pass writes 0 on coarse Dirichlet nodes. Layout: component-major, x fastest.
+template <int D, int AX, class R>
+__global__ void k_restrict_pass(LevelGeo gf, LevelGeo gc, const R* __restrict__ in, R* __restrict__ out) {
+  const int nf = gf.n1, nc = gc.n1;
+  int eo[3], ei[3];   // output and input extents per axis
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (k >= D) { cnt[k] = 1; fn[k][0] = 0; fw[k][0] = 1.0; continue; }
-    cnt[k] = fine_support(j[k], gc.N, fn[k], fw[k]);
+    eo[k] = k >= D ? 1 : (k <= AX ? nc : nf);
+    ei[k] = k >= D ? 1 : (k < AX ? nc : nf);
   }
-  R s = 0;
-  for (int t2 = 0; t2 < cnt[2]; ++t2) {
-    const int i2 = fn[2][t2];
-    if (D == 3 && (i2 == 0 || i2 == 2 * gf.N)) continue;
-    for (int t1 = 0; t1 < cnt[1]; ++t1) {
-      const int i1 = fn[1][t1];
-      if (i1 == 0 || i1 == 2 * gf.N) continue;
-      for (int t0 = 0; t0 < cnt[0]; ++t0) {
-        const int i0 = fn[0][t0];
-        if (i0 == 0 || i0 == 2 * gf.N) continue;
-        s += (R)(fw[0][t0] * fw[1][t1] * fw[2][t2]) * rf[comp * gf.nnodes + node_index<D>(gf, i0, i1, i2)];
-      }
+  const int64_t per = (int64_t)eo[0] * eo[1] * eo[2];
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)D * per) return;
+  const int comp = (int)(idx / per);
+  const int64_t r = idx - (int64_t)comp * per;
+  int o[3];
+  o[0] = (int)(r % eo[0]);
+  o[1] = (int)((r / eo[0]) % eo[1]);
+  o[2] = (int)(r / ((int64_t)eo[0] * eo[1]));
+  if (AX == D - 1) {
+    bool bnd = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) bnd = bnd || o[k] == 0 || o[k] == 2 * gc.N;
+    if (bnd) {
+      out[idx] = (R)0;
+      return;
     }
   }
-  rc[idx] = s;
+  int fn[7];
+  double fw[7];
+  const int cnt = fine_support(o[AX], gc.N, fn, fw);
+  const int64_t stride = AX == 0 ? 1 : (AX == 1 ? (int64_t)ei[0] : (int64_t)ei[0] * ei[1]);
+  int base3[3] = {o[0], o[1], o[2]};
+  base3[AX] = 0;
+  const int64_t base = (int64_t)comp * ei[0] * ei[1] * ei[2] + base3[0] +
+                       (int64_t)ei[0] * (base3[1] + (int64_t)ei[1] * base3[2]);
+  R s = 0;
+  for (int t = 0; t < cnt; ++t) {
+    const int i = fn[t];
+    if (i == 0 || i == 2 * gf.N) continue;
+    s += (R)fw[t] * in[base + stride * i];
+  }
+  out[idx] = s;
 }
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -136,13 +147,28 @@ void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, c
     hipLaunchKernelGGL((k_prolong_std<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
 }
 
+// The intermediate passes go through the fine level's T buffer (nvel
+// entries; the pass outputs need at most 3/4 of it), which is free while a
+// restriction runs: the V-cycle writes it only for the prolongation after the
+// coarse correction.
 template <class R>
 void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const R* rf, R* rc, hipStream_t s) {
-  const int64_t n = (int64_t)H.dim * coarse.g.nnodes;
-  if (H.dim == 2)
-    hipLaunchKernelGGL((k_restrict_std<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
-  else
-    hipLaunchKernelGGL((k_restrict_std<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, rc);
+  const int64_t nf = fine.g.n1, nc = coarse.g.n1;
+  R* t1 = reinterpret_cast<R*>(fine.T);
+  if (H.dim == 2) {
+    const int64_t n1 = 2 * nf * nc, n2 = 2 * nc * nc;
+    hipLaunchKernelGGL((k_restrict_pass<2, 0, R>), dim3(nblk(n1, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, t1);
+    hipLaunchKernelGGL((k_restrict_pass<2, 1, R>), dim3(nblk(n2, 256)), dim3(256), 0, s, fine.g, coarse.g,
+                       (const R*)t1, rc);
+  } else {
+    const int64_t n1 = 3 * nf * nf * nc, n2 = 3 * nf * nc * nc, n3 = 3 * nc * nc * nc;
+    R* t2 = t1 + n1;
+    hipLaunchKernelGGL((k_restrict_pass<3, 0, R>), dim3(nblk(n1, 256)), dim3(256), 0, s, fine.g, coarse.g, rf, t1);
+    hipLaunchKernelGGL((k_restrict_pass<3, 1, R>), dim3(nblk(n2, 256)), dim3(256), 0, s, fine.g, coarse.g,
+                       (const R*)t1, t2);
+    hipLaunchKernelGGL((k_restrict_pass<3, 2, R>), dim3(nblk(n3, 256)), dim3(256), 0, s, fine.g, coarse.g,
+                       (const R*)t2, rc);
+  }
 }
 
 template void launch_prolong_std<double>(const Hier&, const Level&, const Level&, const double*, double*, hipStream_t);

@@ -12,6 +12,10 @@
       two `--pmc` runs), with the factor measured on the copy kernel
       (known bytes / counted bytes), keyed by the exact kernel name and stamped
       with a hash of the kernel sources so a changed kernel invalidates it.
+  python -m paper_2107_00820_amd.profiling rates TRACE_DIR TRAFFIC.json OUT.md --title T
+      per kernel: launches and average duration from a kernel trace, HBM bytes
+      per launch from the counters, and the achieved GB/s against the 8 TB/s
+      HBM3E peak.
 
 The counters are in KiB per dispatch summed over the TCC channels.
 """
@@ -130,6 +134,43 @@ def cmd_traffic(args):
     print(json.dumps(out, indent=1))
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def cmd_rates(args):
+    rows = []
+    for p in _find(args.dir, "*kernel_trace.csv"):
+        with open(p) as f:
+            rows += list(csv.DictReader(f))
+    dur = collections.defaultdict(list)
+    for r in rows:
+        dur[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    with open(args.traffic) as f:
+        tr = json.load(f)
+    c = tr.get("command", "")
+    out = [f"# {args.title}", "",
+           "HBM bytes per launch from `FETCH_SIZE` and `WRITE_SIZE` (two `--pmc` runs, scaled by the "
+           f"copy-kernel factors {tr['factor_fetch']:.3f} / {tr['factor_write']:.3f}); average duration from "
+           "the kernel trace of the same command; GB/s = bytes / duration against the 8 TB/s HBM3E peak.", "",
+           "Counter commands:", "", "```", *(c if isinstance(c, list) else [c]), "```", "",
+           "| kernel | launches (trace) | avg us | HBM read MB | HBM write MB | GB/s | % of peak |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    items = []
+    for k, v in tr["kernels"].items():
+        d = dur.get(k)
+        if not d or not v.get("traffic_bytes_per_launch"):
+            continue
+        avg = sum(d) / len(d) / 1e3
+        gbs = v["traffic_bytes_per_launch"] / (avg * 1e-6) / 1e9
+        items.append((sum(d), k, len(d), avg, v, gbs))
+    for _, k, n, avg, v, gbs in sorted(items, reverse=True)[:args.top]:
+        out.append(f"| `{k}` | {n} | {avg:.2f} | {(v['fetch_bytes_per_launch'] or 0) / 1e6:.2f} | "
+                   f"{(v['write_bytes_per_launch'] or 0) / 1e6:.2f} | {gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f}% |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -149,8 +190,14 @@ def main(argv=None):
     a.add_argument("--kernel", default="k_asm_gemv")
     a.add_argument("--workload", default="")
     a.add_argument("--cmd", default="")
+    a = sub.add_parser("rates")
+    a.add_argument("dir")
+    a.add_argument("traffic")
+    a.add_argument("out")
+    a.add_argument("--title", default="achieved HBM bandwidth per kernel")
+    a.add_argument("--top", type=int, default=16)
     args = ap.parse_args(argv)
-    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd_name](args)
+    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic, "rates": cmd_rates}[args.cmd_name](args)
 
 
 if __name__ == "__main__":
