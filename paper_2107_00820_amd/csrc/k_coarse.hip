@@ -26,7 +26,6 @@ constexpr int kT = 64;           // tile width
 constexpr int kTT = kT * kT;
 constexpr int kLd = kT + 1;      // LDS row stride (doubles)
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Interior unknown i (component-major over the (2N-1)^d interior nodes) ->
 // (component, node coordinates).
@@ -92,21 +91,28 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
 }
 
 // Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64) through its Cholesky
-// factor (accurate to about kappa eps).
+// factor by spd_invert_lower16 (16 x 16 tiles on the FP64 matrix cores).
 __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
                                                       double* __restrict__ Pinv, int* __restrict__ flag) {
-  __shared__ double a[kT * kLd];
-  __shared__ double tmp[kT];
+  constexpr int NB = kT / 16, NT = NB * (NB + 1) / 2;
+  __shared__ double L[NT * kTile17];
+  __shared__ double W[NB * kTile17];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   const double* T = tile_ptr(A, K, K);
-  for (int e = threadIdx.x; e < kTT; e += blockDim.x) a[(e / kT) * kLd + e % kT] = T[e];
+  for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
+    const int t = e / 256, r = (e % 256) / 16, c = e % 16;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    L[t * kTile17 + r * 17 + c] = T[(16 * I + r) * kT + 16 * J + c];
+  }
   __syncthreads();
-  spd_invert_lds(a, kT, kLd, tmp, &bad);
-  __syncthreads();
+  spd_invert_lower16(L, NB, W, &bad);
   for (int e = threadIdx.x; e < kTT; e += blockDim.x) {
-    const int r = e / kT, c = e % kT;
-    Pinv[e] = r >= c ? a[r * kLd + c] : a[c * kLd + r];
+    int r = e / kT, c = e % kT;
+    if (c > r) { const int t = r; r = c; c = t; }
+    Pinv[e] = L[ltile(r / 16, c / 16) * kTile17 + (r % 16) * 17 + c % 16];
   }
   if (threadIdx.x == 0 && bad) *flag = 1;
 }

@@ -72,6 +72,57 @@ __global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, const d
   if (threadIdx.x == 0 && bad) *flag = 1;
 }
 
+// 3D interior patches (81 unknowns): the same entries, assembled into the
+// lower 16 x 16 tiles of the matrix padded to 96 x 96 with the identity, then
+// inverted through its Cholesky factor by spd_invert_lower16 (tile products
+// on the FP64 matrix cores). LDS: 21 matrix tiles and 6 scratch tiles, within
+// the 64 KB a workgroup can use.
+constexpr int kP81 = 81, kP81Blocks = 6;
+
+__global__ void __launch_bounds__(256) k_patch_setup81(LevelGeo g, const double* __restrict__ mu,
+                                                        const double* __restrict__ cw,
+                                                        const double* __restrict__ winv, double gamma,
+                                                        const int* __restrict__ verts, int count,
+                                                        double* __restrict__ inv, int* __restrict__ flag) {
+  constexpr int NT = kP81Blocks * (kP81Blocks + 1) / 2;
+  __shared__ double L[NT * kTile17];
+  __shared__ double W[kP81Blocks * kTile17];
+  __shared__ int bad;
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  constexpr int n = kP81;
+  if (threadIdx.x == 0) bad = 0;
+  int lo[3], ext[3], vc[3];
+  patch_box<3>(g, verts[s], lo, ext, vc);
+  for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
+    const int t = e / 256, r = (e % 256) / 16, c = e % 16;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    if (I == J && c > r) continue;   // mirrored below
+    const int i = 16 * I + r, j = 16 * J + c;
+    double v;
+    if (i < n && j < n) {
+      int ni[3], nj[3];
+      const int ci = patch_dof<3>(i, lo, ext, ni);
+      const int cj = patch_dof<3>(j, lo, ext, nj);
+      v = global_entry<3>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
+    } else {
+      v = i == j ? 1.0 : 0.0;
+    }
+    L[t * kTile17 + r * 17 + c] = v;
+    if (I == J) L[t * kTile17 + c * 17 + r] = v;
+  }
+  __syncthreads();
+  spd_invert_lower16(L, kP81Blocks, W, &bad);
+  const int64_t P = (int64_t)n * (n + 1) / 2;
+  double* dst = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
+  for (int i = 0; i < n; ++i)
+    for (int j = threadIdx.x; j <= i; j += blockDim.x)
+      dst[((int64_t)i * (i + 1) / 2 + j) * 64] = L[ltile(i / 16, j / 16) * kTile17 + (i % 16) * 17 + j % 16];
+  if (threadIdx.x == 0 && bad) *flag = 1;
+}
+
 // ---------------------------------------------------------------------------
 // y = A^{-1} x with A^{-1} packed lower, element stride 64.
 // Packed symmetric GEMV y = A x over one patch, A's element k at A[k*64]
@@ -470,6 +521,11 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
   if (pc.count == 0) return;
+  if (H.dim == 3 && pc.n == kP81) {
+    hipLaunchKernelGGL(k_patch_setup81, dim3(pc.count), dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma,
+                       pc.verts, pc.count, pc.inv, H.flag);
+    return;
+  }
   const size_t shm = (size_t)(pc.n * (pc.n + 1) + pc.n) * sizeof(double);
   const int nt = pc.n > 32 ? 256 : 64;
   if (H.dim == 2)
