@@ -18,7 +18,7 @@
 // rank-64 updates are 64 x 64 x 64 tile products on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64); the pivot inverse is a Cholesky-based inversion
 // in LDS.
-#include "stk_dev.h"
+#include "stk_spd.h"
 
 namespace stk {
 

@@ -1,18 +1,15 @@
-// Vertex-star additive Schwarz (Section 4.1, eq. (viim)): patch setup,
-// the batched patch solve and the deterministic overlap sum; plus the local
-// solves of the robust prolongation (Section 4.2, eq. (Ptilde)), which reuse
-// the factors of the star patches centred in the coarse cells.
+// Vertex-star additive Schwarz (Section 4.1, eq. (viim)): the batched patch
+// solve and the deterministic overlap sum; plus the local solves of the
+// robust prolongation (Section 4.2, eq. (Ptilde)), which reuse the inverses
+// of the star patches centred in the coarse cells. The inverses themselves
+// are formed in k_setup.hip.
 //
 // Patch of vertex v: the unknowns at the nodes strictly inside the cells
 // around v, i.e. per axis the nodes 2v-1, 2v, 2v+1 that are interior to the
 // domain (one node for a vertex on the boundary), all components.
 // Unknown order inside a patch: component-major, then nodes x-fastest.
-//
-// Setup (one workgroup per patch): the patch matrix is assembled from
-// Gauss-point integrals of the cells of the star (equal to the rows and
-// columns of the assembled A_gamma), factored A = L L^T in LDS, inverted
-// (L^{-1}, then L^{-T} L^{-1}) and stored as a packed lower triangle. Patches
-// of one class are interleaved in blocks of 64: element k of patch s sits at
+// Patch inverses are stored as packed lower triangles; patches of one class
+// are interleaved in blocks of 64: element k of patch s sits at
 // ((s/64)*P + k)*64 + s%64 (P = n(n+1)/2), so a wavefront processing 64
 // patches reads 512 contiguous bytes per element.
 //
@@ -35,92 +32,6 @@ __device__ __attribute__((always_inline)) inline void static_for_impl(F& f, std:
 template <int N, class F>
 __device__ __attribute__((always_inline)) inline void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-template <int D>
-__global__ void k_patch_setup(LevelGeo g, const double* __restrict__ mu, const double* __restrict__ cw,
-                              const double* __restrict__ winv, double gamma, int n,
-                              const int* __restrict__ verts, int count, double* __restrict__ inv,
-                              int* __restrict__ flag) {
-  extern __shared__ double sm[];
-  const int s = blockIdx.x;
-  if (s >= count) return;
-  const int ld = n + 1;
-  double* a = sm;
-  double* tmp = sm + n * ld;
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  int lo[3], ext[3], vc[3];
-  patch_box<D>(g, verts[s], lo, ext, vc);
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-    const int i = t / n, j = t % n;
-    if (j > i) continue;
-    int ni[3], nj[3];
-    const int ci = patch_dof<D>(i, lo, ext, ni);
-    const int cj = patch_dof<D>(j, lo, ext, nj);
-    const double v = global_entry<D>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
-    a[i * ld + j] = v;
-    a[j * ld + i] = v;
-  }
-  __syncthreads();
-  spd_invert_lds(a, n, ld, tmp, &bad);
-  const int64_t P = (int64_t)n * (n + 1) / 2;
-  double* dst = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  for (int i = 0; i < n; ++i)
-    for (int j = threadIdx.x; j <= i; j += blockDim.x)
-      dst[((int64_t)i * (i + 1) / 2 + j) * 64] = a[i * ld + j];
-  if (threadIdx.x == 0 && bad) *flag = 1;
-}
-
-// 3D interior patches (81 unknowns): the same entries, assembled into the
-// lower 16 x 16 tiles of the matrix padded to 96 x 96 with the identity, then
-// inverted through its Cholesky factor by spd_invert_lower16 (tile products
-// on the FP64 matrix cores). LDS: 21 matrix tiles and 6 scratch tiles, within
-// the 64 KB a workgroup can use.
-constexpr int kP81 = 81, kP81Blocks = 6;
-
-__global__ void __launch_bounds__(256) k_patch_setup81(LevelGeo g, const double* __restrict__ mu,
-                                                        const double* __restrict__ cw,
-                                                        const double* __restrict__ winv, double gamma,
-                                                        const int* __restrict__ verts, int count,
-                                                        double* __restrict__ inv, int* __restrict__ flag) {
-  constexpr int NT = kP81Blocks * (kP81Blocks + 1) / 2;
-  __shared__ double L[NT * kTile17];
-  __shared__ double W[kP81Blocks * kTile17];
-  __shared__ int bad;
-  const int s = blockIdx.x;
-  if (s >= count) return;
-  constexpr int n = kP81;
-  if (threadIdx.x == 0) bad = 0;
-  int lo[3], ext[3], vc[3];
-  patch_box<3>(g, verts[s], lo, ext, vc);
-  for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
-    const int t = e / 256, r = (e % 256) / 16, c = e % 16;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    const int J = t - I * (I + 1) / 2;
-    if (I == J && c > r) continue;   // mirrored below
-    const int i = 16 * I + r, j = 16 * J + c;
-    double v;
-    if (i < n && j < n) {
-      int ni[3], nj[3];
-      const int ci = patch_dof<3>(i, lo, ext, ni);
-      const int cj = patch_dof<3>(j, lo, ext, nj);
-      v = global_entry<3>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
-    } else {
-      v = i == j ? 1.0 : 0.0;
-    }
-    L[t * kTile17 + r * 17 + c] = v;
-    if (I == J) L[t * kTile17 + c * 17 + r] = v;
-  }
-  __syncthreads();
-  spd_invert_lower16(L, kP81Blocks, W, &bad);
-  const int64_t P = (int64_t)n * (n + 1) / 2;
-  double* dst = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
-  for (int i = 0; i < n; ++i)
-    for (int j = threadIdx.x; j <= i; j += blockDim.x)
-      dst[((int64_t)i * (i + 1) / 2 + j) * 64] = L[ltile(i / 16, j / 16) * kTile17 + (i % 16) * 17 + j % 16];
-  if (threadIdx.x == 0 && bad) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -519,22 +430,6 @@ __global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
-  if (pc.count == 0) return;
-  if (H.dim == 3 && pc.n == kP81) {
-    hipLaunchKernelGGL(k_patch_setup81, dim3(pc.count), dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma,
-                       pc.verts, pc.count, pc.inv, H.flag);
-    return;
-  }
-  const size_t shm = (size_t)(pc.n * (pc.n + 1) + pc.n) * sizeof(double);
-  const int nt = pc.n > 32 ? 256 : 64;
-  if (H.dim == 2)
-    hipLaunchKernelGGL(k_patch_setup<2>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, l.winv, H.gamma, pc.n, pc.verts,
-                       pc.count, pc.inv, H.flag);
-  else
-    hipLaunchKernelGGL(k_patch_setup<3>, dim3(pc.count), dim3(nt), shm, s, l.g, l.mu, l.cw, l.winv, H.gamma, pc.n, pc.verts,
-                       pc.count, pc.inv, H.flag);
-}
 
 template <class R>
 static const R* class_inv(const PatchClass& pc);

@@ -16,6 +16,10 @@
       per kernel: launches and average duration from a kernel trace, HBM bytes
       per launch from the counters, and the achieved GB/s against the 8 TB/s
       HBM3E peak.
+  python -m paper_2107_00820_amd.profiling mfma TRACE_DIR PMC_DIR OUT.md --title T
+      per kernel: FP64 matrix-core flops per launch (SQ_INSTS_VALU_MFMA_MOPS_F64
+      counts units of 512 flops) over the average duration, against the
+      78.6 TFLOP/s FP64 matrix peak.
 
 The counters are in KiB per dispatch summed over the TCC channels.
 """
@@ -171,6 +175,41 @@ def cmd_rates(args):
     print("\n".join(out))
 
 
+MFMA_F64_PEAK_TFLOPS = 78.6
+
+
+def cmd_mfma(args):
+    rows = []
+    for p in _find(args.dir, "*kernel_trace.csv"):
+        with open(p) as f:
+            rows += list(csv.DictReader(f))
+    dur = collections.defaultdict(list)
+    for r in rows:
+        dur[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    mops = _counter(args.pmc, "SQ_INSTS_VALU_MFMA_MOPS_F64", args.kernel)
+    out = [f"# {args.title}", "",
+           "FP64 matrix-core flops per launch = 512 x SQ_INSTS_VALU_MFMA_MOPS_F64 (one `--pmc` run); average "
+           "duration from the kernel trace of the same command; TFLOP/s against the 78.6 TFLOP/s FP64 "
+           "matrix peak.", "", "Commands:", "", "```", *args.cmd, "```", "",
+           "| kernel | launches (trace) | avg us | MFMA GFLOP per launch | TFLOP/s | % of peak |",
+           "|---|---:|---:|---:|---:|---:|"]
+    items = []
+    for k, v in mops.items():
+        d = dur.get(k)
+        if not d or not v:
+            continue
+        fl = 512.0 * sum(v) / len(v)
+        if fl <= 0:
+            continue
+        avg = sum(d) / len(d) / 1e3
+        items.append((sum(d), k, len(d), avg, fl, fl / (avg * 1e-6) / 1e12))
+    for _, k, n, avg, fl, tf in sorted(items, reverse=True):
+        out.append(f"| `{k}` | {n} | {avg:.2f} | {fl / 1e9:.3f} | {tf:.2f} | {100 * tf / MFMA_F64_PEAK_TFLOPS:.1f}% |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -196,8 +235,16 @@ def main(argv=None):
     a.add_argument("out")
     a.add_argument("--title", default="achieved HBM bandwidth per kernel")
     a.add_argument("--top", type=int, default=16)
+    a = sub.add_parser("mfma")
+    a.add_argument("dir")
+    a.add_argument("pmc")
+    a.add_argument("out")
+    a.add_argument("--title", default="FP64 matrix-core rate per kernel")
+    a.add_argument("--kernel", default="k_patch_setup|k_sweep|k_coarse")
+    a.add_argument("--cmd", action="append", default=[])
     args = ap.parse_args(argv)
-    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic, "rates": cmd_rates}[args.cmd_name](args)
+    {"copy": cmd_copy, "stats": cmd_stats, "traffic": cmd_traffic, "rates": cmd_rates,
+     "mfma": cmd_mfma}[args.cmd_name](args)
 
 
 if __name__ == "__main__":
