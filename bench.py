@@ -138,6 +138,11 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"[bench] setup {t_setup:.3f} s")
+    # patch-solve variant per level and precision (bit-identical results; timed, not part of setup)
+    t0 = time.perf_counter()
+    tune = h.stk_autotune(reps=5)
+    t_tune = time.perf_counter() - t0
+    log(f"[bench] autotune {t_tune:.3f} s: {tune}")
     bu, bp = h.stk_rhs()
     xu, xp = h.zeros_u(), h.zeros_p()
     res = {}
@@ -210,7 +215,9 @@ def main():
                       "unknowns": dof, "iterations": r["iterations"], "setup_s": t_setup, "form": best},
            "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
            "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res},
-           "roofline": roofline}
+           "roofline": roofline,
+           "autotune": {"asm_variant": {f"level{l}_{p}": v for (l, p), v in sorted(tune.items())},
+                        "seconds": t_tune}}
     if args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
     if not args.no_cpu_baseline:

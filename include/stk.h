@@ -248,6 +248,25 @@ stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream);
  * solve was started. */
 stk_status stk_poll(stk_hier* h, stk_solve_info* info);
 
+/* Autotuning of the batched star-patch solve. The kernel exists in
+ * STK_ASM_VARIANTS variants that differ only in how many packed inverse
+ * elements a lane loads ahead (and so in registers and occupancy);
+ * all perform the same multiply-adds in the same order, so results are
+ * bit-identical whichever is chosen (the choice never changes a solution).
+ * stk_autotune times every variant on every smoothed level (levels 1..L-1)
+ * and precision in use (FP64; FP32 too if the hierarchy was set up with
+ * mixed = 1) with HIP events around `reps` (1..100) back-to-back launches on
+ * the level's own buffers, keeps the fastest per (level, precision), and
+ * writes the choices to variants[(level - 1) * 2 + dtype] if variants is not
+ * NULL (2 (L - 1) ints, -1 for a precision not in use). Synchronous on
+ * `stream`; drops the captured HIP graphs (they are re-captured on the next
+ * solve). STK_EBUSY while a resumable solve is in progress.
+ * stk_set_asm_variant fixes the variant of one (level, dtype) by hand
+ * (0 <= variant < STK_ASM_VARIANTS; level >= 1). Default: variant 0. */
+#define STK_ASM_VARIANTS 3
+stk_status stk_autotune(stk_hier* h, int reps, int* variants, void* stream);
+stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant);
+
 /* Kernel timing (tracing). stk_profile(h, r), 1 <= r <= 100, clears the
  * records and starts bracketing launches of the instrumented kernel families
  * with HIP events on the launch stream; each instrumented launch is issued r

@@ -172,10 +172,9 @@ __device__ __attribute__((always_inline)) inline void piece_into(const R* __rest
   static_for<PC::ny>([&](auto I) { yc[I] = y[I]; });
 }
 
-template <class R, class Store>
+template <int CHK, class R, class Store>
 __device__ __attribute__((always_inline)) inline void split_symv81(const R* __restrict__ A, R* xs, int lane, int w,
                                                                    Store&& store) {
-  constexpr int CHK = sizeof(R) == 8 ? STK_CH_LDS64 : STK_CH_LDS32;
   auto xr = [&](int j) { return xs[j * 64 + lane]; };
   R yc[61];
   if (w == 0) piece_into<Q81_0, CHK>(A, xr, yc);
@@ -203,19 +202,35 @@ __device__ __attribute__((always_inline)) inline void split_symv81(const R* __re
   }
 }
 
-// x from registers (patches of up to 27 unknowns): four double-buffered chunks
-template <int NPT, class R>
+// x from registers (patches of up to 27 unknowns): double-buffered chunks,
+// NCH of them (0: four for up to 18 unknowns, chunks of 12 above)
+template <int NPT, int NCH = 0, class R>
 __device__ __attribute__((always_inline)) inline void packed_symv(const R* __restrict__ A, const R (&x)[NPT],
                                                                   R (&y)[NPT]) {
   auto xr = [&](int j) { return x[j]; };
   constexpr int NE = NPT * (NPT + 1) / 2;
-  constexpr int CH = NPT <= 18 ? (NE + 3) / 4 : 12;
+  constexpr int CH = NCH > 0 ? (NE + NCH - 1) / NCH : (NPT <= 18 ? (NE + 3) / 4 : 12);
   packed_symv_chunked<NPT, CH>(A, xr, y);
 }
 
+// Tuning variants of the batched patch solve. They differ only in how many
+// packed elements a lane loads ahead (the chunk), which sets the registers a
+// lane holds and with them the occupancy; every variant performs the same multiply-adds in the
+// same order, so their results are bit-identical and a tuner may choose any
+// (kAsmVariants of them).
+template <int D, class R, int V>
+struct AsmTune {
+  // 3D interior patches (81 unknowns, LDS-staged residual): elements per chunk
+  static constexpr int ch81 = sizeof(R) == 8 ? (V == 0 ? 16 : (V == 1 ? 8 : 12)) : (V == 0 ? 32 : (V == 1 ? 16 : 24));
+  // 2D interior patches (18 unknowns from registers): number of chunks
+  static constexpr int nch18 = V == 0 ? 4 : (V == 1 ? 6 : 8);
+  // minimum wavefronts per SIMD requested from the compiler
+  static constexpr int min_waves = 2;
+};
+
 // One lane per patch: gather the patch residual, packed symmetric GEMV,
 // write the result into the vertex-indexed buffer.
-template <int D, int NPT, class R>
+template <int D, int NPT, int NCH = 0, class R>
 __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& g, const int* __restrict__ verts, int count,
                                  const R* __restrict__ inv, const R* __restrict__ r,
                                  R* __restrict__ zbuf, int nvert, int s) {
@@ -237,7 +252,7 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
   const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
   R y[NPT];
-  packed_symv<NPT>(A, x, y);
+  packed_symv<NPT, NCH>(A, x, y);
   // the scatter recomputes its indices rather than keeping the gather's
   // (which would hold NPT index triples in registers across the GEMV)
 #pragma unroll
@@ -262,7 +277,7 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
 // i = comp*27 + a + 3b + 9c sits at node 2v-1 + (a,b,c). Lanes past the
 // class count take part in the barriers with a clamped vertex and store
 // nothing (the inverse storage is padded to whole blocks of 64 patches).
-template <class R>
+template <int CHK, class R>
 __device__ __attribute__((always_inline)) inline void asm_patch81(const LevelGeo& g, const int* __restrict__ verts,
                                                                   int count, const R* __restrict__ inv,
                                                                   const R* __restrict__ r, R* __restrict__ zbuf,
@@ -286,7 +301,7 @@ __device__ __attribute__((always_inline)) inline void asm_patch81(const LevelGeo
   __syncthreads();
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
   const R* A = inv + ((int64_t)blk * P) * 64 + lane;
-  split_symv81(A, xs, lane, w, [&](auto I, R v) {
+  split_symv81<CHK>(A, xs, lane, w, [&](auto I, R v) {
     if (valid) zbuf[(int64_t)I * nvert + vert] = v;
   });
 }
@@ -307,18 +322,18 @@ struct AsmClasses {
 template <int D>
 constexpr int asm_threads() { return D == 2 ? 64 : 256; }
 
-template <int D, class R>
-__global__ void __launch_bounds__(asm_threads<D>()) __attribute__((amdgpu_waves_per_eu(2))) k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r,
-                                                               R* __restrict__ zbuf, int nvert) {
+template <int D, class R, int V>
+__global__ void __launch_bounds__(asm_threads<D>(), (AsmTune<D, R, V>::min_waves))
+k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r, R* __restrict__ zbuf, int nvert) {
   constexpr int NT = asm_threads<D>();
   const int b = blockIdx.x;
   const int t = threadIdx.x;
   if (b < c.first_block[1]) {
     if constexpr (D == 2) {
-      asm_patch<D, 18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + t);
+      asm_patch<D, 18, AsmTune<D, R, V>::nch18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + t);
     } else {
       __shared__ R xs[81 * 64];
-      asm_patch81(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b, xs, t);
+      asm_patch81<AsmTune<D, R, V>::ch81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b, xs, t);
     }
   } else if (b < c.first_block[2]) {
     const int s = (b - c.first_block[1]) * NT + t;
@@ -423,7 +438,7 @@ __global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g
       if (w == (I & 3)) xs[I * 64 + lane] = in[offset(I)];
     });
     __syncthreads();
-    split_symv81(A, xs, lane, w, store);
+    split_symv81<AsmTune<3, R, 0>::ch81>(A, xs, lane, w, store);
   }
 }
 
@@ -438,8 +453,19 @@ const double* class_inv<double>(const PatchClass& pc) { return pc.inv; }
 template <>
 const float* class_inv<float>(const PatchClass& pc) { return pc.inv32; }
 
+template <int D, class R>
+static void asm_gemv_variant(int v, unsigned blocks, hipStream_t s, const LevelGeo& g, const AsmClasses<R>& c,
+                             const R* r, R* zbuf, int nvert) {
+  const dim3 grid(blocks), blk(asm_threads<D>());
+  if (v == 1) hipLaunchKernelGGL((k_asm_gemv<D, R, 1>), grid, blk, 0, s, g, c, r, zbuf, nvert);
+  else if (v == 2) hipLaunchKernelGGL((k_asm_gemv<D, R, 2>), grid, blk, 0, s, g, c, r, zbuf, nvert);
+  else hipLaunchKernelGGL((k_asm_gemv<D, R, 0>), grid, blk, 0, s, g, c, r, zbuf, nvert);
+}
+
+// The batched patch solves of one ASM application into the level's patch
+// output buffer, with the level's chosen variant (reps launches back to back).
 template <class R>
-void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
+void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out) {
   AsmClasses<R> c{};
   int blocks = 0;
   double bytes = (double)sizeof(R) * (double)l.nvel;   // one read of the residual
@@ -459,17 +485,24 @@ void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
   }
   c.first_block[4] = blocks;
   R* zbuf = reinterpret_cast<R*>(l.zbuf);
+  const int v = l.asm_variant[sizeof(R) == 8 ? 0 : 1];
+  for (int k = 0; k < reps; ++k) {
+    if (H.dim == 2) asm_gemv_variant<2, R>(v, blocks, s, l.g, c, r, zbuf, l.nvert);
+    else asm_gemv_variant<3, R>(v, blocks, s, l.g, c, r, zbuf, l.nvert);
+  }
+  if (bytes_out) *bytes_out = bytes;
+}
+
+template <class R>
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
   hipEvent_t ev = nullptr;
   const int reps = prof_begin(H, s, &ev);
   // the kernel is a pure function of (r, inverses) -> zbuf, so a profiled
   // call may repeat it back to back to time it without launch gaps
-  for (int k = 0; k < reps; ++k) {
-    if (H.dim == 2)
-      hipLaunchKernelGGL((k_asm_gemv<2, R>), dim3(blocks), dim3(asm_threads<2>()), 0, s, l.g, c, r, zbuf, l.nvert);
-    else
-      hipLaunchKernelGGL((k_asm_gemv<3, R>), dim3(blocks), dim3(asm_threads<3>()), 0, s, l.g, c, r, zbuf, l.nvert);
-  }
+  double bytes = 0.0;
+  launch_asm_gemv<R>(H, l, r, reps, s, &bytes);
   prof_end(H, s, PROF_ASM_GEMV, ev, bytes, reps);
+  R* zbuf = reinterpret_cast<R*>(l.zbuf);
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
     hipLaunchKernelGGL((k_asm_gather<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
@@ -493,6 +526,8 @@ void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, 
   }
 }
 
+template void launch_asm_gemv<double>(const Hier&, const Level&, const double*, int, hipStream_t, double*);
+template void launch_asm_gemv<float>(const Hier&, const Level&, const float*, int, hipStream_t, double*);
 template void launch_asm<double>(Hier&, const Level&, const double*, double*, hipStream_t);
 template void launch_asm<float>(Hier&, const Level&, const float*, float*, hipStream_t);
 template void launch_center_solve<double>(const Hier&, const Level&, const double*, double*, double, bool,

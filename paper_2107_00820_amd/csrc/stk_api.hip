@@ -688,6 +688,71 @@ stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_
   Hier& H = (h)->H;                                               \
   H.stream = (hipStream_t)stream
 
+stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant) {
+  if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
+  Hier& H = h->H;
+  STKCHK(check_level(H, level, 1));
+  STKCHK(check_dtype(H, dtype));
+  if (variant < 0 || variant >= kAsmVariants) return fail(STK_EINVAL, "variant out of range");
+  if (H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL ||
+      H.sv.phase == Hier::SV_FINISH)
+    return fail(STK_EBUSY, "a solve is in progress");
+  H.lv[level].asm_variant[dtype == STK_F64 ? 0 : 1] = variant;
+  drop_graphs(H);   // captured steps hold the previous variant's kernels
+  return STK_OK;
+}
+
+// Times every patch-solve variant on every smoothed level (and precision in
+// use) with HIP events around `reps` back-to-back launches on the level's own
+// buffers, and keeps the fastest (ties: the lower index).
+stk_status stk_autotune(stk_hier* h, int reps, int* variants, void* stream) {
+  GET_H(h);
+  if (reps < 1 || reps > 100) return fail(STK_EINVAL, "reps must be in [1, 100]");
+  if (H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL ||
+      H.sv.phase == Hier::SV_FINISH)
+    return fail(STK_EBUSY, "a solve is in progress");
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  stk_status st = STK_OK;
+  for (int l = 1; l < H.L && st == STK_OK; ++l) {
+    Level& L = H.lv[l];
+    for (int dt = 0; dt < 2; ++dt) {
+      if (variants) variants[(l - 1) * 2 + dt] = -1;
+      if (dt == 1 && !H.mixed) continue;
+      int best = 0;
+      float best_ms = 0.0f;
+      for (int v = 0; v < kAsmVariants; ++v) {
+        L.asm_variant[dt] = v;
+        // input: the level's residual buffer (any contents; only time matters)
+        if (dt == 0) launch_asm_gemv<double>(H, L, L.r, 1, H.stream, nullptr);
+        else launch_asm_gemv<float>(H, L, reinterpret_cast<const float*>(L.r), 1, H.stream, nullptr);
+        if (hipEventRecord(a, H.stream) != hipSuccess) { st = fail(STK_EDEVICE, "event record failed"); break; }
+        if (dt == 0) launch_asm_gemv<double>(H, L, L.r, reps, H.stream, nullptr);
+        else launch_asm_gemv<float>(H, L, reinterpret_cast<const float*>(L.r), reps, H.stream, nullptr);
+        float ms = 0.0f;
+        if (hipEventRecord(b, H.stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          st = fail(STK_EDEVICE, "event timing failed");
+          break;
+        }
+        if (v == 0 || ms < best_ms) {
+          best = v;
+          best_ms = ms;
+        }
+      }
+      L.asm_variant[dt] = best;
+      if (variants) variants[(l - 1) * 2 + dt] = best;
+      if (st != STK_OK) break;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  drop_graphs(H);   // captured steps hold the previous variants' kernels
+  if (st == STK_OK && hipGetLastError() != hipSuccess) st = fail(STK_EDEVICE, "launch failed during tuning");
+  return st;
+}
+
 stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
   GET_H(h);
   if (!b_u) return fail(STK_EINVAL, "b_u is NULL");

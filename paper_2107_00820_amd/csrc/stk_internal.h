@@ -35,8 +35,14 @@ struct PatchClass {
   float* inv32 = nullptr; // FP32 copy (mixed form)
 };
 
+// Variants of the batched patch solve a tuner may choose between per level
+// and precision (bit-identical results; they differ in load chunking and
+// occupancy only).
+constexpr int kAsmVariants = 3;
+
 struct Level {
   LevelGeo g{};
+  int asm_variant[2] = {0, 0};   // chosen patch-solve variant: [0] FP64, [1] FP32
   int nvert = 0;               // (N+1)^d
   int64_t nvel = 0;            // d * nnodes
   int64_t npres = 0;           // (d+1) * ncell
@@ -172,6 +178,10 @@ void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
 template <class R>
 void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s);
+// The patch-solve kernel alone (reps launches), no gather and no tracing;
+// *bytes_out receives its algorithmic bytes per launch if non-NULL.
+template <class R>
+void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out);
 template <class R>
 void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
                          hipStream_t s);

@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
         "stk_poll": [vp, C.POINTER(SolveInfo)],
         "stk_profile": [vp, i32],
         "stk_profile_read": [vp, i32, i64p, dp, dp],
+        "stk_autotune": [vp, i32, C.POINTER(C.c_int), vp],
+        "stk_set_asm_variant": [vp, i32, i32, i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -302,6 +304,24 @@ class Hierarchy:
         _check(st, allow=(STK_ENOTCONV, STK_ENAN))
         return dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
                     t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
+
+    def stk_autotune(self, reps: int = 5):
+        """Time the bit-identical patch-solve variants on every smoothed level
+        and keep the fastest; returns {(level, "f64"|"f32"): variant}."""
+        out = (C.c_int * (2 * max(self.L - 1, 1)))()
+        _check(load().stk_autotune(self._h, int(reps), out, _stream()))
+        res = {}
+        for l in range(1, self.L):
+            for dt, name in ((0, "f64"), (1, "f32")):
+                v = out[(l - 1) * 2 + dt]
+                if v >= 0:
+                    res[(l, name)] = v
+        return res
+
+    def stk_set_asm_variant(self, level: int, variant: int, dtype=None):
+        import torch
+        dt = STK_F32 if dtype in (torch.float32, "f32") else STK_F64
+        _check(load().stk_set_asm_variant(self._h, int(level), dt, int(variant)))
 
     def stk_profile(self, enable, reps: int = 1):
         """Start (enable) or stop kernel timing; each instrumented launch is
