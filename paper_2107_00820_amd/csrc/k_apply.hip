@@ -490,7 +490,6 @@ constexpr int kE3Cells = 7;
 // other is).
 template <class R>
 struct E3Smem {
-  R u[kE3Cells + 1][3][27];
   union {
     R x[kE3Cells + 1][2][27];
     R red[kE3Cells + 1][9][4];
@@ -521,7 +520,9 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
     c[1] = (int)((cell / g.N) % g.N);
     c[2] = (int)(cell / ((int64_t)g.N * g.N));
   }
-  // ---- stage u: lane (y,z) = (p0,p1) loads the x-pencil of each component
+  // ---- lane (y,z) = (p0,p1) loads the x-pencil of each component; the x
+  // stage below contracts exactly this pencil, so it stays in registers
+  R upen[3][3] = {};   // [comp][x]
   if (need_u) {
     const int a1 = 2 * c[1] + p0, a2 = 2 * c[2] + p1;
     const bool bnd12 = a1 == 0 || a1 == 2 * g.N || a2 == 0 || a2 == 2 * g.N;
@@ -531,14 +532,10 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
       const bool bnd = bnd12 || a0 == 0 || a0 == 2 * g.N;
       const int64_t nd = node_index<3>(g, a0, a1, a2);
 #pragma unroll
-      for (int comp = 0; comp < 3; ++comp) {
-        R v = (R)0;
-        if (valid && !bnd) v = u[comp * g.nnodes + nd];
-        sm.u[lc][comp][i3(a, p0, p1)] = v;
-      }
+      for (int comp = 0; comp < 3; ++comp)
+        if (valid && !bnd) upen[comp][a] = u[comp * g.nnodes + nd];
     }
   }
-  __syncthreads();
   // ---- gradient at the lane's Gauss points (qx,qy) = (p0,p1), qz = 0..2
   R G[3][3][3];   // [qz][comp][k]
 #pragma unroll
@@ -552,8 +549,7 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
     for (int comp = 0; comp < 3; ++comp) {
       // x: lane (y,z) = (p0,p1)
       {
-        const R u0 = sm.u[lc][comp][i3(0, p0, p1)], u1 = sm.u[lc][comp][i3(1, p0, p1)],
-                u2 = sm.u[lc][comp][i3(2, p0, p1)];
+        const R u0 = upen[comp][0], u1 = upen[comp][1], u2 = upen[comp][2];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           sm.x[lc][0][i3(q, p0, p1)] = u0 * (R)kB1[q][0] + u1 * (R)kB1[q][1] + u2 * (R)kB1[q][2];

@@ -221,7 +221,7 @@ __device__ __attribute__((always_inline)) inline void packed_symv(const R* __res
 template <int D, class R, int V>
 struct AsmTune {
   // 3D interior patches (81 unknowns, LDS-staged residual): elements per chunk
-  static constexpr int ch81 = sizeof(R) == 8 ? (V == 0 ? 16 : (V == 1 ? 8 : 12)) : (V == 0 ? 32 : (V == 1 ? 16 : 24));
+  static constexpr int ch81 = sizeof(R) == 8 ? (V == 0 ? 16 : (V == 1 ? 24 : 12)) : (V == 0 ? 32 : (V == 1 ? 48 : 24));
   // 2D interior patches (18 unknowns from registers): number of chunks
   static constexpr int nch18 = V == 0 ? 4 : (V == 1 ? 6 : 8);
   // minimum wavefronts per SIMD requested from the compiler
@@ -438,7 +438,9 @@ __global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g
       if (w == (I & 3)) xs[I * 64 + lane] = in[offset(I)];
     });
     __syncthreads();
-    split_symv81<AsmTune<3, R, 0>::ch81>(A, xs, lane, w, store);
+    // few workgroups (one per 64 coarse cells): long chunks keep more bytes
+    // in flight per wavefront, occupancy does not matter here
+    split_symv81<sizeof(R) == 8 ? 32 : 64>(A, xs, lane, w, store);
   }
 }
 
