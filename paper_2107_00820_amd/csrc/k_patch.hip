@@ -253,10 +253,13 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
   const R* A = inv + ((int64_t)(s / 64) * P) * 64 + (s % 64);
   R y[NPT];
   packed_symv<NPT, NCH>(A, x, y);
-  // the scatter recomputes its indices rather than keeping the gather's
-  // (which would hold NPT index triples in registers across the GEMV)
+  // 27-unknown patches: the scatter recomputes its indices rather than
+  // keeping the gather's, which would hold 27 index triples in registers
+  // across the GEMV and spill (smaller patches keep them)
+  if constexpr (NPT == 27) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(lo[k]), "+v"(ext[k]), "+v"(vc[k]));
+    for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(lo[k]), "+v"(ext[k]), "+v"(vc[k]));
+  }
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     int nd[3];
