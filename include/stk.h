@@ -258,13 +258,19 @@ stk_status stk_poll(stk_hier* h, stk_solve_info* info);
  * mixed = 1) with HIP events around `reps` (1..100) back-to-back launches on
  * the level's own buffers, keeps the fastest per (level, precision), and
  * writes the choices to variants[(level - 1) * 2 + dtype] if variants is not
- * NULL (2 (L - 1) ints, -1 for a precision not in use). Synchronous on
+ * NULL (2 (L - 1) ints, -1 for a precision not in use) and the measured
+ * average launch time of every variant to
+ * times_ms[((level - 1) * 2 + dtype) * STK_ASM_VARIANTS + variant] if
+ * times_ms is not NULL (entries of precisions not in use untouched). Timing
+ * noise can make the choice differ between runs; for reproducible
+ * measurements apply a recorded choice with stk_set_asm_variant instead
+ * (the Python layer keeps such a table). Synchronous on
  * `stream`; drops the captured HIP graphs (they are re-captured on the next
  * solve). STK_EBUSY while a resumable solve is in progress.
  * stk_set_asm_variant fixes the variant of one (level, dtype) by hand
  * (0 <= variant < STK_ASM_VARIANTS; level >= 1). Default: variant 0. */
 #define STK_ASM_VARIANTS 3
-stk_status stk_autotune(stk_hier* h, int reps, int* variants, void* stream);
+stk_status stk_autotune(stk_hier* h, int reps, int* variants, float* times_ms, void* stream);
 stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant);
 
 /* Kernel timing (tracing). stk_profile(h, r), 1 <= r <= 100, clears the

@@ -705,7 +705,7 @@ stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant) {
 // Times every patch-solve variant on every smoothed level (and precision in
 // use) with HIP events around `reps` back-to-back launches on the level's own
 // buffers, and keeps the fastest (ties: the lower index).
-stk_status stk_autotune(stk_hier* h, int reps, int* variants, void* stream) {
+stk_status stk_autotune(stk_hier* h, int reps, int* variants, float* times_ms, void* stream) {
   GET_H(h);
   if (reps < 1 || reps > 100) return fail(STK_EINVAL, "reps must be in [1, 100]");
   if (H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL ||
@@ -736,6 +736,7 @@ stk_status stk_autotune(stk_hier* h, int reps, int* variants, void* stream) {
           st = fail(STK_EDEVICE, "event timing failed");
           break;
         }
+        if (times_ms) times_ms[((l - 1) * 2 + dt) * kAsmVariants + v] = ms / (float)reps;
         if (v == 0 || ms < best_ms) {
           best = v;
           best_ms = ms;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libstk.so")
 
 STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ENOTCONV, STK_ENOTSPD, STK_ENAN, STK_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 STK_F64, STK_F32 = 0, 1
+STK_ASM_VARIANTS = 3
 STK_PC_MIXED, STK_PC_UPPER = 1, 2
 _PC = {"full": 0, "upper": 1}
 _NAMES = {0: "STK_OK", -1: "STK_EINVAL", -2: "STK_ENOMEM", -3: "STK_EDEVICE", -4: "STK_ENOTCONV",
@@ -94,7 +95,7 @@ def load(path: str = LIB_PATH):
         "stk_poll": [vp, C.POINTER(SolveInfo)],
         "stk_profile": [vp, i32],
         "stk_profile_read": [vp, i32, i64p, dp, dp],
-        "stk_autotune": [vp, i32, C.POINTER(C.c_int), vp],
+        "stk_autotune": [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_float), vp],
         "stk_set_asm_variant": [vp, i32, i32, i32],
     }
     for name, args in sig.items():
@@ -305,18 +306,41 @@ class Hierarchy:
         return dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
                     t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
 
-    def stk_autotune(self, reps: int = 5):
+    def stk_autotune(self, reps: int = 5, with_times: bool = False):
         """Time the bit-identical patch-solve variants on every smoothed level
-        and keep the fastest; returns {(level, "f64"|"f32"): variant}."""
-        out = (C.c_int * (2 * max(self.L - 1, 1)))()
-        _check(load().stk_autotune(self._h, int(reps), out, _stream()))
-        res = {}
+        and keep the fastest; returns {(level, "f64"|"f32"): variant} (and the
+        per-variant average launch times in ms if with_times)."""
+        nl = max(self.L - 1, 1)
+        out = (C.c_int * (2 * nl))()
+        tm = (C.c_float * (2 * nl * STK_ASM_VARIANTS))()
+        _check(load().stk_autotune(self._h, int(reps), out, tm, _stream()))
+        res, times = {}, {}
         for l in range(1, self.L):
             for dt, name in ((0, "f64"), (1, "f32")):
                 v = out[(l - 1) * 2 + dt]
                 if v >= 0:
                     res[(l, name)] = v
-        return res
+                    k = ((l - 1) * 2 + dt) * STK_ASM_VARIANTS
+                    times[(l, name)] = [tm[k + i] for i in range(STK_ASM_VARIANTS)]
+        return (res, times) if with_times else res
+
+    def level_cells(self, level: int) -> int:
+        """Cells per axis of a level (level L-1 is the finest)."""
+        return int(self.desc.n_fine) >> (self.L - 1 - int(level))
+
+    def apply_asm_tuning(self, table) -> dict:
+        """Apply a recorded choice {(dim, cells per axis, "f64"|"f32"): variant}
+        to every level it covers; returns {(level, dtype): variant} applied."""
+        applied = {}
+        for l in range(1, self.L):
+            for name in ("f64", "f32"):
+                if name == "f32" and not self.desc.mixed:
+                    continue
+                v = table.get((int(self.dim), self.level_cells(l), name))
+                if v is not None:
+                    self.stk_set_asm_variant(l, v, name)
+                    applied[(l, name)] = v
+        return applied
 
     def stk_set_asm_variant(self, level: int, variant: int, dtype=None):
         import torch
