@@ -78,11 +78,18 @@ def measured_traffic(wl, form):
     from paper_2107_00820_amd.profiling import kernel_source_hash
     if t.get("source_hash") != kernel_source_hash():
         return None, "kernels changed since the counters were taken"
-    r = "float" if form == "mixed" else "double"
+    # all launches of the patch-solve kernel in this precision (every level and
+    # tuning variant), weighted by their launch counts in the counter runs
+    r = "float" if form.startswith("mixed") else "double"
+    tot = n = 0.0
     for k, v in t["kernels"].items():
-        if re.search(rf"k_asm_gemv<{wl.dim}, {r}>", k):
-            return v["traffic_bytes_per_launch"], os.path.relpath(p, ROOT)
-    return None, "kernel not in the counter summary"
+        if re.search(rf"k_asm_gemv<{wl.dim}, {r}(, \d+)?>", k) and v.get("traffic_bytes_per_launch"):
+            c = min(v["launches_fetch_run"], v["launches_write_run"])
+            tot += v["traffic_bytes_per_launch"] * c
+            n += c
+    if n == 0:
+        return None, "kernel not in the counter summary"
+    return tot / n, os.path.relpath(p, ROOT)
 
 
 def serving_leg(n, budget_gb, pc="full"):
