@@ -447,6 +447,85 @@ __global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g
   }
 }
 
+// 3D centre solves with the four pieces of split_symv81 on four separate
+// single-wavefront workgroups (grid: tiles of 64 coarse cells x 4 pieces), so
+// that a level with few coarse cells spreads its inverse stream over four
+// times as many compute units; piece w of tile t writes its partial rows to
+// part[(t*4 + w)*61 + slot][64]. k_center_combine then sums them in the
+// order split_symv81 uses (y0 + y1, y0 + y2, (y1 + y2) + y3), so the result
+// is bit-identical to k_center_solve.
+template <class PC, int CH, class R, class XR>
+__device__ __attribute__((always_inline)) inline void piece_to_global(const R* __restrict__ A, const XR& xr,
+                                                                      R* __restrict__ dst, int lane) {
+  R y[PC::ny];
+  piece_symv<CH, PC>(A, xr, y);
+  static_for<PC::ny>([&](auto I) { dst[(int64_t)I * 64 + lane] = y[I]; });
+}
+
+constexpr int kCenterCH64 = 32, kCenterCH32 = 64;
+
+template <class R>
+__global__ void __launch_bounds__(64) k_center_piece(LevelGeo g, const R* __restrict__ inv,
+                                                      const R* __restrict__ in, R* __restrict__ part) {
+  constexpr int NN = 27, NPT = 81;
+  const int nc = g.N / 2;
+  const int ncc = nc * nc * nc;
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.x, w = blockIdx.y;
+  const int s = tile * 64 + lane;
+  const int sc = s < ncc ? s : ncc - 1;
+  const int K0 = sc % nc, K1 = (sc / nc) % nc, K2 = sc / (nc * nc);
+  const int64_t base = node_index<3>(g, 4 * K0 + 1, 4 * K1 + 1, 4 * K2 + 1);
+  const int64_t n1 = g.n1;
+  // each lane stages and reads only its own column: no barrier needed
+  __shared__ R xs[NPT * 64];
+  static_for<NPT>([&](auto I) {
+    constexpr int i = I;
+    constexpr int comp = i / NN, loc = i % NN;
+    xs[i * 64 + lane] = in[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
+  });
+  const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
+  const R* A = inv + ((int64_t)tile * P) * 64 + lane;
+  auto xr = [&](int j) { return xs[j * 64 + lane]; };
+  R* dst = part + ((int64_t)(tile * 4 + w) * 61) * 64;
+  constexpr int CH = sizeof(R) == 8 ? kCenterCH64 : kCenterCH32;
+  if (w == 0) piece_to_global<Q81_0, CH>(A, xr, dst, lane);
+  else if (w == 1) piece_to_global<Q81_1, CH>(A, xr, dst, lane);
+  else if (w == 2) piece_to_global<Q81_2, CH>(A, xr, dst, lane);
+  else piece_to_global<Q81_3, CH>(A, xr, dst, lane);
+}
+
+template <bool ACC, class R>
+__global__ void __launch_bounds__(64) k_center_combine(LevelGeo g, const R* __restrict__ part, R* __restrict__ out,
+                                                        double alpha_d) {
+  constexpr int NN = 27, NPT = 81;
+  const R alpha = (R)alpha_d;
+  const int nc = g.N / 2;
+  const int ncc = nc * nc * nc;
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int s = tile * 64 + lane;
+  if (s >= ncc) return;
+  const int K0 = s % nc, K1 = (s / nc) % nc, K2 = s / (nc * nc);
+  const int64_t base = node_index<3>(g, 4 * K0 + 1, 4 * K1 + 1, 4 * K2 + 1);
+  const int64_t n1 = g.n1;
+  const R* p0 = part + ((int64_t)(tile * 4 + 0) * 61) * 64 + lane;
+  const R* p1 = part + ((int64_t)(tile * 4 + 1) * 61) * 64 + lane;
+  const R* p2 = part + ((int64_t)(tile * 4 + 2) * 61) * 64 + lane;
+  const R* p3 = part + ((int64_t)(tile * 4 + 3) * 61) * 64 + lane;
+  static_for<NPT>([&](auto I) {
+    constexpr int i = I;
+    R y;
+    if constexpr (i < 20) y = p0[Q81_0::slot(i) * 64] + p1[Q81_1::slot(i) * 64];
+    else if constexpr (i < 40) y = p0[Q81_0::slot(i) * 64] + p2[Q81_2::slot(i) * 64];
+    else y = (p1[Q81_1::slot(i) * 64] + p2[Q81_2::slot(i) * 64]) + p3[Q81_3::slot(i) * 64];
+    constexpr int comp = i / NN, loc = i % NN;
+    const int64_t o = comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2));
+    if constexpr (ACC) out[o] += alpha * y;
+    else out[o] = alpha * y;
+  });
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
@@ -515,6 +594,10 @@ void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
     hipLaunchKernelGGL((k_asm_gather<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
 }
 
+// Below this many 64-cell tiles (about two per compute unit) the 3D centre
+// solves run as four single-wavefront pieces per tile plus a combine kernel.
+constexpr int kSplitCenterTiles = 512;
+
 template <class R>
 void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
                          hipStream_t s) {
@@ -525,6 +608,16 @@ void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, 
   if (H.dim == 2) {
     if (accumulate) hipLaunchKernelGGL((k_center_solve<2, true, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
     else hipLaunchKernelGGL((k_center_solve<2, false, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
+  } else if (grid.x < (unsigned)kSplitCenterTiles &&
+             (int64_t)grid.x * 4 * 61 * 64 * (int64_t)sizeof(R) <= (int64_t)Dims<3>::NL * fine.g.ncell * 8) {
+    // few tiles: pieces on separate workgroups, partial rows through the
+    // fine level's element buffer (unused while a transfer runs its local
+    // solves; it holds 81 doubles per fine cell, enough for the partials
+    // from 6^3 fine cells up)
+    R* part = reinterpret_cast<R*>(fine.E);
+    hipLaunchKernelGGL((k_center_piece<R>), dim3(grid.x, 4), dim3(64), 0, s, fine.g, inv, in, part);
+    if (accumulate) hipLaunchKernelGGL((k_center_combine<true, R>), grid, dim3(64), 0, s, fine.g, (const R*)part, out, alpha);
+    else hipLaunchKernelGGL((k_center_combine<false, R>), grid, dim3(64), 0, s, fine.g, (const R*)part, out, alpha);
   } else {
     if (accumulate) hipLaunchKernelGGL((k_center_solve<3, true, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
     else hipLaunchKernelGGL((k_center_solve<3, false, R>), grid, blk, 0, s, fine.g, inv, in, out, alpha);
