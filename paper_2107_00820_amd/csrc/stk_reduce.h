@@ -59,8 +59,19 @@ __device__ inline void block_sum_n(const double (&v)[M], int m, double* sh, doub
 // gets the result.
 __device__ inline double wave_reduce_parts(const double* __restrict__ part, int nparts, int stride, int k) {
   const int lane = threadIdx.x & 63;
+  // the (at most kRedBlocks / 64) loads of a lane are issued together, then
+  // added in index order (the same order as a plain strided loop)
+  constexpr int kPer = kRedBlocks / 64;
+  double v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int b = lane + 64 * i;
+    v[i] = b < nparts ? part[b * stride + k] : 0.0;
+  }
   double s = 0.0;
-  for (int b = lane; b < nparts; b += 64) s += part[b * stride + k];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) s += v[i];
+  for (int b = lane + 64 * kPer; b < nparts; b += 64) s += part[b * stride + k];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   return s;
