@@ -19,6 +19,14 @@
 
 namespace stk {
 
+// The coefficient kernels (Fourier gradients at Gauss points) keep 256-thread
+// workgroups: their register use would spill at the reductions' 1024.
+constexpr int kCoefThreads = 256;
+inline int coef_parts(int64_t n) {
+  const int64_t p = (n + kCoefThreads - 1) / kCoefThreads;
+  return (int)(p < 1 ? 1 : (p > kRedBlocks ? kRedBlocks : p));
+}
+
 template <int D>
 __device__ inline void cell_coords(const LevelGeo& g, int64_t cell, int c[3]) {
   c[0] = (int)(cell % g.N);
@@ -164,10 +172,10 @@ __device__ inline double strain_sq(const double G[D][D]) {
 // part[b] = sum of eps_II^2 = eps:eps / 2 (s = 1) over block b's Gauss points
 // of the finest level (fixed grid-stride partition).
 template <int D>
-__global__ void __launch_bounds__(kRedThreads) k_eps_partials(LevelGeo g, const double* __restrict__ amp, int M,
+__global__ void __launch_bounds__(kCoefThreads) k_eps_partials(LevelGeo g, const double* __restrict__ amp, int M,
                                                                double* __restrict__ part) {
   constexpr int NQ = Dims<D>::NQ;
-  __shared__ double sh[kRedThreads];
+  __shared__ double sh[kCoefThreads];
   double acc = 0.0;
   const int64_t n = (int64_t)NQ * g.ncell;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -185,7 +193,7 @@ __global__ void __launch_bounds__(kRedThreads) k_eps_partials(LevelGeo g, const 
 // `scale` if positive, else 1/sqrt(mean eps_II^2) from the fine-level
 // partial sums (reduced identically by every block).
 template <int D>
-__global__ void __launch_bounds__(kRedThreads)
+__global__ void __launch_bounds__(kCoefThreads)
 k_coef_tensor(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta, double mu_min,
               double mu_max, const double* __restrict__ amp, int M, double tau_y, double scale,
               const double* __restrict__ part, int nparts, int64_t nfine_pts, double* __restrict__ mu,
@@ -1120,25 +1128,25 @@ static void elem_dispatch(const Hier& H, const Level& l, int mode, const R* u, c
 
 void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s) {
   const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * fine.g.ncell;
-  const int np = red_parts(n);
+  const int np = coef_parts(n);
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_eps_partials<2>, dim3(np), dim3(kRedThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
+    hipLaunchKernelGGL(k_eps_partials<2>, dim3(np), dim3(kCoefThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
                        H.partials);
   else
-    hipLaunchKernelGGL(k_eps_partials<3>, dim3(np), dim3(kRedThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
+    hipLaunchKernelGGL(k_eps_partials<3>, dim3(np), dim3(kCoefThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
                        H.partials);
 }
 
 void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStream_t s) {
   const int64_t nf = (int64_t)(H.dim == 2 ? 9 : 27) * fine.g.ncell;
-  const int np = red_parts(nf);
+  const int np = coef_parts(nf);
   const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
   if (H.dim == 2)
-    hipLaunchKernelGGL(k_coef_tensor<2>, dim3(nblk(n, kRedThreads)), dim3(kRedThreads), 0, s, l.g, H.centers,
+    hipLaunchKernelGGL(k_coef_tensor<2>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, H.centers,
                        H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
                        H.vp_scale, H.partials, np, nf, l.mu, l.cw);
   else
-    hipLaunchKernelGGL(k_coef_tensor<3>, dim3(nblk(n, kRedThreads)), dim3(kRedThreads), 0, s, l.g, H.centers,
+    hipLaunchKernelGGL(k_coef_tensor<3>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, H.centers,
                        H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
                        H.vp_scale, H.partials, np, nf, l.mu, l.cw);
 }
@@ -1165,9 +1173,9 @@ void launch_gather_dots(const Hier& H, const Level& l, R* out, int64_t nvec, con
   const R* E = reinterpret_cast<const R*>(l.E);
   const int np = red_parts(nvec);
   if (H.dim == 2)
-    hipLaunchKernelGGL((k_gather_dots<2, R>), dim3(np), dim3(kRedThreads), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
+    hipLaunchKernelGGL((k_gather_dots<2, R>), dim3(np), dim3(red_threads(nvec)), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
   else
-    hipLaunchKernelGGL((k_gather_dots<3, R>), dim3(np), dim3(kRedThreads), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
+    hipLaunchKernelGGL((k_gather_dots<3, R>), dim3(np), dim3(red_threads(nvec)), 0, s, l.g, E, out, nvec, V, ldv, nk, part);
 }
 
 template void launch_gather_dots<double>(const Hier&, const Level&, double*, int64_t, const double*, int64_t, int,
@@ -1216,10 +1224,10 @@ void launch_schur_apply(const Hier& H, const Level& l, const double* y, const do
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
   const int np = red_parts(l.g.ncell);
   if (H.dim == 2) {
-    hipLaunchKernelGGL(k_p0_partials<3>, dim3(np), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_partials<3>, dim3(np), dim3(red_threads(l.g.ncell)), 0, s, l.g.ncell, p, H.partials);
     hipLaunchKernelGGL(k_p0_subtract<3>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials, np, p);
   } else {
-    hipLaunchKernelGGL(k_p0_partials<4>, dim3(np), dim3(kRedThreads), 0, s, l.g.ncell, p, H.partials);
+    hipLaunchKernelGGL(k_p0_partials<4>, dim3(np), dim3(red_threads(l.g.ncell)), 0, s, l.g.ncell, p, H.partials);
     hipLaunchKernelGGL(k_p0_subtract<4>, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell, H.partials, np, p);
   }
 }

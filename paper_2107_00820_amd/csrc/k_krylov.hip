@@ -249,19 +249,19 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 
 template <class R>
 void launch_dots(const R* V, int64_t ldv, int nk, const R* w, int64_t n, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, partials);
+  hipLaunchKernelGGL(k_dots<R>, dim3(red_parts(n)), dim3(red_threads(n)), 0, s, V, ldv, nk, w, n, partials);
 }
 
 template <class R>
 void launch_orth_update(const R* V, int64_t ldv, int nk, R* w, int64_t n, const double* part_in, double* Hcol,
                         int hstride, bool accumulate, double* part_out, bool next_dots, hipStream_t s) {
-  hipLaunchKernelGGL(k_orth_update<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, V, ldv, nk, w, n, part_in,
+  hipLaunchKernelGGL(k_orth_update<R>, dim3(red_parts(n)), dim3(red_threads(n)), 0, s, V, ldv, nk, w, n, part_in,
                      Hcol, hstride, accumulate ? 1 : 0, part_out, next_dots ? 1 : 0);
 }
 
 template <class R>
 void launch_normalize(const double* norm_partials, R* w, int64_t n, R* dst, double* hout, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize<R>, dim3(red_parts(n)), dim3(kRedThreads), 0, s, norm_partials, red_parts(n), w, n,
+  hipLaunchKernelGGL(k_normalize<R>, dim3(red_parts(n)), dim3(red_threads(n)), 0, s, norm_partials, red_parts(n), w, n,
                      dst, hout);
 }
 

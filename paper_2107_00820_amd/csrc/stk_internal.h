@@ -16,7 +16,8 @@ constexpr int kMaxNu = 8;          // relaxation steps per smoothing call
 // 1 / Mhat: inverse of the reference pressure mass diag(1, 1/12, ..)
 constexpr double kInvMhat[4] = {1.0, 12.0, 12.0, 12.0};
 constexpr int kRedBlocks = 512;    // fixed grid of the deterministic reductions
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;   // largest workgroup of the reductions (see red_threads)
+constexpr int64_t kRedLongVector = 2000000;
 
 // Modes of the element kernel (bit set).
 enum : int {

@@ -8,8 +8,13 @@ namespace stk {
 // Number of partial sums (one per block) used for a vector of length n: one
 // element per thread up to kRedBlocks blocks (short vectors then finish in
 // one memory round trip), grid-stride beyond.
+// Threads per workgroup of the reductions over a vector of length n: 256,
+// or kRedThreads (1024) for long vectors, where fewer grid-stride rounds per
+// thread pay for the wider block sums.
+inline int red_threads(int64_t n) { return n >= kRedLongVector ? kRedThreads : 256; }
 inline int red_parts(int64_t n) {
-  const int64_t p = (n + (int64_t)kRedThreads - 1) / (int64_t)kRedThreads;
+  const int64_t t = red_threads(n);
+  const int64_t p = (n + t - 1) / t;
   return (int)(p < 1 ? 1 : (p > kRedBlocks ? kRedBlocks : p));
 }
 
