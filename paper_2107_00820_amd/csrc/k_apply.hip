@@ -769,28 +769,37 @@ __device__ inline R gather_sum(const LevelGeo& g, const R* __restrict__ E, int64
   for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * g.N;
   dirichlet = bnd;
   if (bnd) return (R)0;
-  // per axis up to two (cell, local) pairs
+  // per axis up to two (cell, local) pairs; an absent second pair repeats
+  // the first so that every address below is valid
   int cc[3][2], ll[3][2], cnt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k >= D) {
-      cnt[k] = 1; cc[k][0] = 0; ll[k][0] = 0;
+      cnt[k] = 1; cc[k][0] = cc[k][1] = 0; ll[k][0] = ll[k][1] = 0;
       continue;
     }
     if (i[k] & 1) {
-      cnt[k] = 1; cc[k][0] = (i[k] - 1) >> 1; ll[k][0] = 1;
+      cnt[k] = 1; cc[k][0] = cc[k][1] = (i[k] - 1) >> 1; ll[k][0] = ll[k][1] = 1;
     } else {
       cnt[k] = 2; cc[k][0] = (i[k] >> 1) - 1; ll[k][0] = 2; cc[k][1] = i[k] >> 1; ll[k][1] = 0;
     }
   }
+  // all (up to 2^d) loads issued together, then summed in the fixed order
+  constexpr int NT = D == 3 ? 8 : 4;
+  R v[NT];
+  bool ok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int t0 = t & 1, t1 = (t >> 1) & 1, t2 = t >> 2;
+    ok[t] = t0 < cnt[0] && t1 < cnt[1] && t2 < cnt[2];
+    const int64_t cell = cell_index<D>(g, cc[0][t0], cc[1][t1], cc[2][t2]);
+    const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
+    v[t] = ok[t] ? E[cell * (D * NN) + comp * NN + loc] : (R)0;
+  }
   R s = 0;
-  for (int t2 = 0; t2 < cnt[2]; ++t2)
-    for (int t1 = 0; t1 < cnt[1]; ++t1)
-      for (int t0 = 0; t0 < cnt[0]; ++t0) {
-        const int64_t cell = cell_index<D>(g, cc[0][t0], cc[1][t1], cc[2][t2]);
-        const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
-        s += E[cell * (D * NN) + comp * NN + loc];
-      }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (ok[t]) s += v[t];
   return s;
 }
 

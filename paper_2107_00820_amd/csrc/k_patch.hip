@@ -369,25 +369,35 @@ __global__ void k_asm_gather(LevelGeo g, const R* __restrict__ zbuf, int nvert, 
     y[idx] = (R)0;
     return;
   }
+  // per axis up to two (vertex, local) pairs; an absent second pair repeats
+  // the first so that every address below is valid
   int vv[3][2], ll[3][2], cnt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (k >= D) { cnt[k] = 1; vv[k][0] = 0; ll[k][0] = 0; continue; }
+    if (k >= D) { cnt[k] = 1; vv[k][0] = vv[k][1] = 0; ll[k][0] = ll[k][1] = 0; continue; }
     if (i[k] & 1) {
       cnt[k] = 2; vv[k][0] = (i[k] - 1) >> 1; ll[k][0] = 2; vv[k][1] = (i[k] + 1) >> 1; ll[k][1] = 0;
     } else {
-      cnt[k] = 1; vv[k][0] = i[k] >> 1; ll[k][0] = 1;
+      cnt[k] = 1; vv[k][0] = vv[k][1] = i[k] >> 1; ll[k][0] = ll[k][1] = 1;
     }
   }
   const int nv = g.N + 1;
+  // all (up to 2^d) loads issued together, then summed in the fixed order
+  constexpr int NT = D == 3 ? 8 : 4;
+  R v[NT];
+  bool ok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int t0 = t & 1, t1 = (t >> 1) & 1, t2 = t >> 2;
+    ok[t] = t0 < cnt[0] && t1 < cnt[1] && t2 < cnt[2];
+    const int vert = vv[0][t0] + nv * (vv[1][t1] + nv * vv[2][t2]);
+    const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
+    v[t] = ok[t] ? zbuf[(int64_t)(comp * NN + loc) * nvert + vert] : (R)0;
+  }
   R s = 0;
-  for (int t2 = 0; t2 < cnt[2]; ++t2)
-    for (int t1 = 0; t1 < cnt[1]; ++t1)
-      for (int t0 = 0; t0 < cnt[0]; ++t0) {
-        const int vert = vv[0][t0] + nv * (vv[1][t1] + nv * vv[2][t2]);
-        const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
-        s += zbuf[(int64_t)(comp * NN + loc) * nvert + vert];
-      }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (ok[t]) s += v[t];
   y[idx] = s;
 }
 
