@@ -34,26 +34,26 @@ __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const R* __restrict__ xc
     r[k] = i[k] & 3;
     if (cell[k] == gc.N) { cell[k] = gc.N - 1; r[k] = 4; }
   }
-  R s = 0;
-  for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2) {
+  // all (up to 3^d) loads issued together, then summed in the fixed order
+  // (a2, a1, a0 ascending, zero weights and coarse Dirichlet nodes skipped)
+  constexpr int NA2 = D == 3 ? 3 : 1, NT = NA2 * 9;
+  R v[NT];
+  double wt[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int a0 = t % 3, a1 = (t / 3) % 3, a2 = t / 9;
     const double w2 = D == 3 ? kProlW[r[2]][a2] : 1.0;
-    if (w2 == 0.0) continue;
-    const int j2 = 2 * cell[2] + a2;
-    if (D == 3 && (j2 == 0 || j2 == 2 * gc.N)) continue;
-    for (int a1 = 0; a1 < 3; ++a1) {
-      const double w1 = kProlW[r[1]][a1];
-      if (w1 == 0.0) continue;
-      const int j1 = 2 * cell[1] + a1;
-      if (j1 == 0 || j1 == 2 * gc.N) continue;
-      for (int a0 = 0; a0 < 3; ++a0) {
-        const double w0 = kProlW[r[0]][a0];
-        if (w0 == 0.0) continue;
-        const int j0 = 2 * cell[0] + a0;
-        if (j0 == 0 || j0 == 2 * gc.N) continue;
-        s += (R)(w0 * w1 * w2) * xc[comp * gc.nnodes + node_index<D>(gc, j0, j1, j2)];
-      }
-    }
+    const double w1 = kProlW[r[1]][a1], w0 = kProlW[r[0]][a0];
+    const int j0 = 2 * cell[0] + a0, j1 = 2 * cell[1] + a1, j2 = D == 3 ? 2 * cell[2] + a2 : 0;
+    bool ok = w0 != 0.0 && w1 != 0.0 && w2 != 0.0 && j0 != 0 && j0 != 2 * gc.N && j1 != 0 && j1 != 2 * gc.N;
+    if (D == 3) ok = ok && j2 != 0 && j2 != 2 * gc.N;
+    wt[t] = ok ? w0 * w1 * w2 : 0.0;
+    v[t] = ok ? xc[comp * gc.nnodes + node_index<D>(gc, j0, j1, j2)] : (R)0;
   }
+  R s = 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (wt[t] != 0.0) s += (R)wt[t] * v[t];
   xf[idx] = s;
 }
 
@@ -119,20 +119,27 @@ __global__ void k_restrict_pass(LevelGeo gf, LevelGeo gc, const R* __restrict__ 
       return;
     }
   }
-  int fn[7];
-  double fw[7];
+  int fn[7] = {};
+  double fw[7] = {};
   const int cnt = fine_support(o[AX], gc.N, fn, fw);
   const int64_t stride = AX == 0 ? 1 : (AX == 1 ? (int64_t)ei[0] : (int64_t)ei[0] * ei[1]);
   int base3[3] = {o[0], o[1], o[2]};
   base3[AX] = 0;
   const int64_t base = (int64_t)comp * ei[0] * ei[1] * ei[2] + base3[0] +
                        (int64_t)ei[0] * (base3[1] + (int64_t)ei[1] * base3[2]);
-  R s = 0;
-  for (int t = 0; t < cnt; ++t) {
-    const int i = fn[t];
-    if (i == 0 || i == 2 * gf.N) continue;
-    s += (R)fw[t] * in[base + stride * i];
+  // all (up to 7) loads issued together, then summed in support order
+  R v[7];
+  bool ok[7];
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int i = t < cnt ? fn[t] : 0;
+    ok[t] = t < cnt && i != 0 && i != 2 * gf.N;
+    v[t] = ok[t] ? in[base + stride * i] : (R)0;
   }
+  R s = 0;
+#pragma unroll
+  for (int t = 0; t < 7; ++t)
+    if (ok[t]) s += (R)fw[t] * v[t];
   out[idx] = s;
 }
 
