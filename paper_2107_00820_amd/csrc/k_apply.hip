@@ -15,6 +15,7 @@
 // No atomics, so repeated applications give bit-identical results.
 #include <type_traits>
 
+#include "stk_asm_sum.h"
 #include "stk_reduce.h"
 
 namespace stk {
@@ -271,10 +272,18 @@ __device__ inline double selc(const double (&tab)[3][3], int r, int c) {
   return c == 0 ? tab[r][0] : (c == 1 ? tab[r][1] : tab[r][2]);
 }
 
-template <int D, int MODE, bool TENSOR, class R>
+//
+// With ZS the input is not a node vector but the smoother's patch-output
+// buffer (u = zbuf, nvert vertices): each lane forms its node's value as the
+// sum of the patch outputs there, exactly as the separate gather does, and
+// the one cell that owns the node (the lowest cell containing it on every
+// axis) also stores that value to zout, so the smoother's search direction
+// is written once without a kernel of its own.
+template <int D, int MODE, bool TENSOR, class R, bool ZS = false>
 __global__ void __launch_bounds__(64)
 k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* __restrict__ winv, double gamma_d,
-       const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
+       const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout,
+       int nvert = 0, R* __restrict__ zout = nullptr) {
   constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
   constexpr int NS = SymIdx<D>::NS;
   constexpr int CPW = 64 / NQ;
@@ -304,10 +313,22 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* 
     bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
     if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
     const int64_t nd = node_index<D>(g, a0, a1, a2);
+    if constexpr (ZS) {
+      const int ai[3] = {a0, a1, a2};
+      bool own = (t0 < 2 || c[0] == g.N - 1) && (t1 < 2 || c[1] == g.N - 1);
+      if (D == 3) own = own && (t2 < 2 || c[2] == g.N - 1);
 #pragma unroll
-    for (int comp = 0; comp < D; ++comp) {
-      const R v = u[comp * g.nnodes + nd];
-      us[lc][comp][t] = bnd ? (R)0 : v;
+      for (int comp = 0; comp < D; ++comp) {
+        const R v = bnd ? (R)0 : asm_node_sum<D, R>(g, u, nvert, comp, ai);
+        us[lc][comp][t] = v;
+        if (own) zout[comp * g.nnodes + nd] = v;
+      }
+    } else {
+#pragma unroll
+      for (int comp = 0; comp < D; ++comp) {
+        const R v = u[comp * g.nnodes + nd];
+        us[lc][comp][t] = bnd ? (R)0 : v;
+      }
     }
   }
   __syncthreads();
@@ -1134,6 +1155,29 @@ static void elem_dispatch(const Hier& H, const Level& l, int mode, const R* u, c
       break;
   }
 }
+
+// 2D smoother: cell kernel of A_gamma on the sum of the patch outputs in the
+// level's patch-output buffer, also storing that sum (the preconditioned
+// direction) to z.
+template <class R>
+void launch_elem_asm(const Hier& H, const Level& l, R* z, hipStream_t s) {
+  if (H.dim != 2) return;
+  constexpr int MODE = EL_VISC | EL_AUG;
+  constexpr int CPW = 64 / Dims<2>::NQ;
+  const dim3 grid(nblk(l.g.ncell, CPW));
+  const R* wi = level_winv<R>(l);
+  const R* zb = reinterpret_cast<const R*>(l.zbuf);
+  if (l.cw)
+    hipLaunchKernelGGL((k_elem<2, MODE, true, R, true>), grid, dim3(64), 0, s, l.g, level_mu<R>(l), level_cw<R>(l),
+                       wi, H.gamma, zb, (const double*)nullptr, reinterpret_cast<R*>(l.E), (double*)nullptr,
+                       l.nvert, z);
+  else
+    hipLaunchKernelGGL((k_elem<2, MODE, false, R, true>), grid, dim3(64), 0, s, l.g, level_mu<R>(l),
+                       (const R*)nullptr, wi, H.gamma, zb, (const double*)nullptr, reinterpret_cast<R*>(l.E),
+                       (double*)nullptr, l.nvert, z);
+}
+template void launch_elem_asm<double>(const Hier&, const Level&, double*, hipStream_t);
+template void launch_elem_asm<float>(const Hier&, const Level&, float*, hipStream_t);
 
 void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s) {
   const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * fine.g.ncell;

@@ -369,36 +369,7 @@ __global__ void k_asm_gather(LevelGeo g, const R* __restrict__ zbuf, int nvert, 
     y[idx] = (R)0;
     return;
   }
-  // per axis up to two (vertex, local) pairs; an absent second pair repeats
-  // the first so that every address below is valid
-  int vv[3][2], ll[3][2], cnt[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (k >= D) { cnt[k] = 1; vv[k][0] = vv[k][1] = 0; ll[k][0] = ll[k][1] = 0; continue; }
-    if (i[k] & 1) {
-      cnt[k] = 2; vv[k][0] = (i[k] - 1) >> 1; ll[k][0] = 2; vv[k][1] = (i[k] + 1) >> 1; ll[k][1] = 0;
-    } else {
-      cnt[k] = 1; vv[k][0] = vv[k][1] = i[k] >> 1; ll[k][0] = ll[k][1] = 1;
-    }
-  }
-  const int nv = g.N + 1;
-  // all (up to 2^d) loads issued together, then summed in the fixed order
-  constexpr int NT = D == 3 ? 8 : 4;
-  R v[NT];
-  bool ok[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int t0 = t & 1, t1 = (t >> 1) & 1, t2 = t >> 2;
-    ok[t] = t0 < cnt[0] && t1 < cnt[1] && t2 < cnt[2];
-    const int vert = vv[0][t0] + nv * (vv[1][t1] + nv * vv[2][t2]);
-    const int loc = ll[0][t0] + 3 * ll[1][t1] + 9 * ll[2][t2];
-    v[t] = ok[t] ? zbuf[(int64_t)(comp * NN + loc) * nvert + vert] : (R)0;
-  }
-  R s = 0;
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (ok[t]) s += v[t];
-  y[idx] = s;
+  y[idx] = asm_node_sum<D, R>(g, zbuf, nvert, comp, i);
 }
 
 // Local solves of the robust transfer: for every coarse cell K, z =
@@ -588,7 +559,7 @@ void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStr
 }
 
 template <class R>
-void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
+void launch_asm_solves(Hier& H, const Level& l, const R* r, hipStream_t s) {
   hipEvent_t ev = nullptr;
   const int reps = prof_begin(H, s, &ev);
   // the kernel is a pure function of (r, inverses) -> zbuf, so a profiled
@@ -596,6 +567,11 @@ void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
   double bytes = 0.0;
   launch_asm_gemv<R>(H, l, r, reps, s, &bytes);
   prof_end(H, s, PROF_ASM_GEMV, ev, bytes, reps);
+}
+
+template <class R>
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
+  launch_asm_solves<R>(H, l, r, s);
   R* zbuf = reinterpret_cast<R*>(l.zbuf);
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
@@ -638,6 +614,8 @@ template void launch_asm_gemv<double>(const Hier&, const Level&, const double*, 
 template void launch_asm_gemv<float>(const Hier&, const Level&, const float*, int, hipStream_t, double*);
 template void launch_asm<double>(Hier&, const Level&, const double*, double*, hipStream_t);
 template void launch_asm<float>(Hier&, const Level&, const float*, float*, hipStream_t);
+template void launch_asm_solves<double>(Hier&, const Level&, const double*, hipStream_t);
+template void launch_asm_solves<float>(Hier&, const Level&, const float*, hipStream_t);
 template void launch_center_solve<double>(const Hier&, const Level&, const double*, double*, double, bool,
                                           hipStream_t);
 template void launch_center_solve<float>(const Hier&, const Level&, const float*, float*, double, bool,

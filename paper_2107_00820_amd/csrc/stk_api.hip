@@ -286,6 +286,28 @@ void apply_A_dots(Hier& H, int l, const R* x, R* y, const R* V, int64_t ldv, int
   launch_gather_dots<R>(H, L, y, L.nvel, V, ldv, nk, part, H.stream);
 }
 
+// 2D smoother step: z = M^{-1} v (ASM) and y = A z with the partial dots of
+// y against V, the sum of the patch outputs formed inside the cell kernel.
+template <class R>
+void asm_apply_A_dots(Hier& H, int l, const R* v, R* z, R* y, const R* V, int64_t ldv, int nk, double* part) {
+  Level& L = H.lv[l];
+  launch_asm_solves<R>(H, L, v, H.stream);
+  hipEvent_t ev = nullptr;
+  const int reps = prof_begin(H, H.stream, &ev);
+  for (int k = 0; k < reps; ++k) launch_elem_asm<R>(H, L, z, H.stream);
+  {
+    // algorithmic bytes: patch outputs read, z written, coefficients and
+    // element vectors of every cell
+    const double nn = 9.0;
+    const double ncoef = L.cw ? 4.0 : 1.0;
+    prof_end(H, H.stream, PROF_ELEM, ev,
+             (double)sizeof(R) * (2.0 * nn * (double)L.nvert + (double)L.nvel +
+                                  (double)L.g.ncell * (ncoef * nn + 2.0 * nn)),
+             reps);
+  }
+  launch_gather_dots<R>(H, L, y, L.nvel, V, ldv, nk, part, H.stream);
+}
+
 template <class R>
 void residual(Hier& H, int l, const R* b, const R* x, R* r) {
   Level& L = H.lv[l];
@@ -338,8 +360,12 @@ void smooth(Hier& H, int l, const R* b, R* x, int nu, bool x_zero) {
     R* Vj = V + (int64_t)j * n;
     R* Zj = Z + (int64_t)j * n;
     R* w = V + (int64_t)(j + 1) * n;
-    launch_asm<R>(H, L, Vj, Zj, H.stream);
-    apply_A_dots<R>(H, l, Zj, w, V, n, j + 1, p1);
+    if (H.dim == 2) {
+      asm_apply_A_dots<R>(H, l, Vj, Zj, w, V, n, j + 1, p1);
+    } else {
+      launch_asm<R>(H, L, Vj, Zj, H.stream);
+      apply_A_dots<R>(H, l, Zj, w, V, n, j + 1, p1);
+    }
     double* Hcol = L.small + kSmallH + j;
     launch_orth_update<R>(V, n, j + 1, w, n, p1, Hcol, kMaxNu, false, p2, true, H.stream);
     launch_orth_update<R>(V, n, j + 1, w, n, p2, Hcol, kMaxNu, true, p1, false, H.stream);

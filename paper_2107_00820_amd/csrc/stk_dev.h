@@ -4,6 +4,7 @@
 #pragma once
 
 #include "stk_internal.h"
+#include "stk_asm_sum.h"
 
 namespace stk {
 

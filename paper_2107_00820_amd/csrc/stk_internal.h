@@ -164,6 +164,10 @@ void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const doub
                  hipStream_t s);
 template <class R>
 void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R* out, hipStream_t s);
+// 2D only: cell kernel on the sum of the patch outputs held in l.zbuf, which
+// it also stores to z (replaces the patch-output gather plus launch_elem)
+template <class R>
+void launch_elem_asm(const Hier& H, const Level& l, R* z, hipStream_t s);
 // gather of the element outputs into out[0, d*nnodes) fused with the partial
 // dot products V_k . out over out[0, nvec) (same partition as launch_dots)
 template <class R>
@@ -179,6 +183,10 @@ void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
 template <class R>
 void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s);
+// The patch solves of one ASM application into l.zbuf (traced like
+// launch_asm), without the gather to a node vector.
+template <class R>
+void launch_asm_solves(Hier& H, const Level& l, const R* r, hipStream_t s);
 // The patch-solve kernel alone (reps launches), no gather and no tracing;
 // *bytes_out receives its algorithmic bytes per launch if non-NULL.
 template <class R>
