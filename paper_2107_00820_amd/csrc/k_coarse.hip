@@ -14,10 +14,16 @@
 // Sweep of pivot block K (symmetric Gauss-Jordan; after all blocks the array
 // holds -A^{-1}): with P = A_KK and C_I = A_IK (old),
 //   A_KK <- -P^{-1};  A_IK <- C_I P^{-1};  A_IJ <- A_IJ - C_I P^{-1} C_J^T,
-// for I, J != K. P stays SPD (a Schur complement of an SPD matrix). The
-// rank-64 updates are 64 x 64 x 64 tile products on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64); the pivot inverse is a Cholesky-based inversion
-// in LDS.
+// for I, J != K. P stays SPD (a Schur complement of an SPD matrix). Every
+// product with P^{-1} goes through the Cholesky factor P = L L^T: with
+// V_I = C_I L^{-T} the update is the symmetric A_IJ -= V_I V_J^T and the new
+// off-diagonal block is V_I L^{-1}. Multiplying by an explicit P^{-1}
+// instead loses accuracy in proportion to kappa(P), and the pivot blocks of
+// these coarse operators are about as ill-conditioned as the whole matrix;
+// the factored form keeps the inverse as accurate as one formed from the
+// Cholesky factor of the whole matrix. The rank-64 updates are 64 x 64 x 64
+// tile products on the FP64 matrix cores (v_mfma_f64_16x16x4f64); the pivot
+// factorisation and inversion run in LDS.
 #include "stk_spd.h"
 
 namespace stk {
@@ -90,10 +96,12 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
   A[idx] = v;
 }
 
-// Pivot: Pinv = A_KK^{-1} (full symmetric 64 x 64) through its Cholesky
-// factor by spd_invert_lower16 (16 x 16 tiles on the FP64 matrix cores).
+// Pivot: with A_KK = L L^T, Linv = L^{-1} (64 x 64 row-major, zeros above
+// the diagonal) and Pinv = A_KK^{-1} = L^{-T} L^{-1} (full symmetric), by the
+// blocked Cholesky inversion in 16 x 16 tiles on the FP64 matrix cores.
 __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
-                                                      double* __restrict__ Pinv, int* __restrict__ flag) {
+                                                      double* __restrict__ Pinv, double* __restrict__ Linv,
+                                                      int* __restrict__ flag) {
   constexpr int NB = kT / 16, NT = NB * (NB + 1) / 2;
   __shared__ double L[NT * kTile17];
   __shared__ double W[NB * kTile17];
@@ -108,7 +116,13 @@ __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ 
     L[t * kTile17 + r * 17 + c] = T[(16 * I + r) * kT + 16 * J + c];
   }
   __syncthreads();
-  spd_invert_lower16(L, NB, W, &bad);
+  spd_cholinv_lower16(L, NB, W, &bad);
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) {
+    const int r = e / kT, c = e % kT;
+    Linv[e] = c > r ? 0.0 : L[ltile(r / 16, c / 16) * kTile17 + (r % 16) * 17 + c % 16];
+  }
+  __syncthreads();   // L is read above before the product below replaces it
+  spd_xtx_lower16(L, NB, W);
   for (int e = threadIdx.x; e < kTT; e += blockDim.x) {
     int r = e / kT, c = e % kT;
     if (c > r) { const int t = r; r = c; c = t; }
@@ -163,15 +177,15 @@ __device__ inline void acc_rc(int a, int b, int r, int& row, int& col) {
   col = 32 * (w & 1) + 16 * b + (lane & 15);
 }
 
-// W_I = C_I P^{-1} for every I != K (grid: one workgroup per block row).
+// V_I = C_I L^{-T} for every I != K (grid: one workgroup per block row).
 __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ A, int K,
-                                                      const double* __restrict__ Pinv, double* __restrict__ W) {
+                                                      const double* __restrict__ Linv, double* __restrict__ W) {
   __shared__ double X[kT * kLd];
   __shared__ double Y[kT * kLd];
   const int I = blockIdx.x;
   if (I == K) return;
   stage_panel(A, I, K, X);
-  stage_full(Pinv, Y);       // P^{-1} is symmetric, so X P^{-1} = X (P^{-1})^T
+  stage_full(Linv, Y);       // X Y^T = C_I L^{-T}
   __syncthreads();
   d4 acc[2][2];
   tile_gemm_xyt(X, Y, acc);
@@ -188,8 +202,8 @@ __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ 
       }
 }
 
-// A_IJ -= W_I C_J^T for every lower tile with I, J != K. The MFMA operands
-// are read straight from global memory (W_I and C_J are shared by a whole
+// A_IJ -= V_I V_J^T for every lower tile with I, J != K. The MFMA operands
+// are read straight from global memory (V_I and V_J are shared by a whole
 // block row / column and stay in L2), so there is no LDS staging or barrier.
 __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
   int I, J;
@@ -198,9 +212,8 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
-  const double* X = W + (int64_t)I * kTT;                  // X[r][k] at r*64 + k
-  const bool below = J > K;                                 // C_J = A_JK (tile (J,K)) or (A_KJ)^T (tile (K,J))
-  const double* Ct = below ? tile_ptr(A, J, K) : tile_ptr(A, K, J);
+  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at r*64 + k
+  const double* Y = W + (int64_t)J * kTT;                  // V_J[c][k] at c*64 + k
   d4 acc[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -210,14 +223,7 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
   for (int k0 = 0; k0 < kT; k0 += 4) {
     const int k = k0 + lk;
     const double a0 = X[(rb + li) * kT + k], a1 = X[(rb + 16 + li) * kT + k];
-    double b0, b1;
-    if (below) {
-      b0 = Ct[(cb + li) * kT + k];
-      b1 = Ct[(cb + 16 + li) * kT + k];
-    } else {
-      b0 = Ct[k * kT + cb + li];
-      b1 = Ct[k * kT + cb + 16 + li];
-    }
+    const double b0 = Y[(cb + li) * kT + k], b1 = Y[(cb + 16 + li) * kT + k];
     acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -236,22 +242,48 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
       }
 }
 
-// A_IK <- W_I (tile (I,K) for I > K, tile (K,I) = W_I^T for I < K); A_KK <- -P^{-1}.
+// A_IK <- V_I L^{-1} (tile (I,K) for I > K, its transpose in tile (K,I) for
+// I < K); A_KK <- -P^{-1}. Operands straight from global memory as in the
+// update.
 __global__ void __launch_bounds__(256) k_sweep_write(double* __restrict__ A, int K, const double* __restrict__ Pinv,
-                                                      const double* __restrict__ W) {
+                                                      const double* __restrict__ Linv, const double* __restrict__ W) {
   const int I = blockIdx.x;
   if (I == K) {
     double* T = tile_ptr(A, K, K);
     for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = -Pinv[e];
-  } else if (I > K) {
-    double* T = tile_ptr(A, I, K);
-    const double* S = W + (int64_t)I * kTT;
-    for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = S[e];
-  } else {
-    double* T = tile_ptr(A, K, I);
-    const double* S = W + (int64_t)I * kTT;
-    for (int e = threadIdx.x; e < kTT; e += blockDim.x) T[e] = S[(e % kT) * kT + e / kT];
+    return;
   }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at r*64 + k
+  d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < kT; k0 += 4) {
+    const int k = k0 + lk;
+    const double a0 = X[(rb + li) * kT + k], a1 = X[(rb + 16 + li) * kT + k];
+    const double b0 = Linv[k * kT + cb + li], b1 = Linv[k * kT + cb + 16 + li];   // B[k][c] = L^{-1}[k][c]
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  double* T = I > K ? tile_ptr(A, I, K) : tile_ptr(A, K, I);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_rc(a, b, r, row, col);
+        if (I > K) T[row * kT + col] = acc[a][b][r];
+        else T[col * kT + row] = acc[a][b][r];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -370,17 +402,20 @@ void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_
     hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);
 }
 
-// work: P^{-1} (kTT) + W (nb * kTT) doubles.
+// work: P^{-1} (kTT) + V (nb * kTT) doubles; the pivot's L^{-1} sits in the
+// block-row slot K of V, which the panel leaves unused.
 int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s) {
   const int nb = coarse_tiles(n);
   const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
   double* Pinv = work;
-  double* W = work + kTT;
+  double* V = work + kTT;
   for (int K = 0; K < nb; ++K) {
-    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, H.flag);
-    hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
-    hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, W);
-    hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, Pinv, W);
+    double* Linv = V + (int64_t)K * kTT;
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, Linv, H.flag);
+    hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, (const double*)Linv, V);
+    hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, (const double*)V);
+    hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, (const double*)Pinv, (const double*)Linv,
+                       (const double*)V);
   }
   return 0;
 }

@@ -96,9 +96,10 @@ __device__ inline int ltile(int I, int J) { return I * (I + 1) / 2 + J; }
 //   3. A^{-1} = X^T X by block rows: (A^{-1})_IJ = sum_{m>=I} X_mI^T X_mJ.
 // On exit the lower tiles hold A^{-1} (diagonal tiles in full). W is LDS
 // scratch of nb tiles. Sets *bad on a non-positive pivot. All threads of the
-// workgroup must call this.
-__device__ inline void spd_invert_lower16(double* L, int nb, double* W, int* bad) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+// workgroup must call this. Phases 1-2 are spd_cholinv_lower16 (on exit the
+// lower tiles hold X = L^{-1}), phase 3 is spd_xtx_lower16.
+__device__ inline void spd_cholinv_lower16(double* L, int nb, double* W, int* bad) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int k = 0; k < nb; ++k) {
     double* tkk = L + ltile(k, k) * kTile17;
     if (w == 0) chol_inv16_wave(tkk, lane, bad);
@@ -140,6 +141,11 @@ __device__ inline void spd_invert_lower16(double* L, int nb, double* W, int* bad
       }
   }
   __syncthreads();
+}
+
+// Lower tiles of X^T X for X = L^{-1} held in the lower tiles (in place).
+__device__ inline void spd_xtx_lower16(double* L, int nb, double* W) {
+  const int tid = threadIdx.x, w = tid >> 6, nw = blockDim.x >> 6;
   for (int I = 0; I < nb; ++I) {
     for (int J = w; J <= I; J += nw) {
       d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -154,6 +160,11 @@ __device__ inline void spd_invert_lower16(double* L, int nb, double* W, int* bad
     }
     __syncthreads();
   }
+}
+
+__device__ inline void spd_invert_lower16(double* L, int nb, double* W, int* bad) {
+  spd_cholinv_lower16(L, nb, W, bad);
+  spd_xtx_lower16(L, nb, W);
 }
 
 }  // namespace stk
