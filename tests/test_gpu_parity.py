@@ -166,10 +166,20 @@ def test_solve_matches_oracle(name):
     # true residual checked with the oracle's assembled operator
     b = orc.rhs()
     assert np.linalg.norm(b - orc.K @ x) <= wl.rtol * np.linalg.norm(b)
-    # residual histories agree
+    # residual histories agree. Within the first cycle both are Arnoldi
+    # estimates; each restart recomputes b - K x, whose rounding error is up
+    # to eps || |b| + |K| |x| || (componentwise bound of a computed residual),
+    # so the entries after a restart are compared to that bound
     h_o = np.array(info_o["hist"])
     h_g = np.array(info["hist"])
-    assert np.allclose(h_g, h_o, rtol=1e-6, atol=1e-14)
+    assert h_g.shape == h_o.shape
+    m = min(len(h_o), wl.restart + 1)
+    assert np.allclose(h_g[:m], h_o[:m], rtol=1e-6, atol=1e-14)
+    if len(h_o) > m:
+        eps = np.finfo(float).eps
+        atol = eps * np.linalg.norm(np.abs(b) + abs(orc.K) @ np.abs(x)) / np.linalg.norm(b)
+        log(f"  history after restart: max diff {np.max(np.abs(h_g[m:] - h_o[m:])):.1e} (bound {atol:.1e})")
+        assert np.allclose(h_g[m:], h_o[m:], rtol=1e-6, atol=atol)
     # determinism: a second solve is bit-identical
     xu2, xp2, info2 = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
     assert info2["iters"] == info["iters"]
