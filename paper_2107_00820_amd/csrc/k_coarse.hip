@@ -189,6 +189,8 @@ __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ 
   __syncthreads();
   d4 acc[2][2];
   tile_gemm_xyt(X, Y, acc);
+  // stored transposed, V_I[r][k] at k*64 + r: the consumers' MFMA operand
+  // loads (16 rows at a fixed k per lane group) then read 128 contiguous bytes
   double* out = W + (int64_t)I * kTT;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         int row, col;
         acc_rc(a, b, r, row, col);
-        out[row * kT + col] = acc[a][b][r];
+        out[col * kT + row] = acc[a][b][r];
       }
 }
 
@@ -212,8 +214,8 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
-  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at r*64 + k
-  const double* Y = W + (int64_t)J * kTT;                  // V_J[c][k] at c*64 + k
+  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at k*64 + r
+  const double* Y = W + (int64_t)J * kTT;                  // V_J[c][k] at k*64 + c
   d4 acc[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -222,8 +224,8 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
 #pragma unroll
   for (int k0 = 0; k0 < kT; k0 += 4) {
     const int k = k0 + lk;
-    const double a0 = X[(rb + li) * kT + k], a1 = X[(rb + 16 + li) * kT + k];
-    const double b0 = Y[(cb + li) * kT + k], b1 = Y[(cb + 16 + li) * kT + k];
+    const double a0 = X[k * kT + rb + li], a1 = X[k * kT + rb + 16 + li];
+    const double b0 = Y[k * kT + cb + li], b1 = Y[k * kT + cb + 16 + li];
     acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -256,7 +258,7 @@ __global__ void __launch_bounds__(256) k_sweep_write(double* __restrict__ A, int
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
-  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at r*64 + k
+  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at k*64 + r
   d4 acc[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -265,7 +267,7 @@ __global__ void __launch_bounds__(256) k_sweep_write(double* __restrict__ A, int
 #pragma unroll
   for (int k0 = 0; k0 < kT; k0 += 4) {
     const int k = k0 + lk;
-    const double a0 = X[(rb + li) * kT + k], a1 = X[(rb + 16 + li) * kT + k];
+    const double a0 = X[k * kT + rb + li], a1 = X[k * kT + rb + 16 + li];
     const double b0 = Linv[k * kT + cb + li], b1 = Linv[k * kT + cb + 16 + li];   // B[k][c] = L^{-1}[k][c]
     acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
