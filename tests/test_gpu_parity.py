@@ -105,7 +105,10 @@ def test_coarse_solve(name):
     A = orc.mg.ops[0].Agamma.toarray()
     ref = orc.mg.coarse_lu.solve(b)
     err = rel(x, ref)
-    tol = max(1e-12, 50 * np.linalg.cond(A) * np.finfo(float).eps)
+    # the inverse is formed through Cholesky factors (square-root sweep), whose
+    # forward error is a small fraction of kappa eps (at most 0.07 kappa eps
+    # over these cases; the explicit-pivot-inverse sweep reached 87)
+    tol = max(1e-12, 2 * np.linalg.cond(A) * np.finfo(float).eps)
     log(f"  rel err {err:.2e} (tol {tol:.1e})")
     assert err <= tol
 
