@@ -61,12 +61,33 @@ __global__ void __launch_bounds__(kRedThreads) k_orth_update(const R* __restrict
                                                               double* __restrict__ part_out, int next_dots) {
   __shared__ double h[64];
   __shared__ double sh[kRedThreads];
+  // this thread's first entry of w and of the first KP basis vectors are
+  // loaded before the partials are reduced (they do not depend on them), so
+  // the two memory round trips overlap; the arithmetic below is unchanged
+  constexpr int KP = 4;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const bool has0 = i0 < n;
+  const double w0 = has0 ? (double)w[i0] : 0.0;
+  double v0[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) v0[k] = (has0 && k < nk) ? (double)V[(int64_t)k * ldv + i0] : 0.0;
   reduce_parts_to_lds(part_in, gridDim.x, nk, h);
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < nk; k += blockDim.x)
       Hcol[k * hstride] = (accumulate ? Hcol[k * hstride] : 0.0) + h[k];
   double nrm = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  if (has0) {
+    double v = w0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (k < nk) v -= h[k] * v0[k];
+    for (int k = KP; k < nk; ++k) v -= h[k] * (double)V[(int64_t)k * ldv + i0];
+    const R vr = (R)v;
+    w[i0] = vr;
+    nrm += (double)vr * (double)vr;
+  }
+  for (int64_t i = i0 + step; i < n; i += step) {
     double v = (double)w[i];
     for (int k = 0; k < nk; ++k) v -= h[k] * (double)V[(int64_t)k * ldv + i];
     const R vr = (R)v;
@@ -106,6 +127,11 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
                                                             const R* w, int64_t n, R* dst,
                                                             double* __restrict__ hout) {
   __shared__ double nrm;
+  // first entry loaded before the norm is reduced (dst may alias w: each
+  // entry is read and written by the same thread only)
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const double w0 = i0 < n ? (double)w[i0] : 0.0;
   if (threadIdx.x < 64) {
     const double s = wave_reduce_parts(part, nparts, 1, 0);
     if (threadIdx.x == 0) {
@@ -115,7 +141,8 @@ __global__ void __launch_bounds__(kRedThreads) k_normalize(const double* __restr
   }
   __syncthreads();
   const double d = nrm;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  if (i0 < n) dst[i0] = (R)(d > 0.0 ? w0 / d : 0.0);
+  for (int64_t i = i0 + step; i < n; i += step)
     dst[i] = (R)(d > 0.0 ? (double)w[i] / d : 0.0);
 }
 
@@ -193,6 +220,14 @@ __global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, const doubl
                                int x_zero) {
   __shared__ double y[NU];
   __shared__ double hl;
+  // this thread's x and Z entries are loaded before the reduction and the
+  // small least-squares solve, which they do not depend on
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const double x0 = (in && !x_zero) ? (double)x[i] : 0.0;
+  double zk[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) zk[k] = in ? (double)Z[(int64_t)k * ldz + i] : 0.0;
   if (threadIdx.x < 64) {
     const double s = wave_reduce_parts(norm_part, nparts, 1, 0);
     if (threadIdx.x == 0) hl = sqrt(s);
@@ -200,11 +235,10 @@ __global__ void k_relax_update(const R* __restrict__ Z, int64_t ldz, const doubl
   __syncthreads();
   if (threadIdx.x == 0) ls_solve<NU>(small, hl, y);
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double v = x_zero ? 0.0 : (double)x[i];
+  if (!in) return;
+  double v = x0;
 #pragma unroll
-  for (int k = 0; k < NU; ++k) v += y[k] * (double)Z[(int64_t)k * ldz + i];
+  for (int k = 0; k < NU; ++k) v += y[k] * zk[k];
   x[i] = (R)v;
 }
 
