@@ -852,6 +852,11 @@ k_gather_dots(LevelGeo g, const R* __restrict__ E, R* __restrict__ out, int64_t 
     for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvec;
          i += (int64_t)gridDim.x * blockDim.x) {
+      // the V entries do not depend on the gather: their loads go first so
+      // that both sets are in flight together
+      double vk[8];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) vk[kk] = k0 + kk < nk ? (double)V[(int64_t)(k0 + kk) * ldv + i] : 0.0;
       R wi;
       if (i < nvel) {
         if (k0 == 0) {
@@ -866,7 +871,7 @@ k_gather_dots(LevelGeo g, const R* __restrict__ E, R* __restrict__ out, int64_t 
       }
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk)
-        if (k0 + kk < nk) acc[kk] += (double)V[(int64_t)(k0 + kk) * ldv + i] * (double)wi;
+        if (k0 + kk < nk) acc[kk] += vk[kk] * (double)wi;
     }
     double tot[8];
     block_sum_n<8>(acc, nk - k0, sh, tot);
