@@ -413,8 +413,17 @@ __global__ void __launch_bounds__(center_threads<D>()) k_center_solve(LevelGeo g
   if constexpr (D == 2) {
     R x[NPT], y[NPT];
     static_for<NPT>([&](auto I) { x[I] = in[offset(I)]; });
-    packed_symv<NPT>(A, x, y);
-    static_for<NPT>([&](auto I) { store(I, y[I]); });
+    if constexpr (ACC) {
+      // the accumulated output is read before the patch product, which it
+      // does not depend on, so its loads overlap the inverse stream
+      R xo[NPT];
+      static_for<NPT>([&](auto I) { xo[I] = out[offset(I)]; });
+      packed_symv<NPT>(A, x, y);
+      static_for<NPT>([&](auto I) { out[offset(I)] = xo[I] + alpha * y[I]; });
+    } else {
+      packed_symv<NPT>(A, x, y);
+      static_for<NPT>([&](auto I) { store(I, y[I]); });
+    }
   } else {
     __shared__ R xs[NPT * 64];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
