@@ -307,6 +307,19 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* 
     c[2] = D == 3 ? (int)(cell / ((int64_t)g.N * g.N)) : 0;
   }
   const R h = (R)g.h;
+  // coefficients at this lane's Gauss point, loaded ahead of the velocity
+  // (they do not depend on it) so the two sets of loads overlap
+  R muq = 0;
+  R wv[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) wv[k] = 0;
+  if ((MODE & EL_VISC) && valid) {
+    muq = mu[cell * NQ + t];
+    if constexpr (TENSOR) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) wv[k] = cw[(cell * NS + k) * NQ + t];
+    }
+  }
   // ---- stage u: lane t loads node t of its cell (Dirichlet nodes masked)
   if (need_u && valid) {
     const int a0 = 2 * c[0] + t0, a1 = 2 * c[1] + t1, a2 = D == 3 ? 2 * c[2] + t2 : 0;
@@ -385,16 +398,13 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* 
       }
     }
     if (MODE & EL_VISC) {
-      const R wm = wq * mu[cell * NQ + t];
+      const R wm = wq * muq;
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) S[SymIdx<D>::at(a, b)] = wm * (G[a][b] + G[b][a]);
       if constexpr (TENSOR) {
         // C:eps = 2 mu eps - (w:eps) w, and w:eps = w:G for symmetric w
-        R wv[NS];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) wv[k] = cw[(cell * NS + k) * NQ + t];
         R wg = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
