@@ -95,8 +95,9 @@ def test_lemma_eigenvalue_bounds_p1(gamma):
 
 def test_exact_block_gives_triangular_spectrum():
     """Remark: with A_gamma inverted exactly, P K is block upper triangular with
-    the identity and Shat_gamma^{-1} S_gamma on the diagonal."""
-    from oracle.krylov import BlockPreconditioner
+    the identity and Shat_gamma^{-1} S_gamma on the diagonal (the oracle's
+    BlockPreconditioner is pinned to the same dense factors in
+    test_oracle_pins.py)."""
     gamma = 50.0
     ops, Z = setup(2, 3, gamma, schur=1)
     K = dense(ops.stokes())
