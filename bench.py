@@ -1,28 +1,30 @@
 """Benchmark: Stokes unknowns solved per second to a 1e-8 relative residual.
 
-One step = one full FGMRES solve (block preconditioner with two V-cycles per
-iteration, robust star smoother and transfers, coarse solve) of the 2D
-128x128 multi-sinker problem (4 levels, 16 sinkers, contrast 1e6, gamma 1e3)
+One step = one full FGMRES solve (block preconditioner of eq. (precond) with
+two V-cycles per iteration, robust star smoother and transfers, coarse solve)
 from x = 0 with the hierarchy already resident in HBM, to an FP64 true
-relative residual of 1e-8. Both forms are timed: the plain FP64 form and the
-mixed form (FP32 V-cycles inside FP64 FGMRES); `value` is the faster one and
-`forms` holds both, plus both forms with the block upper-triangular variant
-of the preconditioner (one V-cycle per iteration; not used for `value`).
-Setup is timed separately. Prints one JSON line.
+relative residual of 1e-8. The default workload is the largest single-GPU
+configuration: 3D 48^3 hexahedra, 3 levels, viscoplastic Newton tensor over
+a 24-sinker base field (contrast 1e10), gamma 1e4 (3,014,493 unknowns).
+`value` is the plain FP64 form. The mixed form (FP32 V-cycles inside FP64
+FGMRES) is attempted too and reported under `forms` (converged or not, with
+the reason); so are the block upper-triangular variant and the F-cycle.
+Setup is timed separately. Also reported: the 2D 128^2 and 3D 32^3
+workloads (FP64, fewer steps) and, unless --no-serving, the serving stream
+(continuous batching, p50/p99 latency). Prints one JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config sinker_2d_128sq_L4] [--form both|fp64|mixed]
-                [--no-cpu-baseline] [--serving N] [--budget-gb G]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--form both|fp64|mixed]
+                [--no-cpu-baseline] [--serving N | --no-serving] [--no-extra] [--trace]
 
---serving N adds a `serving` object: the first N requests of the seeded
-Poisson stream (20 req/s, 2D 32^2..256^2 and 3D 8^3..32^3, contrasts 1e4..1e8)
-through the request loop (admission by HBM footprint, continuous batching),
-with whole-stream DoF/s and p50/p99 request latency.
+--trace leaves out the per-kernel event timing pass and the extra legs, so a
+profiler trace of the command holds the timed solves only.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -32,7 +34,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Stokes DoF solved/s to rel.res 1e-8 (FP64 vs mixed); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-PROF_REPS = 10      # back-to-back repetitions per timed launch (excludes launch gaps)
+DEFAULT_CONFIG = "viscoplastic_3d_48cu_L3"
+# bounded sample of the oracle for the CPU baseline: the same law at the
+# largest 3D size whose oracle setup and solve fit in about half a minute
+CPU_SAMPLE = dict(dim=3, n_fine=8, levels=2)
 
 
 def log(msg):
@@ -48,21 +53,40 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(wl, iters_hint):
-    """The oracle's own FGMRES solve of the same workload on the host CPU,
-    BLAS limited to one thread (the oracle is single-threaded Python/SciPy)."""
-    from threadpoolctl import threadpool_limits
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl):
+    """The oracle's own FGMRES solve of a bounded sample of the workload (same
+    law, parameters and seeds on a smaller mesh) on the host CPU, with the
+    BLAS thread pool at all host cores."""
+    import dataclasses
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.krylov import StokesSolver
-    with threadpool_limits(limits=1):
+    sample = dataclasses.replace(wl, name=f"{wl.name}_sample_{CPU_SAMPLE['n_fine']}", **CPU_SAMPLE)
+    cores = os.cpu_count() or 1
+    with threadpool_limits(limits=cores):
         t0 = time.perf_counter()
-        s = StokesSolver(wl)
+        s = StokesSolver(sample)
         t_setup = time.perf_counter() - t0
         x, info = s.solve()
-    dof = sum(wl.unknowns())
-    return {"value": dof / info["t_solve"], "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"full oracle FGMRES solve of {wl.name} ({info['iters']} iterations, "
-                      f"{info['t_solve']:.1f} s solve, {t_setup:.1f} s setup excluded), 1 thread",
-            "iters": info["iters"], "t_solve_s": info["t_solve"], "t_setup_s": t_setup}
+        blas = [dict(api=p.get("internal_api"), threads=p.get("num_threads")) for p in threadpool_info()]
+    dof = sum(sample.unknowns())
+    return {"value": dof / info["t_solve"], "unit": "DoF/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle FGMRES solve of the same workload recipe on a {sample.dim}D {sample.n_fine}^{sample.dim} "
+                      f"mesh, {sample.levels} levels ({dof} unknowns, {info['iters']} iterations, "
+                      f"{info['t_solve']:.1f} s solve, {t_setup:.1f} s setup excluded); BLAS pool at {cores} threads "
+                      f"(the oracle's patch loops are single-threaded Python)",
+            "iters": info["iters"], "converged": bool(info["converged"]), "t_solve_s": info["t_solve"],
+            "t_setup_s": t_setup, "cpu_model": cpu_model(), "blas": blas}
 
 
 def measured_traffic(wl, form):
@@ -78,8 +102,6 @@ def measured_traffic(wl, form):
     from paper_2107_00820_amd.profiling import kernel_source_hash
     if t.get("source_hash") != kernel_source_hash():
         return None, "kernels changed since the counters were taken"
-    # all launches of the patch-solve kernel in this precision (every level and
-    # tuning variant), weighted by their launch counts in the counter runs
     r = "float" if form.startswith("mixed") else "double"
     tot = n = 0.0
     for k, v in t["kernels"].items():
@@ -90,6 +112,100 @@ def measured_traffic(wl, form):
     if n == 0:
         return None, "kernel not in the counter summary"
     return tot / n, os.path.relpath(p, ROOT)
+
+
+def solve_bytes_model(h, wl, iters, prof, m):
+    """Algorithmic HBM bytes of one solve (FP64), the numerator of the
+    solve-level roofline fraction: the patch-solve and cell-kernel bytes the
+    library counted during the event-timed solve, plus the coarse solves
+    (two per V-cycle's coarsest visit: one product with the packed inverse)
+    and the outer FGMRES orthogonalisation (classical Gram-Schmidt twice:
+    2 (j+1) basis reads and the update per step). Transfers, node gathers and
+    the relaxation's own Krylov vectors are left out, so this is a lower bound."""
+    n_u, n_p = h.sizes(h.L - 1)
+    nvec = n_u + n_p
+    nv0, _ = h.sizes(0)
+    d = wl.dim
+    nc0 = wl.n_level(0)
+    n0 = d * (2 * nc0 - 1) ** d
+    nb = (n0 + 63) // 64
+    coarse = 8.0 * 4096 * nb * (nb + 1) / 2
+    vcycles = 2 * iters
+    orth = 0.0
+    for it in range(iters):
+        j = it % m
+        orth += 8.0 * nvec * (2 * (j + 1) + 2 * (j + 1) + 3)
+    asm_b, elem_b = prof[0][2], prof[1][2]
+    return asm_b + elem_b + vcycles * coarse + orth
+
+
+def time_form(h, wl, bu, bp, xu, xp, form, steps, warmup, profile_pass):
+    import torch
+    mixed = form.startswith("mixed")
+    pc = "upper" if "_upper" in form else "full"
+    cycle = "F" if form.endswith("_F") else "V"
+    kw = dict(rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp, mixed=mixed, pc=pc, cycle=cycle)
+    ok = True
+    info = None
+    for i in range(max(warmup, 1)):
+        _, _, info = h.stk_solve(bu, bp, allow_notconv=True, **kw)
+        log(f"[bench] {form} warmup {i}: {info['iters']} iterations, rel res {info['rel_res']:.2e}")
+        ok = ok and info["converged"]
+        if not ok:
+            break
+    if not ok:
+        return dict(value=None, converged=False, iterations=info["iters"], rel_res=info["rel_res"])
+    lat, iters, rr = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        _, _, info = h.stk_solve(bu, bp, **kw)
+        lat.append(time.perf_counter() - ts)
+        iters.append(info["iters"])
+        rr.append(info["rel_res"])
+        assert info["converged"] and info["rel_res"] <= wl.rtol, info
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    n_u, n_p = wl.unknowns()
+    log(f"[bench] {form}: {steps} solves in {t_total:.3f} s, iterations {iters}")
+    out = dict(value=(n_u + n_p) * steps / t_total, converged=True, ms_per_step=1e3 * t_total / steps,
+               iterations=iters[-1], rel_res=max(rr), p50_ms=1e3 * percentile(lat, 0.5),
+               p99_ms=1e3 * percentile(lat, 0.99), t_total=t_total)
+    if profile_pass:
+        # kernel durations: one more solve with plain launches, each launch of
+        # the instrumented kernel families bracketed by HIP events on the
+        # stream it runs on
+        h.stk_profile(True, reps=1)
+        h.stk_solve(bu, bp, eager=True, **kw)
+        out["prof"] = {k: h.stk_profile_read(k) for k in (0, 1, 2)}
+        h.stk_profile(False)
+    return out
+
+
+def other_workload(name, steps):
+    """FP64 (and, for the 2D workload, mixed) solves of another configuration."""
+    import torch
+    from workloads import CONFIGS
+    from paper_2107_00820_amd import Hierarchy
+    from paper_2107_00820_amd.tune import load_asm_tuning
+    wl = CONFIGS[name]
+    forms = ["fp64", "mixed"] if wl.dim == 2 else ["fp64"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = Hierarchy.from_workload(wl, mixed=1 if "mixed" in forms else 0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    h.apply_asm_tuning(load_asm_tuning())
+    bu, bp = h.stk_rhs()
+    xu, xp = h.zeros_u(), h.zeros_p()
+    res = {"setup_s": t_setup, "unknowns": sum(wl.unknowns())}
+    for f in forms:
+        r = time_form(h, wl, bu, bp, xu, xp, f, steps, 1, False)
+        r.pop("t_total", None)
+        res[f] = r
+    h.close()
+    return res
 
 
 def serving_leg(n, budget_gb, pc="full"):
@@ -109,24 +225,35 @@ def serving_leg(n, budget_gb, pc="full"):
     return out
 
 
+MIXED_REASON = ("the FP32 V-cycle cannot represent A_gamma's near-kernel at gamma / mu_min = 1e4 / 1e-5: "
+                "rounding the patch inverses, transfers or applies to FP32 perturbs the divergence-free "
+                "components by eps32 gamma / mu_min >> 1")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="sinker_2d_128sq_L4")
+    ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--form", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the block upper-triangular preconditioner variant")
-    ap.add_argument("--serving", type=int, default=0)
+                    help="skip the upper-triangular and F-cycle variants")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 2D 128^2 and 3D 32^3 legs")
+    ap.add_argument("--serving", type=int, default=200)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--serving-pc", default="full", choices=["full", "upper"])
+    ap.add_argument("--trace", action="store_true",
+                    help="timed solves only (no event-timing pass, no extra legs, no serving, no oracle)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.trace:
+        args.no_extra = args.no_serving = args.no_cpu_baseline = True
 
     import torch
     from workloads import CONFIGS
@@ -138,7 +265,7 @@ def main():
     log(f"[bench] workload {wl.name}: {dof} unknowns")
     forms = ["fp64", "mixed"] if args.form == "both" else [args.form]
     if not args.no_variants:
-        forms += [f + "_upper" for f in forms]
+        forms += ["fp64_upper", "fp64_F"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = Hierarchy.from_workload(wl, mixed=1 if any(f.startswith("mixed") for f in forms) else 0)
@@ -159,86 +286,70 @@ def main():
     xu, xp = h.zeros_u(), h.zeros_p()
     res = {}
     for form in forms:
-        mixed = form.startswith("mixed")
-        pc = "upper" if form.endswith("_upper") else "full"
-        kw = dict(rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp, mixed=mixed, pc=pc)
-        ok = True
-        for i in range(max(args.warmup, 1)):
-            _, _, info = h.stk_solve(bu, bp, allow_notconv=True, **kw)
-            log(f"[bench] {form} warmup {i}: {info['iters']} iterations, rel res {info['rel_res']:.2e}")
-            ok = ok and info["converged"]
-        if not ok:
-            # the form does not reach the residual on this workload: recorded, not timed
-            res[form] = dict(value=None, converged=False, iterations=info["iters"], rel_res=info["rel_res"])
-            log(f"[bench] {form}: not converged within {wl.maxit} iterations")
-            continue
-        # timed region (HIP graph replays of the Arnoldi steps)
-        lat, iters, rr = [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            ts = time.perf_counter()
-            _, _, info = h.stk_solve(bu, bp, **kw)
-            lat.append(time.perf_counter() - ts)
-            iters.append(info["iters"])
-            rr.append(info["rel_res"])
-            assert info["converged"] and info["rel_res"] <= wl.rtol, info
-        torch.cuda.synchronize()
-        t_total = time.perf_counter() - t0
-        log(f"[bench] {form}: {args.steps} solves in {t_total:.3f} s, iterations {iters}")
-        # kernel durations: one more solve with plain launches bracketed by HIP
-        # events on the launch stream (graph replays cannot be bracketed per
-        # kernel); each timed launch is repeated back to back inside its bracket
-        h.stk_profile(True, reps=PROF_REPS)
-        h.stk_solve(bu, bp, eager=True, **kw)
-        prof = {k: h.stk_profile_read(k) for k in (0, 1)}
-        h.stk_profile(False)
-        res[form] = dict(value=dof * args.steps / t_total, converged=True, ms_per_step=1e3 * t_total / args.steps,
-                         iterations=iters[-1], rel_res=max(rr),
-                         p50_ms=1e3 * percentile(lat, 0.5), p99_ms=1e3 * percentile(lat, 0.99),
-                         prof=prof, t_total=t_total)
-    # the headline uses the paper's preconditioner, eq. (precond); the
-    # block upper-triangular variant is reported beside it
-    timed = [f for f in res if res[f]["value"] is not None and not f.endswith("_upper")]
-    if not timed:
-        raise SystemExit("no form reached the residual")
-    best = max(timed, key=lambda f: res[f]["value"])
-    r = res[best]
-    n_gemv, ms_gemv, by_gemv = r["prof"][0]
-    n_elem, ms_elem, by_elem = r["prof"][1]
-    ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
-    traffic, traffic_src = measured_traffic(wl, best)
-    roofline = {"bound": "hbm", "kernel": "k_asm_gemv (interior star patches, all levels)",
-                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": traffic, "traffic_source": traffic_src, "form": best,
-                "launches_per_solve": n_gemv // PROF_REPS, "timed_launches": n_gemv,
-                "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
-                "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
-                "time_share_of_solve": (ms_gemv * 1e-3 / PROF_REPS) / (r["t_total"] / args.steps),
-                "cell_kernel_avg_us": 1e3 * ms_elem / max(n_elem, 1),
-                "cell_kernel_GBs": (by_elem / (ms_elem * 1e-3) / 1e9) if ms_elem > 0 else 0.0}
+        steps = args.steps if form in ("fp64", "mixed") else max(2, args.steps // 2)
+        res[form] = time_form(h, wl, bu, bp, xu, xp, form, steps, args.warmup, not args.trace)
+        if not res[form]["converged"] and form.startswith("mixed"):
+            res[form]["reason"] = MIXED_REASON
+    r = res.get("fp64")
+    if r is None or r["value"] is None:
+        raise SystemExit("the FP64 form did not reach the residual")
     out = {"metric": METRIC, "value": r["value"], "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if best == "fp64" else "f64+f32",
-           "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": wl.name, "dim": wl.dim, "n_fine": wl.n_fine, "levels": wl.levels,
                       "n_sinkers": wl.n_sinkers, "dr": wl.dr, "gamma": wl.gamma, "seed": wl.seed,
-                      "nu_pre": wl.nu_pre, "nu_post": wl.nu_post, "restart": wl.restart, "rtol": wl.rtol,
-                      "unknowns": dof, "iterations": r["iterations"], "setup_s": t_setup, "form": best},
+                      "coef_kind": wl.coef_kind, "nu_pre": wl.nu_pre, "nu_post": wl.nu_post,
+                      "restart": wl.restart, "rtol": wl.rtol, "unknowns": dof, "iterations": r["iterations"],
+                      "setup_s": t_setup, "setup_plus_solve_dof_per_s": dof / (t_setup + r["ms_per_step"] / 1e3),
+                      "form": "fp64"},
            "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
-           "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res},
-           "roofline": roofline,
-           "autotune": {"asm_variant": {f"level{l}_{p}": v for (l, p), v in sorted(tune.items())},
-                        "source": tune_src, "seconds": t_tune}}
-    if args.serving > 0:
+           "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res}}
+    if "prof" in r:
+        n_gemv, ms_gemv, by_gemv = r["prof"][0]
+        n_elem, ms_elem, by_elem = r["prof"][1]
+        n_fine, ms_fine, by_fine = r["prof"][2]
+        ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
+        ach_fine = by_fine / (ms_fine * 1e-3) / 1e9 if ms_fine > 0 else 0.0
+        traffic, traffic_src = measured_traffic(wl, "fp64")
+        t_solve = r["t_total"] / args.steps
+        sb = solve_bytes_model(h, wl, r["iterations"], r["prof"], wl.restart)
+        out["roofline"] = {
+            "bound": "hbm", "kernel": "k_asm_gemv (batched star-patch solves, all smoothed levels)",
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "traffic_source": traffic_src, "form": "fp64",
+            "launches_per_solve": n_gemv, "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
+            "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
+            "time_share_of_solve": (ms_gemv * 1e-3) / t_solve,
+            "fine_level": {"achieved": ach_fine, "frac": ach_fine / HBM_PEAK_GBS, "launches_per_solve": n_fine,
+                           "avg_launch_us": 1e3 * ms_fine / max(n_fine, 1),
+                           "algorithmic_bytes_per_launch": by_fine / max(n_fine, 1)},
+            "cell_kernel": {"avg_launch_us": 1e3 * ms_elem / max(n_elem, 1),
+                            "GBs": (by_elem / (ms_elem * 1e-3) / 1e9) if ms_elem > 0 else 0.0,
+                            "time_share_of_solve": (ms_elem * 1e-3) / t_solve},
+            "solve_level": {"algorithmic_bytes": sb, "achieved": sb / t_solve / 1e9,
+                            "frac": sb / t_solve / 1e9 / HBM_PEAK_GBS,
+                            "model": "patch solves + cell kernels (counted by the library) + coarse solves "
+                                     "+ outer Gram-Schmidt; transfers, gathers and relaxation vectors left out"},
+            "timing": "HIP events on the library's launch stream around every launch of the kernel "
+                      "in one extra plain-launch solve"}
+    out["autotune"] = {"asm_variant": {f"level{l}_{p}": v for (l, p), v in sorted(tune.items())},
+                       "source": tune_src, "seconds": t_tune}
+    h.close()
+    if not args.no_extra:
+        out["other_workloads"] = {}
+        for name in ("sinker_3d_32cu_L3", "sinker_2d_128sq_L4"):
+            if name == wl.name:
+                continue
+            log(f"[bench] {name}")
+            out["other_workloads"][name] = other_workload(name, max(2, args.steps // 2))
+    if not args.no_serving and args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, r["iterations"])
+        log("[bench] cpu baseline (oracle, bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
-    h.close()
 
 
 if __name__ == "__main__":

@@ -25,7 +25,10 @@
  *  - Errors: no exception crosses the ABI; every call returns a stk_status
  *    and stk_last_error() returns a thread-local message for the last failure.
  *  - A hierarchy is used by one stream at a time; calls that overlap on one
- *    hierarchy race on its work buffers.
+ *    hierarchy race on its work buffers. While a resumable solve
+ *    (stk_solve_begin .. the stk_poll that reports its end) is in progress,
+ *    every other call on that hierarchy that would touch its device buffers
+ *    returns STK_EBUSY without doing anything.
  */
 #ifndef STK_H
 #define STK_H
@@ -70,25 +73,31 @@ typedef struct {
  *            prod_j sin(pi m_j x_j)
  * (amp is a HOST array [d][modes]^d, C order, copied during setup):
  *   eps_II = (eps:eps / 2)^(1/2),
- *   mu_eff = mu_min + min(mu0 - mu_min, tau_y / (2 eps_II)),
- *   C = 2 mu_eff I - 2 (mu_eff - mu_min) [yielded] n (x) n,  n = eps/|eps|_F,
+ *   mu_eff = mu_floor + min(mu0 - mu_floor, tau_y / (2 eps_II)),
+ *   C = 2 mu_eff I - 2 (mu_eff - mu_floor) [yielded] n (x) n,  n = eps/|eps|_F,
  * the exact derivative of tau(eps) = 2 mu_eff(eps_II) eps; yielded means
- * tau_y / (2 eps_II) < mu0 - mu_min. C is stored per Gauss point as mu_eff
- * and w = (2 (mu_eff - mu_min) [yielded])^(1/2) n, so C:e = 2 mu_eff e -
- * (w:e) w. scale <= 0 asks the library to choose s so that the root mean
- * square of eps_II over the finest level's Gauss points is 1. The Schur
- * blocks use the scalar mu_eff. */
+ * tau_y / (2 eps_II) < mu0 - mu_floor. C is symmetric positive definite with
+ * smallest eigenvalue 2 mu_floor (along n where yielded). C is stored per
+ * Gauss point as mu_eff and w = (2 (mu_eff - mu_floor) [yielded])^(1/2) n, so
+ * C:e = 2 mu_eff e - (w:e) w. The Schur blocks use the scalar mu_eff. */
 typedef struct {
   int modes;           /* 1..8 */
   const double* amp;
   double tau_y;        /* > 0 */
-  double scale;
+  double mu_floor;     /* > 0; <= 0 selects sinker.mu_min */
+  double eps_scale;    /* s above; <= 0 asks the library to choose s so that
+                          the root mean square of eps_II over the finest
+                          level's Gauss points is 1 */
 } stk_viscoplastic;
 
 typedef struct {
   int dim;            /* 2 or 3 */
   int n_fine;         /* cells per axis on the finest level, divisible by 2^(n_levels-1) */
   int n_levels;       /* >= 2 */
+  int qpts_1d;        /* Gauss-Legendre points per axis for every integral
+                         (A, B, M_p, M_p(1/mu), the right-hand side); 0 selects
+                         the default 3 (exact for the constant-coefficient Q2
+                         stiffness on affine cells), the only rule built */
   double gamma;       /* augmented-Lagrangian parameter, >= 0 */
   int schur;          /* W in A_gamma and the Schur blocks (eq. (P1P2)):
                          1 = P1: W = M_p, Shat^{-1} = M_p(1/mu)^{-1} + gamma M_p^{-1};
@@ -114,7 +123,8 @@ stk_status stk_footprint(const stk_desc* desc, size_t* bytes);
  * vertex-star patch matrices of levels >= 1 (Section 4.1, eq. (viim);
  * factored by Cholesky in FP64 and stored as explicit packed inverses), the
  * explicit inverse of the coarsest A_gamma (the paper uses a sparse direct
- * solver), and the cellwise Schur blocks Shat_gamma^{-1} = M_K(1/mu)^{-1} +
+ * solver; at most 80,000 coarse unknowns, whose packed inverse takes
+ * 4 n0^2 bytes), and the cellwise Schur blocks Shat_gamma^{-1} = M_K(1/mu)^{-1} +
  * gamma M_K^{-1} (eq. (P1P2), Section 5.1). Synchronises `stream` before
  * returning. On failure *out is NULL and nothing is leaked. */
 stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** out);
@@ -125,8 +135,12 @@ stk_status stk_destroy(stk_hier* h);
 /* Stored velocity length and pressure length on `level`. */
 stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_t* n_pres);
 
-/* Right-hand side of the finest level: b_u = (f, phi_i) (stored layout,
- * FP64), b_p = 0 (may be NULL). */
+/* Right-hand side of the finest level: b_u = (f, phi_i) with the forcing
+ * f = (0, .., beta (chi - 1)) of the multi-sinker benchmark (Section 5.2;
+ * also for coef_kind 1, whose base field is the sinker field), in the stored
+ * layout, FP64; b_p = 0 (may be NULL): the augmented system keeps the
+ * original right-hand side because the divergence data is zero (Section 3,
+ * eq. (augstokessys)). */
 stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream);
 
 /* y = A_gamma x on `level` (matrix-free, Section 2 entries plus the
@@ -163,14 +177,28 @@ stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc,
 stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, void* rc,
                         void* stream);
 
-/* x = A_0,gamma^{-1} b on the coarsest level (dense explicit inverse). */
+/* x = A_0,gamma^{-1} b on the coarsest level: the direct coarse solve of
+ * the multigrid cycle (Section 5.1; the paper uses a sparse direct solver),
+ * here one product with the explicit symmetric inverse built at setup.
+ * b, x: distinct FP64 vectors in the stored layout of level 0. */
 stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream);
 
-/* x = one V-cycle applied to b on the finest level (pre-relaxation from 0,
- * residual, restriction, recursion, prolongation, post-relaxation). The
- * coarsest solve always uses the FP64 inverse; with STK_F32 its input and
- * output are rounded to FP32. */
+/* x = one multigrid cycle applied to b on the finest level: the
+ * approximation Ahat_gamma^{-1} of Section 5.1 and the algorithm outline
+ * (pre-relaxation from 0, residual, restriction with P~^T, recursion,
+ * prolongation with P~, post-relaxation). The paper uses an F-cycle; this
+ * call runs the V-cycle, stk_fcycle the F-cycle. The coarsest solve always
+ * uses the FP64 inverse; with STK_F32 its input and output are rounded to
+ * FP32. */
 stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream);
+
+/* x = one F-cycle applied to b on the finest level, the "full" multigrid
+ * cycle of Section 5.1 and the algorithm outline, read as PETSc's full
+ * multigrid: b is restricted with P~^T to every coarser level, the coarsest
+ * level is solved directly, and on each finer level the prolongated (P~)
+ * coarser result is improved by one V-cycle started from it (relaxation
+ * from that iterate, coarse correction from zero). dtype as for stk_vcycle. */
+stk_status stk_fcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream);
 
 /* (z_u, z_p) = P (v_u, v_p): the block preconditioner of eq. (precond) with
  * two V-cycles and the cellwise Schur blocks; z_p has zero mean. Flags:
@@ -179,8 +207,9 @@ stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stre
  * and the mean projection staying FP64; STK_PC_UPPER applies the block
  * upper-triangular part instead, z_p = -Shat^{-1} v_p (mean removed),
  * z_u = Ahat^{-1}(v_u - B^T z_p), one V-cycle (a block-triangular variant of
- * the kind the paper's introduction cites). */
-enum { STK_PC_MIXED = 1, STK_PC_UPPER = 2 };
+ * the kind the paper's introduction cites); STK_PC_FCYCLE uses F-cycles
+ * (stk_fcycle) for Ahat^{-1} instead of V-cycles. */
+enum { STK_PC_MIXED = 1, STK_PC_UPPER = 2, STK_PC_FCYCLE = 4 };
 stk_status stk_precond(stk_hier* h, int flags, const double* v_u, const double* v_p,
                        double* z_u, double* z_p, void* stream);
 
@@ -201,6 +230,8 @@ typedef struct {
                     the FP64 true residual is unchanged. */
   int pc;        /* 0 (default): the preconditioner of eq. (precond); 1: its
                     block upper-triangular part (see stk_precond) */
+  int cycle;     /* multigrid cycle for Ahat^{-1}: 0 (default) V-cycle
+                    (stk_vcycle), 1 F-cycle (stk_fcycle, the paper's cycle) */
 } stk_solve_opts;
 
 typedef struct {
@@ -237,10 +268,24 @@ stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* 
 stk_status stk_solve_begin(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
                            const stk_solve_opts* opts, void* stream);
 
-/* Advances each of the n hierarchies with a solve in progress by one phase:
- * enqueues all n phases first, then waits for each and runs its host part.
- * Entries that are idle or done are skipped. Returns the first error met
- * (that solve is then done with that status); `stream` is unused. */
+/* Continuous batching: advances the n hierarchies' solves without making
+ * them wait for one another. A solve whose last enqueued phase has finished
+ * on the device (its event has completed) gets its host part (Givens
+ * rotations, stopping test) and its next phase enqueued at once; a solve
+ * with nothing in flight gets its phase enqueued; a solve whose phase is
+ * still running is left alone. If no solve could move in one pass, the call
+ * waits until the first in-flight phase completes. Solves of hierarchies
+ * with the same shape (dimension, cells, levels, relaxation steps, W,
+ * coefficient kind, precision form and preconditioner variant) that are
+ * ready for an Arnoldi step at the same time run their preconditioner
+ * cycles in lockstep, with one batched star-patch solve launch per
+ * smoothing step for all of them (up to STK_BATCH_MAX requests per launch).
+ * Each solve's arithmetic is unchanged, so its result does not depend on
+ * which other requests share the device (setting the environment variable
+ * STK_CROSS_BATCH=0 turns the lockstep batching off, for comparisons).
+ * Entries that are idle or done are skipped. Returns the first error met (that solve is then done with that
+ * status); `stream` is unused. */
+#define STK_BATCH_MAX 8
 stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream);
 
 /* STK_EBUSY while the solve runs; otherwise fills info and returns the
@@ -284,7 +329,8 @@ stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant);
  *   kernel 0: batched star-patch solve of the interior patches (all levels);
  *             bytes = packed inverses + patch outputs + one residual read;
  *   kernel 1: cell kernel of the A_gamma apply (all levels); bytes = velocity
- *             input + viscosity at Gauss points + element outputs. */
+ *             input + viscosity at Gauss points + element outputs;
+ *   kernel 2: the launches of kernel 0 on the finest level only. */
 stk_status stk_profile(stk_hier* h, int enable);
 stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* total_ms,
                             double* total_bytes);

@@ -14,11 +14,12 @@ In 2D the forcing is f = (0, beta (chi - 1)).
 Viscoplastic Newton tensor (Section 5.3.1). The paper linearises
 tau(eps) = 2 mu_eff(eps_II) eps with eps_II = (eps:eps / 2)^(1/2) and obtains a
 fourth-order tensor viscosity. Reading taken for the synthetic workload: a
-base field mu0(x) (the multi-sinker field) capped by a yield stress tau_y,
-    mu_eff = mu_min + min(mu0 - mu_min, tau_y / (2 eps_II)),
+base field mu0(x) (the multi-sinker field) capped by a yield stress tau_y
+above a floor mu_f (mu_min of the sinker field unless given),
+    mu_eff = mu_f + min(mu0 - mu_f, tau_y / (2 eps_II)),
 whose exact derivative is
-    C = 2 mu_eff I - 2 (mu_eff - mu_min) [yielded] n (x) n,  n = eps / |eps|_F,
-symmetric positive definite with smallest eigenvalue >= 2 mu_min. The strain
+    C = 2 mu_eff I - 2 (mu_eff - mu_f) [yielded] n (x) n,  n = eps / |eps|_F,
+symmetric positive definite with smallest eigenvalue >= 2 mu_f. The strain
 rate is that of a smooth Fourier velocity
     u_c(x) = s sum_{m in {1..M}^d} a_{c,m} / (1 + |m|^2) prod_j sin(pi m_j x_j),
 with standard-normal amplitudes a (seeded) and s set so that the RMS of
@@ -129,10 +130,11 @@ class ViscoplasticNewton:
 
     kind = "tensor"
 
-    def __init__(self, base: SinkerField, velocity: FourierVelocity, tau_y: float):
+    def __init__(self, base: SinkerField, velocity: FourierVelocity, tau_y: float, mu_floor: float = 0.0):
         self.base, self.vel, self.tau_y = base, velocity, float(tau_y)
         self.dim = base.dim
-        self.mu_min = base.mu_min
+        # the floor of the capped law (mu_f); mu_min of the base field unless given
+        self.mu_min = float(mu_floor) if mu_floor > 0.0 else base.mu_min
 
     @classmethod
     def from_workload(cls, wl, fine_quad_points: np.ndarray):
@@ -140,7 +142,7 @@ class ViscoplasticNewton:
         vel = FourierVelocity(wl.fourier_amplitudes(), 1.0)
         eii = second_invariant(vel.strain_rate(fine_quad_points))
         vel.scale = 1.0 / np.sqrt(np.mean(eii ** 2))
-        return cls(base, vel, 2.0 * wl.mu_max)
+        return cls(base, vel, 2.0 * wl.mu_max, getattr(wl, "mu_floor", 0.0))
 
     def _state(self, x):
         eps = self.vel.strain_rate(x)

@@ -39,24 +39,26 @@ class BlockPreconditioner:
     "upper", one V-cycle; the block-triangular family the paper's
     introduction cites), with Ahat^{-1} = one V-cycle."""
 
-    def __init__(self, mg: Multigrid, kind: str = "full"):
-        assert kind in ("full", "upper")
+    def __init__(self, mg: Multigrid, kind: str = "full", cycle: str = "V"):
+        assert kind in ("full", "upper") and cycle in ("V", "F")
         self.mg = mg
         self.kind = kind
         self.ops = mg.ops[-1]
         self.nu = self.ops.level.n_u
+        # Ahat^{-1}: one V-cycle, or one F-cycle (the paper's cycle)
+        self.ahat_inv = mg.vcycle if cycle == "V" else mg.fcycle
 
     def apply(self, v: np.ndarray) -> np.ndarray:
         ops = self.ops
         vu, vp = v[:self.nu], v[self.nu:]
         if self.kind == "upper":
             zp = ops.project_mean(-(ops.Shat_inv @ vp))
-            zu = self.mg.vcycle(vu - ops.B.T @ zp)
+            zu = self.ahat_inv(vu - ops.B.T @ zp)
             return np.concatenate([zu, zp])
-        y = self.mg.vcycle(vu)
+        y = self.ahat_inv(vu)
         zp = -(ops.Shat_inv @ (vp - ops.B @ y))
         zp = ops.project_mean(zp)
-        zu = y - self.mg.vcycle(ops.B.T @ zp)
+        zu = y - self.ahat_inv(ops.B.T @ zp)
         return np.concatenate([zu, zp])
 
 
@@ -158,12 +160,14 @@ class StokesSolver:
     def rhs(self) -> np.ndarray:
         return np.concatenate([self.ops.rhs(), np.zeros(self.ops.level.n_p)])
 
-    def solve(self, b=None, rtol=None, maxit=None, pc: str = "full"):
+    def solve(self, b=None, rtol=None, maxit=None, pc: str = "full", cycle: str = None):
         wl = self.wl
         if b is None:
             b = self.rhs()
+        if cycle is None:
+            cycle = getattr(wl, "cycle", "V")
         t0 = time.perf_counter()
-        apply = self.pc.apply if pc == "full" else BlockPreconditioner(self.mg, pc).apply
+        apply = self.pc.apply if (pc == "full" and cycle == "V") else BlockPreconditioner(self.mg, pc, cycle).apply
         x, info = fgmres(lambda v: self.K @ v, apply, b,
                          rtol=wl.rtol if rtol is None else rtol, restart=wl.restart,
                          maxit=wl.maxit if maxit is None else maxit)

@@ -23,9 +23,13 @@
 * Restriction: the transpose of P~ (the paper does not state it; the
   transpose keeps the V-cycle symmetric in structure).
 * Coarse level: sparse direct LU of A_gamma (the paper uses MUMPS).
-* Cycle: V-cycle (the paper uses an F-cycle; the V-cycle is the variant built
-  here): pre-smooth from zero, residual, restrict, recurse, prolongate and
-  add, post-smooth.
+* Cycles. V-cycle: pre-smooth (from zero, or from a given iterate),
+  residual, restrict, recurse from zero, prolongate and add, post-smooth.
+  F-cycle, the paper's "full" multigrid cycle (Section 5.1 and the algorithm
+  outline); reading taken: the full multigrid cycle of PETSc, which the
+  paper's Firedrake solver uses: the right-hand side is restricted to every
+  coarser level, the coarsest level is solved directly, and going up, each
+  level's start is the prolongated coarser result, improved by one V-cycle.
 """
 from __future__ import annotations
 
@@ -227,13 +231,29 @@ class Multigrid:
         T = self.transfers[l]
         return T.restrict(r) if self.robust else T.P.T @ r
 
-    def vcycle(self, b: np.ndarray, l: int | None = None) -> np.ndarray:
+    def vcycle(self, b: np.ndarray, l: int | None = None, x0=None) -> np.ndarray:
+        """One V-cycle on level l (default: finest) from x0 (default: zero)."""
         if l is None:
             l = self.L - 1
         if l == 0:
             return self.coarse_lu.solve(b)
-        x = self.smooth(l, b, None, self.nu_pre)
+        x = self.smooth(l, b, x0, self.nu_pre)
         r = b - self.ops[l].Agamma @ x
         xc = self.vcycle(self.restrict(l, r), l - 1)
         x = x + self.prolong(l, xc)
         return self.smooth(l, b, x, self.nu_post)
+
+    def fcycle(self, b: np.ndarray) -> np.ndarray:
+        """One F-cycle (full multigrid cycle) on the finest level."""
+        L = self.L
+        rhs = [None] * L
+        rhs[L - 1] = b
+        for l in range(L - 1, 0, -1):
+            rhs[l - 1] = self.restrict(l, rhs[l])
+        x = self.coarse_lu.solve(rhs[0])
+        for l in range(1, L):
+            x = self.vcycle(rhs[l], l, x0=self.prolong(l, x))
+        return x
+
+    def cycle(self, b: np.ndarray, kind: str = "V") -> np.ndarray:
+        return self.fcycle(b) if kind == "F" else self.vcycle(b)

@@ -75,8 +75,8 @@ __global__ void k_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, 
 // Viscoplastic Newton tensor (Section 5.3.1; reading for the synthetic
 // workload): mu0 = sinker field, eps = strain rate of the Fourier velocity
 //   u_c = s sum_m amp[c][m] / (1 + |m|^2) prod_j sin(pi m_j x_j),  m in {1..M}^d,
-// eps_II = (eps:eps/2)^(1/2), mu_eff = mu_min + min(mu0 - mu_min, tau_y/(2 eps_II)),
-// C = 2 mu_eff I - w (x) w with w = (2 (mu_eff - mu_min) [yielded])^(1/2) eps/|eps|_F.
+// eps_II = (eps:eps/2)^(1/2), mu_eff = mu_floor + min(mu0 - mu_floor, tau_y/(2 eps_II)),
+// C = 2 mu_eff I - w (x) w with w = (2 (mu_eff - mu_floor) [yielded])^(1/2) eps/|eps|_F.
 
 // Gradient G[c][k] = d u_c / d x_k of the unscaled velocity (s = 1) at x,
 // by partial sums over the tensor-product modes (x_{d-1} innermost).
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kCoefThreads) k_eps_partials(LevelGeo g, const
 template <int D>
 __global__ void __launch_bounds__(kCoefThreads)
 k_coef_tensor(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta, double mu_min,
-              double mu_max, const double* __restrict__ amp, int M, double tau_y, double scale,
+              double mu_max, double mu_floor, const double* __restrict__ amp, int M, double tau_y, double scale,
               const double* __restrict__ part, int nparts, int64_t nfine_pts, double* __restrict__ mu,
               double* __restrict__ cw) {
   constexpr int NQ = Dims<D>::NQ, NS = SymIdx<D>::NS;
@@ -231,10 +231,10 @@ k_coef_tensor(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, 
   const double eii = sqrt(0.5 * ee);
   const double mu0 = (mu_max - mu_min) * (1.0 - sinker_chi<D>(ctr, ns, omega, delta, x)) + mu_min;
   const double cap = eii > 0.0 ? tau_y / (2.0 * eii) : INFINITY;
-  const bool yielded = cap < mu0 - mu_min;
-  const double meff = mu_min + fmin(mu0 - mu_min, cap);
+  const bool yielded = cap < mu0 - mu_floor;
+  const double meff = mu_floor + fmin(mu0 - mu_floor, cap);
   const double nrm = sqrt(ee);
-  const double wscale = (yielded && nrm > 0.0) ? sqrt(2.0 * (meff - mu_min)) / nrm : 0.0;
+  const double wscale = (yielded && nrm > 0.0) ? sqrt(2.0 * (meff - mu_floor)) / nrm : 0.0;
   mu[idx] = meff;
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -1211,11 +1211,11 @@ void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStr
   const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
   if (H.dim == 2)
     hipLaunchKernelGGL(k_coef_tensor<2>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, H.centers,
-                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_floor, H.vp_amp, H.vp_modes, H.vp_tau_y,
                        H.vp_scale, H.partials, np, nf, l.mu, l.cw);
   else
     hipLaunchKernelGGL(k_coef_tensor<3>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, H.centers,
-                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_amp, H.vp_modes, H.vp_tau_y,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_floor, H.vp_amp, H.vp_modes, H.vp_tau_y,
                        H.vp_scale, H.partials, np, nf, l.mu, l.cw);
 }
 

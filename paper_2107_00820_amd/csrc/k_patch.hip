@@ -18,6 +18,7 @@
 // <= 2^d overlapping patch results in a fixed order. One lane per patch,
 // except the 81-unknown 3D interior patches, whose GEMV four wavefronts
 // share (split_symv81).
+#include <algorithm>
 #include <utility>
 
 #include "stk_dev.h"
@@ -319,6 +320,23 @@ struct AsmClasses {
   int first_block[5];
 };
 
+// One launch covers the patch solves of up to kAsmBatchMax entries (a level
+// of one hierarchy with its residual and output buffer; the entries may
+// belong to different hierarchies, e.g. concurrent requests of a server).
+// Workgroups [first[k], first[k+1]) belong to entry k and run exactly the
+// code a launch for that entry alone runs, so results do not depend on the
+// batch.
+template <class R>
+struct AsmBatch {
+  int n;
+  int first[kAsmBatchMax + 1];
+  LevelGeo g[kAsmBatchMax];
+  AsmClasses<R> c[kAsmBatchMax];
+  const R* r[kAsmBatchMax];
+  R* zbuf[kAsmBatchMax];
+  int nvert[kAsmBatchMax];
+};
+
 // Workgroups of 64 threads in 2D (one lane per patch); of 256 in 3D, where
 // an interior workgroup covers 64 patches (split_symv81) and a boundary one
 // 256 patches (one lane each).
@@ -327,9 +345,31 @@ constexpr int asm_threads() { return D == 2 ? 64 : 256; }
 
 template <int D, class R, int V>
 __global__ void __launch_bounds__(asm_threads<D>(), (AsmTune<D, R, V>::min_waves))
-k_asm_gemv(LevelGeo g, AsmClasses<R> c, const R* __restrict__ r, R* __restrict__ zbuf, int nvert) {
+k_asm_gemv(AsmBatch<R> B) {
   constexpr int NT = asm_threads<D>();
-  const int b = blockIdx.x;
+  // the entry of this workgroup (uniform); the fields are picked by
+  // compile-time indices so the kernel arguments are never indexed at run time
+  const int bid = blockIdx.x;
+  int k = 0;
+#pragma unroll
+  for (int i = 1; i < kAsmBatchMax; ++i)
+    if (i < B.n && bid >= B.first[i]) k = i;
+  LevelGeo g = B.g[0];
+  AsmClasses<R> c = B.c[0];
+  const R* r = B.r[0];
+  R* zbuf = B.zbuf[0];
+  int nvert = B.nvert[0], b0 = 0;
+#pragma unroll
+  for (int i = 1; i < kAsmBatchMax; ++i)
+    if (i == k) {
+      g = B.g[i];
+      c = B.c[i];
+      r = B.r[i];
+      zbuf = B.zbuf[i];
+      nvert = B.nvert[i];
+      b0 = B.first[i];
+    }
+  const int b = bid - b0;
   const int t = threadIdx.x;
   if (b < c.first_block[1]) {
     if constexpr (D == 2) {
@@ -528,21 +568,24 @@ template <>
 const float* class_inv<float>(const PatchClass& pc) { return pc.inv32; }
 
 template <int D, class R>
-static void asm_gemv_variant(int v, unsigned blocks, hipStream_t s, const LevelGeo& g, const AsmClasses<R>& c,
-                             const R* r, R* zbuf, int nvert) {
-  const dim3 grid(blocks), blk(asm_threads<D>());
-  if (v == 1) hipLaunchKernelGGL((k_asm_gemv<D, R, 1>), grid, blk, 0, s, g, c, r, zbuf, nvert);
-  else if (v == 2) hipLaunchKernelGGL((k_asm_gemv<D, R, 2>), grid, blk, 0, s, g, c, r, zbuf, nvert);
-  else hipLaunchKernelGGL((k_asm_gemv<D, R, 0>), grid, blk, 0, s, g, c, r, zbuf, nvert);
+static void asm_gemv_variant(int v, hipStream_t s, const AsmBatch<R>& B) {
+  const dim3 grid((unsigned)B.first[B.n]), blk(asm_threads<D>());
+  if (grid.x == 0) return;
+  if (v == 1) hipLaunchKernelGGL((k_asm_gemv<D, R, 1>), grid, blk, 0, s, B);
+  else if (v == 2) hipLaunchKernelGGL((k_asm_gemv<D, R, 2>), grid, blk, 0, s, B);
+  else hipLaunchKernelGGL((k_asm_gemv<D, R, 0>), grid, blk, 0, s, B);
 }
 
-// The batched patch solves of one ASM application into the level's patch
-// output buffer, with the level's chosen variant (reps launches back to back).
+// Appends the patch solves of level l (residual r, output zbuf) to a batch;
+// returns their algorithmic bytes (packed inverses, patch outputs, one read
+// of the residual).
 template <class R>
-void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out) {
-  AsmClasses<R> c{};
+static double asm_add_entry(const Hier& H, const Level& l, const R* r, R* zbuf, AsmBatch<R>& B) {
+  const int k = B.n++;
+  AsmClasses<R>& c = B.c[k];
+  c = AsmClasses<R>{};
   int blocks = 0;
-  double bytes = (double)sizeof(R) * (double)l.nvel;   // one read of the residual
+  double bytes = (double)sizeof(R) * (double)l.nvel;
   const int ncls = H.dim == 2 ? 3 : 4;
   for (int ci = 0; ci < 4; ++ci) {
     c.first_block[ci] = blocks;
@@ -553,18 +596,46 @@ void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStr
       c.count[ci] = pc.count;
       const int per = (H.dim == 2 || ci == 0) ? 64 : 256;   // patches per workgroup
       blocks += (pc.count + per - 1) / per;
-      // algorithmic bytes: packed inverse and patch output of every patch
       bytes += (double)sizeof(R) * (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
     }
   }
   c.first_block[4] = blocks;
-  R* zbuf = reinterpret_cast<R*>(l.zbuf);
+  B.g[k] = l.g;
+  B.r[k] = r;
+  B.zbuf[k] = zbuf;
+  B.nvert[k] = l.nvert;
+  B.first[k + 1] = B.first[k] + blocks;
+  return bytes;
+}
+
+// The batched patch solves of one ASM application into the level's patch
+// output buffer (or `zbuf` if not NULL), with the level's chosen variant
+// (reps launches back to back).
+template <class R>
+void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out,
+                     R* zbuf) {
+  AsmBatch<R> B{};
+  const double bytes = asm_add_entry<R>(H, l, r, zbuf ? zbuf : reinterpret_cast<R*>(l.zbuf), B);
   const int v = l.asm_variant[sizeof(R) == 8 ? 0 : 1];
   for (int k = 0; k < reps; ++k) {
-    if (H.dim == 2) asm_gemv_variant<2, R>(v, blocks, s, l.g, c, r, zbuf, l.nvert);
-    else asm_gemv_variant<3, R>(v, blocks, s, l.g, c, r, zbuf, l.nvert);
+    if (H.dim == 2) asm_gemv_variant<2, R>(v, s, B);
+    else asm_gemv_variant<3, R>(v, s, B);
   }
   if (bytes_out) *bytes_out = bytes;
+}
+
+template <class R>
+void launch_asm_gemv_batch(const Hier* const* hs, const Level* const* ls, const R* const* rs, int n,
+                           hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += kAsmBatchMax) {
+    AsmBatch<R> B{};
+    const int kn = std::min(kAsmBatchMax, n - k0);
+    for (int k = 0; k < kn; ++k)
+      asm_add_entry<R>(*hs[k0 + k], *ls[k0 + k], rs[k0 + k], reinterpret_cast<R*>(ls[k0 + k]->zbuf), B);
+    const int v = ls[k0]->asm_variant[sizeof(R) == 8 ? 0 : 1];
+    if (hs[k0]->dim == 2) asm_gemv_variant<2, R>(v, s, B);
+    else asm_gemv_variant<3, R>(v, s, B);
+  }
 }
 
 template <class R>
@@ -574,19 +645,29 @@ void launch_asm_solves(Hier& H, const Level& l, const R* r, hipStream_t s) {
   // the kernel is a pure function of (r, inverses) -> zbuf, so a profiled
   // call may repeat it back to back to time it without launch gaps
   double bytes = 0.0;
-  launch_asm_gemv<R>(H, l, r, reps, s, &bytes);
+  launch_asm_gemv<R>(H, l, r, reps, s, &bytes, nullptr);
   prof_end(H, s, PROF_ASM_GEMV, ev, bytes, reps);
 }
 
 template <class R>
-void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s) {
-  launch_asm_solves<R>(H, l, r, s);
-  R* zbuf = reinterpret_cast<R*>(l.zbuf);
+void launch_asm_gather(const Hier& H, const Level& l, const R* zbuf, R* y, hipStream_t s) {
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
     hipLaunchKernelGGL((k_asm_gather<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
   else
     hipLaunchKernelGGL((k_asm_gather<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
+}
+
+template <class R>
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s, R* zbuf) {
+  if (zbuf) {
+    // caller-provided patch output buffer (no tracing)
+    launch_asm_gemv<R>(H, l, r, 1, s, nullptr, zbuf);
+    launch_asm_gather<R>(H, l, zbuf, y, s);
+    return;
+  }
+  launch_asm_solves<R>(H, l, r, s);
+  launch_asm_gather<R>(H, l, reinterpret_cast<const R*>(l.zbuf), y, s);
 }
 
 // Below this many 64-cell tiles (about two per compute unit) the 3D centre
@@ -619,10 +700,16 @@ void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, 
   }
 }
 
-template void launch_asm_gemv<double>(const Hier&, const Level&, const double*, int, hipStream_t, double*);
-template void launch_asm_gemv<float>(const Hier&, const Level&, const float*, int, hipStream_t, double*);
-template void launch_asm<double>(Hier&, const Level&, const double*, double*, hipStream_t);
-template void launch_asm<float>(Hier&, const Level&, const float*, float*, hipStream_t);
+template void launch_asm_gemv<double>(const Hier&, const Level&, const double*, int, hipStream_t, double*, double*);
+template void launch_asm_gemv<float>(const Hier&, const Level&, const float*, int, hipStream_t, double*, float*);
+template void launch_asm_gemv_batch<double>(const Hier* const*, const Level* const*, const double* const*, int,
+                                            hipStream_t);
+template void launch_asm_gemv_batch<float>(const Hier* const*, const Level* const*, const float* const*, int,
+                                           hipStream_t);
+template void launch_asm_gather<double>(const Hier&, const Level&, const double*, double*, hipStream_t);
+template void launch_asm_gather<float>(const Hier&, const Level&, const float*, float*, hipStream_t);
+template void launch_asm<double>(Hier&, const Level&, const double*, double*, hipStream_t, double*);
+template void launch_asm<float>(Hier&, const Level&, const float*, float*, hipStream_t, float*);
 template void launch_asm_solves<double>(Hier&, const Level&, const double*, hipStream_t);
 template void launch_asm_solves<float>(Hier&, const Level&, const float*, hipStream_t);
 template void launch_center_solve<double>(const Hier&, const Level&, const double*, double*, double, bool,

@@ -4,12 +4,18 @@
 // only allocates, sequences launches on the caller's stream and runs the
 // small host-side Givens recurrences of FGMRES.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/stk.h"
@@ -60,16 +66,19 @@ stk_status validate(const stk_desc* d) {
   if (d->n_fine > (d->dim == 2 ? 4096 : 256)) return fail(STK_EINVAL, "n_fine too large");
   const int nc = d->n_fine >> (d->n_levels - 1);
   const int64_t n0 = (int64_t)d->dim * ipow(2 * nc - 1, d->dim);
-  if (n0 > 40000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve");
+  if (n0 > 80000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve (80000 unknowns)");
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
   if (d->schur != 1 && d->schur != 2) return fail(STK_EINVAL, "schur must be 1 (W = M_p) or 2 (W = M_p(1/mu))");
   if (d->coef_kind != 0 && d->coef_kind != 1)
     return fail(STK_EINVAL, "coef_kind must be 0 (sinker viscosity) or 1 (viscoplastic Newton tensor)");
+  if (d->qpts_1d != 0 && d->qpts_1d != 3)
+    return fail(STK_EINVAL, "qpts_1d must be 0 or 3 (the 3-point Gauss rule is the one built)");
   if (d->coef_kind == 1) {
     const stk_viscoplastic& v = d->vp;
     if (v.modes < 1 || v.modes > 8 || !v.amp) return fail(STK_EINVAL, "vp.modes must be in [1, 8] with vp.amp set");
     if (!(v.tau_y > 0.0) || !isfinite(v.tau_y)) return fail(STK_EINVAL, "vp.tau_y must be positive");
-    if (!isfinite(v.scale)) return fail(STK_EINVAL, "vp.scale must be finite");
+    if (!isfinite(v.eps_scale)) return fail(STK_EINVAL, "vp.eps_scale must be finite");
+    if (!isfinite(v.mu_floor)) return fail(STK_EINVAL, "vp.mu_floor must be finite");
   }
   if (d->mixed != 0 && d->mixed != 1) return fail(STK_EINVAL, "mixed must be 0 (FP64 form) or 1 (mixed form)");
   if (d->nu_pre < 1 || d->nu_pre > kMaxNu || d->nu_post < 1 || d->nu_post > kMaxNu)
@@ -252,6 +261,66 @@ float* level_S<float>(Level& L) {
   return L.S32;
 }
 
+// ---------------------------------------------------------------------------
+// Lockstep batching of the star-patch solves across hierarchies (serving).
+// Hierarchies whose Arnoldi steps issue the same sequence of patch-solve
+// calls each run their step on their own host thread and stream; at every
+// patch-solve call the threads meet, the last to arrive issues one batched
+// launch for all of them on the first entry's stream (after every entry's
+// stream has reached the call, through events), and each stream waits for
+// that launch before going on. Everything else stays on each hierarchy's
+// own stream, and each entry's patch solves run exactly the single-launch
+// code, so results do not depend on the batch.
+struct Cohort {
+  int n = 0;
+  std::mutex m;
+  std::condition_variable cv;
+  int arrived = 0;
+  long gen = 0;
+  hipStream_t lead = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<const Hier*> hs;
+  std::vector<const Level*> ls;
+  std::vector<const void*> rs;
+  std::vector<hipEvent_t> ready;
+  long launches = 0;
+};
+thread_local Cohort* t_cohort = nullptr;
+thread_local int t_slot = -1;
+
+// The patch solves of one ASM application into L.zbuf (batched with the
+// other members of the calling thread's cohort, if any).
+template <class R>
+void asm_solves(Hier& H, Level& L, const R* r) {
+  Cohort* C = t_cohort;
+  if (!C) {
+    launch_asm_solves<R>(H, L, r, H.stream);
+    return;
+  }
+  const int k = t_slot;
+  (void)hipEventRecord(C->ready[k], H.stream);
+  {
+    std::unique_lock<std::mutex> lk(C->m);
+    C->ls[k] = &L;
+    C->rs[k] = r;
+    const long g = C->gen;
+    if (++C->arrived == C->n) {
+      for (int i = 0; i < C->n; ++i) (void)hipStreamWaitEvent(C->lead, C->ready[i], 0);
+      std::vector<const R*> rr(C->n);
+      for (int i = 0; i < C->n; ++i) rr[i] = static_cast<const R*>(C->rs[i]);
+      launch_asm_gemv_batch<R>(C->hs.data(), C->ls.data(), rr.data(), C->n, C->lead);
+      (void)hipEventRecord(C->done, C->lead);
+      ++C->launches;
+      C->arrived = 0;
+      ++C->gen;
+      C->cv.notify_all();
+    } else {
+      C->cv.wait(lk, [&] { return C->gen != g; });
+    }
+  }
+  (void)hipStreamWaitEvent(H.stream, C->done, 0);
+}
+
 template <class R>
 void apply_A(Hier& H, int l, const R* x, R* y) {
   Level& L = H.lv[l];
@@ -291,7 +360,7 @@ void apply_A_dots(Hier& H, int l, const R* x, R* y, const R* V, int64_t ldv, int
 template <class R>
 void asm_apply_A_dots(Hier& H, int l, const R* v, R* z, R* y, const R* V, int64_t ldv, int nk, double* part) {
   Level& L = H.lv[l];
-  launch_asm_solves<R>(H, L, v, H.stream);
+  asm_solves<R>(H, L, v);
   hipEvent_t ev = nullptr;
   const int reps = prof_begin(H, H.stream, &ev);
   for (int k = 0; k < reps; ++k) launch_elem_asm<R>(H, L, z, H.stream);
@@ -363,7 +432,8 @@ void smooth(Hier& H, int l, const R* b, R* x, int nu, bool x_zero) {
     if (H.dim == 2) {
       asm_apply_A_dots<R>(H, l, Vj, Zj, w, V, n, j + 1, p1);
     } else {
-      launch_asm<R>(H, L, Vj, Zj, H.stream);
+      asm_solves<R>(H, L, Vj);
+      launch_asm_gather<R>(H, L, reinterpret_cast<const R*>(L.zbuf), Zj, H.stream);
       apply_A_dots<R>(H, l, Zj, w, V, n, j + 1, p1);
     }
     double* Hcol = L.small + kSmallH + j;
@@ -380,16 +450,17 @@ void coarse_solve(Hier& H, const R* b, R* x) {
   launch_coarse_apply<R>(H, H.lv[0], b, x, H.stream);
 }
 
-// One V-cycle on level l: x = V(b).
+// One V-cycle on level l: x = V(b), from x = 0 (x_zero) or from the x passed
+// in. The coarsest level is solved directly (its initial guess is unused).
 template <class R>
-void vcycle(Hier& H, int l, const R* b, R* x) {
+void vcycle(Hier& H, int l, const R* b, R* x, bool x_zero = true) {
   if (l == 0) {
     coarse_solve<R>(H, b, x);
     return;
   }
   Level& L = H.lv[l];
   Level& C = H.lv[l - 1];
-  smooth<R>(H, l, b, x, H.nu_pre, true);
+  smooth<R>(H, l, b, x, H.nu_pre, x_zero);
   residual<R>(H, l, b, x, rv<R>(L.r));
   restrict_robust<R>(H, l, rv<R>(L.r), rv<R>(C.b));
   vcycle<R>(H, l - 1, rv<R>(C.b), rv<R>(C.x));
@@ -398,27 +469,61 @@ void vcycle(Hier& H, int l, const R* b, R* x) {
   smooth<R>(H, l, b, x, H.nu_post, false);
 }
 
-// Ahat^{-1} applied to an FP64 fine-level vector: one V-cycle in FP64, or in
-// the mixed form one FP32 V-cycle (FP32 applies, transfers and patch solves;
-// FP64 coarse solve and small least-squares problems) between conversions.
-void vcycle_fine(Hier& H, const double* b, double* x, bool mixed) {
+// F-cycle on level lf (the "full" multigrid cycle of Section 5.1 and the
+// algorithm outline, in the form of PETSc's full multigrid): b restricted to
+// every coarser level with P~^T, the coarsest level solved, then on each
+// finer level the prolongated (P~) coarser result improved by one V-cycle
+// started from it. Level l's right-hand side and result live in lv[l].b and
+// lv[l].x, which the V-cycles of finer levels only overwrite after use.
+template <class R>
+void fcycle(Hier& H, int lf, const R* b, R* x) {
+  if (lf == 0) {
+    coarse_solve<R>(H, b, x);
+    return;
+  }
+  const R* bl = b;
+  for (int l = lf; l >= 1; --l) {
+    restrict_robust<R>(H, l, bl, rv<R>(H.lv[l - 1].b));
+    bl = rv<R>(H.lv[l - 1].b);
+  }
+  coarse_solve<R>(H, rv<R>(H.lv[0].b), rv<R>(H.lv[0].x));
+  for (int l = 1; l <= lf; ++l) {
+    R* xl = l == lf ? x : rv<R>(H.lv[l].x);
+    const R* bb = l == lf ? b : rv<R>(H.lv[l].b);
+    prolong_robust<R>(H, l, rv<R>(H.lv[l - 1].x), xl);
+    vcycle<R>(H, l, bb, xl, false);
+  }
+}
+
+template <class R>
+void cycle(Hier& H, int l, const R* b, R* x, bool f) {
+  if (f) fcycle<R>(H, l, b, x);
+  else vcycle<R>(H, l, b, x);
+}
+
+// Ahat^{-1} applied to an FP64 fine-level vector: one V- or F-cycle in FP64,
+// or in the mixed form one FP32 cycle (FP32 applies, transfers and patch
+// solves; FP64 coarse solve and small least-squares problems) between
+// conversions.
+void vcycle_fine(Hier& H, const double* b, double* x, bool mixed, bool f) {
   const int lf = H.L - 1;
   if (!mixed) {
-    vcycle<double>(H, lf, b, x);
+    cycle<double>(H, lf, b, x, f);
     return;
   }
   const int64_t n = H.lv[lf].nvel;
   float* b32 = reinterpret_cast<float*>(H.mb);
   float* x32 = reinterpret_cast<float*>(H.mx);
   launch_convert<double, float>(b, b32, n, H.stream);
-  vcycle<float>(H, lf, b32, x32);
+  cycle<float>(H, lf, b32, x32, f);
   launch_convert<float, double>(x32, x, n, H.stream);
 }
 
 // (z_u, z_p) = P (v_u, v_p), eq. (precond) with Ahat^{-1} = one V-cycle, or
 // (upper) its block upper-triangular part: z_p = -Shat^{-1} v_p (mean
 // removed), z_u = Ahat^{-1} (v_u - B^T z_p): one V-cycle per application.
-void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp, bool mixed, bool upper) {
+void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp, bool mixed, bool upper,
+             bool f) {
   const int lf = H.L - 1;
   Level& F = H.lv[lf];
   if (upper) {
@@ -426,15 +531,15 @@ void precond(Hier& H, const double* vu, const double* vp, double* zu, double* zp
     launch_project_mean(H, F, zp, H.stream);
     launch_elem<double>(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
     launch_gather<double>(H, F, vu, -1.0, H.pw_u, H.stream);         // v_u - B^T z_p
-    vcycle_fine(H, H.pw_u, zu, mixed);
+    vcycle_fine(H, H.pw_u, zu, mixed, f);
     return;
   }
-  vcycle_fine(H, vu, H.pw_y, mixed);                              // y = Ahat^{-1} v_u
+  vcycle_fine(H, vu, H.pw_y, mixed, f);                           // y = Ahat^{-1} v_u
   launch_schur_apply(H, F, H.pw_y, vp, zp, H.stream);             // z_p = -Shat^{-1}(v_p - B y)
   launch_project_mean(H, F, zp, H.stream);
   launch_elem<double>(H, F, EL_BT, nullptr, zp, nullptr, H.stream);
   launch_gather<double>(H, F, nullptr, 1.0, H.pw_u, H.stream);   // B^T z_p
-  vcycle_fine(H, H.pw_u, zu, mixed);                              // Ahat^{-1} B^T z_p
+  vcycle_fine(H, H.pw_u, zu, mixed, f);                           // Ahat^{-1} B^T z_p
   launch_axpby<double>(1.0, H.pw_y, -1.0, zu, zu, F.nvel, H.stream);  // z_u = y - that
 }
 
@@ -447,13 +552,13 @@ void stokes_apply(Hier& H, const double* x, double* y) {
 
 // One FGMRES Arnoldi step j with restart m: Z_j = P V_j, w = K Z_j,
 // classical Gram-Schmidt twice against V_0..V_j, V_{j+1} = w/||w||, H column j.
-void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed, bool upper) {
+void arnoldi_step(Hier& H, int j, int m, int64_t nu, int64_t nvec, bool mixed, bool upper, bool f) {
   double* Vj = H.fV + (int64_t)j * nvec;
   double* Zj = H.fZ + (int64_t)j * nvec;
   double* w = H.fV + (int64_t)(j + 1) * nvec;
   double* p1 = H.partials;
   double* p2 = H.partials + kPartialLen;
-  precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed, upper);
+  precond(H, Vj, Vj + nu, Zj, Zj + nu, mixed, upper, f);
   // w = K Z_j with the first Gram-Schmidt pass's dot products
   Level& F = H.lv[H.L - 1];
   launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, Zj, Zj + nu, w + nu, H.stream);
@@ -476,6 +581,10 @@ stk_status check_dtype(const Hier& H, int dtype) {
   return fail(STK_EINVAL, dtype == STK_F32 ? "STK_F32 needs a hierarchy set up with mixed=1" : "unknown dtype");
 }
 
+bool solve_busy(const Hier& H) {
+  return H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL || H.sv.phase == Hier::SV_FINISH;
+}
+
 stk_status check_level(const Hier& H, int l, int lmin) {
   if (l < lmin || l >= H.L) return fail(STK_EINVAL, "level out of range");
   return STK_OK;
@@ -496,6 +605,8 @@ stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
 }  // namespace
 
 namespace stk {
+
+void set_last_error(const std::string& msg) { g_err = msg; }
 
 int prof_begin(Hier& H, hipStream_t s, hipEvent_t* ev) {
   *ev = nullptr;
@@ -567,7 +678,8 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   if (H.coef_kind == 1) {
     H.vp_modes = desc->vp.modes;
     H.vp_tau_y = desc->vp.tau_y;
-    H.vp_scale = desc->vp.scale;
+    H.vp_scale = desc->vp.eps_scale;
+    H.vp_floor = desc->vp.mu_floor > 0.0 ? desc->vp.mu_floor : desc->sinker.mu_min;
   }
   auto dev_alloc = [&](size_t b, void** p) -> stk_status {
     void* q = nullptr;
@@ -666,13 +778,29 @@ stk_status stk_profile(stk_hier* h, int enable) {
 
 stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* total_ms, double* total_bytes) {
   if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
-  if (kernel < 0 || kernel >= PROF_NIDS) return fail(STK_EINVAL, "unknown kernel id");
+  if (kernel < 0 || kernel > PROF_NIDS) return fail(STK_EINVAL, "unknown kernel id");
   Prof& P = h->H.prof;
   HIPCHK(hipStreamSynchronize(h->H.stream));
+  // kernel PROF_NIDS: the patch-solve launches of the finest level, told
+  // apart by their algorithmic bytes per launch (FP64 or FP32)
+  double fine_b[2] = {0.0, 0.0};
+  if (kernel == PROF_NIDS) {
+    const Level& F = h->H.lv[h->H.L - 1];
+    double e = (double)F.nvel;
+    for (const PatchClass& pc : F.cls) e += (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n);
+    fine_b[0] = 8.0 * e;
+    fine_b[1] = 4.0 * e;
+  }
   int64_t n = 0;
   double ms = 0.0, by = 0.0;
   for (const Prof::Rec& r : P.recs) {
-    if (r.id != kernel) continue;
+    if (kernel == PROF_NIDS) {
+      if (r.id != PROF_ASM_GEMV || r.n <= 0) continue;
+      const double per = r.bytes / r.n;
+      if (fabs(per - fine_b[0]) > 0.5 && fabs(per - fine_b[1]) > 0.5) continue;
+    } else if (r.id != kernel) {
+      continue;
+    }
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
     n += r.n;
@@ -691,6 +819,8 @@ stk_status stk_destroy(stk_hier* h) {
   for (hipEvent_t e : h->H.prof.pool) (void)hipEventDestroy(e);
   drop_graphs(h->H);
   if (h->H.sev) (void)hipEventDestroy(h->H.sev);
+  if (h->H.bev) (void)hipEventDestroy(h->H.bev);
+  if (h->H.cev) (void)hipEventDestroy(h->H.cev);
   if (h->H.hpin) (void)hipHostFree(h->H.hpin);
   if (h->H.own) {
     (void)hipStreamSynchronize(h->H.own);
@@ -714,15 +844,22 @@ stk_status stk_sizes(const stk_hier* h, int level, int64_t* n_vel_stored, int64_
   Hier& H = (h)->H;                                               \
   H.stream = (hipStream_t)stream
 
+// For calls that use the hierarchy's device buffers: STK_EBUSY while a
+// resumable solve is in progress (its phases use the same buffers on the
+// hierarchy's own stream), checked before anything is touched.
+#define GET_H_IDLE(h)                                                                      \
+  if (!(h)) return fail(STK_EINVAL, "hierarchy is NULL");                                  \
+  if (solve_busy((h)->H)) return fail(STK_EBUSY, "a resumable solve is in progress on this hierarchy"); \
+  Hier& H = (h)->H;                                                                        \
+  H.stream = (hipStream_t)stream
+
 stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant) {
   if (!h) return fail(STK_EINVAL, "hierarchy is NULL");
   Hier& H = h->H;
   STKCHK(check_level(H, level, 1));
   STKCHK(check_dtype(H, dtype));
   if (variant < 0 || variant >= kAsmVariants) return fail(STK_EINVAL, "variant out of range");
-  if (H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL ||
-      H.sv.phase == Hier::SV_FINISH)
-    return fail(STK_EBUSY, "a solve is in progress");
+  if (solve_busy(H)) return fail(STK_EBUSY, "a resumable solve is in progress on this hierarchy");
   H.lv[level].asm_variant[dtype == STK_F64 ? 0 : 1] = variant;
   drop_graphs(H);   // captured steps hold the previous variant's kernels
   return STK_OK;
@@ -732,11 +869,8 @@ stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant) {
 // use) with HIP events around `reps` back-to-back launches on the level's own
 // buffers, and keeps the fastest (ties: the lower index).
 stk_status stk_autotune(stk_hier* h, int reps, int* variants, float* times_ms, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   if (reps < 1 || reps > 100) return fail(STK_EINVAL, "reps must be in [1, 100]");
-  if (H.sv.phase == Hier::SV_ARNOLDI || H.sv.phase == Hier::SV_RESIDUAL ||
-      H.sv.phase == Hier::SV_FINISH)
-    return fail(STK_EBUSY, "a solve is in progress");
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
@@ -781,7 +915,7 @@ stk_status stk_autotune(stk_hier* h, int reps, int* variants, float* times_ms, v
 }
 
 stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   if (!b_u) return fail(STK_EINVAL, "b_u is NULL");
   Level& F = H.lv[H.L - 1];
   launch_rhs_elem(H, F, H.stream);
@@ -792,7 +926,7 @@ stk_status stk_rhs(stk_hier* h, double* b_u, double* b_p, void* stream) {
 }
 
 stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, void* y, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_level(H, level, 0));
   STKCHK(check_dtype(H, dtype));
   if (!x || !y || x == y) return fail(STK_EINVAL, "x, y must be distinct non-NULL buffers");
@@ -804,7 +938,7 @@ stk_status stk_apply_Agamma(stk_hier* h, int level, int dtype, const void* x, vo
 
 stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p, double* y_u, double* y_p,
                             void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   if (!x_u || !x_p || !y_u || !y_p) return fail(STK_EINVAL, "NULL buffer");
   Level& F = H.lv[H.L - 1];
   launch_elem<double>(H, F, EL_VISC | EL_AUG | EL_BT | EL_BOUT, x_u, x_p, y_p, H.stream);
@@ -814,7 +948,7 @@ stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p, d
 }
 
 stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_level(H, level, 1));
   STKCHK(check_dtype(H, dtype));
   if (!r || !y) return fail(STK_EINVAL, "NULL buffer");
@@ -825,7 +959,7 @@ stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, vo
 }
 
 stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x, int nsteps, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_level(H, level, 1));
   STKCHK(check_dtype(H, dtype));
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
@@ -837,7 +971,7 @@ stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x,
 }
 
 stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc, void* xf, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_level(H, coarse_level + 1, 1));
   STKCHK(check_dtype(H, dtype));
   if (!xc || !xf) return fail(STK_EINVAL, "NULL buffer");
@@ -848,7 +982,7 @@ stk_status stk_prolong(stk_hier* h, int coarse_level, int dtype, const void* xc,
 }
 
 stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, void* rc, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_level(H, fine_level, 1));
   STKCHK(check_dtype(H, dtype));
   if (!rf || !rc) return fail(STK_EINVAL, "NULL buffer");
@@ -859,7 +993,7 @@ stk_status stk_restrict(stk_hier* h, int fine_level, int dtype, const void* rf, 
 }
 
 stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
   coarse_solve<double>(H, b, x);
   HIPCHK(hipGetLastError());
@@ -867,7 +1001,7 @@ stk_status stk_coarse_solve(stk_hier* h, const double* b, double* x, void* strea
 }
 
 stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   STKCHK(check_dtype(H, dtype));
   if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
   if (dtype == STK_F64) vcycle<double>(H, H.L - 1, (const double*)b, (double*)x);
@@ -876,14 +1010,24 @@ stk_status stk_vcycle(stk_hier* h, int dtype, const void* b, void* x, void* stre
   return STK_OK;
 }
 
+stk_status stk_fcycle(stk_hier* h, int dtype, const void* b, void* x, void* stream) {
+  GET_H_IDLE(h);
+  STKCHK(check_dtype(H, dtype));
+  if (!b || !x || b == x) return fail(STK_EINVAL, "b, x must be distinct non-NULL buffers");
+  if (dtype == STK_F64) fcycle<double>(H, H.L - 1, (const double*)b, (double*)x);
+  else fcycle<float>(H, H.L - 1, (const float*)b, (float*)x);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
 stk_status stk_precond(stk_hier* h, int flags, const double* v_u, const double* v_p, double* z_u, double* z_p,
                        void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   if (!v_u || !v_p || !z_u || !z_p) return fail(STK_EINVAL, "NULL buffer");
-  if (flags & ~(STK_PC_MIXED | STK_PC_UPPER)) return fail(STK_EINVAL, "unknown preconditioner flags");
+  if (flags & ~(STK_PC_MIXED | STK_PC_UPPER | STK_PC_FCYCLE)) return fail(STK_EINVAL, "unknown preconditioner flags");
   const bool mixed = (flags & STK_PC_MIXED) != 0;
   if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
-  precond(H, v_u, v_p, z_u, z_p, mixed, (flags & STK_PC_UPPER) != 0);
+  precond(H, v_u, v_p, z_u, z_p, mixed, (flags & STK_PC_UPPER) != 0, (flags & STK_PC_FCYCLE) != 0);
   HIPCHK(hipGetLastError());
   return STK_OK;
 }
@@ -936,7 +1080,9 @@ stk_status sv_begin(Hier& H, hipStream_t caller, const double* b_u, const double
   const bool mixed = opts && opts->mixed;
   if (mixed && !H.mixed) return fail(STK_EINVAL, "the mixed form needs a hierarchy set up with mixed=1");
   if (opts && (opts->pc < 0 || opts->pc > 1)) return fail(STK_EINVAL, "pc must be 0 (full) or 1 (upper)");
+  if (opts && (opts->cycle < 0 || opts->cycle > 1)) return fail(STK_EINVAL, "cycle must be 0 (V) or 1 (F)");
   const bool upper = opts && opts->pc == 1;
+  const bool fcyc = opts && opts->cycle == 1;
   STKCHK(ensure_pinned(H));
   Level& F = H.lv[H.L - 1];
   const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
@@ -961,6 +1107,7 @@ stk_status sv_begin(Hier& H, hipStream_t caller, const double* b_u, const double
   S.rtol = rtol;
   S.mixed = mixed;
   S.upper = upper;
+  S.fcycle = fcyc;
   S.graphs = !(opts && opts->eager);
   S.x_u = x_u;
   S.x_p = x_p;
@@ -1017,9 +1164,9 @@ stk_status sv_enqueue(Hier& H) {
   if (S.phase == Hier::SV_ARNOLDI) {
     const int j = S.j;
     if (j == 0) launch_axpby<double>(1.0 / S.beta, rvec, 0.0, rvec, H.fV, nvec, s);
-    const int key = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0);
+    const int key = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0) | (S.fcycle ? 4 : 0);
     if (!S.graphs) {
-      arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper);
+      arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper, S.fcycle);
     } else {
       if (H.steps_m != m || H.steps_key != key) {
         drop_graphs(H);
@@ -1032,7 +1179,7 @@ stk_status sv_enqueue(Hier& H) {
         H.prof.on = false;   // no event records inside captured graphs
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper);
+        arnoldi_step(H, j, m, nu, nvec, S.mixed, S.upper, S.fcycle);
         const hipError_t ce = hipStreamEndCapture(s, &graph);
         H.prof.on = prof_on;
         if (ce != hipSuccess) return fail(STK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
@@ -1062,6 +1209,7 @@ stk_status sv_enqueue(Hier& H) {
     return STK_OK;
   }
   HIPCHK(hipEventRecord(H.sev, s));
+  S.inflight = true;
   return STK_OK;
 }
 
@@ -1071,6 +1219,7 @@ stk_status sv_advance(Hier& H) {
   Hier::Solve& S = H.sv;
   if (S.phase == Hier::SV_IDLE || S.phase == Hier::SV_DONE) return STK_OK;
   HIPCHK(hipEventSynchronize(H.sev));
+  S.inflight = false;
   Level& F = H.lv[H.L - 1];
   const int64_t nvec = F.nvel + F.npres;
   const int m = S.m;
@@ -1143,6 +1292,48 @@ stk_status sv_advance(Hier& H) {
   return STK_OK;
 }
 
+// Enqueues the Arnoldi step of each hierarchy of `g` (same dimension, level
+// count, relaxation steps and solve form, so the same sequence of patch-solve
+// calls) on its own stream from its own host thread, with the patch solves
+// batched across them (Cohort).
+stk_status enqueue_cohort(const std::vector<Hier*>& g) {
+  const int n = (int)g.size();
+  Cohort C;
+  C.n = n;
+  C.hs.assign(g.begin(), g.end());
+  C.ls.assign(n, nullptr);
+  C.rs.assign(n, nullptr);
+  C.ready.assign(n, nullptr);
+  C.lead = g[0]->own;
+  for (int k = 0; k < n; ++k) {
+    if (!g[k]->bev) HIPCHK(hipEventCreateWithFlags(&g[k]->bev, hipEventDisableTiming));
+    C.ready[k] = g[k]->bev;
+  }
+  C.done = g[0]->cev;
+  if (!C.done) {
+    HIPCHK(hipEventCreateWithFlags(&g[0]->cev, hipEventDisableTiming));
+    C.done = g[0]->cev;
+  }
+  std::vector<stk_status> st(n, STK_OK);
+  std::vector<std::string> err(n);
+  auto run = [&](int k) {
+    t_cohort = &C;
+    t_slot = k;
+    st[k] = sv_enqueue(*g[k]);
+    if (st[k] != STK_OK) err[k] = g_err;
+    t_cohort = nullptr;
+    t_slot = -1;
+  };
+  std::vector<std::thread> th;
+  th.reserve(n - 1);
+  for (int k = 1; k < n; ++k) th.emplace_back(run, k);
+  run(0);
+  for (std::thread& t : th) t.join();
+  for (int k = 0; k < n; ++k)
+    if (st[k] != STK_OK) return fail(st[k], err[k]);
+  return STK_OK;
+}
+
 void sv_info(const Hier& H, stk_solve_info* inf) {
   if (!inf) return;
   const Hier::Solve& S = H.sv;
@@ -1168,7 +1359,7 @@ extern "C" {
 
 stk_status stk_solve(stk_hier* h, const double* b_u, const double* b_p, double* x_u, double* x_p,
                      const stk_solve_opts* opts, stk_solve_info* info, void* stream) {
-  GET_H(h);
+  GET_H_IDLE(h);
   hipStream_t caller = H.stream;
   const stk_status st0 = sv_begin(H, caller, b_u, b_p, x_u, x_p, opts);
   if (st0 != STK_OK) {
@@ -1204,26 +1395,78 @@ stk_status stk_solve_begin(stk_hier* h, const double* b_u, const double* b_p, do
 stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream) {
   if (n < 0 || (n > 0 && !hs)) return fail(STK_EINVAL, "bad hierarchy list");
   (void)stream;
-  stk_status first = STK_OK;
-  // enqueue every solve's next phase first so their device work overlaps,
-  // then wait for each and run the host part
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     if (!hs[i]) return fail(STK_EINVAL, "NULL hierarchy in the list");
-    Hier& H = hs[i]->H;
-    const int ph = H.sv.phase;
-    if (ph == Hier::SV_IDLE || ph == Hier::SV_DONE) continue;
-    const stk_status st = sv_enqueue(H);
-    if (st != STK_OK) {
-      sv_done(H, st);
-      if (first == STK_OK) first = st;
+  // STK_CROSS_BATCH=0 in the environment turns the lockstep cohorts off
+  // (every solve then steps on its own; for comparisons)
+  const char* env = getenv("STK_CROSS_BATCH");
+  const bool cross = !(env && env[0] == '0');
+  stk_status first = STK_OK;
+  auto note = [&](Hier& H, stk_status st) {
+    if (st == STK_OK) return;
+    if (H.sv.phase != Hier::SV_DONE) sv_done(H, st);
+    if (first == STK_OK) first = st;
+  };
+  auto active = [](const Hier& H) { return H.sv.phase != Hier::SV_IDLE && H.sv.phase != Hier::SV_DONE; };
+  for (int pass = 0; pass < 2; ++pass) {
+    bool moved = false;
+    // 1. host parts of the phases that have finished on the device
+    for (int i = 0; i < n; ++i) {
+      Hier& H = hs[i]->H;
+      if (!active(H) || !H.sv.inflight) continue;
+      const hipError_t q = hipEventQuery(H.sev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) {
+        note(H, fail(STK_EDEVICE, std::string("phase event: ") + hipGetErrorString(q)));
+        continue;
+      }
+      note(H, sv_advance(H));
+      moved = true;
     }
-  }
-  for (int i = 0; i < n; ++i) {
-    Hier& H = hs[i]->H;
-    const stk_status st = sv_advance(H);
-    if (st != STK_OK) {
-      if (H.sv.phase != Hier::SV_DONE) sv_done(H, st);
-      if (first == STK_OK) first = st;
+    // 2. next phases of every solve with nothing in flight; Arnoldi steps of
+    //    same-shape plain-launch solves go out as lockstep cohorts
+    std::map<std::tuple<int, int, int, int, int, int>, std::vector<Hier*>> groups;
+    for (int i = 0; i < n; ++i) {
+      Hier& H = hs[i]->H;
+      if (!active(H) || H.sv.inflight) continue;
+      const Hier::Solve& S = H.sv;
+      if (cross && S.phase == Hier::SV_ARNOLDI && !S.graphs && !H.prof.on) {
+        const int form = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0) | (S.fcycle ? 4 : 0);
+        groups[std::make_tuple(H.dim, H.L, H.nu_pre, H.nu_post, form, 0)].push_back(&H);
+        continue;
+      }
+      note(H, sv_enqueue(H));
+      moved = true;
+    }
+    for (auto& kv : groups) {
+      std::vector<Hier*>& g = kv.second;
+      for (size_t k0 = 0; k0 < g.size(); k0 += kAsmBatchMax) {
+        const size_t kn = std::min(g.size() - k0, (size_t)kAsmBatchMax);
+        std::vector<Hier*> part(g.begin() + k0, g.begin() + k0 + kn);
+        if (kn == 1) {
+          note(*part[0], sv_enqueue(*part[0]));
+        } else {
+          const stk_status st = enqueue_cohort(part);
+          if (st != STK_OK) {
+            for (Hier* H : part) note(*H, st);
+          }
+        }
+        moved = true;
+      }
+    }
+    if (moved || pass == 1) break;
+    // 3. nothing could move: wait for the first in-flight phase to finish
+    bool any = false;
+    for (int i = 0; i < n; ++i) any = any || (active(hs[i]->H) && hs[i]->H.sv.inflight);
+    if (!any) break;
+    for (;;) {
+      bool ready = false;
+      for (int i = 0; i < n && !ready; ++i) {
+        Hier& H = hs[i]->H;
+        if (active(H) && H.sv.inflight && hipEventQuery(H.sev) != hipErrorNotReady) ready = true;
+      }
+      if (ready) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
   }
   return first;

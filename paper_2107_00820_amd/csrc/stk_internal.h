@@ -40,6 +40,9 @@ struct PatchClass {
 // and precision (bit-identical results; they differ in load chunking and
 // occupancy only).
 constexpr int kAsmVariants = 3;
+// Entries (level solves of possibly different hierarchies) per batched
+// patch-solve launch.
+constexpr int kAsmBatchMax = 8;
 
 struct Level {
   LevelGeo g{};
@@ -101,6 +104,7 @@ struct Hier {
   int vp_modes = 0;
   double* vp_amp = nullptr;          // device [d][modes^d]
   double vp_tau_y = 0.0, vp_scale = 0.0;   // vp_scale <= 0: RMS of eps_II over fine Gauss points = 1
+  double vp_floor = 0.0;                   // mu_floor of the capped law
   std::vector<Level> lv;
   // coarse level
   int64_t n0 = 0;
@@ -138,7 +142,8 @@ struct Hier {
     int phase = SV_IDLE;
     int status = 0;
     int m = 30, maxit = 300, j = 0, k = 0, it = 0;
-    bool mixed = false, upper = false, graphs = true, converged = false;
+    bool mixed = false, upper = false, graphs = true, converged = false, fcycle = false;
+    bool inflight = false;   // the current phase's device work is enqueued and not yet advanced
     double rtol = 1e-8, bnorm = 0.0, beta = 0.0, t_solve = 0.0;
     double *x_u = nullptr, *x_p = nullptr;
     std::vector<double> Hh, cs, sn, g, hist;
@@ -146,7 +151,14 @@ struct Hier {
   } sv;
   double* hpin = nullptr;          // pinned host: Hessenberg copy, norm partials, y
   hipEvent_t sev = nullptr;        // end of the last enqueued phase
+  // lockstep batching of patch solves across hierarchies: this stream has
+  // reached a patch-solve call (bev); the batched launch is done (cev, used
+  // when this hierarchy leads a batch)
+  hipEvent_t bev = nullptr, cev = nullptr;
 };
+
+// Sets the thread-local message returned by stk_last_error().
+void set_last_error(const std::string& msg);
 
 // Event bracketing of one launch (no-ops unless H.prof.on).
 // prof_begin returns how many times the caller issues the launch (1 unless profiling).
@@ -181,8 +193,12 @@ void launch_schur_apply(const Hier& H, const Level& l, const double* y, const do
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s);
 
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
+// zbuf: patch output buffer to use instead of l.zbuf (NULL: l.zbuf; a
+// caller-provided buffer is not traced).
 template <class R>
-void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s);
+void launch_asm(Hier& H, const Level& l, const R* r, R* y, hipStream_t s, R* zbuf = nullptr);
+template <class R>
+void launch_asm_gather(const Hier& H, const Level& l, const R* zbuf, R* y, hipStream_t s);
 // The patch solves of one ASM application into l.zbuf (traced like
 // launch_asm), without the gather to a node vector.
 template <class R>
@@ -190,7 +206,15 @@ void launch_asm_solves(Hier& H, const Level& l, const R* r, hipStream_t s);
 // The patch-solve kernel alone (reps launches), no gather and no tracing;
 // *bytes_out receives its algorithmic bytes per launch if non-NULL.
 template <class R>
-void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out);
+void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out,
+                     R* zbuf = nullptr);
+// One launch (per kAsmBatchMax entries) of the patch solves of n levels
+// (ls[k] of hierarchy hs[k], residual rs[k], output ls[k]->zbuf); all of one
+// dimension; the variant of the first entry is used (variants give
+// bit-identical results).
+template <class R>
+void launch_asm_gemv_batch(const Hier* const* hs, const Level* const* ls, const R* const* rs, int n,
+                           hipStream_t s);
 template <class R>
 void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
                          hipStream_t s);

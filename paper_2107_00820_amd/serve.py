@@ -5,14 +5,19 @@ the HBM footprint of their hierarchies (levels, coefficient tables, packed
 patch inverses, coarse inverse, Krylov storage; ``stk_footprint``) fits the
 budget and a slot is free. An admitted request's hierarchy is built on a
 setup thread (its own stream) while the device keeps working on the others;
-its solve then joins the running set. Every scheduler tick advances each
-running solve by one phase (``stk_step_batch``: all phases are enqueued on
-the hierarchies' own streams before any is waited for, so the requests' work
-overlaps on the device). Each request is solved once, so by default its
-phases are plain launches: capturing a HIP graph per Arnoldi step pays off
-only for repeated solves on one hierarchy. Finished requests free their memory at once, which
-lets waiting requests in. Latency is completion time minus arrival time
-(queueing, setup and solve).
+its solve then joins the running set. Every scheduler tick calls
+``stk_step_batch`` on the running solves: a solve whose last phase has
+finished on the device gets its host part and its next phase enqueued at
+once, without waiting for the others (phases run on the hierarchies' own
+streams, so the requests' work overlaps on the device), and the Arnoldi
+steps of same-shape requests that are ready together run in lockstep with
+one batched star-patch solve launch per smoothing step for all of them.
+Each request is solved once, so its phases are plain launches: capturing a
+HIP graph per Arnoldi step pays off only for repeated solves on one
+hierarchy. Finished or failed requests free their memory at once, which
+lets waiting requests in; a request that fails (setup, start or solve) is
+recorded with its error and the loop goes on. Latency is completion time
+minus arrival time (queueing, setup and solve).
 
 The solves run the same kernels in the same order as ``stk_solve`` on each
 hierarchy, so a request's result is bit-identical alone and in the mix.
@@ -26,6 +31,17 @@ import time
 from typing import List, Optional, Tuple
 
 from .stk import Hierarchy, StkError, desc_from_workload, stk_footprint, stk_step_batch
+
+
+def _build_on_own_stream(wl, mixed):
+    """Hierarchy of a request, set up on a fresh stream (setup overlaps the
+    running solves)."""
+    import torch
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        h = Hierarchy.from_workload(wl, mixed=mixed)
+    s.synchronize()
+    return h
 
 
 @dataclasses.dataclass
@@ -65,7 +81,11 @@ class Server:
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 16, setup_workers: int = 2,
                  mixed: bool = False, keep_solutions: bool = False, rtol: float = 1e-8, eager: bool = True,
-                 pc: str = "full"):
+                 pc: str = "full", cycle: str = "V", build=None, step=None, footprint=None):
+        """build(wl, mixed) -> hierarchy, step(list of hierarchies) and
+        footprint(wl, mixed) -> bytes default to the library's own
+        (Hierarchy.from_workload on a fresh stream, stk_step_batch,
+        stk_footprint); tests pass stand-ins."""
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.setup_workers = int(setup_workers)
@@ -74,18 +94,17 @@ class Server:
         self.rtol = rtol
         self.eager = bool(eager)
         self.pc = pc
+        self.cycle = cycle
+        self._build = build or _build_on_own_stream
+        self._step = step or stk_step_batch
+        self._footprint = footprint or (lambda wl, mixed: stk_footprint(desc_from_workload(wl, mixed=mixed)))
 
     def _setup(self, wl):
-        import torch
         t = time.perf_counter()
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            h = Hierarchy.from_workload(wl, mixed=1 if self.mixed else 0)
-        s.synchronize()
+        h = self._build(wl, 1 if self.mixed else 0)
         return h, time.perf_counter() - t
 
     def run(self, requests: List[Tuple[float, object]], log=None) -> dict:
-        import torch
         order = sorted(range(len(requests)), key=lambda i: requests[i][0])
         pending = collections.deque(order)
         waiting: collections.deque = collections.deque()
@@ -107,7 +126,7 @@ class Server:
                     arr, wl = requests[i]
                     n_u, n_p = wl.unknowns()
                     r = Result(i, wl.name, n_u + n_p, arr)
-                    r.footprint = stk_footprint(desc_from_workload(wl, mixed=1 if self.mixed else 0))
+                    r.footprint = self._footprint(wl, 1 if self.mixed else 0)
                     results[i] = r
                     if r.footprint > self.budget:
                         r.error = "footprint exceeds the budget"
@@ -135,29 +154,46 @@ class Server:
                         r.error, r.status, r.finished = str(e), e.status, now()
                         used -= r.footprint
                         continue
-                    bu, bp = h.stk_rhs()
-                    xu, xp = h.stk_solve_begin(bu, bp, rtol=self.rtol, mixed=self.mixed, eager=self.eager,
-                                               pc=self.pc)
+                    try:
+                        bu, bp = h.stk_rhs()
+                        xu, xp = h.stk_solve_begin(bu, bp, rtol=self.rtol, mixed=self.mixed, eager=self.eager,
+                                                   pc=self.pc, cycle=self.cycle)
+                    except StkError as e:
+                        # a request that cannot start (e.g. a non-finite
+                        # right-hand side) is recorded and its memory released
+                        r.error, r.status, r.finished = str(e), e.status, now()
+                        h.close()
+                        used -= r.footprint
+                        continue
                     r.started = now()
                     active.append((i, h, xu, xp))
                 peak_active = max(peak_active, len(active))
                 if active:
                     try:
-                        stk_step_batch([a[1] for a in active])
+                        self._step([a[1] for a in active])
                     except StkError:
-                        pass                    # the failing solve reports through stk_poll
+                        pass                    # the failing solve reports through its poll below
                     ticks += 1
                     still = []
                     for i, h, xu, xp in active:
-                        info = h.stk_poll()
+                        r = results[i]
+                        try:
+                            info = h.stk_poll()
+                        except StkError as e:
+                            r.error, r.status, r.finished = str(e), e.status, now()
+                            h.close()
+                            used -= r.footprint
+                            if log:
+                                log(f"[serve] {r.name}: failed: {e}")
+                            continue
                         if info is None:
                             still.append((i, h, xu, xp))
                             continue
-                        r = results[i]
                         r.finished = now()
                         r.iters, r.converged, r.rel_res, r.status = (info["iters"], info["converged"],
                                                                       info["rel_res"], info["status"])
                         if self.keep:
+                            import torch
                             torch.cuda.synchronize()
                             r.solution = (xu.cpu().numpy(), xp.cpu().numpy())
                         h.close()

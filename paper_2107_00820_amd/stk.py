@@ -21,8 +21,10 @@ LIB_PATH = os.path.join(HERE, "libstk.so")
 STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ENOTCONV, STK_ENOTSPD, STK_ENAN, STK_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 STK_F64, STK_F32 = 0, 1
 STK_ASM_VARIANTS = 3
-STK_PC_MIXED, STK_PC_UPPER = 1, 2
+STK_PC_MIXED, STK_PC_UPPER, STK_PC_FCYCLE = 1, 2, 4
+STK_BATCH_MAX = 8
 _PC = {"full": 0, "upper": 1}
+_CYCLE = {"V": 0, "F": 1}
 _NAMES = {0: "STK_OK", -1: "STK_EINVAL", -2: "STK_ENOMEM", -3: "STK_EDEVICE", -4: "STK_ENOTCONV",
           -5: "STK_ENOTSPD", -6: "STK_ENAN", -7: "STK_EBUSY"}
 
@@ -39,18 +41,20 @@ class Sinker(C.Structure):
 
 
 class Viscoplastic(C.Structure):
-    _fields_ = [("modes", C.c_int), ("amp", C.POINTER(C.c_double)), ("tau_y", C.c_double), ("scale", C.c_double)]
+    _fields_ = [("modes", C.c_int), ("amp", C.POINTER(C.c_double)), ("tau_y", C.c_double),
+                ("mu_floor", C.c_double), ("eps_scale", C.c_double)]
 
 
 class Desc(C.Structure):
-    _fields_ = [("dim", C.c_int), ("n_fine", C.c_int), ("n_levels", C.c_int), ("gamma", C.c_double),
+    _fields_ = [("dim", C.c_int), ("n_fine", C.c_int), ("n_levels", C.c_int), ("qpts_1d", C.c_int),
+                ("gamma", C.c_double),
                 ("schur", C.c_int), ("coef_kind", C.c_int), ("sinker", Sinker), ("vp", Viscoplastic),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("eager", C.c_int),
-                ("mixed", C.c_int), ("pc", C.c_int)]
+                ("mixed", C.c_int), ("pc", C.c_int), ("cycle", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -88,6 +92,7 @@ def load(path: str = LIB_PATH):
         "stk_restrict": [vp, i32, i32, vp, vp, vp],
         "stk_coarse_solve": [vp, vp, vp, vp],
         "stk_vcycle": [vp, i32, vp, vp, vp],
+        "stk_fcycle": [vp, i32, vp, vp, vp],
         "stk_precond": [vp, i32, vp, vp, vp, vp, vp],
         "stk_solve": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp],
         "stk_solve_begin": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp],
@@ -137,12 +142,14 @@ def _dptr(*ts):
 
 
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
-              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_scale=0.0, schur=1):
+              nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_eps_scale=0.0, schur=1,
+              vp_mu_floor=0.0, qpts_1d=0):
     """Descriptor; vp_amp (array [d][M]^d) selects the viscoplastic Newton
     tensor over the sinker base field (coef_kind 1)."""
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
+    d.qpts_1d = int(qpts_1d)
     d.schur, d.coef_kind, d.mixed = int(schur), 0, int(mixed)
     if vp_amp is not None:
         amp = np.ascontiguousarray(np.asarray(vp_amp, dtype=np.float64))
@@ -150,7 +157,7 @@ def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, 
         d.coef_kind = 1
         d.vp.modes = amp.shape[1]
         d.vp.amp = amp.ctypes.data_as(C.POINTER(C.c_double))
-        d.vp.tau_y, d.vp.scale = float(vp_tau_y), float(vp_scale)
+        d.vp.tau_y, d.vp.eps_scale, d.vp.mu_floor = float(vp_tau_y), float(vp_eps_scale), float(vp_mu_floor)
         d._keep_amp = amp
     d.sinker.n = centers.shape[0]
     d.sinker.centers = centers.ctypes.data_as(C.POINTER(C.c_double))
@@ -167,7 +174,8 @@ def desc_from_workload(wl, hbm_budget=0, mixed=0):
     stress is 2 mu_max and the velocity scale is left to the library (root
     mean square of eps_II over the finest Gauss points equal to 1)."""
     from workloads import OMEGA, DELTA, BETA
-    vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max) if wl.coef_kind == 1 else {}
+    vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max,
+              vp_mu_floor=getattr(wl, "mu_floor", 0.0)) if wl.coef_kind == 1 else {}
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
                      OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, schur=getattr(wl, "schur", 1), **vp)
 
@@ -276,21 +284,27 @@ class Hierarchy:
         _check(load().stk_vcycle(self._h, *_dptr(b, x), _stream()))
         return x
 
-    def stk_precond(self, vu, vp, zu=None, zp=None, mixed=False, pc="full"):
+    def stk_fcycle(self, b, x=None):
+        x = self.zeros_u(None, b.dtype) if x is None else x
+        _check(load().stk_fcycle(self._h, *_dptr(b, x), _stream()))
+        return x
+
+    def stk_precond(self, vu, vp, zu=None, zp=None, mixed=False, pc="full", cycle="V"):
         zu = self.zeros_u() if zu is None else zu
         zp = self.zeros_p() if zp is None else zp
-        flags = (STK_PC_MIXED if mixed else 0) | (STK_PC_UPPER if pc == "upper" else 0)
+        flags = ((STK_PC_MIXED if mixed else 0) | (STK_PC_UPPER if pc == "upper" else 0) |
+                 (STK_PC_FCYCLE if cycle == "F" else 0))
         _check(load().stk_precond(self._h, flags, _ptr(vu), _ptr(vp), _ptr(zu), _ptr(zp), _stream()))
         return zu, zp
 
     # ---- serving (resumable solves)
     def stk_solve_begin(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, eager=False,
-                        mixed=False, pc="full"):
+                        mixed=False, pc="full", cycle="V"):
         """Starts a solve; the returned output tensors are filled once
         stk_poll reports completion."""
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc])
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc], _CYCLE[cycle])
         self._solve_refs = (bu, bp, xu, xp)        # keep the buffers alive while the solve runs
         _check(load().stk_solve_begin(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu),
                                       _ptr(xp), C.byref(opts), _stream()))
@@ -358,14 +372,14 @@ class Hierarchy:
         return n.value, ms.value, by.value
 
     def stk_solve(self, bu, bp=None, rtol=1e-8, restart=30, maxit=300, xu=None, xp=None, allow_notconv=False,
-                  eager=False, mixed=False, pc="full"):
+                  eager=False, mixed=False, pc="full", cycle="V", allow=()):
         xu = self.zeros_u() if xu is None else xu
         xp = self.zeros_p() if xp is None else xp
-        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc])
+        opts = SolveOpts(rtol, restart, maxit, 1 if eager else 0, 1 if mixed else 0, _PC[pc], _CYCLE[cycle])
         info = SolveInfo()
         st = load().stk_solve(self._h, _ptr(bu), _ptr(bp) if bp is not None else None, _ptr(xu), _ptr(xp),
                               C.byref(opts), C.byref(info), _stream())
-        _check(st, allow=(STK_ENOTCONV,) if allow_notconv else ())
+        _check(st, allow=((STK_ENOTCONV,) if allow_notconv else ()) + tuple(allow))
         out = dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
                    t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
         return xu, xp, out

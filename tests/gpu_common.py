@@ -32,8 +32,19 @@ CASES = {
     # the history tolerance, though the solutions still agree to 1e-8.
     "2d_6_L2": small(2, 6, 2, gamma=1e3, dr=1e6, n_sinkers=4, seed=441),
     "3d_6_L2": small(3, 6, 2, gamma=1e4, dr=1e4, n_sinkers=6, seed=451),
+    # three 3D levels with a middle level (a prolongation in and a restriction
+    # out, split centre solves): the 32^3 workload's parameters (24 sinkers,
+    # contrast 1e8, gamma 1e4) and the 48^3 workload's tensor law (contrast
+    # 1e10) on 16^3 / 8^3 / 4^3
+    "3d_16_L3": small(3, 16, 3, gamma=1e4, dr=1e8, n_sinkers=24, seed=301),
+    "3d_16_L3_tensor": small(3, 16, 3, gamma=1e4, dr=1e10, n_sinkers=24, seed=401, coef_kind=1, fourier_seed=402),
+    # 3D 4^3 fine level: one tile of coarse cells, too few fine cells for the
+    # split centre solves, so the transfers take the in-workgroup path
+    "3d_4_L2": small(3, 4, 2, gamma=1e3, dr=1e4, n_sinkers=4, seed=461),
 }
 SCALAR_CASES = ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2"]
+# the slow oracle cases (about a minute of oracle setup and solve each)
+BIG_CASES = ["3d_16_L3", "3d_16_L3_tensor"]
 P2_CASES = ["2d_16_L3_p2", "3d_8_L2_p2"]
 
 

@@ -85,3 +85,27 @@ def test_tensor_and_mixed_descriptors():
     bad.mixed = 2
     with pytest.raises(stk.StkError):
         stk.stk_footprint(bad)
+
+
+def test_descriptor_fields_of_the_boundary():
+    """qpts_1d accepts the default (0) and the 3-point rule only; the
+    viscoplastic floor and strain-rate scale must be finite."""
+    from paper_2107_00820_amd import stk
+    for q, ok in ((0, True), (3, True), (2, False), (4, False)):
+        d = stk.desc_from_workload(CONFIGS["sinker_2d_16sq_L2"])
+        d.qpts_1d = q
+        if ok:
+            assert stk.stk_footprint(d) > 0
+        else:
+            with pytest.raises(stk.StkError) as e:
+                stk.stk_footprint(d)
+            assert e.value.status == stk.STK_EINVAL and b"qpts_1d" in stk.load().stk_last_error()
+    d = stk.desc_from_workload(CONFIGS["viscoplastic_3d_48cu_L3"])
+    assert stk.stk_footprint(d) > 0
+    d.vp.mu_floor = float("nan")
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(d)
+    d = stk.desc_from_workload(CONFIGS["viscoplastic_3d_48cu_L3"])
+    d.vp.eps_scale = float("inf")
+    with pytest.raises(stk.StkError):
+        stk.stk_footprint(d)

@@ -1,14 +1,21 @@
 """GPU parity: every operation of the hot path through the C ABI against the
 CPU FP64 oracle on the same seeded inputs.
 
-Tolerances: operator applications (A_gamma, K) 1e-12 relative; patch solves
-(star smoother, local transfer solves, coarse solve) 50 kappa eps64 with
-kappa the largest condition number of the patch (or coarse) matrices, at
-least 1e-12; compositions (relaxation, V-cycle, preconditioner), which chain
-several such solves and small least-squares problems, 50 kappa eps64, at
-least 1e-10; solves: identical iteration count and solutions within 1e-8
-relative.
+Tolerances: operator applications (A_gamma, K) 1e-12 relative. Patch
+solves are only defined to kappa eps: the star smoother is checked entry by
+entry against the sum, over the patches containing the entry, of the
+per-patch forward-error bound 50 kappa_i eps64 ||A_i^{-1}||_2 ||r_i||_2 (kappa_i
+and ||A_i^{-1}|| from the SVD of every patch matrix), and the transfers
+likewise per coarse cell (their local solves), plus 32 eps64 times the
+absolute values of the other terms; on the 2D 16^2 workload, whose patches
+have kappa <= 1.4e3, both must also hold to 1e-12 relative. Coarse solve:
+2 kappa eps64. Compositions (relaxation, V- and F-cycle, preconditioner),
+which chain several such solves and small least-squares problems:
+50 kappa eps64 with kappa the largest patch condition number, at least
+1e-10. Solves: identical iteration count and solutions within 1e-8 relative.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -17,17 +24,35 @@ from gpu_common import CASES, oracle_for, gpu_for, to_dev, to_host, rel, rand_u,
 pytestmark = pytest.mark.gpu
 
 NAMES = list(CASES)
+EPS = np.finfo(float).eps
+STRICT = "sinker_2d_16sq_L2"
 
 
-def cond_bound(orc, l):
-    """Largest condition number of the star patch matrices of level l (oracle)."""
-    import scipy.linalg as sla
+@functools.lru_cache(maxsize=None)
+def patch_svd(name, l, which):
+    """(index arrays, kappa_i, ||A_i^{-1}||_2) of the star patches (which =
+    "star") or the coarse-cell blocks of the transfer into level l ("cell")."""
     from oracle.multigrid import extract_dense
+    orc = oracle_for(name)
     A = orc.mg.ops[l].Agamma
-    worst = 1.0
-    for idx in orc.mg.smoothers[l].patches[::7]:
-        worst = max(worst, np.linalg.cond(extract_dense(A, idx)))
-    return worst
+    blocks = orc.mg.smoothers[l].patches if which == "star" else orc.mg.transfers[l].blocks
+    kap, ninv = [], []
+    for idx in blocks:
+        sv = np.linalg.svd(extract_dense(A, idx), compute_uv=False)
+        kap.append(sv[0] / sv[-1])
+        ninv.append(1.0 / sv[-1])
+    return blocks, np.array(kap), np.array(ninv)
+
+
+def local_bound(name, l, which, r, kappa=True):
+    """Entrywise sum over the blocks containing each unknown of 50 kappa_i
+    eps ||A_i^{-1}|| ||r_i|| (the forward error of a solve with A_i), or
+    without kappa_i (the effect of an error r in the right-hand side)."""
+    blocks, kap, ninv = patch_svd(name, l, which)
+    out = np.zeros_like(r)
+    for idx, k, ni in zip(blocks, kap, ninv):
+        out[idx] += 50.0 * (k if kappa else 1.0) * EPS * ni * np.linalg.norm(r[idx])
+    return out
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -71,10 +96,12 @@ def test_star_asm_all_levels(name):
         r, rs = rand_u(lv, 20 + l)
         y = lv.from_stored(to_host(gpu.stk_asm(l, to_dev(rs))))
         ref = orc.mg.smoothers[l].apply(r)
-        tol = max(1e-12, 50 * cond_bound(orc, l) * np.finfo(float).eps)
-        err = rel(y, ref)
-        log(f"  level {l}: rel err {err:.2e} (tol {tol:.1e})")
-        assert err <= tol
+        bnd = local_bound(name, l, "star", r)
+        worst = np.max(np.abs(y - ref) / bnd)
+        log(f"  level {l}: rel err {rel(y, ref):.2e}, largest error / per-patch bound {worst:.2e}")
+        assert np.all(np.abs(y - ref) <= bnd)
+        if name == STRICT:
+            assert rel(y, ref) <= 1e-12
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -84,15 +111,31 @@ def test_robust_transfers(name):
     for l in range(1, CASES[name].levels):
         fine, coarse = orc.mg.hier[l], orc.mg.hier[l - 1]
         T = orc.mg.transfers[l]
-        tol = max(1e-12, 50 * cond_bound(orc, l) * np.finfo(float).eps)
+        absP, absG = abs(T.P), abs(T.G)
         xc, xcs = rand_u(coarse, 30 + l)
         xf = fine.from_stored(to_host(gpu.stk_prolong(l - 1, to_dev(xcs))))
-        e1 = rel(xf, T.prolong(xc))
+        t = T.P @ xc
+        g = T.G @ t
+        corr = T.local_correction(g)
+        ref = t - corr
+        # local solves of each coarse cell, the rounding of G P xc seen
+        # through them, and the rounding of P xc and of the difference
+        bnd = (local_bound(name, l, "cell", g) + local_bound(name, l, "cell", absG @ (absP @ np.abs(xc)), False)
+               + 32 * EPS * (absP @ np.abs(xc) + np.abs(corr)))
+        e1 = np.max(np.abs(xf - ref) / bnd)
+        assert np.all(np.abs(xf - ref) <= bnd), e1
         rf, rfs = rand_u(fine, 40 + l)
         rc = coarse.from_stored(to_host(gpu.stk_restrict(l, to_dev(rfs))))
-        e2 = rel(rc, T.restrict(rf))
-        log(f"  level {l}: prolong {e1:.2e} restrict {e2:.2e} (tol {tol:.1e})")
-        assert e1 <= tol and e2 <= tol
+        s_loc = T.local_correction(rf, trans=1)
+        ref_c = T.P.T @ (rf - T.GT @ s_loc)
+        ds = local_bound(name, l, "cell", rf)
+        bnd_c = abs(T.P.T) @ (absG.T @ ds) + 32 * EPS * (abs(T.P.T) @ (np.abs(rf) + absG.T @ np.abs(s_loc)))
+        e2 = np.max(np.abs(rc - ref_c) / bnd_c)
+        log(f"  level {l}: prolong rel {rel(xf, ref):.2e} ({e1:.2e} of bound), "
+            f"restrict rel {rel(rc, ref_c):.2e} ({e2:.2e} of bound)")
+        assert np.all(np.abs(rc - ref_c) <= bnd_c), e2
+        if name == STRICT:
+            assert rel(xf, ref) <= 1e-12 and rel(rc, ref_c) <= 1e-12
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -123,7 +166,7 @@ def test_relaxation_vcycle_precond(name):
     lv = orc.mg.hier[lf]
     b, bs = rand_u(lv, 60)
     x0, x0s = rand_u(lv, 61)
-    tol = max(1e-10, 50 * cond_bound(orc, lf) * np.finfo(float).eps)
+    tol = max(1e-10, 50 * patch_svd(name, lf, "star")[1].max() * EPS)
     log(f"  composition tolerance {tol:.1e}")
     x = to_dev(x0s)
     gpu.stk_smooth(lf, to_dev(bs), x, 3)
@@ -135,21 +178,31 @@ def test_relaxation_vcycle_precond(name):
     e = rel(v, orc.mg.vcycle(b))
     log(f"  vcycle {e:.2e}")
     assert e <= tol
+    v = lv.from_stored(to_host(gpu.stk_fcycle(to_dev(bs))))
+    e = rel(v, orc.mg.fcycle(b))
+    log(f"  fcycle {e:.2e}")
+    assert e <= tol
     p = np.random.default_rng(62).standard_normal(lv.n_p)
-    zu, zp = gpu.stk_precond(to_dev(bs), to_dev(p))
-    ref = orc.pc.apply(np.concatenate([b, p]))
-    e1 = rel(lv.from_stored(to_host(zu)), ref[:lv.n_u])
-    e2 = rel(to_host(zp), ref[lv.n_u:])
-    log(f"  precond u {e1:.2e} p {e2:.2e}")
-    assert e1 <= tol and e2 <= tol
-    # block upper-triangular variant
-    from oracle.krylov import BlockPreconditioner
-    zu, zp = gpu.stk_precond(to_dev(bs), to_dev(p), pc="upper")
-    ref = BlockPreconditioner(orc.mg, "upper").apply(np.concatenate([b, p]))
-    e1 = rel(lv.from_stored(to_host(zu)), ref[:lv.n_u])
-    e2 = rel(to_host(zp), ref[lv.n_u:])
-    log(f"  upper precond u {e1:.2e} p {e2:.2e}")
-    assert e1 <= tol and e2 <= tol
+    ops = orc.ops
+    for pc, cycle in (("full", "V"), ("upper", "V"), ("full", "F")):
+        zu, zp = gpu.stk_precond(to_dev(bs), to_dev(p), pc=pc, cycle=cycle)
+        # the oracle's eq. (precond) step by step; z_u = y - w (full) ends in
+        # a difference of two cycles, so its error is measured against the
+        # size of the two terms
+        ahat = orc.mg.vcycle if cycle == "V" else orc.mg.fcycle
+        if pc == "full":
+            y = ahat(b)
+            zp_ref = ops.project_mean(-(ops.Shat_inv @ (p - ops.B @ y)))
+            w = ahat(ops.B.T @ zp_ref)
+            zu_ref, scale = y - w, np.linalg.norm(y) + np.linalg.norm(w)
+        else:
+            zp_ref = ops.project_mean(-(ops.Shat_inv @ p))
+            zu_ref = ahat(b - ops.B.T @ zp_ref)
+            scale = np.linalg.norm(zu_ref)
+        e1 = np.linalg.norm(lv.from_stored(to_host(zu)) - zu_ref) / scale
+        e2 = rel(to_host(zp), zp_ref)
+        log(f"  precond {pc} {cycle}: u {e1:.2e} (of |y| + |w|) p {e2:.2e}")
+        assert e1 <= tol and e2 <= tol
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -190,17 +243,20 @@ def test_solve_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2", "3d_8_L2_tensor"])
-def test_solve_upper_matches_oracle(name):
-    """FGMRES with the block upper-triangular preconditioner: same iteration
-    count as the oracle's, solution within 1e-8, true residual checked with
-    the oracle's operator."""
-    log(f"[solve upper] {name}")
+@pytest.mark.parametrize("cycle", ["V", "F"])
+def test_solve_variants_match_oracle(name, cycle):
+    """FGMRES with the block upper-triangular preconditioner (V-cycle) or
+    with the full preconditioner on F-cycles: same iteration count as the
+    oracle's, solution within 1e-8, true residual checked with the oracle's
+    operator."""
+    pc = "upper" if cycle == "V" else "full"
+    log(f"[solve {pc} {cycle}] {name}")
     orc, gpu = oracle_for(name), gpu_for(name)
     wl = CASES[name]
     lv = orc.mg.hier[-1]
-    x_o, info_o = orc.solve(pc="upper")
+    x_o, info_o = orc.solve(pc=pc, cycle=cycle)
     bu, bp = gpu.stk_rhs()
-    xu, xp, info = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, pc="upper")
+    xu, xp, info = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, pc=pc, cycle=cycle)
     log(f"  iterations gpu {info['iters']} oracle {info_o['iters']}")
     assert info["converged"] and info["iters"] == info_o["iters"]
     x = np.concatenate([lv.from_stored(to_host(xu)), to_host(xp)])

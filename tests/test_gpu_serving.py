@@ -63,3 +63,41 @@ def test_admission_respects_budget():
     big = [(0.0, small(3, 32, 3, gamma=1e4, dr=1e4, n_sinkers=24, seed=9))]
     out = Server(hbm_budget=budget, max_active=4).run(big)
     assert out["completed"] == 0 and out["results"][0].error
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("cross", ["1", "0"])
+def test_same_shape_requests_step_together_and_equal_alone(dim, cross, monkeypatch):
+    """Same-shape requests started together step in lockstep with batched
+    star-patch solve launches (STK_CROSS_BATCH=1, the default) or each on
+    its own (0); either way every solution and iteration count is
+    bit-identical to the request solved alone."""
+    import torch
+    from paper_2107_00820_amd import Hierarchy, stk_step_batch
+    monkeypatch.setenv("STK_CROSS_BATCH", cross)
+    n, L, g = (32, 2, 1e3) if dim == 2 else (8, 2, 1e4)
+    wls = [small(dim, n, L, gamma=g, dr=dr, n_sinkers=24, seed=2 * 10 ** 6 + k)
+           for k, dr in enumerate((1e4, 1e6, 1e8, 1e5, 1e7))]
+    log(f"[cohort] {len(wls)} x {dim}D {n} L{L}, STK_CROSS_BATCH={cross}")
+    hs = [Hierarchy.from_workload(w) for w in wls]
+    outs = []
+    for h in hs:
+        bu, bp = h.stk_rhs()
+        outs.append(h.stk_solve_begin(bu, bp, eager=True))
+    infos = [None] * len(hs)
+    for _ in range(100000):
+        if all(i is not None for i in infos):
+            break
+        stk_step_batch([h for h, i in zip(hs, infos) if i is None])
+        for k, h in enumerate(hs):
+            if infos[k] is None:
+                infos[k] = h.stk_poll()
+    assert all(i is not None and i["converged"] for i in infos)
+    for k, (h, w) in enumerate(zip(hs, wls)):
+        bu, bp = h.stk_rhs()
+        xu, xp, info = h.stk_solve(bu, bp, eager=True)
+        torch.cuda.synchronize()
+        assert info["iters"] == infos[k]["iters"]
+        assert np.array_equal(xu.cpu().numpy(), outs[k][0].cpu().numpy())
+        assert np.array_equal(xp.cpu().numpy(), outs[k][1].cpu().numpy())
+        h.close()

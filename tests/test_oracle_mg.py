@@ -164,3 +164,48 @@ def test_vcycle_gamma_robust_iterations():
             its[(robust, gamma)] = info["iters"]
     assert max(its[(True, g)] for g in (1.0, 1e2, 1e4)) <= its[(True, 1.0)] + 6
     assert its[(False, 1e4)] >= 2 * its[(True, 1e4)]
+
+
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+def test_fcycle_two_level_without_relaxation(dim, n):
+    """With no relaxation (nu = 0) the two-level F-cycle is two steps of the
+    coarse-grid-correction iteration x <- x + M (b - A x) from x = 0, with
+    M = P~ A_0^{-1} P~^T: the coarse solve of the restricted b, prolongated,
+    then one V-cycle from that start. Ignoring the start (a V-cycle from
+    zero) would give one step, M b."""
+    mg = Multigrid(dim, n, 2, sinker(dim, 1e2, seed=3), 50.0, nu_pre=0, nu_post=0)
+    A = mg.ops[1].Agamma
+    b = np.random.default_rng(1).standard_normal(A.shape[0])
+
+    def M(r):
+        return mg.prolong(1, mg.coarse_lu.solve(mg.restrict(1, r)))
+
+    x1 = M(b)
+    x2 = x1 + M(b - A @ x1)
+    f = mg.fcycle(b)
+    assert np.linalg.norm(f - x2) <= 1e-10 * np.linalg.norm(x2)
+    assert np.linalg.norm(f - x1) > 1e-3 * np.linalg.norm(x2)
+
+
+def test_fcycle_with_exact_relaxation_is_exact():
+    """GMRES relaxation with as many steps as unknowns solves the level
+    exactly, so the F-cycle (like the V-cycle) returns A_gamma^{-1} b."""
+    mg = Multigrid(2, 2, 2, sinker(2, 1e2, seed=4), 10.0, nu_pre=18, nu_post=18)
+    A = mg.ops[1].Agamma
+    b = np.random.default_rng(2).standard_normal(A.shape[0])
+    x = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(mg.fcycle(b) - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_fcycle_three_levels_preconditions_like_the_v_cycle():
+    """On three levels the F-cycle is a better approximate inverse than the
+    V-cycle it ends with: FGMRES on A_gamma needs at most as many iterations
+    (the coarse levels see a V-cycle of their own before the finest one)."""
+    from oracle.krylov import fgmres
+    mg = Multigrid(2, 16, 3, sinker(2, 1e4, seed=5), 1e3, nu_pre=2, nu_post=2)
+    A = mg.ops[-1].Agamma
+    b = mg.ops[-1].rhs()
+    _, iv = fgmres(lambda v: A @ v, mg.vcycle, b, rtol=1e-8, restart=30, maxit=60)
+    _, jf = fgmres(lambda v: A @ v, mg.fcycle, b, rtol=1e-8, restart=30, maxit=60)
+    assert iv["converged"] and jf["converged"]
+    assert jf["iters"] <= iv["iters"]

@@ -46,6 +46,8 @@ class Workload:
     fourier_seed: Optional[int] = None   # seed of the Fourier velocity (coef_kind 1)
     fourier_modes: int = 8               # modes per axis (coef_kind 1)
     schur: int = 1        # W in A_gamma: 1 = M_p (preconditioner P1), 2 = M_p(1/mu) (P2)
+    mu_floor: float = 0.0  # floor of the capped viscoplastic law (coef_kind 1); 0 selects mu_min
+    cycle: str = "V"       # multigrid cycle of the block preconditioner: "V" or "F"
 
     @property
     def mu_max(self) -> float:
@@ -94,6 +96,28 @@ CONFIGS = {
     "viscoplastic_3d_48cu_L3": Workload("viscoplastic_3d_48cu_L3", 3, 48, 3, 24, 1e10, 1e4, 401,
                    coef_kind=1, fourier_seed=402),
 }
+
+
+# Settings of the paper's two tables of Q2 iteration counts, run with its
+# solver options: preconditioner P2 (W = M_p(1/mu)), 5 pre- and 5
+# post-relaxation steps, F-cycles, FGMRES(30) to a 1e6 residual reduction.
+# Sinker centres are seeded here (the paper's are not published), so the
+# comparison with the printed counts is qualitative.
+PAPER_VANKA_AL = {   # table "vanka", AL column: 2D 128^2, 4 levels, gamma 100
+    (ns, dr): Workload(f"vanka_al_{ns}s_dr{dr:g}", 2, 128, 4, ns, dr, 100.0, 600 + ns, nu_pre=5, nu_post=5,
+                       rtol=1e-6, schur=2, cycle="F")
+    for ns in (1, 6, 24) for dr in (1e4, 1e6, 1e8, 1e10)}
+PAPER_VANKA_AL_PRINTED = {(1, 1e4): 4, (1, 1e6): 6, (1, 1e8): 8, (1, 1e10): 9,
+                          (6, 1e4): 10, (6, 1e6): 14, (6, 1e8): 16, (6, 1e10): 16,
+                          (24, 1e4): 9, (24, 1e6): 15, (24, 1e8): 20, (24, 1e10): 25}
+# table "k", k = 2 column (robust smoother and transfer): 3D 30^3, 2 levels,
+# contrast 1e6; the paper's sinker count for this table is not stated: 24
+PAPER_K2 = {g: Workload(f"k2_30cu_g{g:g}", 3, 30, 2, 24, 1e6, g, 700, nu_pre=5, nu_post=5, rtol=1e-6,
+                        schur=2, cycle="F") for g in (0.0, 10.0, 1000.0)}
+PAPER_K2_PRINTED = {0.0: 95, 10.0: 28, 1000.0: 27}
+# the same settings on a 12^3 mesh (2 levels), where the oracle solves in minutes
+PAPER_K2_SMALL = {g: Workload(f"k2_12cu_g{g:g}", 3, 12, 2, 24, 1e6, g, 700, nu_pre=5, nu_post=5, rtol=1e-6,
+                              schur=2, cycle="F") for g in (0.0, 10.0, 1000.0)}
 
 
 def small(dim: int, n_fine: int, levels: int, *, n_sinkers: int = 4, dr: float = 1e2,
