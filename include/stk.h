@@ -160,6 +160,18 @@ stk_status stk_apply_stokes(stk_hier* h, const double* x_u, const double* x_p,
  * vertex-star additive Schwarz operator on `level` >= 1 (Section 4.1). */
 stk_status stk_asm(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream);
 
+/* stk_asm for callers that cannot allocate device memory around the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, same kernels and bit-identical results, but
+ * the patch outputs between the batched patch solves and the node sums go
+ * to a fixed 64 MiB device array of the library instead of the hierarchy's
+ * own buffer, and the call allocates nothing. Each GPU holds its own array
+ * until the process ends; calls on one GPU share it, so calls that overlap
+ * on one GPU (any hierarchies, any streams) race. A level whose patch outputs
+ * (d 3^d values of the dtype per vertex) exceed 64 MiB is rejected with
+ * STK_EINVAL before anything is launched; STK_EBUSY during a resumable solve. */
+stk_status stk_asm_noalloc(stk_hier* h, int level, int dtype, const void* r, void* y, void* stream);
+
 /* x <- nsteps of GMRES relaxation on A_gamma x = b on `level` >= 1, right-
  * preconditioned by D^{-1}, starting from the x passed in (zero allowed). */
 stk_status stk_smooth(stk_hier* h, int level, int dtype, const void* b, void* x, int nsteps,

@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
         "stk_apply_Agamma": [vp, i32, i32, vp, vp, vp],
         "stk_apply_stokes": [vp, vp, vp, vp, vp, vp],
         "stk_asm": [vp, i32, i32, vp, vp, vp],
+        "stk_asm_noalloc": [vp, i32, i32, vp, vp, vp],
         "stk_smooth": [vp, i32, i32, vp, vp, i32, vp],
         "stk_prolong": [vp, i32, i32, vp, vp, vp],
         "stk_restrict": [vp, i32, i32, vp, vp, vp],
@@ -257,6 +258,13 @@ class Hierarchy:
     def stk_asm(self, level, r, y=None):
         y = self.zeros_u(level, r.dtype) if y is None else y
         _check(load().stk_asm(self._h, level, *_dptr(r, y), _stream()))
+        return y
+
+    def stk_asm_noalloc(self, level, r, y=None):
+        """stk_asm with the patch outputs in the library's fixed device array
+        (the call allocates nothing; y must be preallocated for that)."""
+        y = self.zeros_u(level, r.dtype) if y is None else y
+        _check(load().stk_asm_noalloc(self._h, level, *_dptr(r, y), _stream()))
         return y
 
     def stk_smooth(self, level, b, x, nsteps):
