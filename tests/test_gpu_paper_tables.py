@@ -1,0 +1,68 @@
+"""The paper's Q2 iteration tables, run on the GPU with the paper's solver
+options (preconditioner P2, 5 + 5 relaxation steps, F-cycles, FGMRES(30) to a
+1e6 residual reduction):
+
+* table "vanka", AL column (2D 128^2, 4 levels, gamma 100, 1/6/24 sinkers,
+  contrast 1e4..1e10): the GPU count must equal the oracle's
+  (tests/golden/paper_tables_oracle.json, written by make_paper_tables.py
+  from the oracle alone); the paper's printed count is logged beside them
+  (the sinker positions differ, so that comparison is qualitative);
+* table "k", k = 2 (3D, 2 levels, contrast 1e6, gamma 0/10/1000): GPU =
+  oracle on a 12^3 mesh, and the GPU count on the paper's 30^3 mesh logged
+  beside the printed one, with the gamma-robustness the table shows (counts
+  at gamma 10 and 1000 well below the count at gamma 0).
+"""
+import json
+import os
+
+import pytest
+
+from gpu_common import log
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_tables_oracle.json")
+
+
+def gpu_count(wl):
+    from paper_2107_00820_amd import Hierarchy
+    h = Hierarchy.from_workload(wl)
+    bu, bp = h.stk_rhs()
+    _, _, info = h.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, cycle=wl.cycle,
+                             allow_notconv=True)
+    h.close()
+    return info
+
+
+def test_table_vanka_al_column():
+    from workloads import PAPER_VANKA_AL, PAPER_VANKA_AL_PRINTED
+    orc = json.load(open(GOLDEN))
+    for key, wl in PAPER_VANKA_AL.items():
+        info = gpu_count(wl)
+        o = orc[wl.name]
+        log(f"[vanka] {key[0]:2d} sinkers, DR {key[1]:.0e}: GPU {info['iters']}, oracle {o['iters']}, "
+            f"paper {PAPER_VANKA_AL_PRINTED[key]}")
+        assert info["converged"] and o["converged"]
+        assert info["iters"] == o["iters"]
+
+
+def test_table_k_quadratic_column():
+    from workloads import PAPER_K2, PAPER_K2_SMALL, PAPER_K2_PRINTED
+    orc = json.load(open(GOLDEN))
+    for g, wl in PAPER_K2_SMALL.items():
+        info = gpu_count(wl)
+        o = orc[wl.name]
+        log(f"[k=2, 12^3] gamma {g:g}: GPU {info['iters']}, oracle {o['iters']}")
+        assert info["converged"] == o["converged"]
+        assert info["iters"] == o["iters"]
+    its = {}
+    for g, wl in PAPER_K2.items():
+        info = gpu_count(wl)
+        its[g] = info["iters"]
+        log(f"[k=2, 30^3] gamma {g:g}: GPU {info['iters']} (converged {info['converged']}), "
+            f"paper {PAPER_K2_PRINTED[g]}")
+        # without augmentation (gamma = 0) the count may reach maxit, as it
+        # does on the 12^3 mesh; with it the solver must converge
+        if g > 0:
+            assert info["converged"]
+    assert its[10.0] < its[0.0] / 2 and its[1000.0] < its[0.0] / 2

