@@ -103,7 +103,10 @@ typedef struct {
                          1 = P1: W = M_p, Shat^{-1} = M_p(1/mu)^{-1} + gamma M_p^{-1};
                          2 = P2: W = M_p(1/mu), Shat^{-1} = (1 + gamma) M_p(1/mu)^{-1}.
                          The augmented system has the Stokes solution for either W. */
-  int coef_kind;      /* 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor */
+  int coef_kind;      /* 0 = scalar sinker viscosity; 1 = viscoplastic Newton
+                         tensor at the Fourier velocity of `vp`; 2 = the same law
+                         at an FE velocity state (the Newton loop below; state
+                         u = 0 after setup, vp.amp unused, schur must be 1) */
   stk_sinker sinker;  /* the viscosity (coef_kind 0) or the base field mu0 (1); forcing in both */
   stk_viscoplastic vp;  /* read for coef_kind 1 only */
   int nu_pre, nu_post;   /* right-preconditioned GMRES relaxation steps, 1..8 */
@@ -346,6 +349,66 @@ stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant);
 stk_status stk_profile(stk_hier* h, int enable);
 stk_status stk_profile_read(stk_hier* h, int kernel, int64_t* launches, double* total_ms,
                             double* total_bytes);
+
+/* ---- Viscoplastic Newton loop (Section 5.3, the root of the algorithm
+ * outline; hierarchy set up with coef_kind 2) ----
+ * The nonlinear problem: find (u, p) with
+ *   F_u = a(u; u) + gamma B^T W^{-1} B u + B^T p - b = 0,  F_p = B u = 0,
+ *   a(w; v) = (2 mu_eff(eps_II(w)) eps(w), eps(v)),
+ *   mu_eff  = mu_floor + min(mu0 - mu_floor, tau_y / (2 eps_II)),
+ * mu0 the multi-sinker field, b = (f, phi_i) (stk_rhs). The augmented term
+ * vanishes where B u = 0, so the solutions are those of the viscoplastic
+ * Stokes problem. Its Jacobian at u_k is the augmented Stokes operator with
+ * the fourth-order viscosity C = d tau / d eps at eps(u_k) (the law of
+ * stk_viscoplastic), so every Newton step is one stk_solve on the hierarchy
+ * relinearised at u_k. Readings: standard Newton (the paper's
+ * stress-velocity variant differs in the tensor's rank-one term and needs an
+ * update formula from another reference); coarse levels linearised at the
+ * velocity injected to their nodes; x_0 = 0.
+ *
+ * stk_relinearize: coefficients (mu_eff, w) at the Gauss points of every
+ * level from the FE velocity x_u of the finest level (stored layout;
+ * injected to the coarser levels), then the star-patch inverses, the coarse
+ * inverse and the Schur blocks rebuilt from them. Host-synchronous;
+ * STK_ENOTSPD as for setup.
+ * stk_nl_residual: (r_u, r_p) = (F_u, F_p) at (x_u, x_p) (stored layout,
+ * Dirichlet entries 0; r_u must not alias x_u).
+ * stk_newton: x = 0; until ||F|| <= rtol ||F(0)||: relinearise at x, solve
+ * J d = -F with stk_solve (lin_rtol, restart, lin_maxit, pc, cycle, eager),
+ * backtrack x + alpha d, alpha = 1, 1/2, .. until ||F|| <= (1 - 1e-4 alpha)
+ * times the current norm (at most max_halvings halvings, the last trial is
+ * taken regardless). Writes the last iterate to (x_u, x_p) and fills info;
+ * STK_ENOTCONV after maxit steps, STK_ENAN for a non-finite residual.
+ * Host-synchronous. */
+#define STK_NEWTON_MAXIT 64
+typedef struct {
+  double rtol;        /* nonlinear residual reduction (default 1e-8) */
+  int maxit;          /* Newton steps (default 30, at most STK_NEWTON_MAXIT) */
+  double lin_rtol;    /* relative residual of each linear solve (default 1e-6) */
+  int lin_maxit;      /* FGMRES iterations per step (default 300) */
+  int restart;        /* FGMRES restart (default 30) */
+  int max_halvings;   /* line-search halvings (default 10) */
+  int pc;             /* as stk_solve_opts.pc */
+  int cycle;          /* as stk_solve_opts.cycle */
+  int eager;          /* as stk_solve_opts.eager */
+} stk_newton_opts;
+
+typedef struct {
+  int iters;                            /* Newton steps taken */
+  int converged;
+  double rel_res;                       /* ||F(x)|| / ||F(0)|| at exit */
+  double res0;                          /* ||F(0)|| */
+  double t_s;                           /* wall time */
+  double hist[STK_NEWTON_MAXIT + 1];    /* ||F|| / ||F(0)|| after each step */
+  double alpha[STK_NEWTON_MAXIT];       /* accepted step length of each step */
+  int lin_iters[STK_NEWTON_MAXIT];      /* FGMRES iterations of each step */
+} stk_newton_info;
+
+stk_status stk_relinearize(stk_hier* h, const double* x_u, void* stream);
+stk_status stk_nl_residual(stk_hier* h, const double* x_u, const double* x_p, double* r_u, double* r_p,
+                           void* stream);
+stk_status stk_newton(stk_hier* h, double* x_u, double* x_p, const stk_newton_opts* opts, stk_newton_info* info,
+                      void* stream);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* stk_last_error(void);

@@ -125,6 +125,29 @@ def second_invariant(eps: np.ndarray) -> np.ndarray:
     return np.sqrt(0.5 * np.sum(eps * eps, axis=(-1, -2)))
 
 
+def capped_law(eps: np.ndarray, mu0: np.ndarray, tau_y: float, mu_f: float):
+    """The capped viscoplastic law at strain rates eps[..., d, d] over base
+    viscosities mu0[...]: (mu_eff, C) with
+        mu_eff = mu_f + min(mu0 - mu_f, tau_y / (2 eps_II)),
+        C = 2 mu_eff I_sym - 2 (mu_eff - mu_f) [yielded] n (x) n,  n = eps/|eps|_F,
+    the derivative of tau(eps) = 2 mu_eff(eps_II) eps (yielded: the cap is
+    below mu0 - mu_f; eps = 0 never yields)."""
+    eii = second_invariant(eps)
+    with np.errstate(divide="ignore"):
+        cap = np.where(eii > 0, tau_y / (2.0 * np.where(eii > 0, eii, 1.0)), np.inf)
+    yielded = cap < (mu0 - mu_f)
+    mu_eff = mu_f + np.minimum(mu0 - mu_f, cap)
+    d = eps.shape[-1]
+    eye = np.eye(d)
+    ident = 0.5 * (np.einsum("ac,bd->abcd", eye, eye) + np.einsum("ad,bc->abcd", eye, eye))
+    nrm = np.sqrt(np.sum(eps * eps, axis=(-1, -2)))
+    n = eps / np.where(nrm > 0, nrm, 1.0)[..., None, None]
+    C = 2.0 * mu_eff[..., None, None, None, None] * ident
+    coef = 2.0 * (mu_eff - mu_f) * yielded
+    C = C - coef[..., None, None, None, None] * np.einsum("...ab,...cd->...abcd", n, n)
+    return mu_eff, C
+
+
 class ViscoplasticNewton:
     """Newton tensor of tau(eps) = 2 mu_eff(eps_II) eps for the capped law."""
 
@@ -142,41 +165,27 @@ class ViscoplasticNewton:
         vel = FourierVelocity(wl.fourier_amplitudes(), 1.0)
         eii = second_invariant(vel.strain_rate(fine_quad_points))
         vel.scale = 1.0 / np.sqrt(np.mean(eii ** 2))
-        return cls(base, vel, 2.0 * wl.mu_max, getattr(wl, "mu_floor", 0.0))
+        tau_y = getattr(wl, "tau_y", 0.0)
+        return cls(base, vel, tau_y if tau_y > 0 else 2.0 * wl.mu_max, getattr(wl, "mu_floor", 0.0))
 
-    def _state(self, x):
-        eps = self.vel.strain_rate(x)
-        eii = second_invariant(eps)
-        mu0 = self.base.mu(x)
+    def yielded(self, x):
+        """Where the cap is active (tau_y / (2 eps_II) < mu0 - mu_f)."""
+        eii = second_invariant(self.vel.strain_rate(x))
         with np.errstate(divide="ignore"):
             cap = np.where(eii > 0, self.tau_y / (2.0 * np.where(eii > 0, eii, 1.0)), np.inf)
-        yielded = cap < (mu0 - self.mu_min)
-        mu_eff = self.mu_min + np.minimum(mu0 - self.mu_min, cap)
-        return eps, eii, mu_eff, yielded
+        return cap < self.base.mu(x) - self.mu_min
 
     def mu_eff(self, x):
-        return self._state(x)[2]
+        return capped_law(self.vel.strain_rate(x), self.base.mu(x), self.tau_y, self.mu_min)[0]
 
     def scalar_viscosity(self, x):
         """The scalar in front of the tensor, used for M_p(1/mu) (Section 5.3.2)."""
         return self.mu_eff(x)
 
     def stress_tensor(self, x):
-        eps, eii, mu_eff, yielded = self._state(x)
-        d = self.dim
-        eye = np.eye(d)
-        ident = 0.5 * (np.einsum("ac,bd->abcd", eye, eye) + np.einsum("ad,bc->abcd", eye, eye))
-        nrm = np.sqrt(np.sum(eps * eps, axis=(-1, -2)))
-        n = eps / np.where(nrm > 0, nrm, 1.0)[..., None, None]
-        C = 2.0 * mu_eff[..., None, None, None, None] * ident
-        coef = 2.0 * (mu_eff - self.mu_min) * yielded
-        C = C - coef[..., None, None, None, None] * np.einsum("...ab,...cd->...abcd", n, n)
-        return C
+        return capped_law(self.vel.strain_rate(x), self.base.mu(x), self.tau_y, self.mu_min)[1]
 
     def stress(self, eps: np.ndarray, x: np.ndarray) -> np.ndarray:
         """tau(eps) = 2 mu_eff(eps_II) eps at positions x (for derivative checks)."""
-        eii = second_invariant(eps)
-        mu0 = self.base.mu(x)
-        cap = self.tau_y / (2.0 * eii)
-        mu_eff = self.mu_min + np.minimum(mu0 - self.mu_min, cap)
+        mu_eff = capped_law(eps, self.base.mu(x), self.tau_y, self.mu_min)[0]
         return 2.0 * mu_eff[..., None, None] * eps

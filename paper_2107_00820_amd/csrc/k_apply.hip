@@ -156,6 +156,50 @@ __device__ inline void gauss_point(const LevelGeo& g, int64_t cell, int q, doubl
   for (int k = 0; k < D; ++k) x[k] = g.h * ((double)c[k] + kGaussX[digit(q, k)]);
 }
 
+// The capped viscoplastic law at a physical strain rate e: returns
+//   mu_eff = mu_f + min(mu0 - mu_f, tau_y / (2 eps_II)),  eps_II = (e:e/2)^(1/2),
+// and sets w = (2 (mu_eff - mu_f) [yielded])^(1/2) e / |e|_F in symmetric
+// storage, so that the derivative of tau(e) = 2 mu_eff(eps_II) e is
+// C:x = 2 mu_eff x - (w:x) w (yielded: the cap below mu0 - mu_f; e = 0
+// never yields).
+template <int D>
+__device__ inline double capped_law(const double (&e)[D][D], double mu0, double tau_y, double mu_f,
+                                    double (&w)[SymIdx<D>::NS]) {
+  double ee = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) ee += e[a][b] * e[a][b];
+  const double eii = sqrt(0.5 * ee);
+  const double cap = eii > 0.0 ? tau_y / (2.0 * eii) : INFINITY;
+  const bool yielded = cap < mu0 - mu_f;
+  const double meff = mu_f + fmin(mu0 - mu_f, cap);
+  const double nrm = sqrt(ee);
+  const double ws = (yielded && nrm > 0.0) ? sqrt(2.0 * (meff - mu_f)) / nrm : 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) w[SymIdx<D>::at(a, b)] = ws * e[a][b];
+  return meff;
+}
+
+// The effective viscosity of the capped law alone (no tensor), for a
+// strain rate given as a reference gradient G (physical: sym G / h).
+template <int D, class R>
+__device__ inline R capped_mu_ref(const R (&G)[D][D], R h, double mu0, double tau_y, double mu_f) {
+  double ee = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double e = 0.5 * ((double)G[a][b] + (double)G[b][a]) / (double)h;
+      ee += e * e;
+    }
+  const double eii = sqrt(0.5 * ee);
+  const double cap = eii > 0.0 ? tau_y / (2.0 * eii) : INFINITY;
+  return (R)(mu_f + fmin(mu0 - mu_f, cap));
+}
+
 // eps:eps of the unscaled strain rate (eps = sym G).
 template <int D>
 __device__ inline double strain_sq(const double G[D][D]) {
@@ -223,23 +267,77 @@ k_coef_tensor(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, 
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int b = 0; b < D; ++b) eps[a][b] = 0.5 * sc * (G[a][b] + G[b][a]);
-  double ee = 0.0;
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = 0; b < D; ++b) ee += eps[a][b] * eps[a][b];
-  const double eii = sqrt(0.5 * ee);
   const double mu0 = (mu_max - mu_min) * (1.0 - sinker_chi<D>(ctr, ns, omega, delta, x)) + mu_min;
-  const double cap = eii > 0.0 ? tau_y / (2.0 * eii) : INFINITY;
-  const bool yielded = cap < mu0 - mu_floor;
-  const double meff = mu_floor + fmin(mu0 - mu_floor, cap);
-  const double nrm = sqrt(ee);
-  const double wscale = (yielded && nrm > 0.0) ? sqrt(2.0 * (meff - mu_floor)) / nrm : 0.0;
-  mu[idx] = meff;
+  double wv[NS];
+  mu[idx] = capped_law<D>(eps, mu0, tau_y, mu_floor, wv);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) cw[(cell * NS + k) * NQ + q] = wv[k];
+}
+
+// mu_eff and w at the Gauss points of one level from an FE velocity u of
+// that level (stored layout): eps(u) = sym grad u from the cell's 3^d nodal
+// values, mu0 from the sinker field (the state of a Newton linearisation).
+template <int D>
+__global__ void __launch_bounds__(kCoefThreads)
+k_coef_fe(LevelGeo g, const double* __restrict__ u, const double* __restrict__ ctr, int ns, double omega,
+          double delta, double mu_min, double mu_max, double mu_floor, double tau_y, double* __restrict__ mu,
+          double* __restrict__ cw) {
+  constexpr int NQ = Dims<D>::NQ, NN = Dims<D>::NN, NS = SymIdx<D>::NS;
+  constexpr const RefTab<D>& T = Ref<D>::T;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)NQ * g.ncell) return;
+  const int64_t cell = idx / NQ;
+  const int q = (int)(idx - cell * NQ);
+  int c[3];
+  cell_coords<D>(g, cell, c);
+  double G[D][D];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int b = a; b < D; ++b) cw[(cell * NS + SymIdx<D>::at(a, b)) * NQ + q] = wscale * eps[a][b];
+    for (int b = 0; b < D; ++b) G[a][b] = 0.0;
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    const int a0 = 2 * c[0] + digit(n, 0), a1 = 2 * c[1] + digit(n, 1), a2 = D == 3 ? 2 * c[2] + digit(n, 2) : 0;
+    bool bnd = a0 == 0 || a0 == 2 * g.N || a1 == 0 || a1 == 2 * g.N;
+    if (D == 3) bnd = bnd || a2 == 0 || a2 == 2 * g.N;
+    const int64_t nd = node_index<D>(g, a0, a1, a2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double ua = bnd ? 0.0 : u[a * g.nnodes + nd];
+#pragma unroll
+      for (int b = 0; b < D; ++b) G[a][b] += ua * T.dphi[q][n][b];
+    }
+  }
+  double eps[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) eps[a][b] = 0.5 * (G[a][b] + G[b][a]) / g.h;
+  double x[D];
+  gauss_point<D>(g, cell, q, x);
+  const double mu0 = (mu_max - mu_min) * (1.0 - sinker_chi<D>(ctr, ns, omega, delta, x)) + mu_min;
+  double wv[NS];
+  mu[idx] = capped_law<D>(eps, mu0, tau_y, mu_floor, wv);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) cw[(cell * NS + k) * NQ + q] = wv[k];
+}
+
+// Injection of a fine stored velocity to the next coarser level: coarse
+// node i is fine node 2i (nested Q2 spaces); Dirichlet entries 0.
+template <int D>
+__global__ void k_inject(LevelGeo gf, LevelGeo gc, const double* __restrict__ uf, double* __restrict__ uc) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)D * gc.nnodes) return;
+  const int comp = (int)(idx / gc.nnodes);
+  const int64_t nd = idx - (int64_t)comp * gc.nnodes;
+  int i[3];
+  i[0] = (int)(nd % gc.n1);
+  i[1] = (int)((nd / gc.n1) % gc.n1);
+  i[2] = D == 3 ? (int)(nd / ((int64_t)gc.n1 * gc.n1)) : 0;
+  bool bnd = false;
+#pragma unroll
+  for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * gc.N;
+  uc[idx] = bnd ? 0.0 : uf[comp * gf.nnodes + node_index<D>(gf, 2 * i[0], 2 * i[1], 2 * i[2])];
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +381,7 @@ template <int D, int MODE, bool TENSOR, class R, bool ZS = false>
 __global__ void __launch_bounds__(64)
 k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* __restrict__ winv, double gamma_d,
        const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout,
-       int nvert = 0, R* __restrict__ zout = nullptr) {
+       int nvert = 0, R* __restrict__ zout = nullptr, double nl_tau = 0.0, double nl_floor = 0.0) {
   constexpr int NN = Dims<D>::NN, NQ = NN, NL = Dims<D>::NL, NP = Dims<D>::NP;
   constexpr int NS = SymIdx<D>::NS;
   constexpr int CPW = 64 / NQ;
@@ -398,6 +496,7 @@ k_elem(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* 
       }
     }
     if (MODE & EL_VISC) {
+      if constexpr ((MODE & EL_NL) != 0) muq = capped_mu_ref<D, R>(G, h, (double)muq, nl_tau, nl_floor);
       const R wm = wq * muq;
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -541,7 +640,8 @@ __device__ constexpr int i3(int a, int b, int c) { return a + 3 * b + 9 * c; }
 template <int MODE, bool TENSOR, class R>
 __global__ void __launch_bounds__(64)
 k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R* __restrict__ winv, double gamma_d,
-        const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout) {
+        const R* __restrict__ u, const double* __restrict__ p, R* __restrict__ E, double* __restrict__ pout,
+        double nl_tau = 0.0, double nl_floor = 0.0) {
   constexpr int NQ = 27, NL = 81, NP = 4, NS = 6;
   constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
   constexpr bool need_c = (MODE & (EL_AUG | EL_BT | EL_BOUT)) != 0;
@@ -646,7 +746,9 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
 #pragma unroll
     for (int k = 0; k < NS; ++k) S[qz][k] = (R)0;
     if ((MODE & EL_VISC) && valid) {
-      const R wm = wq * mu[cell * NQ + q];
+      R muq = mu[cell * NQ + q];
+      if constexpr ((MODE & EL_NL) != 0) muq = capped_mu_ref<3, R>(G[qz], (R)g.h, (double)muq, nl_tau, nl_floor);
+      const R wm = wq * muq;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -1203,6 +1305,49 @@ void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_eps_partials<3>, dim3(np), dim3(kCoefThreads), 0, s, fine.g, H.vp_amp, H.vp_modes,
                        H.partials);
+}
+
+void launch_mu_sinker_to(const Hier& H, const Level& l, double* out, hipStream_t s) {
+  const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_mu_sinker<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
+                       H.delta, H.mu_min, H.mu_max, out);
+  else
+    hipLaunchKernelGGL(k_mu_sinker<3>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
+                       H.delta, H.mu_min, H.mu_max, out);
+}
+
+void launch_coef_fe(const Hier& H, const Level& l, const double* u, hipStream_t s) {
+  const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
+  if (H.dim == 2)
+    hipLaunchKernelGGL(k_coef_fe<2>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, u, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_floor, H.vp_tau_y, l.mu, l.cw);
+  else
+    hipLaunchKernelGGL(k_coef_fe<3>, dim3(nblk(n, kCoefThreads)), dim3(kCoefThreads), 0, s, l.g, u, H.centers,
+                       H.n_sinkers, H.omega, H.delta, H.mu_min, H.mu_max, H.vp_floor, H.vp_tau_y, l.mu, l.cw);
+}
+
+void launch_inject(const Hier& H, const Level& fine, const Level& coarse, const double* uf, double* uc,
+                   hipStream_t s) {
+  const int64_t n = (int64_t)H.dim * coarse.g.nnodes;
+  if (H.dim == 2) hipLaunchKernelGGL(k_inject<2>, dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, uf, uc);
+  else hipLaunchKernelGGL(k_inject<3>, dim3(nblk(n, 256)), dim3(256), 0, s, fine.g, coarse.g, uf, uc);
+}
+
+void launch_nl_elem(const Hier& H, const Level& l, const double* u, const double* p, double* pout, hipStream_t s) {
+  constexpr int MODE = EL_NL | EL_VISC | EL_AUG | EL_BT | EL_BOUT;
+  const double* wi = level_winv<double>(l);
+  double* E = l.E;
+  if (H.dim == 3) {
+    hipLaunchKernelGGL((k_elem3<MODE, false, double>), dim3(nblk(l.g.ncell, kE3Cells)), dim3(64), 0, s, l.g,
+                       (const double*)H.mu0, (const double*)nullptr, wi, H.gamma, u, p, E, pout, H.vp_tau_y,
+                       H.vp_floor);
+  } else {
+    constexpr int CPW = 64 / Dims<2>::NQ;
+    hipLaunchKernelGGL((k_elem<2, MODE, false, double>), dim3(nblk(l.g.ncell, CPW)), dim3(64), 0, s, l.g,
+                       (const double*)H.mu0, (const double*)nullptr, wi, H.gamma, u, p, E, pout, 0, (double*)nullptr,
+                       H.vp_tau_y, H.vp_floor);
+  }
 }
 
 void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStream_t s) {

@@ -69,8 +69,15 @@ stk_status validate(const stk_desc* d) {
   if (n0 > 80000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve (80000 unknowns)");
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
   if (d->schur != 1 && d->schur != 2) return fail(STK_EINVAL, "schur must be 1 (W = M_p) or 2 (W = M_p(1/mu))");
-  if (d->coef_kind != 0 && d->coef_kind != 1)
-    return fail(STK_EINVAL, "coef_kind must be 0 (sinker viscosity) or 1 (viscoplastic Newton tensor)");
+  if (d->coef_kind < 0 || d->coef_kind > 2)
+    return fail(STK_EINVAL, "coef_kind must be 0 (sinker viscosity), 1 (viscoplastic Newton tensor at the "
+                            "Fourier velocity) or 2 (viscoplastic law at an FE velocity state)");
+  if (d->coef_kind == 2) {
+    const stk_viscoplastic& v = d->vp;
+    if (!(v.tau_y > 0.0) || !isfinite(v.tau_y)) return fail(STK_EINVAL, "vp.tau_y must be positive");
+    if (!isfinite(v.mu_floor)) return fail(STK_EINVAL, "vp.mu_floor must be finite");
+    if (d->schur != 1) return fail(STK_EINVAL, "the Newton state (coef_kind 2) needs W = M_p (schur = 1)");
+  }
   if (d->qpts_1d != 0 && d->qpts_1d != 3)
     return fail(STK_EINVAL, "qpts_1d must be 0 or 3 (the 3-point Gauss rule is the one built)");
   if (d->coef_kind == 1) {
@@ -167,7 +174,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
       STKCHK(alloc((size_t)NP * NP * L.g.ncell * 8, (void**)&L.winv));
       if (d->mixed) STKCHK(alloc((size_t)NP * NP * L.g.ncell * 4, (void**)&L.winv32));
     }
-    if (d->coef_kind == 1) {
+    if (d->coef_kind >= 1) {
       const int NS = D * (D + 1) / 2;
       STKCHK(alloc((size_t)NS * NN * L.g.ncell * 8, (void**)&L.cw));
       if (d->mixed) STKCHK(alloc((size_t)NS * NN * L.g.ncell * 4, (void**)&L.cw32));
@@ -228,6 +235,14 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   if (d->mixed) {
     STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.mb));
     STKCHK(alloc((size_t)Lf.nvel * 8, (void**)&H.mx));
+  }
+  if (d->coef_kind == 2) {
+    STKCHK(alloc((size_t)NN * Lf.g.ncell * 8, (void**)&H.mu0));
+    STKCHK(alloc((size_t)nvec * 8, (void**)&H.nl_b));
+    STKCHK(alloc((size_t)nvec * 8, (void**)&H.nl_F));
+    STKCHK(alloc((size_t)nvec * 8, (void**)&H.nl_d));
+    STKCHK(alloc((size_t)nvec * 8, (void**)&H.nl_x));
+    STKCHK(alloc((size_t)nvec * 8, (void**)&H.nl_t));
   }
   (void)build_classes;
   return STK_OK;
@@ -602,6 +617,42 @@ stk_status device_norm(Hier& H, const double* x, int64_t n, double* out) {
   return STK_OK;
 }
 
+// Everything the coefficients at the Gauss points determine: the W = M_p(1/mu)
+// blocks (P2), the star-patch inverses of levels >= 1, the FP32 copies (mixed
+// form), the coarse inverse and the Schur blocks; host-synchronous, with the
+// factorisations' pivot check (STK_ENOTSPD).
+stk_status build_operators(Hier& H, hipStream_t s) {
+  const int D = H.dim;
+  launch_fill_int(H.flag, 0, 16, s);
+  for (int l = 0; l < H.L; ++l) {
+    Level& L = H.lv[l];
+    if (L.winv) launch_winv_setup(H, L, s);
+    if (l >= 1)
+      for (PatchClass& pc : L.cls) launch_patch_setup(H, L, pc, s);
+  }
+  if (H.mixed) {
+    // FP32 copies for the mixed form, rounded from the FP64 factors
+    for (int l = 0; l < H.L; ++l) {
+      Level& L = H.lv[l];
+      launch_convert<double, float>(L.mu, L.mu32, (int64_t)(D == 2 ? 9 : 27) * L.g.ncell, s);
+      if (L.cw)
+        launch_convert<double, float>(L.cw, L.cw32, (int64_t)(D * (D + 1) / 2) * (D == 2 ? 9 : 27) * L.g.ncell, s);
+      if (L.winv) launch_convert<double, float>(L.winv, L.winv32, (int64_t)(D + 1) * (D + 1) * L.g.ncell, s);
+      for (PatchClass& pc : L.cls)
+        launch_convert<double, float>(pc.inv, pc.inv32, packed_doubles(pc.n, pc.count), s);
+    }
+  }
+  launch_coarse_assemble(H, H.lv[0], H.Ainv0, s);
+  launch_coarse_invert(H, H.Ainv0, H.n0, H.cwork, s);
+  launch_schur_setup(H, H.lv[H.L - 1], s);
+  if (hipGetLastError() != hipSuccess) return fail(STK_EDEVICE, "kernel launch failed while building the operators");
+  int flag = 0;
+  if (hipMemcpyAsync(&flag, H.flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(STK_EDEVICE, "synchronisation failed while building the operators");
+  if (flag) return fail(STK_ENOTSPD, "non-positive pivot in a patch or coarse factorisation");
+  return STK_OK;
+}
+
 }  // namespace
 
 namespace stk {
@@ -675,6 +726,10 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   H.mu_max = desc->sinker.mu_max;
   H.beta = desc->sinker.beta;
   H.coef_kind = desc->coef_kind;
+  if (H.coef_kind == 2) {
+    H.vp_tau_y = desc->vp.tau_y;
+    H.vp_floor = desc->vp.mu_floor > 0.0 ? desc->vp.mu_floor : desc->sinker.mu_min;
+  }
   if (H.coef_kind == 1) {
     H.vp_modes = desc->vp.modes;
     H.vp_tau_y = desc->vp.tau_y;
@@ -722,9 +777,13 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
   if (H.coef_kind == 1 && !(H.vp_scale > 0.0)) launch_eps_partials(H, H.lv[H.L - 1], s);
   for (int l = 0; l < H.L; ++l) {
     Level& L = H.lv[l];
-    if (H.coef_kind == 1) launch_coef_tensor(H, L, H.lv[H.L - 1], s);
-    else launch_mu_sinker(H, L, s);
-    if (L.winv) launch_winv_setup(H, L, s);
+    if (H.coef_kind == 1) {
+      launch_coef_tensor(H, L, H.lv[H.L - 1], s);
+    } else {
+      // coef_kind 2 starts from the state u = 0: nothing yields, C = 2 mu0 I
+      launch_mu_sinker(H, L, s);
+      if (L.cw) launch_fill<double>(L.cw, 0.0, (int64_t)(D * (D + 1) / 2) * (D == 2 ? 9 : 27) * L.g.ncell, s);
+    }
     launch_fill<double>(L.S, 0.0, L.nvel, s);
     if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
     launch_fill<double>(L.x, 0.0, L.nvel, s);
@@ -736,31 +795,12 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
           return bail(fail(STK_EDEVICE, "copy of patch vertex lists failed"));
         // the host vector must outlive the copy
         if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(STK_EDEVICE, "sync failed"));
-        launch_patch_setup(H, L, L.cls[c], s);
       }
     }
   }
-  if (H.mixed) {
-    // FP32 copies for the mixed form, rounded from the FP64 factors
-    for (int l = 0; l < H.L; ++l) {
-      Level& L = H.lv[l];
-      launch_convert<double, float>(L.mu, L.mu32, (int64_t)(D == 2 ? 9 : 27) * L.g.ncell, s);
-      if (L.cw)
-        launch_convert<double, float>(L.cw, L.cw32, (int64_t)(D * (D + 1) / 2) * (D == 2 ? 9 : 27) * L.g.ncell, s);
-      if (L.winv) launch_convert<double, float>(L.winv, L.winv32, (int64_t)(D + 1) * (D + 1) * L.g.ncell, s);
-      for (PatchClass& pc : L.cls)
-        launch_convert<double, float>(pc.inv, pc.inv32, packed_doubles(pc.n, pc.count), s);
-    }
-  }
-  launch_coarse_assemble(H, H.lv[0], H.Ainv0, s);
-  launch_coarse_invert(H, H.Ainv0, H.n0, H.cwork, s);
-  launch_schur_setup(H, H.lv[H.L - 1], s);
-  if (hipGetLastError() != hipSuccess) return bail(fail(STK_EDEVICE, "kernel launch failed during setup"));
-  int flag = 0;
-  if (hipMemcpyAsync(&flag, H.flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return bail(fail(STK_EDEVICE, "setup synchronisation failed"));
-  if (flag) return bail(fail(STK_ENOTSPD, "non-positive pivot in a patch or coarse factorisation"));
+  if (H.mu0) launch_mu_sinker_to(H, H.lv[H.L - 1], H.mu0, s);
+  const stk_status st2 = build_operators(H, s);
+  if (st2 != STK_OK) return bail(st2);
   *out = h;
   return STK_OK;
 }
@@ -1480,6 +1520,138 @@ stk_status stk_poll(stk_hier* h, stk_solve_info* info) {
   if (ph != Hier::SV_DONE) return STK_EBUSY;
   sv_info(H, info);
   return sv_final(H);
+}
+
+}  // extern "C"
+
+// =========================================================================== viscoplastic Newton
+namespace {
+
+// F = (F_u, F_p) of the viscoplastic problem at (u, p): F_u = a(u; u) +
+// gamma B^T W^{-1} B u + B^T p - b, F_p = B u; b the velocity right-hand side.
+void nl_residual(Hier& H, const double* u, const double* p, const double* b, double* Fu, double* Fp) {
+  Level& F = H.lv[H.L - 1];
+  launch_nl_elem(H, F, u, p, Fp, H.stream);
+  launch_gather<double>(H, F, b, -1.0, Fu, H.stream);                 // b - a(u; u) - ...
+  launch_axpby<double>(-1.0, Fu, 0.0, Fu, Fu, F.nvel, H.stream);
+}
+
+// Coefficients of the linearisation at the fine velocity u on every level
+// (coarser levels take the velocity injected to their nodes), then every
+// operator built from them.
+stk_status relinearize(Hier& H, const double* u) {
+  hipStream_t s = H.stream;
+  const double* ul = u;
+  for (int l = H.L - 1; l >= 0; --l) {
+    Level& L = H.lv[l];
+    launch_coef_fe(H, L, ul, s);
+    if (l > 0) {
+      launch_inject(H, L, H.lv[l - 1], ul, H.lv[l - 1].T, s);
+      ul = H.lv[l - 1].T;
+    }
+  }
+  return build_operators(H, s);
+}
+
+stk_status newton_check(const Hier& H) {
+  if (H.coef_kind != 2) return fail(STK_EINVAL, "the hierarchy holds no viscoplastic state (set up with coef_kind 2)");
+  return STK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stk_status stk_relinearize(stk_hier* h, const double* x_u, void* stream) {
+  GET_H_IDLE(h);
+  STKCHK(newton_check(H));
+  if (!x_u) return fail(STK_EINVAL, "x_u is NULL");
+  return relinearize(H, x_u);
+}
+
+stk_status stk_nl_residual(stk_hier* h, const double* x_u, const double* x_p, double* r_u, double* r_p,
+                           void* stream) {
+  GET_H_IDLE(h);
+  STKCHK(newton_check(H));
+  if (!x_u || !x_p || !r_u || !r_p || x_u == r_u) return fail(STK_EINVAL, "bad buffers");
+  Level& F = H.lv[H.L - 1];
+  launch_rhs_elem(H, F, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, H.nl_b, H.stream);
+  nl_residual(H, x_u, x_p, H.nl_b, r_u, r_p);
+  HIPCHK(hipGetLastError());
+  return STK_OK;
+}
+
+stk_status stk_newton(stk_hier* h, double* x_u, double* x_p, const stk_newton_opts* opts, stk_newton_info* info,
+                      void* stream) {
+  GET_H_IDLE(h);
+  STKCHK(newton_check(H));
+  if (!x_u || !x_p) return fail(STK_EINVAL, "NULL buffer");
+  stk_newton_opts o{1e-8, 30, 1e-6, 300, 30, 10, 0, 0, 0};
+  if (opts) o = *opts;
+  if (!(o.rtol > 0.0) || o.maxit < 1 || o.maxit > STK_NEWTON_MAXIT || !(o.lin_rtol > 0.0) || o.lin_maxit < 1 ||
+      o.max_halvings < 0 || o.max_halvings > 30 || o.restart < 1 || o.restart > 64)
+    return fail(STK_EINVAL, "bad Newton options");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t caller = H.stream;
+  Level& F = H.lv[H.L - 1];
+  const int64_t nu = F.nvel, np = F.npres, nvec = nu + np;
+  double *b = H.nl_b, *R = H.nl_F, *d = H.nl_d, *x = H.nl_x, *t = H.nl_t;
+  if (info) memset(info, 0, sizeof(*info));
+  // right-hand side, x = 0, F(x), ||F||
+  launch_rhs_elem(H, F, H.stream);
+  launch_gather<double>(H, F, nullptr, 1.0, b, H.stream);
+  launch_fill<double>(x, 0.0, nvec, H.stream);
+  nl_residual(H, x, x + nu, b, R, R + nu);
+  double fn = 0.0;
+  STKCHK(device_norm(H, R, nvec, &fn));
+  if (!isfinite(fn)) return fail(STK_ENAN, "non-finite nonlinear residual");
+  const double f0 = fn;
+  stk_solve_opts so{o.lin_rtol, o.restart, o.lin_maxit, o.eager, 0, o.pc, o.cycle};
+  int k = 0;
+  bool converged = f0 == 0.0;
+  if (info) info->hist[0] = 1.0;
+  stk_status st = STK_OK;
+  while (!converged && k < o.maxit) {
+    STKCHK(relinearize(H, x));
+    // Newton step: J d = -F
+    launch_axpby<double>(-1.0, R, 0.0, R, t, nvec, H.stream);
+    stk_solve_info li;
+    const stk_status ls = stk_solve(h, t, t + nu, d, d + nu, &so, &li, caller);
+    H.stream = caller;
+    if (ls != STK_OK && ls != STK_ENOTCONV) return ls;
+    // backtracking on the residual norm
+    double alpha = 1.0, ft = 0.0;
+    for (int hv = 0; hv <= o.max_halvings; ++hv) {
+      launch_axpby<double>(1.0, x, alpha, d, t, nvec, H.stream);
+      nl_residual(H, t, t + nu, b, R, R + nu);
+      STKCHK(device_norm(H, R, nvec, &ft));
+      if (!isfinite(ft)) return fail(STK_ENAN, "non-finite nonlinear residual");
+      if (ft <= (1.0 - 1e-4 * alpha) * fn || hv == o.max_halvings) break;
+      alpha *= 0.5;
+    }
+    launch_copy(t, x, nvec, H.stream);
+    fn = ft;
+    if (info) {
+      info->lin_iters[k] = li.iters;
+      info->alpha[k] = alpha;
+      info->hist[k + 1] = fn / f0;
+    }
+    ++k;
+    converged = fn <= o.rtol * f0;
+  }
+  HIPCHK(hipMemcpyAsync(x_u, x, nu * 8, hipMemcpyDeviceToDevice, H.stream));
+  HIPCHK(hipMemcpyAsync(x_p, x + nu, np * 8, hipMemcpyDeviceToDevice, H.stream));
+  HIPCHK(hipStreamSynchronize(H.stream));
+  if (info) {
+    info->iters = k;
+    info->converged = converged ? 1 : 0;
+    info->rel_res = f0 > 0.0 ? fn / f0 : 0.0;
+    info->res0 = f0;
+    info->t_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!converged) st = fail(STK_ENOTCONV, "Newton reached maxit");
+  return st;
 }
 
 }  // extern "C"

@@ -24,7 +24,9 @@ enum : int {
   EL_VISC = 1,   // viscous term (2 mu eps(u), eps(v))
   EL_AUG = 2,    // augmented term gamma (Pi div u, div v)
   EL_BT = 4,     // B^T p from the pressure input
-  EL_BOUT = 8    // write (B u) to the pressure output
+  EL_BOUT = 8,   // write (B u) to the pressure output
+  EL_NL = 16     // viscous term of the capped viscoplastic law at the input's own strain rate
+                 // (mu_eff from the base viscosity table; nonlinear residual)
 };
 
 // One class of vertex-star patches with the same number of unknowns.
@@ -155,6 +157,11 @@ struct Hier {
   // reached a patch-solve call (bev); the batched launch is done (cev, used
   // when this hierarchy leads a batch)
   hipEvent_t bev = nullptr, cev = nullptr;
+  // viscoplastic Newton (coef_kind 2): base viscosity mu0 at the finest
+  // level's Gauss points, and the Newton work vectors [u | p] (right-hand
+  // side, residual, step, trial iterate)
+  double* mu0 = nullptr;
+  double *nl_b = nullptr, *nl_F = nullptr, *nl_d = nullptr, *nl_x = nullptr, *nl_t = nullptr;
 };
 
 // Sets the thread-local message returned by stk_last_error().
@@ -167,6 +174,17 @@ void prof_end(Hier& H, hipStream_t s, int id, hipEvent_t a, double bytes, int re
 
 // ---- kernel launchers (templated on dimension inside the .hip files) ----
 void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s);
+// the sinker viscosity at the level's Gauss points into out ([ncell][3^d])
+void launch_mu_sinker_to(const Hier& H, const Level& l, double* out, hipStream_t s);
+// Viscoplastic state of a Newton linearisation: mu_eff and w on a level from
+// an FE velocity u of that level (stored layout).
+void launch_coef_fe(const Hier& H, const Level& l, const double* u, hipStream_t s);
+// uc = fine velocity at the coarse nodes (coarse node i = fine node 2i)
+void launch_inject(const Hier& H, const Level& fine, const Level& coarse, const double* uf, double* uc,
+                   hipStream_t s);
+// Cell kernel of the nonlinear residual on the finest level: element vectors
+// of a(u; v) + gamma (W^{-1} B u, B v) + (p, B v) into l.E and B u into pout.
+void launch_nl_elem(const Hier& H, const Level& l, const double* u, const double* p, double* pout, hipStream_t s);
 // Viscoplastic Newton tensor: partial sums of the unscaled eps_II^2 over the
 // finest level's Gauss points (into H.partials), then mu_eff and w per level.
 void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s);

@@ -57,6 +57,21 @@ class SolveOpts(C.Structure):
                 ("mixed", C.c_int), ("pc", C.c_int), ("cycle", C.c_int)]
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("lin_rtol", C.c_double), ("lin_maxit", C.c_int),
+                ("restart", C.c_int), ("max_halvings", C.c_int), ("pc", C.c_int), ("cycle", C.c_int),
+                ("eager", C.c_int)]
+
+
+STK_NEWTON_MAXIT = 64
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_res", C.c_double), ("res0", C.c_double),
+                ("t_s", C.c_double), ("hist", C.c_double * (STK_NEWTON_MAXIT + 1)),
+                ("alpha", C.c_double * STK_NEWTON_MAXIT), ("lin_iters", C.c_int * STK_NEWTON_MAXIT)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_res", C.c_double),
                 ("t_solve_s", C.c_double), ("hist", C.c_double * 1001)]
@@ -103,6 +118,9 @@ def load(path: str = LIB_PATH):
         "stk_profile_read": [vp, i32, i64p, dp, dp],
         "stk_autotune": [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_float), vp],
         "stk_set_asm_variant": [vp, i32, i32, i32],
+        "stk_relinearize": [vp, vp, vp],
+        "stk_nl_residual": [vp, vp, vp, vp, vp, vp],
+        "stk_newton": [vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -144,9 +162,10 @@ def _dptr(*ts):
 
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
               nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_eps_scale=0.0, schur=1,
-              vp_mu_floor=0.0, qpts_1d=0):
+              vp_mu_floor=0.0, qpts_1d=0, newton=False):
     """Descriptor; vp_amp (array [d][M]^d) selects the viscoplastic Newton
-    tensor over the sinker base field (coef_kind 1)."""
+    tensor over the sinker base field (coef_kind 1); newton=True the
+    viscoplastic state for the Newton loop (coef_kind 2, with vp_tau_y)."""
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
@@ -160,6 +179,9 @@ def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, 
         d.vp.amp = amp.ctypes.data_as(C.POINTER(C.c_double))
         d.vp.tau_y, d.vp.eps_scale, d.vp.mu_floor = float(vp_tau_y), float(vp_eps_scale), float(vp_mu_floor)
         d._keep_amp = amp
+    if newton:
+        d.coef_kind = 2
+        d.vp.tau_y, d.vp.mu_floor = float(vp_tau_y), float(vp_mu_floor)
     d.sinker.n = centers.shape[0]
     d.sinker.centers = centers.ctypes.data_as(C.POINTER(C.c_double))
     d.sinker.omega, d.sinker.delta, d.sinker.beta = omega, delta, beta
@@ -175,8 +197,12 @@ def desc_from_workload(wl, hbm_budget=0, mixed=0):
     stress is 2 mu_max and the velocity scale is left to the library (root
     mean square of eps_II over the finest Gauss points equal to 1)."""
     from workloads import OMEGA, DELTA, BETA
-    vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=2.0 * wl.mu_max,
-              vp_mu_floor=getattr(wl, "mu_floor", 0.0)) if wl.coef_kind == 1 else {}
+    vp = {}
+    if wl.coef_kind == 1:
+        vp = dict(vp_amp=wl.fourier_amplitudes(), vp_tau_y=wl.tau_y if wl.tau_y > 0 else 2.0 * wl.mu_max,
+                  vp_mu_floor=wl.mu_floor)
+    elif wl.coef_kind == 2:
+        vp = dict(newton=True, vp_tau_y=wl.tau_y, vp_mu_floor=wl.mu_floor)
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
                      OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, schur=getattr(wl, "schur", 1), **vp)
 
@@ -327,6 +353,30 @@ class Hierarchy:
         _check(st, allow=(STK_ENOTCONV, STK_ENAN))
         return dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
                     t_solve=info.t_solve_s, hist=list(info.hist[:info.iters + 1]), status=st)
+
+    # ---- viscoplastic Newton (hierarchies set up with coef_kind 2)
+    def stk_relinearize(self, xu):
+        _check(load().stk_relinearize(self._h, _ptr(xu), _stream()))
+
+    def stk_nl_residual(self, xu, xp, ru=None, rp=None):
+        ru = self.zeros_u() if ru is None else ru
+        rp = self.zeros_p() if rp is None else rp
+        _check(load().stk_nl_residual(self._h, _ptr(xu), _ptr(xp), _ptr(ru), _ptr(rp), _stream()))
+        return ru, rp
+
+    def stk_newton(self, rtol=1e-8, maxit=30, lin_rtol=1e-6, lin_maxit=300, restart=30, max_halvings=10,
+                   pc="full", cycle="V", eager=False, xu=None, xp=None, allow_notconv=False):
+        xu = self.zeros_u() if xu is None else xu
+        xp = self.zeros_p() if xp is None else xp
+        o = NewtonOpts(rtol, maxit, lin_rtol, lin_maxit, restart, max_halvings, _PC[pc], _CYCLE[cycle],
+                       1 if eager else 0)
+        info = NewtonInfo()
+        st = load().stk_newton(self._h, _ptr(xu), _ptr(xp), C.byref(o), C.byref(info), _stream())
+        _check(st, allow=(STK_ENOTCONV,) if allow_notconv else ())
+        k = info.iters
+        return xu, xp, dict(iters=k, converged=bool(info.converged), rel_res=info.rel_res, res0=info.res0,
+                            t_s=info.t_s, hist=list(info.hist[:k + 1]), alpha=list(info.alpha[:k]),
+                            lin_iters=list(info.lin_iters[:k]), status=st)
 
     def stk_autotune(self, reps: int = 5, with_times: bool = False):
         """Time the bit-identical patch-solve variants on every smoothed level

@@ -213,7 +213,7 @@ def test_newton_tensor_spd_and_scalar_limit():
     assert np.abs(Mm - np.swapaxes(Mm, 1, 2)).max() <= 1e-12 * np.abs(Mm).max()
     ev = np.linalg.eigvalsh(Mm)
     assert ev.min() >= 2 * law.mu_min - 1e-14 * ev.max()
-    _, _, mu_eff, yielded = law._state(x)
+    mu_eff, yielded = law.mu_eff(x), law.yielded(x)
     assert yielded.any() and (~yielded).any()
     # where nothing yields the tensor is 2 mu I
     iso = Mm[~yielded]

@@ -42,11 +42,13 @@ class Workload:
     restart: int = 30     # FGMRES restart length
     rtol: float = 1e-8    # relative residual target ||b - Kx|| <= rtol ||b||
     maxit: int = 300
-    coef_kind: int = 0    # 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor
+    coef_kind: int = 0    # 0 = scalar sinker viscosity, 1 = viscoplastic Newton tensor at the
+                          # Fourier velocity, 2 = viscoplastic problem solved by Newton's method
     fourier_seed: Optional[int] = None   # seed of the Fourier velocity (coef_kind 1)
     fourier_modes: int = 8               # modes per axis (coef_kind 1)
     schur: int = 1        # W in A_gamma: 1 = M_p (preconditioner P1), 2 = M_p(1/mu) (P2)
-    mu_floor: float = 0.0  # floor of the capped viscoplastic law (coef_kind 1); 0 selects mu_min
+    mu_floor: float = 0.0  # floor of the capped viscoplastic law (coef_kind 1, 2); 0 selects mu_min
+    tau_y: float = 0.0     # yield stress of the capped law; 0 selects 2 mu_max (coef_kind 1)
     cycle: str = "V"       # multigrid cycle of the block preconditioner: "V" or "F"
 
     @property
@@ -118,6 +120,17 @@ PAPER_K2_PRINTED = {0.0: 95, 10.0: 28, 1000.0: 27}
 # the same settings on a 12^3 mesh (2 levels), where the oracle solves in minutes
 PAPER_K2_SMALL = {g: Workload(f"k2_12cu_g{g:g}", 3, 12, 2, 24, 1e6, g, 700, nu_pre=5, nu_post=5, rtol=1e-6,
                               schur=2, cycle="F") for g in (0.0, 10.0, 1000.0)}
+
+
+# Viscoplastic Newton problems (capped law over a multi-sinker base field,
+# solved from rest): 8 sinkers, contrast 1e4; tau_y is about the 90th
+# percentile of 2 mu0 eps_II of the first (Newtonian) iterate, so roughly a
+# tenth of the domain yields at the start.
+NEWTON = {
+    "newton_2d_32sq_L3": Workload("newton_2d_32sq_L3", 2, 32, 3, 8, 1e4, 1e3, 503, coef_kind=2, tau_y=1.0),
+    "newton_3d_8cu_L2": Workload("newton_3d_8cu_L2", 3, 8, 2, 8, 1e4, 1e4, 504, coef_kind=2, tau_y=0.12),
+    "newton_3d_32cu_L3": Workload("newton_3d_32cu_L3", 3, 32, 3, 8, 1e4, 1e4, 504, coef_kind=2, tau_y=0.12),
+}
 
 
 def small(dim: int, n_fine: int, levels: int, *, n_sinkers: int = 4, dr: float = 1e2,
