@@ -10,8 +10,10 @@ a 24-sinker base field (contrast 1e10), gamma 1e4 (3,014,493 unknowns).
 FGMRES) is attempted too and reported under `forms` (converged or not, with
 the reason); so are the block upper-triangular variant and the F-cycle.
 Setup is timed separately. Also reported: the 2D 128^2 and 3D 32^3
-workloads (FP64, fewer steps) and, unless --no-serving, the serving stream
-(continuous batching, p50/p99 latency). Prints one JSON line.
+workloads (FP64, fewer steps), the viscoplastic Newton loop on 3D 32^3 and,
+unless --no-serving, the serving stream (continuous batching, p50/p99
+latency; also run once with the cross-request batched patch solves turned
+off). Prints one JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--form both|fp64|mixed]
                 [--no-cpu-baseline] [--serving N | --no-serving] [--no-extra] [--trace]
@@ -225,6 +227,29 @@ def serving_leg(n, budget_gb, pc="full"):
     return out
 
 
+def newton_leg(name):
+    """The viscoplastic problem solved by Newton's method on the GPU
+    (stk_newton: relinearise, FGMRES step, line search), timed whole."""
+    import torch
+    from workloads import NEWTON
+    from paper_2107_00820_amd import Hierarchy
+    from paper_2107_00820_amd.tune import load_asm_tuning
+    wl = NEWTON[name]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = Hierarchy.from_workload(wl)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    h.apply_asm_tuning(load_asm_tuning())
+    _, _, info = h.stk_newton(rtol=1e-8, maxit=30, lin_rtol=1e-6)
+    h.close()
+    n_u, n_p = wl.unknowns()
+    log(f"[bench] newton {name}: {info['iters']} steps, linear {info['lin_iters']}, {info['t_s']:.2f} s")
+    return {"workload": name, "unknowns": n_u + n_p, "steps": info["iters"], "converged": info["converged"],
+            "rel_res": info["rel_res"], "lin_iters": info["lin_iters"], "alpha": info["alpha"],
+            "t_s": info["t_s"], "setup_s": t_setup, "tau_y": wl.tau_y}
+
+
 MIXED_REASON = ("the FP32 V-cycle cannot represent A_gamma's near-kernel at gamma / mu_min = 1e4 / 1e-5: "
                 "rounding the patch inverses, transfers or applies to FP32 perturbs the divergence-free "
                 "components by eps32 gamma / mu_min >> 1")
@@ -342,8 +367,19 @@ def main():
                 continue
             log(f"[bench] {name}")
             out["other_workloads"][name] = other_workload(name, max(2, args.steps // 2))
+    if not args.no_extra:
+        out["newton"] = newton_leg("newton_3d_32cu_L3")
     if not args.no_serving and args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
+        # the same stream with the cross-request batched patch solves turned off
+        os.environ["STK_CROSS_BATCH"] = "0"
+        try:
+            nb = serving_leg(args.serving, args.budget_gb, args.serving_pc)
+        finally:
+            del os.environ["STK_CROSS_BATCH"]
+        out["serving"]["without_cross_batching"] = {k: nb[k] for k in (
+            "completed", "makespan_s", "dof_per_s", "latency_p50_ms", "latency_p99_ms", "solve_s_mean",
+            "queue_s_mean")}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(wl)
