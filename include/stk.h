@@ -310,7 +310,8 @@ stk_status stk_poll(stk_hier* h, stk_solve_info* info);
 
 /* Autotuning of the batched star-patch solve. The kernel exists in
  * STK_ASM_VARIANTS variants that differ only in how many packed inverse
- * elements a lane loads ahead (and so in registers and occupancy);
+ * elements a lane loads ahead (and so in registers and occupancy) and in
+ * the cache policy of those loads (non-temporal in variant 3);
  * all perform the same multiply-adds in the same order, so results are
  * bit-identical whichever is chosen (the choice never changes a solution).
  * stk_autotune times every variant on every smoothed level (levels 1..L-1)
@@ -329,7 +330,7 @@ stk_status stk_poll(stk_hier* h, stk_solve_info* info);
  * solve). STK_EBUSY while a resumable solve is in progress.
  * stk_set_asm_variant fixes the variant of one (level, dtype) by hand
  * (0 <= variant < STK_ASM_VARIANTS; level >= 1). Default: variant 0. */
-#define STK_ASM_VARIANTS 3
+#define STK_ASM_VARIANTS 4
 stk_status stk_autotune(stk_hier* h, int reps, int* variants, float* times_ms, void* stream);
 stk_status stk_set_asm_variant(stk_hier* h, int level, int dtype, int variant);
 

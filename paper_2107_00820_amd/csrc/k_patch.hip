@@ -81,13 +81,16 @@ using FullTri = TriPiece<0, NPT, 0, NPT>;
 // The elements of the piece stream in chunks of CH with the next chunk's
 // loads issued before the current chunk's arithmetic (scheduling barriers
 // keep the compiler from hoisting all loads at once, which would spill).
-template <class PC, int CH, int C, class R>
+// NT: non-temporal loads (the packed inverses are streamed once per
+// application and never reused within it).
+template <class PC, int CH, int C, bool NT, class R>
 __device__ __attribute__((always_inline)) inline void symv_chunk_load(const R* __restrict__ A, R (&buf)[CH]) {
   static_for<CH>([&](auto T) {
     constexpr int t = C * CH + T;
     if constexpr (t < PC::count()) {
       constexpr int e = PC::elem(t);   // folded at compile time
-      buf[T] = A[(int64_t)e * 64];
+      if constexpr (NT) buf[T] = __builtin_nontemporal_load(A + (int64_t)e * 64);
+      else buf[T] = A[(int64_t)e * 64];
     }
   });
 }
@@ -113,19 +116,19 @@ __device__ __attribute__((always_inline)) inline void symv_chunk_fma(const X& x,
 
 // y = (piece PC of A) x over the piece's result slots, counting each
 // off-diagonal element for both (i, j) and (j, i).
-template <int CH, class PC, class X, class R>
+template <int CH, class PC, bool NT = false, class X, class R>
 __device__ __attribute__((always_inline)) inline void piece_symv(const R* __restrict__ A, const X& xr,
                                                                  R (&y)[PC::ny]) {
   constexpr int NC = (PC::count() + CH - 1) / CH;
 #pragma unroll
   for (int i = 0; i < PC::ny; ++i) y[i] = (R)0;
   R b0[CH], b1[CH];
-  symv_chunk_load<PC, CH, 0>(A, b0);
+  symv_chunk_load<PC, CH, 0, NT>(A, b0);
   static_for<NC>([&](auto C) {
     constexpr int c = C;
     if constexpr (c + 1 < NC) {
-      if constexpr ((c & 1) == 0) symv_chunk_load<PC, CH, c + 1>(A, b1);
-      else symv_chunk_load<PC, CH, c + 1>(A, b0);
+      if constexpr ((c & 1) == 0) symv_chunk_load<PC, CH, c + 1, NT>(A, b1);
+      else symv_chunk_load<PC, CH, c + 1, NT>(A, b0);
     }
     __builtin_amdgcn_sched_barrier(0);
     if constexpr ((c & 1) == 0) symv_chunk_fma<PC, CH, c>(xr, b0, y);
@@ -135,10 +138,10 @@ __device__ __attribute__((always_inline)) inline void piece_symv(const R* __rest
 }
 
 // Whole packed triangle: y = A x.
-template <int NPT, int CH, class X, class R>
+template <int NPT, int CH, bool NT = false, class X, class R>
 __device__ __attribute__((always_inline)) inline void packed_symv_chunked(const R* __restrict__ A, const X& xr,
                                                                           R (&y)[NPT]) {
-  piece_symv<CH, FullTri<NPT>>(A, xr, y);
+  piece_symv<CH, FullTri<NPT>, NT>(A, xr, y);
 }
 
 #ifndef STK_CH_LDS64
@@ -166,10 +169,10 @@ using Q81_3 = TriPiece<40, 81, 40, 81>;  // slots: rows 40..80
 static_assert(Q81_0::count() + Q81_1::count() + Q81_2::count() + Q81_3::count() == 81 * 82 / 2, "pieces");
 static_assert(Q81_1::ny == 61 && Q81_2::ny == 61, "slots");
 
-template <class PC, int CH, class X, class R>
+template <class PC, int CH, bool NT = false, class X, class R>
 __device__ __attribute__((always_inline)) inline void piece_into(const R* __restrict__ A, const X& xr, R (&yc)[61]) {
   R y[PC::ny];
-  piece_symv<CH, PC>(A, xr, y);
+  piece_symv<CH, PC, NT>(A, xr, y);
   static_for<PC::ny>([&](auto I) { yc[I] = y[I]; });
 }
 
@@ -203,6 +206,46 @@ __device__ __attribute__((always_inline)) inline void split_symv81(const R* __re
   }
 }
 
+// split_symv81 with x[0..80) in the LDS tile (80 x 64, exactly a quarter of
+// the 160 KB LDS, so four workgroups fit on a compute unit) and x[80] in a
+// register of every lane. The partial results meet in the tile as in
+// split_symv81, row 80's two partials through tile rows 0 and 1 once the
+// first 40 rows are final, with the same additions in the same order:
+//   y[0,20) = y0 + y1,  y[20,40) = y0 + y2,  y[40,81) = (y1 + y2) + y3.
+template <int CHK, bool NT, class R, class Store>
+__device__ __attribute__((always_inline)) inline void split_symv81_t80(const R* __restrict__ A, R* xs, R x80,
+                                                                       int lane, int w, Store&& store) {
+  auto xr = [&](int j) { return j == 80 ? x80 : xs[j * 64 + lane]; };
+  R yc[61];
+  if (w == 0) piece_into<Q81_0, CHK, NT>(A, xr, yc);
+  else if (w == 1) piece_into<Q81_1, CHK, NT>(A, xr, yc);
+  else if (w == 2) piece_into<Q81_2, CHK, NT>(A, xr, yc);
+  else piece_into<Q81_3, CHK, NT>(A, xr, yc);
+  __syncthreads();   // every wavefront is done reading x
+  if (w == 1) {
+    static_for<20>([&](auto I) { xs[I * 64 + lane] = yc[I]; });
+    static_for<40>([&](auto I) { xs[(40 + I) * 64 + lane] = yc[20 + I]; });
+  } else if (w == 2) {
+    static_for<20>([&](auto I) { xs[(20 + I) * 64 + lane] = yc[I]; });
+  }
+  __syncthreads();
+  if (w == 0) {
+    static_for<40>([&](auto I) { store(I, yc[I] + xs[I * 64 + lane]); });
+  } else if (w == 2) {
+    static_for<40>([&](auto I) { xs[(40 + I) * 64 + lane] += yc[20 + I]; });
+  }
+  __syncthreads();   // rows 0..39 are free again
+  if (w == 1) xs[lane] = yc[60];
+  else if (w == 2) xs[64 + lane] = yc[60];
+  __syncthreads();
+  if (w == 3) {
+    static_for<40>([&](auto I) {
+      store(std::integral_constant<int, 40 + I>{}, xs[(40 + I) * 64 + lane] + yc[I]);
+    });
+    store(std::integral_constant<int, 80>{}, (xs[lane] + xs[64 + lane]) + yc[40]);
+  }
+}
+
 // x from registers (patches of up to 27 unknowns): double-buffered chunks,
 // NCH of them (0: four for up to 18 unknowns, chunks of 12 above)
 template <int NPT, int NCH = 0, class R>
@@ -216,15 +259,18 @@ __device__ __attribute__((always_inline)) inline void packed_symv(const R* __res
 
 // Tuning variants of the batched patch solve. They differ only in how many
 // packed elements a lane loads ahead (the chunk), which sets the registers a
-// lane holds and with them the occupancy; every variant performs the same multiply-adds in the
-// same order, so their results are bit-identical and a tuner may choose any
-// (kAsmVariants of them).
+// lane holds and with them the occupancy, and in the cache policy of those
+// loads (variant 3: variant 2's chunks with non-temporal loads); every
+// variant performs the same multiply-adds in the same order, so their results
+// are bit-identical and a tuner may choose any (kAsmVariants of them).
 template <int D, class R, int V>
 struct AsmTune {
   // 3D interior patches (81 unknowns, LDS-staged residual): elements per chunk
   static constexpr int ch81 = sizeof(R) == 8 ? (V == 0 ? 16 : (V == 1 ? 24 : 12)) : (V == 0 ? 32 : (V == 1 ? 48 : 24));
   // 2D interior patches (18 unknowns from registers): number of chunks
-  static constexpr int nch18 = V == 0 ? 4 : (V == 1 ? 6 : 8);
+  static constexpr int nch18 = V == 0 ? 4 : (V == 1 ? 6 : 8);   // variant 3: as variant 2
+  // non-temporal loads of the packed inverses (variant 3: otherwise variant 2)
+  static constexpr bool nt = V == 3;
   // minimum wavefronts per SIMD requested from the compiler
   static constexpr int min_waves = 2;
 };
@@ -281,7 +327,7 @@ __device__ __attribute__((always_inline)) inline void asm_patch(const LevelGeo& 
 // i = comp*27 + a + 3b + 9c sits at node 2v-1 + (a,b,c). Lanes past the
 // class count take part in the barriers with a clamped vertex and store
 // nothing (the inverse storage is padded to whole blocks of 64 patches).
-template <int CHK, class R>
+template <int CHK, bool NT, class R>
 __device__ __attribute__((always_inline)) inline void asm_patch81(const LevelGeo& g, const int* __restrict__ verts,
                                                                   int count, const R* __restrict__ inv,
                                                                   const R* __restrict__ r, R* __restrict__ zbuf,
@@ -296,16 +342,19 @@ __device__ __attribute__((always_inline)) inline void asm_patch81(const LevelGeo
   patch_box<3>(g, vert, lo, ext, vc);
   const int64_t base = node_index<3>(g, lo[0], lo[1], lo[2]);
   const int64_t n1 = g.n1;
-  static_for<NPT>([&](auto I) {
+  // rows 0..79 into the tile (round robin over the wavefronts), row 80
+  // (component 2, local node 26) into a register of every lane
+  static_for<NPT - 1>([&](auto I) {
     constexpr int i = I;
     constexpr int comp = i / NN, loc = i % NN;
     if (w == (i & 3))
       xs[i * 64 + lane] = r[comp * g.nnodes + base + digit(loc, 0) + n1 * (digit(loc, 1) + n1 * digit(loc, 2))];
   });
+  const R x80 = r[2 * g.nnodes + base + 2 + n1 * (2 + n1 * 2)];
   __syncthreads();
   const int64_t P = (int64_t)NPT * (NPT + 1) / 2;
   const R* A = inv + ((int64_t)blk * P) * 64 + lane;
-  split_symv81<CHK>(A, xs, lane, w, [&](auto I, R v) {
+  split_symv81_t80<CHK, NT>(A, xs, x80, lane, w, [&](auto I, R v) {
     if (valid) zbuf[(int64_t)I * nvert + vert] = v;
   });
 }
@@ -375,8 +424,9 @@ k_asm_gemv(AsmBatch<R> B) {
     if constexpr (D == 2) {
       asm_patch<D, 18, AsmTune<D, R, V>::nch18>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b * 64 + t);
     } else {
-      __shared__ R xs[81 * 64];
-      asm_patch81<AsmTune<D, R, V>::ch81>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf, nvert, b, xs, t);
+      __shared__ R xs[80 * 64];
+      asm_patch81<AsmTune<D, R, V>::ch81, AsmTune<D, R, V>::nt>(g, c.verts[0], c.count[0], c.inv[0], r, zbuf,
+                                                               nvert, b, xs, t);
     }
   } else if (b < c.first_block[2]) {
     const int s = (b - c.first_block[1]) * NT + t;
@@ -573,6 +623,7 @@ static void asm_gemv_variant(int v, hipStream_t s, const AsmBatch<R>& B) {
   if (grid.x == 0) return;
   if (v == 1) hipLaunchKernelGGL((k_asm_gemv<D, R, 1>), grid, blk, 0, s, B);
   else if (v == 2) hipLaunchKernelGGL((k_asm_gemv<D, R, 2>), grid, blk, 0, s, B);
+  else if (v == 3) hipLaunchKernelGGL((k_asm_gemv<D, R, 3>), grid, blk, 0, s, B);
   else hipLaunchKernelGGL((k_asm_gemv<D, R, 0>), grid, blk, 0, s, B);
 }
 

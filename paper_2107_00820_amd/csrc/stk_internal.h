@@ -41,7 +41,7 @@ struct PatchClass {
 // Variants of the batched patch solve a tuner may choose between per level
 // and precision (bit-identical results; they differ in load chunking and
 // occupancy only).
-constexpr int kAsmVariants = 3;
+constexpr int kAsmVariants = 4;
 // Entries (level solves of possibly different hierarchies) per batched
 // patch-solve launch.
 constexpr int kAsmBatchMax = 8;

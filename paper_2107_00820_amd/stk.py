@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libstk.so")
 
 STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ENOTCONV, STK_ENOTSPD, STK_ENAN, STK_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 STK_F64, STK_F32 = 0, 1
-STK_ASM_VARIANTS = 3
+STK_ASM_VARIANTS = 4
 STK_PC_MIXED, STK_PC_UPPER, STK_PC_FCYCLE = 1, 2, 4
 STK_BATCH_MAX = 8
 _PC = {"full": 0, "upper": 1}

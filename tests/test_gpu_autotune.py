@@ -7,11 +7,12 @@ import numpy as np
 import pytest
 
 from gpu_common import CASES, log
+from paper_2107_00820_amd.stk import STK_ASM_VARIANTS
 
 pytestmark = pytest.mark.gpu
 
 NAMES = ["2d_32_L3", "3d_8_L2"]
-NVAR = 3
+NVAR = STK_ASM_VARIANTS
 
 
 @pytest.mark.parametrize("name", NAMES)
