@@ -13,7 +13,7 @@ from paper_2107_00820_amd import profiling
 from paper_2107_00820_amd.tune import load_asm_tuning, TABLE
 from workloads import CONFIGS
 
-NVAR = 3
+from paper_2107_00820_amd.stk import STK_ASM_VARIANTS as NVAR   # variants the library offers
 
 
 def test_tuning_table_covers_benchmark_levels():
