@@ -11,8 +11,8 @@ Augmented block (Section 3, eq. (augstokessys)):
 Right-hand side: (f, phi_i) for the velocity and 0 for the pressure (r_2 = 0,
 so the augmented right-hand side equals the original one).
 
-All integrals use the tensor 3-point Gauss rule on every cell (the paper does
-not state its rule; this rule is exact for the constant-coefficient Q2
+All integrals use the tensor (k+1)-point Gauss rule on every cell (the paper
+does not state its rule; this rule is exact for the constant-coefficient Q_k
 stiffness on affine cells and it defines the discrete problem otherwise).
 """
 from __future__ import annotations
@@ -25,10 +25,10 @@ from .fem import Level, reference_tables, pressure_basis
 
 def basis_strain(level: Level):
     """Strain eps(phi_i) of every local vector basis function at every
-    reference quadrature point: array [q, i, a, b], i = comp * 3^d + node,
+    reference quadrature point: array [q, i, a, b], i = comp * (k+1)^d + node,
     physical units (reference gradient / h)."""
     d = level.dim
-    xi, w, phi, dphi = reference_tables(d)
+    xi, w, phi, dphi = reference_tables(d, level.k)
     nq, nn = phi.shape
     grad = np.zeros((nq, d * nn, d, d))
     for c in range(d):
@@ -40,7 +40,7 @@ def element_viscous(level: Level, coef, cells=None) -> np.ndarray:
     """Element matrices (n_cells, nl, nl) of a(u, v) = (sigma(u), eps(v));
     only those of `cells` (an index array) if given."""
     d = level.dim
-    xi, w, phi, dphi = reference_tables(d)
+    xi, w, phi, dphi = reference_tables(d, level.k)
     eps, _ = basis_strain(level)
     nq, nl = eps.shape[0], eps.shape[1]
     vol = level.h ** d
@@ -65,18 +65,18 @@ def element_viscous(level: Level, coef, cells=None) -> np.ndarray:
 def element_divergence(level: Level) -> np.ndarray:
     """Be[m, j] = -(psi_m, div phi_j) on one cell (identical on all cells)."""
     d = level.dim
-    xi, w, phi, dphi = reference_tables(d)
+    xi, w, phi, dphi = reference_tables(d, level.k)
     _, grad = basis_strain(level)
     div = np.trace(grad, axis1=-2, axis2=-1)                      # (nq, nl)
-    psi = pressure_basis(xi)                                      # (nq, d+1)
+    psi = pressure_basis(xi, level.k)                             # (nq, n_pb)
     return -np.einsum("q,qm,qj->mj", w * level.h ** d, psi, div)
 
 
 def element_pressure_mass(level: Level, weight=None) -> np.ndarray:
-    """(w psi_m, psi_n) on every cell: (n_cells, d+1, d+1); weight(x) optional."""
+    """(w psi_m, psi_n) on every cell: (n_cells, n_pb, n_pb); weight(x) optional."""
     d = level.dim
-    xi, w, phi, dphi = reference_tables(d)
-    psi = pressure_basis(xi)
+    xi, w, phi, dphi = reference_tables(d, level.k)
+    psi = pressure_basis(xi, level.k)
     vol = level.h ** d
     if weight is None:
         wq = np.ones((level.n_cells, len(w)))
@@ -94,7 +94,7 @@ def _assemble(rows_e, cols_e, vals_e, shape):
 
 
 def pressure_dofs(level: Level) -> np.ndarray:
-    return np.arange(level.n_p).reshape(level.n_cells, level.dim + 1)
+    return np.arange(level.n_p).reshape(level.n_cells, level.n_pb)
 
 
 class Operators:
@@ -104,10 +104,10 @@ class Operators:
         self.level, self.coef, self.gamma, self.schur = level, coef, float(gamma), schur
         d = level.dim
         ed = level.element_dofs()                                   # (nc, nl)
-        pd = pressure_dofs(level)                                   # (nc, d+1)
+        pd = pressure_dofs(level)                                   # (nc, n_pb)
         Ae = element_viscous(level, coef)
         self.A = _assemble(ed[:, :, None], ed[:, None, :], Ae, (level.n_u, level.n_u))
-        Be = np.broadcast_to(element_divergence(level), (level.n_cells,) + (d + 1, ed.shape[1]))
+        Be = np.broadcast_to(element_divergence(level), (level.n_cells,) + (level.n_pb, ed.shape[1]))
         self.B = _assemble(pd[:, :, None], ed[:, None, :], Be, (level.n_p, level.n_u))
         Me = element_pressure_mass(level)
         Mmu = element_pressure_mass(level, lambda x: 1.0 / coef.scalar_viscosity(x))
@@ -139,7 +139,7 @@ class Operators:
         """Velocity right-hand side (f, phi_i)."""
         level = self.level
         d = level.dim
-        xi, w, phi, dphi = reference_tables(d)
+        xi, w, phi, dphi = reference_tables(d, level.k)
         x = level.quad_points()
         f = self.coef_force(x)                                      # (nc, nq, d)
         vol = level.h ** d
@@ -166,7 +166,7 @@ def stokes_rows(level: Level, coef, gamma: float, u: np.ndarray, p: np.ndarray, 
     summed from the element matrices of only the cells those entries touch:
     the same entries as the assembled operators of `Operators`, for spot
     checks on meshes too large to assemble. Returns (velocity entries at
-    `vel_rows`, pressure entries of the cells `pres_cells` as (len, d+1))."""
+    `vel_rows`, pressure entries of the cells `pres_cells` as (len, n_pb))."""
     vel_rows = np.asarray(vel_rows)
     pres_cells = np.asarray(pres_cells)
     ed = level.element_dofs()
@@ -196,7 +196,7 @@ def rhs_rows(level: Level, coef, vel_rows) -> np.ndarray:
     cells that touch them (same element loads as `Operators.rhs`)."""
     vel_rows = np.asarray(vel_rows)
     d = level.dim
-    xi, w, phi, dphi = reference_tables(d)
+    xi, w, phi, dphi = reference_tables(d, level.k)
     ed = level.element_dofs()
     cells = np.nonzero(np.isin(ed, vel_rows).any(axis=1))[0]
     base = coef if coef.kind == "scalar" else coef.base

@@ -147,11 +147,12 @@ class StokesSolver:
             if wl.coef_kind == 0:
                 coef = SinkerField.from_workload(wl)
             else:
-                coef = ViscoplasticNewton.from_workload(wl, Level(wl.dim, wl.n_fine).quad_points())
+                coef = ViscoplasticNewton.from_workload(
+                    wl, Level(wl.dim, wl.n_fine, getattr(wl, "degree", 2)).quad_points())
         self.coef = coef
         t0 = time.perf_counter()
         self.mg = Multigrid(wl.dim, wl.n_fine, wl.levels, coef, wl.gamma, wl.nu_pre, wl.nu_post,
-                            schur=schur, robust=robust)
+                            schur=schur, robust=robust, k=getattr(wl, "degree", 2))
         self.ops = self.mg.ops[-1]
         self.K = self.ops.stokes(augmented=True)
         self.pc = BlockPreconditioner(self.mg)

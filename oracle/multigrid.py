@@ -46,13 +46,14 @@ from .assembly import Operators
 
 # --------------------------------------------------------------------------- patches
 def star_patch_dofs(level: Level, vertex) -> np.ndarray:
-    """Unknowns strictly inside star(vertex): per axis the nodes 2v-1, 2v, 2v+1
-    that are interior to the domain, all components; sorted ascending."""
-    d = level.dim
+    """Unknowns strictly inside star(vertex): per axis the nodes kv-(k-1) ..
+    kv+(k-1) that are interior to the domain, all components; sorted
+    ascending ((2k-1)^d nodes at an interior vertex)."""
+    d, k = level.dim, level.k
     ranges = []
-    for k in range(d):
-        v = int(vertex[k])
-        ranges.append([i for i in (2 * v - 1, 2 * v, 2 * v + 1) if 1 <= i <= 2 * level.n - 1])
+    for a in range(d):
+        v = int(vertex[a])
+        ranges.append([i for i in range(k * v - (k - 1), k * v + k) if 1 <= i <= k * level.n - 1])
     nodes = np.array(list(itertools.product(*ranges)), dtype=np.int64)
     if nodes.size == 0:
         return np.zeros(0, dtype=np.int64)
@@ -65,9 +66,10 @@ def all_vertices(level: Level) -> np.ndarray:
 
 
 def coarse_cell_dofs(fine: Level, coarse_cell) -> np.ndarray:
-    """Fine unknowns strictly inside a coarse cell (fine nodes 4c+1..4c+3 per axis)."""
-    d = fine.dim
-    ranges = [range(4 * int(c) + 1, 4 * int(c) + 4) for c in coarse_cell]
+    """Fine unknowns strictly inside a coarse cell (fine nodes 2kc+1 .. 2kc+2k-1
+    per axis)."""
+    d, k = fine.dim, fine.k
+    ranges = [range(2 * k * int(c) + 1, 2 * k * int(c) + 2 * k) for c in coarse_cell]
     nodes = np.array(list(itertools.product(*ranges)), dtype=np.int64)
     dofs = np.concatenate([fine.u_dof(c, nodes) for c in range(d)])
     return np.sort(dofs)
@@ -100,21 +102,21 @@ class StarASM:
 
 # --------------------------------------------------------------------------- transfers
 def standard_prolongation(coarse: Level, fine: Level) -> sp.csr_matrix:
-    """P_H: coarse Q2 field evaluated at the fine nodes (nested spaces)."""
-    d = coarse.dim
-    assert fine.n == 2 * coarse.n
+    """P_H: coarse Q_k field evaluated at the fine nodes (nested spaces)."""
+    d, kk = coarse.dim, coarse.k
+    assert fine.n == 2 * coarse.n and fine.k == kk
     fnodes = unlex(np.arange(fine.n_int_nodes), fine.ni, d) + 1      # fine node indices
-    # position in coarse-cell units: fine node i sits at i/4 coarse cells
-    s = fnodes / 4.0
+    # position in coarse-cell units: fine node i sits at i/(2k) coarse cells
+    s = fnodes / (2.0 * kk)
     cell = np.minimum(np.floor(s).astype(np.int64), coarse.n - 1)
     xi = s - cell
-    val, _ = lagrange_1d(xi)                                          # (nf, d, 3)
+    val, _ = lagrange_1d(xi, kk)                                      # (nf, d, k+1)
     rows, cols, vals = [], [], []
-    for loc in itertools.product(range(3), repeat=d):
+    for loc in itertools.product(range(kk + 1), repeat=d):
         w = np.ones(len(fnodes))
         for k in range(d):
             w = w * val[:, k, loc[k]]
-        cnode = 2 * cell + np.array(loc)[None, :]
+        cnode = kk * cell + np.array(loc)[None, :]
         for c in range(d):
             cd = coarse.u_dof(c, cnode)
             fd = c * fine.n_int_nodes + np.arange(fine.n_int_nodes)
@@ -203,8 +205,8 @@ class Multigrid:
     """Rediscretised hierarchy with star-ASM relaxation and robust transfers."""
 
     def __init__(self, dim: int, n_fine: int, n_levels: int, coef, gamma: float,
-                 nu_pre: int = 2, nu_post: int = 2, schur: int = 1, robust: bool = True):
-        self.hier = Hierarchy(dim, n_fine, n_levels)
+                 nu_pre: int = 2, nu_post: int = 2, schur: int = 1, robust: bool = True, k: int = 2):
+        self.hier = Hierarchy(dim, n_fine, n_levels, k)
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.ops = [Operators(lv, coef, gamma, schur) for lv in self.hier.levels]
         self.robust = robust

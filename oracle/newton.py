@@ -117,6 +117,7 @@ class NewtonSolver:
 
     def __init__(self, wl, tau_y: float, mu_floor: float = 0.0):
         from .krylov import StokesSolver
+        assert getattr(wl, "degree", 2) == 2, "the Newton loop is built for [Q2]^d x P1disc"
         self.wl = wl
         self.base = SinkerField.from_workload(wl)
         self.tau_y = float(tau_y)

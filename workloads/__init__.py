@@ -50,6 +50,7 @@ class Workload:
     mu_floor: float = 0.0  # floor of the capped viscoplastic law (coef_kind 1, 2); 0 selects mu_min
     tau_y: float = 0.0     # yield stress of the capped law; 0 selects 2 mu_max (coef_kind 1)
     cycle: str = "V"       # multigrid cycle of the block preconditioner: "V" or "F"
+    degree: int = 2        # velocity degree k of [Q_k]^d x P_{k-1}^disc (2 or 3)
 
     @property
     def mu_max(self) -> float:
@@ -74,8 +75,9 @@ class Workload:
 
     def unknowns(self) -> Tuple[int, int]:
         """(interior velocity unknowns, pressure unknowns) on the finest level."""
-        d, n = self.dim, self.n_fine
-        return d * (2 * n - 1) ** d, (d + 1) * n ** d
+        d, n, k = self.dim, self.n_fine, self.degree
+        n_pb = math.comb(k - 1 + d, d)       # monomials of total degree <= k-1
+        return d * (k * n - 1) ** d, n_pb * n ** d
 
 
 def sinker_centers(n: int, dim: int, seed: int) -> np.ndarray:
