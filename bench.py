@@ -13,7 +13,8 @@ Setup is timed separately. Also reported: the 2D 128^2 and 3D 32^3
 workloads (FP64, fewer steps), the viscoplastic Newton loop on 3D 32^3 and,
 unless --no-serving, the serving stream (continuous batching, p50/p99
 latency; also run once with the cross-request batched patch solves turned
-off). Prints one JSON line.
+on, and bursts of same-shape requests with them off and on). Prints one
+JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--form both|fp64|mixed]
                 [--no-cpu-baseline] [--serving N | --no-serving] [--no-extra] [--trace]
@@ -227,6 +228,46 @@ def serving_leg(n, budget_gb, pc="full"):
     return out
 
 
+def cohort_bursts(m=8):
+    """Bursts of m same-shape requests started together and stepped with
+    stk_step_batch until all are done, with the cross-request batched patch
+    solves off and on (best of two runs each)."""
+    import torch
+    from workloads import small
+    from paper_2107_00820_amd import Hierarchy, stk_step_batch
+
+    def burst(dim, n, L, g, cross):
+        os.environ["STK_CROSS_BATCH"] = cross
+        wls = [small(dim, n, L, gamma=g, dr=10.0 ** (4 + k % 5), n_sinkers=24, seed=3 * 10 ** 6 + k)
+               for k in range(m)]
+        hs = [Hierarchy.from_workload(w) for w in wls]
+        rhs = [h.stk_rhs() for h in hs]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for h, (bu, bp) in zip(hs, rhs):
+            h.stk_solve_begin(bu, bp, eager=True)
+        infos = [None] * m
+        while any(i is None for i in infos):
+            stk_step_batch([h for h, i in zip(hs, infos) if i is None])
+            for k, h in enumerate(hs):
+                if infos[k] is None:
+                    infos[k] = h.stk_poll()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for h in hs:
+            h.close()
+        return dt
+
+    out = {}
+    for dim, n, L, g in ((2, 64, 3, 1e3), (2, 128, 4, 1e3), (3, 8, 2, 1e4), (3, 16, 2, 1e4)):
+        t = {c: min(burst(dim, n, L, g, c) for _ in range(2)) for c in ("0", "1")}
+        key = f"{m}x_{dim}d_{n}_L{L}"
+        out[key] = {"ms_off": 1e3 * t["0"], "ms_on": 1e3 * t["1"]}
+        log(f"[bench] burst {key}: batching off {1e3 * t['0']:.1f} ms, on {1e3 * t['1']:.1f} ms")
+    os.environ["STK_CROSS_BATCH"] = "1"
+    return out
+
+
 def newton_leg(name):
     """The viscoplastic problem solved by Newton's method on the GPU
     (stk_newton: relinearise, FGMRES step, line search), timed whole."""
@@ -371,15 +412,17 @@ def main():
         out["newton"] = newton_leg("newton_3d_32cu_L3")
     if not args.no_serving and args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
-        # the same stream with the cross-request batched patch solves turned off
-        os.environ["STK_CROSS_BATCH"] = "0"
+        # the same stream with the cross-request batched patch solves turned on
+        os.environ["STK_CROSS_BATCH"] = "1"
         try:
             nb = serving_leg(args.serving, args.budget_gb, args.serving_pc)
+            bursts = cohort_bursts()
         finally:
             del os.environ["STK_CROSS_BATCH"]
-        out["serving"]["without_cross_batching"] = {k: nb[k] for k in (
+        out["serving"]["with_cross_batching"] = {k: nb[k] for k in (
             "completed", "makespan_s", "dof_per_s", "latency_p50_ms", "latency_p99_ms", "solve_s_mean",
             "queue_s_mean")}
+        out["serving"]["same_shape_bursts"] = bursts
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -289,15 +289,17 @@ stk_status stk_solve_begin(stk_hier* h, const double* b_u, const double* b_p, do
  * rotations, stopping test) and its next phase enqueued at once; a solve
  * with nothing in flight gets its phase enqueued; a solve whose phase is
  * still running is left alone. If no solve could move in one pass, the call
- * waits until the first in-flight phase completes. Solves of hierarchies
- * with the same shape (dimension, cells, levels, relaxation steps, W,
- * coefficient kind, precision form and preconditioner variant) that are
- * ready for an Arnoldi step at the same time run their preconditioner
- * cycles in lockstep, with one batched star-patch solve launch per
- * smoothing step for all of them (up to STK_BATCH_MAX requests per launch).
- * Each solve's arithmetic is unchanged, so its result does not depend on
- * which other requests share the device (setting the environment variable
- * STK_CROSS_BATCH=0 turns the lockstep batching off, for comparisons).
+ * waits until the first in-flight phase completes. With the environment
+ * variable STK_CROSS_BATCH=1, solves of hierarchies with the same shape
+ * (dimension, fine cells, levels, relaxation steps and precision /
+ * preconditioner form) that are ready for an Arnoldi step at the same time
+ * run their preconditioner cycles in lockstep, with one batched star-patch
+ * solve launch per smoothing step of the levels below 512 workgroups for
+ * all of them (up to STK_BATCH_MAX requests per launch); this pays on bursts
+ * of same-shape small requests and is off by default, since on a mixed
+ * stream the lockstep waits cost the other requests more than it gains.
+ * Each solve's arithmetic is unchanged either way, so its result does not
+ * depend on which other requests share the device.
  * Entries that are idle or done are skipped. Returns the first error met (that solve is then done with that
  * status); `stream` is unused. */
 #define STK_BATCH_MAX 8

@@ -8,7 +8,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <functional>
 #include <condition_variable>
 #include <cstdio>
 #include <map>
@@ -285,52 +287,123 @@ float* level_S<float>(Level& L) {
 // stream has reached the call, through events), and each stream waits for
 // that launch before going on. Everything else stays on each hierarchy's
 // own stream, and each entry's patch solves run exactly the single-launch
-// code, so results do not depend on the batch.
+// code, so results do not depend on the batch. The threads meet at a
+// spinning barrier (a step has dozens of meetings of a few microseconds of
+// host work each) and come from a persistent pool.
 struct Cohort {
   int n = 0;
-  std::mutex m;
-  std::condition_variable cv;
-  int arrived = 0;
-  long gen = 0;
+  std::atomic<int> arrived{0};
+  std::atomic<long> gen{0};
+  // a member whose step failed never arrives again: the others then launch
+  // their own patch solves
+  std::atomic<bool> broken{false};
   hipStream_t lead = nullptr;
   hipEvent_t done = nullptr;
   std::vector<const Hier*> hs;
   std::vector<const Level*> ls;
   std::vector<const void*> rs;
   std::vector<hipEvent_t> ready;
-  long launches = 0;
 };
 thread_local Cohort* t_cohort = nullptr;
 thread_local int t_slot = -1;
+
+// Workgroups of one entry of a batched patch-solve launch (64 patches per
+// workgroup, 256 for the 3D boundary classes). Levels at or above
+// kCohortMaxBlocks fill the device on their own and are launched without
+// meeting the cohort.
+constexpr int kCohortMaxBlocks = 512;
+int asm_blocks(const Hier& H, const Level& L) {
+  int blocks = 0;
+  const int ncls = H.dim == 2 ? 3 : 4;
+  for (int ci = 0; ci < ncls && ci < (int)L.cls.size(); ++ci) {
+    const int per = (H.dim == 2 || ci == 0) ? 64 : 256;
+    blocks += (L.cls[ci].count + per - 1) / per;
+  }
+  return blocks;
+}
+
+// Persistent worker threads for the cohorts: run(tasks) runs tasks[1..] on
+// the workers and tasks[0] on the caller, and returns when all have ended.
+class CohortPool {
+ public:
+  void run(std::vector<std::function<void()>>& tasks) {
+    const int nw = (int)tasks.size() - 1;
+    {
+      std::unique_lock<std::mutex> lk(m_);
+      while ((int)th_.size() < nw) th_.emplace_back([this] { work(); });
+      for (int i = 1; i <= nw; ++i) q_.push_back(&tasks[i]);
+      left_ = nw;
+    }
+    cv_.notify_all();
+    tasks[0]();
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [this] { return left_ == 0; });
+  }
+  ~CohortPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread& t : th_) t.join();
+  }
+
+ private:
+  void work() {
+    for (;;) {
+      std::function<void()>* f = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
+        if (stop_ && q_.empty()) return;
+        f = q_.back();
+        q_.pop_back();
+      }
+      (*f)();
+      std::lock_guard<std::mutex> lk(m_);
+      if (--left_ == 0) done_.notify_all();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable cv_, done_;
+  std::vector<std::thread> th_;
+  std::vector<std::function<void()>*> q_;
+  int left_ = 0;
+  bool stop_ = false;
+};
 
 // The patch solves of one ASM application into L.zbuf (batched with the
 // other members of the calling thread's cohort, if any).
 template <class R>
 void asm_solves(Hier& H, Level& L, const R* r) {
   Cohort* C = t_cohort;
-  if (!C) {
+  // members have the same level shapes, so they all take the same branch
+  if (!C || C->broken.load(std::memory_order_acquire) || asm_blocks(H, L) >= kCohortMaxBlocks) {
     launch_asm_solves<R>(H, L, r, H.stream);
     return;
   }
   const int k = t_slot;
   (void)hipEventRecord(C->ready[k], H.stream);
-  {
-    std::unique_lock<std::mutex> lk(C->m);
-    C->ls[k] = &L;
-    C->rs[k] = r;
-    const long g = C->gen;
-    if (++C->arrived == C->n) {
-      for (int i = 0; i < C->n; ++i) (void)hipStreamWaitEvent(C->lead, C->ready[i], 0);
-      std::vector<const R*> rr(C->n);
-      for (int i = 0; i < C->n; ++i) rr[i] = static_cast<const R*>(C->rs[i]);
-      launch_asm_gemv_batch<R>(C->hs.data(), C->ls.data(), rr.data(), C->n, C->lead);
-      (void)hipEventRecord(C->done, C->lead);
-      ++C->launches;
-      C->arrived = 0;
-      ++C->gen;
-      C->cv.notify_all();
-    } else {
-      C->cv.wait(lk, [&] { return C->gen != g; });
+  C->ls[k] = &L;
+  C->rs[k] = r;
+  // the generation cannot move before this member has arrived
+  const long g = C->gen.load(std::memory_order_acquire);
+  if (C->arrived.fetch_add(1, std::memory_order_acq_rel) + 1 == C->n) {
+    for (int i = 0; i < C->n; ++i) (void)hipStreamWaitEvent(C->lead, C->ready[i], 0);
+    std::vector<const R*> rr(C->n);
+    for (int i = 0; i < C->n; ++i) rr[i] = static_cast<const R*>(C->rs[i]);
+    launch_asm_gemv_batch<R>(C->hs.data(), C->ls.data(), rr.data(), C->n, C->lead);
+    (void)hipEventRecord(C->done, C->lead);
+    C->arrived.store(0, std::memory_order_relaxed);
+    C->gen.fetch_add(1, std::memory_order_release);
+  } else {
+    while (C->gen.load(std::memory_order_acquire) == g) {
+      if (C->broken.load(std::memory_order_acquire)) {
+        // this generation can no longer fill up
+        launch_asm_solves<R>(H, L, r, H.stream);
+        return;
+      }
+      std::this_thread::yield();
     }
   }
   (void)hipStreamWaitEvent(H.stream, C->done, 0);
@@ -1333,9 +1406,10 @@ stk_status sv_advance(Hier& H) {
 }
 
 // Enqueues the Arnoldi step of each hierarchy of `g` (same dimension, level
-// count, relaxation steps and solve form, so the same sequence of patch-solve
-// calls) on its own stream from its own host thread, with the patch solves
-// batched across them (Cohort).
+// count, fine mesh, relaxation steps and solve form, so the same sequence of
+// patch-solve calls on levels of the same shapes) on its own stream from its
+// own host thread, with the patch solves of the small levels batched across
+// them (Cohort).
 stk_status enqueue_cohort(const std::vector<Hier*>& g) {
   const int n = (int)g.size();
   Cohort C;
@@ -1356,19 +1430,25 @@ stk_status enqueue_cohort(const std::vector<Hier*>& g) {
   }
   std::vector<stk_status> st(n, STK_OK);
   std::vector<std::string> err(n);
-  auto run = [&](int k) {
-    t_cohort = &C;
-    t_slot = k;
-    st[k] = sv_enqueue(*g[k]);
-    if (st[k] != STK_OK) err[k] = g_err;
-    t_cohort = nullptr;
-    t_slot = -1;
-  };
-  std::vector<std::thread> th;
-  th.reserve(n - 1);
-  for (int k = 1; k < n; ++k) th.emplace_back(run, k);
-  run(0);
-  for (std::thread& t : th) t.join();
+  std::vector<std::function<void()>> tasks(n);
+  for (int k = 0; k < n; ++k)
+    tasks[k] = [&, k] {
+      t_cohort = &C;
+      t_slot = k;
+      st[k] = sv_enqueue(*g[k]);
+      if (st[k] != STK_OK) {
+        err[k] = g_err;
+        C.broken.store(true, std::memory_order_release);
+      }
+      t_cohort = nullptr;
+      t_slot = -1;
+    };
+  static CohortPool pool;
+  static std::mutex pool_m;   // one cohort at a time uses the pool
+  {
+    std::lock_guard<std::mutex> lk(pool_m);
+    pool.run(tasks);
+  }
   for (int k = 0; k < n; ++k)
     if (st[k] != STK_OK) return fail(st[k], err[k]);
   return STK_OK;
@@ -1437,10 +1517,11 @@ stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream) {
   (void)stream;
   for (int i = 0; i < n; ++i)
     if (!hs[i]) return fail(STK_EINVAL, "NULL hierarchy in the list");
-  // STK_CROSS_BATCH=0 in the environment turns the lockstep cohorts off
-  // (every solve then steps on its own; for comparisons)
+  // STK_CROSS_BATCH=1 in the environment turns the lockstep cohorts on
+  // (off by default: on a mixed request stream their cross-stream waits cost
+  // more than the fuller launches gain)
   const char* env = getenv("STK_CROSS_BATCH");
-  const bool cross = !(env && env[0] == '0');
+  const bool cross = env && env[0] == '1';
   stk_status first = STK_OK;
   auto note = [&](Hier& H, stk_status st) {
     if (st == STK_OK) return;
@@ -1472,7 +1553,7 @@ stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream) {
       const Hier::Solve& S = H.sv;
       if (cross && S.phase == Hier::SV_ARNOLDI && !S.graphs && !H.prof.on) {
         const int form = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0) | (S.fcycle ? 4 : 0);
-        groups[std::make_tuple(H.dim, H.L, H.nu_pre, H.nu_post, form, 0)].push_back(&H);
+        groups[std::make_tuple(H.dim, H.L, H.lv.back().g.N, H.nu_pre, H.nu_post, form)].push_back(&H);
         continue;
       }
       note(H, sv_enqueue(H));

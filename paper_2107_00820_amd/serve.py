@@ -9,9 +9,10 @@ its solve then joins the running set. Every scheduler tick calls
 ``stk_step_batch`` on the running solves: a solve whose last phase has
 finished on the device gets its host part and its next phase enqueued at
 once, without waiting for the others (phases run on the hierarchies' own
-streams, so the requests' work overlaps on the device), and the Arnoldi
-steps of same-shape requests that are ready together run in lockstep with
-one batched star-patch solve launch per smoothing step for all of them.
+streams, so the requests' work overlaps on the device). With
+STK_CROSS_BATCH=1 in the environment, the Arnoldi steps of same-shape
+requests that are ready together also run in lockstep with one batched
+star-patch solve launch per smoothing step of their small levels.
 Each request is solved once, so its phases are plain launches: capturing a
 HIP graph per Arnoldi step pays off only for repeated solves on one
 hierarchy. Finished or failed requests free their memory at once, which

@@ -26,12 +26,14 @@ def _requests():
             for k, (d, n, L, g, dr, s) in enumerate(specs)]
 
 
-def test_mix_equals_alone_and_overlaps():
+@pytest.mark.parametrize("cross", ["0", "1"])
+def test_mix_equals_alone_and_overlaps(cross, monkeypatch):
     import torch
     from paper_2107_00820_amd import Hierarchy
     from paper_2107_00820_amd.serve import Server
+    monkeypatch.setenv("STK_CROSS_BATCH", cross)
     reqs = _requests()
-    log("[serving] mix of 6 requests")
+    log(f"[serving] mix of 6 requests, STK_CROSS_BATCH={cross}")
     out = Server(hbm_budget=8 << 30, max_active=4, keep_solutions=True).run(reqs)
     assert out["completed"] == len(reqs), [r.error for r in out["results"]]
     assert out["peak_active"] >= 2            # solves were in flight together
@@ -69,8 +71,8 @@ def test_admission_respects_budget():
 @pytest.mark.parametrize("cross", ["1", "0"])
 def test_same_shape_requests_step_together_and_equal_alone(dim, cross, monkeypatch):
     """Same-shape requests started together step in lockstep with batched
-    star-patch solve launches (STK_CROSS_BATCH=1, the default) or each on
-    its own (0); either way every solution and iteration count is
+    star-patch solve launches (STK_CROSS_BATCH=1) or each on its own (0,
+    the default); either way every solution and iteration count is
     bit-identical to the request solved alone."""
     import torch
     from paper_2107_00820_amd import Hierarchy, stk_step_batch
