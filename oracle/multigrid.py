@@ -106,10 +106,11 @@ def standard_prolongation(coarse: Level, fine: Level) -> sp.csr_matrix:
     d, kk = coarse.dim, coarse.k
     assert fine.n == 2 * coarse.n and fine.k == kk
     fnodes = unlex(np.arange(fine.n_int_nodes), fine.ni, d) + 1      # fine node indices
-    # position in coarse-cell units: fine node i sits at i/(2k) coarse cells
-    s = fnodes / (2.0 * kk)
-    cell = np.minimum(np.floor(s).astype(np.int64), coarse.n - 1)
-    xi = s - cell
+    # position in coarse-cell units: fine node i sits at i/(2k) coarse cells,
+    # in cell floor(i/(2k)) at the local coordinate (i - 2k cell)/(2k), formed
+    # from the integer offset so that it is correctly rounded
+    cell = np.minimum(fnodes // (2 * kk), coarse.n - 1)
+    xi = (fnodes - 2 * kk * cell) / (2.0 * kk)
     val, _ = lagrange_1d(xi, kk)                                      # (nf, d, k+1)
     rows, cols, vals = [], [], []
     for loc in itertools.product(range(kk + 1), repeat=d):
