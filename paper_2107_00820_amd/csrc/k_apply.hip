@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "stk_asm_sum.h"
+#include "stk_q3.h"
 #include "stk_reduce.h"
 
 namespace stk {
@@ -1024,6 +1025,43 @@ __global__ void k_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, d
   for (int n = 0; n < NN; ++n) E[cell * (D * NN) + (D - 1) * NN + n] = vol * be[n];
 }
 
+// [Q3]^2 x P2disc: the sinker viscosity at a cell's 4 x 4 Gauss points, and
+// the element loads (f, phi) of the cubic basis with the same forcing.
+__global__ void k3_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta,
+                             double mu_min, double mu_max, double* __restrict__ mu) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)q3::NQ * g.ncell) return;
+  const int64_t cell = idx / q3::NQ;
+  const int q = (int)(idx - cell * q3::NQ);
+  const double x[2] = {g.h * ((double)(cell % g.N) + q3::kGx[q % q3::NA]),
+                       g.h * ((double)(cell / g.N) + q3::kGx[q / q3::NA])};
+  const double chi = sinker_chi<2>(ctr, ns, omega, delta, x);
+  mu[idx] = (mu_max - mu_min) * (1.0 - chi) + mu_min;
+}
+
+__global__ void k3_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta,
+                            double beta, double* __restrict__ E) {
+  constexpr const q3::Tab& T = q3::RefQ3::T;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  double be[q3::NN];
+#pragma unroll
+  for (int n = 0; n < q3::NN; ++n) be[n] = 0.0;
+  for (int q = 0; q < q3::NQ; ++q) {
+    const double x[2] = {g.h * ((double)(cell % g.N) + q3::kGx[q % q3::NA]),
+                         g.h * ((double)(cell / g.N) + q3::kGx[q / q3::NA])};
+    const double f = beta * (sinker_chi<2>(ctr, ns, omega, delta, x) - 1.0);
+#pragma unroll
+    for (int n = 0; n < q3::NN; ++n) be[n] += T.w[q] * T.phi[q][n] * f;
+  }
+  const double vol = g.h * g.h;
+#pragma unroll
+  for (int n = 0; n < q3::NN; ++n) {
+    E[cell * q3::NL + n] = 0.0;
+    E[cell * q3::NL + q3::NN + n] = vol * be[n];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per cell: Winv = (sum_q w_q / mu_q psi psi^T)^{-1} on the reference cell,
 // the inverse weighted pressure mass of W = M_p(1/mu) (eq. (P1P2), P2) without
@@ -1202,7 +1240,19 @@ __global__ void k_p0_subtract(int64_t ncell, const double* __restrict__ part, in
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+void q3_mu_sinker(const Hier& H, const Level& l, double* out, hipStream_t s) {
+  const int64_t n = (int64_t)q3::NQ * l.g.ncell;
+  hipLaunchKernelGGL(k3_mu_sinker, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega, H.delta,
+                     H.mu_min, H.mu_max, out);
+}
+
+void q3_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
+  hipLaunchKernelGGL(k3_rhs_elem, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
+                     H.delta, H.beta, l.E);
+}
+
 void launch_mu_sinker(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.deg == 3) return q3_mu_sinker(H, l, l.mu, s);
   if (H.dim == 2) {
     const int64_t n = (int64_t)Dims<2>::NQ * l.g.ncell;
     hipLaunchKernelGGL(k_mu_sinker<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers,
@@ -1279,6 +1329,13 @@ static void elem_dispatch(const Hier& H, const Level& l, int mode, const R* u, c
 template <class R>
 void launch_elem_asm(const Hier& H, const Level& l, R* z, hipStream_t s) {
   if (H.dim != 2) return;
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) {
+      q3_asm_gather(H, l, l.zbuf, z, s);
+      q3_elem(H, l, EL_VISC | EL_AUG, z, nullptr, nullptr, s);
+      return;
+    }
+  }
   constexpr int MODE = EL_VISC | EL_AUG;
   constexpr int CPW = 64 / Dims<2>::NQ;
   const dim3 grid(nblk(l.g.ncell, CPW));
@@ -1308,6 +1365,7 @@ void launch_eps_partials(const Hier& H, const Level& fine, hipStream_t s) {
 }
 
 void launch_mu_sinker_to(const Hier& H, const Level& l, double* out, hipStream_t s) {
+  if (H.deg == 3) return q3_mu_sinker(H, l, out, s);
   const int64_t n = (int64_t)(H.dim == 2 ? 9 : 27) * l.g.ncell;
   if (H.dim == 2)
     hipLaunchKernelGGL(k_mu_sinker<2>, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
@@ -1366,12 +1424,18 @@ void launch_coef_tensor(const Hier& H, const Level& l, const Level& fine, hipStr
 
 template <class R>
 void launch_elem(const Hier& H, const Level& l, int mode, const R* u, const double* p, double* pout, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_elem(H, l, mode, u, p, pout, s);
+  }
   if (H.dim == 2) elem_dispatch<2, R>(H, l, mode, u, p, pout, s);
   else elem_dispatch<3, R>(H, l, mode, u, p, pout, s);
 }
 
 template <class R>
 void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R* out, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_gather(H, l, base, alpha, out, s);
+  }
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   const R* E = reinterpret_cast<const R*>(l.E);
   if (H.dim == 2)
@@ -1383,6 +1447,14 @@ void launch_gather(const Hier& H, const Level& l, const R* base, double alpha, R
 template <class R>
 void launch_gather_dots(const Hier& H, const Level& l, R* out, int64_t nvec, const R* V, int64_t ldv, int nk,
                         double* part, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) {
+      // the gather, then the dot products on the same partition
+      q3_gather(H, l, nullptr, 1.0, out, s);
+      launch_dots<R>(V, ldv, nk, out, nvec, part, s);
+      return;
+    }
+  }
   const R* E = reinterpret_cast<const R*>(l.E);
   const int np = red_parts(nvec);
   if (H.dim == 2)
@@ -1401,6 +1473,7 @@ template void launch_gather<double>(const Hier&, const Level&, const double*, do
 template void launch_gather<float>(const Hier&, const Level&, const float*, double, float*, hipStream_t);
 
 void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.deg == 3) return q3_rhs_elem(H, l, s);
   if (H.dim == 2)
     hipLaunchKernelGGL(k_rhs_elem<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.centers,
                        H.n_sinkers, H.omega, H.delta, H.beta, l.E);
@@ -1410,6 +1483,7 @@ void launch_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
 }
 
 void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.deg == 3) return q3_schur_setup(H, l, s);
   const int p2 = H.schur == 2 ? 1 : 0;
   if (H.dim == 2)
     hipLaunchKernelGGL(k_schur_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, H.gamma, p2,
@@ -1420,6 +1494,7 @@ void launch_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
 }
 
 void launch_winv_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.deg == 3) return q3_winv_setup(H, l, s);
   if (H.dim == 2)
     hipLaunchKernelGGL(k_winv_setup<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, l.mu, l.winv);
   else
@@ -1428,6 +1503,7 @@ void launch_winv_setup(const Hier& H, const Level& l, hipStream_t s) {
 
 void launch_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp,
                         hipStream_t s) {
+  if (H.deg == 3) return q3_schur_apply(H, l, y, vp, zp, s);
   if (H.dim == 2)
     hipLaunchKernelGGL(k_schur_apply<2>, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.Sinv, y, vp, zp);
   else
@@ -1435,6 +1511,7 @@ void launch_schur_apply(const Hier& H, const Level& l, const double* y, const do
 }
 
 void launch_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
+  if (H.deg == 3) return q3_project_mean(H, l, p, s);
   const int np = red_parts(l.g.ncell);
   if (H.dim == 2) {
     hipLaunchKernelGGL(k_p0_partials<3>, dim3(np), dim3(red_threads(l.g.ncell)), 0, s, l.g.ncell, p, H.partials);

@@ -24,6 +24,7 @@
 // Cholesky factor of the whole matrix. The rank-64 updates are 64 x 64 x 64
 // tile products on the FP64 matrix cores (v_mfma_f64_16x16x4f64); the pivot
 // factorisation and inversion run in LDS.
+#include "stk_q3.h"
 #include "stk_spd.h"
 
 namespace stk {
@@ -33,11 +34,11 @@ constexpr int kTT = kT * kT;
 constexpr int kLd = kT + 1;      // LDS row stride (doubles)
 
 
-// Interior unknown i (component-major over the (2N-1)^d interior nodes) ->
-// (component, node coordinates).
+// Interior unknown i (component-major over the (n1-2)^d interior nodes,
+// (kN-1)^d for degree k) -> (component, node coordinates).
 template <int D>
 __device__ inline int interior_dof(const LevelGeo& g, int64_t i, int nd[3]) {
-  const int ni = 2 * g.N - 1;
+  const int ni = g.n1 - 2;
   const int64_t nin = D == 2 ? (int64_t)ni * ni : (int64_t)ni * ni * ni;
   const int comp = (int)(i / nin);
   int64_t b = i - comp * nin;
@@ -90,6 +91,29 @@ __global__ void __launch_bounds__(256) k_coarse_assemble(LevelGeo g, const doubl
     const int ci = interior_dof<D>(g, i, ni);
     const int cj = interior_dof<D>(g, j, nj);
     v = global_entry<D>(g, mu, cw, winv, gamma, ci, ni, cj, nj);
+  } else {
+    v = i == j ? 1.0 : 0.0;
+  }
+  A[idx] = v;
+}
+
+// [Q3]^2 x P2disc: the same tiles from the degree-3 entries of A_gamma.
+__global__ void __launch_bounds__(256) k3_coarse_assemble(LevelGeo g, const double* __restrict__ mu,
+                                                           const double* __restrict__ winv, double gamma,
+                                                           int64_t n, int64_t ntiles, double* __restrict__ A) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= ntiles * kTT) return;
+  const int64_t t = idx / kTT;
+  const int e = (int)(idx - t * kTT);
+  int I, J;
+  tile_ij(t, I, J);
+  const int64_t i = (int64_t)I * kT + e / kT, j = (int64_t)J * kT + e % kT;
+  double v;
+  if (i < n && j < n) {
+    int ni[3], nj[3];
+    const int ci = interior_dof<2>(g, i, ni);
+    const int cj = interior_dof<2>(g, j, nj);
+    v = q3::global_entry(g, mu, winv, gamma, ci, ni[0], ni[1], cj, nj[0], nj[1]);
   } else {
     v = i == j ? 1.0 : 0.0;
   }
@@ -398,7 +422,10 @@ void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_
   const int64_t nb = coarse_tiles(H.n0);
   const int64_t ntiles = nb * (nb + 1) / 2;
   const dim3 grid(nblk(ntiles * kTT, 256));
-  if (H.dim == 2)
+  if (H.deg == 3)
+    hipLaunchKernelGGL(k3_coarse_assemble, grid, dim3(256), 0, s, l.g, (const double*)l.mu, (const double*)l.winv,
+                       H.gamma, H.n0, ntiles, A);
+  else if (H.dim == 2)
     hipLaunchKernelGGL(k_coarse_assemble<2>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);
   else
     hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);

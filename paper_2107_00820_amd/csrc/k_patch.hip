@@ -19,6 +19,7 @@
 // except the 81-unknown 3D interior patches, whose GEMV four wavefronts
 // share (split_symv81).
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "stk_dev.h"
@@ -665,6 +666,15 @@ static double asm_add_entry(const Hier& H, const Level& l, const R* r, R* zbuf, 
 template <class R>
 void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStream_t s, double* bytes_out,
                      R* zbuf) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) {
+      // [Q3]^2 x P2disc: one class of 50-unknown patches
+      const PatchClass& pc = l.cls[0];
+      for (int k = 0; k < reps; ++k) q3_asm_solves(H, l, r, zbuf ? zbuf : l.zbuf, s);
+      if (bytes_out) *bytes_out = 8.0 * ((double)l.nvel + (double)pc.count * (pc.n * (pc.n + 1) / 2 + pc.n));
+      return;
+    }
+  }
   AsmBatch<R> B{};
   const double bytes = asm_add_entry<R>(H, l, r, zbuf ? zbuf : reinterpret_cast<R*>(l.zbuf), B);
   const int v = l.asm_variant[sizeof(R) == 8 ? 0 : 1];
@@ -678,6 +688,10 @@ void launch_asm_gemv(const Hier& H, const Level& l, const R* r, int reps, hipStr
 template <class R>
 void launch_asm_gemv_batch(const Hier* const* hs, const Level* const* ls, const R* const* rs, int n,
                            hipStream_t s) {
+  if (n > 0 && hs[0]->deg == 3) {
+    for (int k = 0; k < n; ++k) launch_asm_gemv<R>(*hs[k], *ls[k], rs[k], 1, s, nullptr, nullptr);
+    return;
+  }
   for (int k0 = 0; k0 < n; k0 += kAsmBatchMax) {
     AsmBatch<R> B{};
     const int kn = std::min(kAsmBatchMax, n - k0);
@@ -702,6 +716,9 @@ void launch_asm_solves(Hier& H, const Level& l, const R* r, hipStream_t s) {
 
 template <class R>
 void launch_asm_gather(const Hier& H, const Level& l, const R* zbuf, R* y, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_asm_gather(H, l, zbuf, y, s);
+  }
   const int64_t n = (int64_t)H.dim * l.g.nnodes;
   if (H.dim == 2)
     hipLaunchKernelGGL((k_asm_gather<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
@@ -728,6 +745,9 @@ constexpr int kSplitCenterTiles = 512;
 template <class R>
 void launch_center_solve(const Hier& H, const Level& fine, const R* in, R* out, double alpha, bool accumulate,
                          hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_center_solve(H, fine, in, out, alpha, accumulate, s);
+  }
   const int nc = fine.g.N / 2;
   const int ncc = H.dim == 2 ? nc * nc : nc * nc * nc;
   const dim3 grid(nblk(ncc, 64)), blk(H.dim == 2 ? center_threads<2>() : center_threads<3>());

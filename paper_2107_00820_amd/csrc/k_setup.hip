@@ -165,6 +165,7 @@ __global__ void __launch_bounds__(256) k_patch_setup81(LevelGeo g, const double*
 // ---------------------------------------------------------------------------
 void launch_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
   if (pc.count == 0) return;
+  if (H.deg == 3) return q3_patch_setup(H, l, pc, s);
   if (H.dim == 3 && pc.n == kP81) {
     hipLaunchKernelGGL(k_patch_setup81, dim3(pc.count), dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma,
                        pc.verts, pc.count, pc.inv, H.flag);

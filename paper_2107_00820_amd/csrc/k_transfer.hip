@@ -5,6 +5,8 @@
 // fractions (1, 3/8, 3/4, -1/8, ...), so P_H itself introduces no rounding
 // beyond the sums. Both are node-parallel gathers (no atomics); the transpose
 // runs one axis at a time.
+#include <type_traits>
+
 #include "stk_internal.h"
 
 namespace stk {
@@ -147,6 +149,9 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 
 template <class R>
 void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const R* xc, R* xf, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_prolong_std(H, coarse, fine, xc, xf, s);
+  }
   const int64_t n = (int64_t)H.dim * fine.g.nnodes;
   if (H.dim == 2)
     hipLaunchKernelGGL((k_prolong_std<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
@@ -160,6 +165,9 @@ void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, c
 // coarse correction.
 template <class R>
 void launch_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const R* rf, R* rc, hipStream_t s) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (H.deg == 3) return q3_restrict_std(H, fine, coarse, rf, rc, s);
+  }
   const int64_t nf = fine.g.n1, nc = coarse.g.n1;
   R* t1 = reinterpret_cast<R*>(fine.T);
   if (H.dim == 2) {

@@ -66,8 +66,18 @@ stk_status validate(const stk_desc* d) {
   if (d->n_fine < 2 || d->n_fine % (1 << (d->n_levels - 1)) != 0)
     return fail(STK_EINVAL, "n_fine must be a positive multiple of 2^(n_levels-1)");
   if (d->n_fine > (d->dim == 2 ? 4096 : 256)) return fail(STK_EINVAL, "n_fine too large");
+  if (d->degree != 0 && d->degree != 2 && d->degree != 3) return fail(STK_EINVAL, "degree must be 0, 2 or 3");
+  const int deg = d->degree == 3 ? 3 : 2;
+  if (deg == 3) {
+    if (d->dim != 2) return fail(STK_EINVAL, "degree 3 ([Q3]^2 x P2disc) is built in 2D only");
+    if (d->coef_kind != 0) return fail(STK_EINVAL, "degree 3 takes the scalar sinker viscosity (coef_kind 0)");
+    if (d->mixed != 0) return fail(STK_EINVAL, "degree 3 has the FP64 form only (mixed 0)");
+    if (d->qpts_1d != 0 && d->qpts_1d != 4)
+      return fail(STK_EINVAL, "degree 3 uses the 4-point Gauss rule (qpts_1d 0 or 4)");
+    if (d->n_fine > 2048) return fail(STK_EINVAL, "n_fine too large");
+  }
   const int nc = d->n_fine >> (d->n_levels - 1);
-  const int64_t n0 = (int64_t)d->dim * ipow(2 * nc - 1, d->dim);
+  const int64_t n0 = (int64_t)d->dim * ipow(deg * nc - 1, d->dim);
   if (n0 > 80000) return fail(STK_EINVAL, "coarsest level too large for the dense coarse solve (80000 unknowns)");
   if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return fail(STK_EINVAL, "gamma must be finite and >= 0");
   if (d->schur != 1 && d->schur != 2) return fail(STK_EINVAL, "schur must be 1 (W = M_p) or 2 (W = M_p(1/mu))");
@@ -80,7 +90,7 @@ stk_status validate(const stk_desc* d) {
     if (!isfinite(v.mu_floor)) return fail(STK_EINVAL, "vp.mu_floor must be finite");
     if (d->schur != 1) return fail(STK_EINVAL, "the Newton state (coef_kind 2) needs W = M_p (schur = 1)");
   }
-  if (d->qpts_1d != 0 && d->qpts_1d != 3)
+  if (deg == 2 && d->qpts_1d != 0 && d->qpts_1d != 3)
     return fail(STK_EINVAL, "qpts_1d must be 0 or 3 (the 3-point Gauss rule is the one built)");
   if (d->coef_kind == 1) {
     const stk_viscoplastic& v = d->vp;
@@ -105,6 +115,21 @@ struct ClassPlan {
   int n;
   std::vector<int> verts;
 };
+
+// Degree 3: one class of 50-unknown patches (boundary patches padded), the
+// coarse-cell centre vertices first in lexicographic order of the coarse
+// cell, then the other vertices in lexicographic order.
+std::vector<ClassPlan> plan_patches_q3(int N) {
+  const int nv = N + 1, nc = N / 2;
+  ClassPlan all{50, {}};
+  for (int s = 0; s < nc * nc; ++s) all.verts.push_back((2 * (s % nc) + 1) + nv * (2 * (s / nc) + 1));
+  for (int vert = 0; vert < nv * nv; ++vert) {
+    const int v0 = vert % nv, v1 = vert / nv;
+    if ((v0 & 1) && (v1 & 1)) continue;
+    all.verts.push_back(vert);
+  }
+  return {all};
+}
 
 std::vector<ClassPlan> plan_patches(int D, int N) {
   const int nv = N + 1;
@@ -155,15 +180,18 @@ int64_t packed_doubles(int n, int count) {
 template <class F>
 stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes) {
   const int D = d->dim;
-  const int NN = ipow(3, D), NL = D * NN, NP = D + 1;
+  const int deg = d->degree == 3 ? 3 : 2;
+  const int NN = ipow(deg + 1, D), NL = D * NN, NP = deg == 3 ? 6 : D + 1;
+  const int PU = D * ipow(2 * deg - 1, D);   // unknowns of an interior star patch
   H.dim = D;
+  H.deg = deg;
   H.L = d->n_levels;
   H.lv.assign(H.L, Level{});
   for (int l = 0; l < H.L; ++l) {
     Level& L = H.lv[l];
     const int N = d->n_fine >> (H.L - 1 - l);
     L.g.N = N;
-    L.g.n1 = 2 * N + 1;
+    L.g.n1 = deg * N + 1;
     L.g.nnodes = D == 2 ? (int64_t)L.g.n1 * L.g.n1 : (int64_t)L.g.n1 * L.g.n1 * L.g.n1;
     L.g.ncell = D == 2 ? (int64_t)N * N : (int64_t)N * N * N;
     L.g.h = 1.0 / N;
@@ -193,8 +221,8 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     if (l >= 1) {
       STKCHK(alloc((size_t)(kMaxNu + 1) * L.nvel * 8, (void**)&L.V));
       STKCHK(alloc((size_t)kMaxNu * L.nvel * 8, (void**)&L.Z));
-      STKCHK(alloc((size_t)NL * L.nvert * 8, (void**)&L.zbuf));
-      std::vector<ClassPlan> plan = plan_patches(D, N);
+      STKCHK(alloc((size_t)PU * L.nvert * 8, (void**)&L.zbuf));
+      std::vector<ClassPlan> plan = deg == 3 ? plan_patches_q3(N) : plan_patches(D, N);
       L.cls.assign(plan.size(), PatchClass{});
       for (size_t c = 0; c < plan.size(); ++c) {
         L.cls[c].n = plan[c].n;
@@ -207,7 +235,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
     }
   }
   const Level& L0 = H.lv[0];
-  H.n0 = (int64_t)D * ipow(2 * L0.g.N - 1, D);
+  H.n0 = (int64_t)D * ipow(deg * L0.g.N - 1, D);
   {
     const size_t nb = (size_t)coarse_tiles(H.n0);
     STKCHK(alloc(nb * (nb + 1) / 2 * 4096 * 8, (void**)&H.Ainv0));
@@ -378,7 +406,7 @@ template <class R>
 void asm_solves(Hier& H, Level& L, const R* r) {
   Cohort* C = t_cohort;
   // members have the same level shapes, so they all take the same branch
-  if (!C || C->broken.load(std::memory_order_acquire) || asm_blocks(H, L) >= kCohortMaxBlocks) {
+  if (!C || C->broken.load(std::memory_order_acquire) || H.deg == 3 || asm_blocks(H, L) >= kCohortMaxBlocks) {
     launch_asm_solves<R>(H, L, r, H.stream);
     return;
   }
@@ -418,7 +446,7 @@ void apply_A(Hier& H, int l, const R* x, R* y) {
   for (int k = 0; k < reps; ++k) launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
   // algorithmic bytes of the cell kernel: u, coefficients at Gauss points, element outputs
   {
-    const double nn = H.dim == 2 ? 9.0 : 27.0;   // Gauss points (= nodes) per cell
+    const double nn = (double)ipow(H.deg + 1, H.dim);   // Gauss points (= nodes) per cell
     const double ncoef = L.cw ? 1.0 + H.dim * (H.dim + 1) / 2 : 1.0;   // mu [and w] per Gauss point
     prof_end(H, H.stream, PROF_ELEM, ev,
              (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)), reps);
@@ -435,7 +463,7 @@ void apply_A_dots(Hier& H, int l, const R* x, R* y, const R* V, int64_t ldv, int
   const int reps = prof_begin(H, H.stream, &ev);
   for (int k = 0; k < reps; ++k) launch_elem<R>(H, L, EL_VISC | EL_AUG, x, nullptr, nullptr, H.stream);
   {
-    const double nn = H.dim == 2 ? 9.0 : 27.0;
+    const double nn = (double)ipow(H.deg + 1, H.dim);
     const double ncoef = L.cw ? 1.0 + H.dim * (H.dim + 1) / 2 : 1.0;
     prof_end(H, H.stream, PROF_ELEM, ev,
              (double)sizeof(R) * ((double)L.nvel + (double)L.g.ncell * (ncoef * nn + H.dim * nn)), reps);
@@ -455,7 +483,7 @@ void asm_apply_A_dots(Hier& H, int l, const R* v, R* z, R* y, const R* V, int64_
   {
     // algorithmic bytes: patch outputs read, z written, coefficients and
     // element vectors of every cell
-    const double nn = 9.0;
+    const double nn = (double)ipow(H.deg + 1, 2);
     const double ncoef = L.cw ? 4.0 : 1.0;
     prof_end(H, H.stream, PROF_ELEM, ev,
              (double)sizeof(R) * (2.0 * nn * (double)L.nvert + (double)L.nvel +
@@ -861,7 +889,7 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
     if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
     launch_fill<double>(L.x, 0.0, L.nvel, s);
     if (l >= 1) {
-      std::vector<ClassPlan> plan = plan_patches(D, L.g.N);
+      std::vector<ClassPlan> plan = H.deg == 3 ? plan_patches_q3(L.g.N) : plan_patches(D, L.g.N);
       for (size_t c = 0; c < plan.size(); ++c) {
         if (hipMemcpyAsync(L.cls[c].verts, plan[c].verts.data(), plan[c].verts.size() * 4, hipMemcpyHostToDevice,
                            s) != hipSuccess)
@@ -1552,7 +1580,7 @@ stk_status stk_step_batch(stk_hier* const* hs, int n, void* stream) {
       if (!active(H) || H.sv.inflight) continue;
       const Hier::Solve& S = H.sv;
       if (cross && S.phase == Hier::SV_ARNOLDI && !S.graphs && !H.prof.on) {
-        const int form = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0) | (S.fcycle ? 4 : 0);
+        const int form = (S.mixed ? 1 : 0) | (S.upper ? 2 : 0) | (S.fcycle ? 4 : 0) | (H.deg == 3 ? 8 : 0);
         groups[std::make_tuple(H.dim, H.L, H.lv.back().g.N, H.nu_pre, H.nu_post, form)].push_back(&H);
         continue;
       }

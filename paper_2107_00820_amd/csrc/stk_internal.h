@@ -97,6 +97,7 @@ struct Prof {
 
 struct Hier {
   int dim = 2, L = 0, nu_pre = 2, nu_post = 2, schur = 1;
+  int deg = 2;                       // velocity degree k: 2, or 3 ([Q3]^2 x P2disc, 2D, FP64)
   double gamma = 0.0;
   int n_sinkers = 0;
   double omega = 0.1, delta = 200.0, mu_min = 1.0, mu_max = 1.0, beta = 10.0;
@@ -269,6 +270,27 @@ template <class A, class B>
 void launch_convert(const A* x, B* y, int64_t n, hipStream_t s);
 void launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
 void launch_fill_int(int* x, int v, int64_t n, hipStream_t s);
+
+// ---- [Q3]^2 x P2disc levels (Hier::deg == 3; 2D, FP64, scalar viscosity):
+// the same operations as the launchers above, which route to these ----
+void q3_mu_sinker(const Hier& H, const Level& l, double* out, hipStream_t s);
+void q3_rhs_elem(const Hier& H, const Level& l, hipStream_t s);
+void q3_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
+             hipStream_t s);
+void q3_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out, hipStream_t s);
+void q3_winv_setup(const Hier& H, const Level& l, hipStream_t s);
+void q3_schur_setup(const Hier& H, const Level& l, hipStream_t s);
+void q3_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp, hipStream_t s);
+void q3_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s);
+void q3_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s);
+void q3_asm_solves(const Hier& H, const Level& l, const double* r, double* zbuf, hipStream_t s);
+void q3_asm_gather(const Hier& H, const Level& l, const double* zbuf, double* y, hipStream_t s);
+void q3_center_solve(const Hier& H, const Level& fine, const double* in, double* out, double alpha,
+                     bool accumulate, hipStream_t s);
+void q3_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc, double* xf,
+                    hipStream_t s);
+void q3_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf, double* rc,
+                     hipStream_t s);
 
 // layout of Level::small
 constexpr int kSmallH = 0;                               // H[(kMaxNu+1) x kMaxNu], row i col j at i*kMaxNu+j

@@ -65,7 +65,9 @@ stk_status stk_asm_noalloc(stk_hier* h, int level, int dtype, const void* r, voi
   if (!r || !y || r == y) return fail_na(STK_EINVAL, "r, y must be distinct non-NULL buffers");
   const Level& L = H.lv[level];
   const size_t per = dtype == STK_F64 ? 8 : 4;
-  const size_t need = (size_t)H.dim * (H.dim == 2 ? 9 : 27) * (size_t)L.nvert * per;
+  // patch outputs per vertex: d (2k-1)^d for velocity degree k
+  const size_t side = (size_t)(2 * H.deg - 1);
+  const size_t need = (size_t)H.dim * (H.dim == 2 ? side * side : side * side * side) * (size_t)L.nvert * per;
   if (need > kScratchBytes)
     return fail_na(STK_EINVAL, "level needs " + std::to_string(need) + " B of patch outputs; the static buffer holds " +
                                    std::to_string(kScratchBytes) + " B");

@@ -49,7 +49,8 @@ class Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_fine", C.c_int), ("n_levels", C.c_int), ("qpts_1d", C.c_int),
                 ("gamma", C.c_double),
                 ("schur", C.c_int), ("coef_kind", C.c_int), ("sinker", Sinker), ("vp", Viscoplastic),
-                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t)]
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("mixed", C.c_int), ("hbm_budget", C.c_size_t),
+                ("degree", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -162,10 +163,11 @@ def _dptr(*ts):
 
 def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, delta=200.0, beta=10.0,
               nu_pre=2, nu_post=2, hbm_budget=0, mixed=0, vp_amp=None, vp_tau_y=0.0, vp_eps_scale=0.0, schur=1,
-              vp_mu_floor=0.0, qpts_1d=0, newton=False):
+              vp_mu_floor=0.0, qpts_1d=0, newton=False, degree=2):
     """Descriptor; vp_amp (array [d][M]^d) selects the viscoplastic Newton
     tensor over the sinker base field (coef_kind 1); newton=True the
-    viscoplastic state for the Newton loop (coef_kind 2, with vp_tau_y)."""
+    viscoplastic state for the Newton loop (coef_kind 2, with vp_tau_y);
+    degree=3 the [Q3]^2 x P2disc discretisation."""
     centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, dim))
     d = Desc()
     d.dim, d.n_fine, d.n_levels, d.gamma = dim, n_fine, n_levels, float(gamma)
@@ -188,6 +190,7 @@ def make_desc(dim, n_fine, n_levels, gamma, centers, mu_min, mu_max, omega=0.1, 
     d.sinker.mu_min, d.sinker.mu_max = mu_min, mu_max
     d.nu_pre, d.nu_post = nu_pre, nu_post
     d.hbm_budget = int(hbm_budget)
+    d.degree = int(degree)
     d._keep = centers          # keep the host array alive while the desc is used
     return d
 
@@ -204,7 +207,8 @@ def desc_from_workload(wl, hbm_budget=0, mixed=0):
     elif wl.coef_kind == 2:
         vp = dict(newton=True, vp_tau_y=wl.tau_y, vp_mu_floor=wl.mu_floor)
     return make_desc(wl.dim, wl.n_fine, wl.levels, wl.gamma, wl.centers(), wl.mu_min, wl.mu_max,
-                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, schur=getattr(wl, "schur", 1), **vp)
+                     OMEGA, DELTA, BETA, wl.nu_pre, wl.nu_post, hbm_budget, mixed, schur=getattr(wl, "schur", 1),
+                     degree=getattr(wl, "degree", 2), **vp)
 
 
 def stk_step_batch(hierarchies) -> int:

@@ -109,3 +109,31 @@ def test_descriptor_fields_of_the_boundary():
     d.vp.eps_scale = float("inf")
     with pytest.raises(stk.StkError):
         stk.stk_footprint(d)
+
+
+def test_degree_three_descriptor():
+    """degree 3 ([Q3]^2 x P2disc) is accepted in 2D with the scalar law and
+    the FP64 form; its footprint holds 16 Gauss points per cell, 6 pressure
+    unknowns per cell and 50-unknown patch inverses; other combinations are
+    rejected on the host."""
+    from paper_2107_00820_amd import stk
+    from workloads import small
+    wl3 = small(2, 64, 3, gamma=1e3, dr=1e4, degree=3)
+    wl2 = small(2, 64, 3, gamma=1e3, dr=1e4)
+    f3, f2 = stk.stk_footprint(stk.desc_from_workload(wl3)), stk.stk_footprint(stk.desc_from_workload(wl2))
+    # packed 50-unknown inverses on the finest level alone: 65^2 patches x 1275 doubles
+    assert f3 - f2 >= 8 * 65 * 65 * (1275 - 171)
+    for q, ok in ((0, True), (4, True), (3, False)):
+        d = stk.desc_from_workload(wl3)
+        d.qpts_1d = q
+        if ok:
+            assert stk.stk_footprint(d) > 0
+        else:
+            with pytest.raises(stk.StkError):
+                stk.stk_footprint(d)
+    for field, value in (("mixed", 1), ("dim", 3), ("coef_kind", 1), ("degree", 4)):
+        d = stk.desc_from_workload(wl3)
+        setattr(d, field, value)
+        with pytest.raises(stk.StkError) as e:
+            stk.stk_footprint(d)
+        assert e.value.status == stk.STK_EINVAL

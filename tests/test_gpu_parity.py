@@ -252,7 +252,7 @@ def test_solve_matches_oracle(name):
     assert np.array_equal(to_host(xu2), to_host(xu)) and np.array_equal(to_host(xp2), to_host(xp))
 
 
-@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2", "3d_8_L2_tensor"])
+@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2", "3d_8_L2_tensor", "q3_2d_16_L3"])
 @pytest.mark.parametrize("cycle", ["V", "F"])
 def test_solve_variants_match_oracle(name, cycle):
     """FGMRES with the block upper-triangular preconditioner (V-cycle) or
@@ -275,7 +275,7 @@ def test_solve_variants_match_oracle(name, cycle):
     assert np.linalg.norm(b - orc.K @ x) <= wl.rtol * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "3d_8_L2"])
+@pytest.mark.parametrize("name", ["sinker_2d_16sq_L2", "3d_8_L2", "q3_2d_8_L2"])
 def test_graph_replay_matches_eager(name):
     """Each Arnoldi step is captured once as a HIP graph and replayed; every
     replay must reproduce the plain-launch solve bit for bit, also with

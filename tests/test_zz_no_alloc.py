@@ -20,7 +20,7 @@ def noalloc(h, level, r, y):
     return stk.load().stk_asm_noalloc(h._h, level, code, pr, py, stk._stream())
 
 
-@pytest.mark.parametrize("name", ["2d_32_L3", "3d_16_L3"])
+@pytest.mark.parametrize("name", ["2d_32_L3", "3d_16_L3", "q3_2d_16_L3"])
 def test_noalloc_asm_equals_asm_twice(name):
     log(f"[noalloc] {name}")
     orc, gpu = oracle_for(name), gpu_for(name)
@@ -59,5 +59,12 @@ def test_noalloc_rejects_oversized_level():
     st = noalloc(h, 4, r, y)
     assert st == stk.STK_EINVAL and b"static buffer" in stk.load().stk_last_error()
     # a smaller level of the same hierarchy fits
+    assert noalloc(h, 3, h.zeros_u(3), h.zeros_u(3)) == 0
+    h.close()
+    # degree 3: 50 patch outputs per vertex, so 2D 512^2 (263,169 vertices,
+    # 105 MB) is over the limit where Q2 (38 MB) is not
+    h = Hierarchy.from_workload(small(2, 512, 5, gamma=1e2, dr=1e2, n_sinkers=4, seed=5, degree=3))
+    st = noalloc(h, 4, h.zeros_u(4), h.zeros_u(4))
+    assert st == stk.STK_EINVAL and b"static buffer" in stk.load().stk_last_error()
     assert noalloc(h, 3, h.zeros_u(3), h.zeros_u(3)) == 0
     h.close()
