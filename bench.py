@@ -268,6 +268,54 @@ def cohort_bursts(m=8):
     return out
 
 
+def q3_leg(steps):
+    """[Q3]^2 x P2disc on the 2D 128^2 mesh (4 levels, 24 sinkers) with the
+    settings of the paper's table "linear" (P1, gamma 1000, contrast 1e10,
+    F-cycles, 5 + 5 relaxation steps, FGMRES(30) to a 1e6 reduction): timed
+    solves, and the degree-3 patch-solve kernel's rate on the finest level
+    from HIP events in one plain-launch solve."""
+    import json as _json
+    import torch
+    from workloads import PAPER_LINEAR_Q3, PAPER_LINEAR_Q3_PRINTED
+    from paper_2107_00820_amd import Hierarchy
+    key = (1, 1000.0, 1e10)
+    wl = PAPER_LINEAR_Q3[key]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = Hierarchy.from_workload(wl)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bu, bp = h.stk_rhs()
+    xu, xp = h.zeros_u(), h.zeros_p()
+    kw = dict(rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp, cycle=wl.cycle)
+    _, _, info = h.stk_solve(bu, bp, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, info = h.stk_solve(bu, bp, **kw)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    h.stk_profile(True, reps=1)
+    h.stk_solve(bu, bp, eager=True, **kw)
+    n_f, ms_f, by_f = h.stk_profile_read(2)
+    h.stk_profile(False)
+    h.close()
+    n_u, n_p = wl.unknowns()
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "paper_tables_oracle.json")
+    orc = _json.load(open(golden)).get(wl.name, {}).get("iters")
+    ach = by_f / (ms_f * 1e-3) / 1e9 if ms_f > 0 else 0.0
+    log(f"[bench] Q3 {wl.name}: {info['iters']} iterations (oracle {orc}, paper {PAPER_LINEAR_Q3_PRINTED[key]}), "
+        f"{1e3 * t:.1f} ms, fine-level patch solves {ach:.0f} GB/s")
+    return {"workload": wl.name, "degree": 3, "unknowns": n_u + n_p,
+            "unknowns_paper_convention": 2 * (3 * wl.n_fine + 1) ** 2 + n_p, "setup_s": t_setup,
+            "ms_per_solve": 1e3 * t, "dof_per_s": (n_u + n_p) / t, "iterations": info["iters"],
+            "iterations_oracle": orc, "iterations_paper": PAPER_LINEAR_Q3_PRINTED[key], "rel_res": info["rel_res"],
+            "patch_solve_fine_level": {"kernel": "k3_asm_solves", "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+                                       "avg_launch_us": 1e3 * ms_f / max(n_f, 1),
+                                       "algorithmic_bytes_per_launch": by_f / max(n_f, 1),
+                                       "launches_per_solve": n_f}}
+
+
 def newton_leg(name):
     """The viscoplastic problem solved by Newton's method on the GPU
     (stk_newton: relinearise, FGMRES step, line search), timed whole."""
@@ -410,6 +458,7 @@ def main():
             out["other_workloads"][name] = other_workload(name, max(2, args.steps // 2))
     if not args.no_extra:
         out["newton"] = newton_leg("newton_3d_32cu_L3")
+        out["q3"] = q3_leg(max(2, args.steps // 2))
     if not args.no_serving and args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.budget_gb, args.serving_pc)
         # the same stream with the cross-request batched patch solves turned on

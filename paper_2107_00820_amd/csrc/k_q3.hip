@@ -410,11 +410,20 @@ __global__ void __launch_bounds__(64) k3_center_solve(LevelGeo g, const double* 
     x[i] = in[c * g.nnodes + nd];
   }
   patch_symv(inv, s, x, y);
+  // with ACC, all 50 old values are loaded before the first store (loads and
+  // stores interleaved per entry would each wait for the previous store)
+  if (ACC) {
+#pragma unroll
+    for (int i = 0; i < PU; ++i) {
+      const int c = i / PN, a = i % PN;
+      x[i] = out[c * g.nnodes + (int64_t)(6 * k0 + 1 + a % PA) + (int64_t)g.n1 * (6 * k1 + 1 + a / PA)];
+    }
+  }
 #pragma unroll
   for (int i = 0; i < PU; ++i) {
     const int c = i / PN, a = i % PN;
     const int64_t idx = c * g.nnodes + (int64_t)(6 * k0 + 1 + a % PA) + (int64_t)g.n1 * (6 * k1 + 1 + a / PA);
-    out[idx] = ACC ? out[idx] + alpha * y[i] : alpha * y[i];
+    out[idx] = ACC ? x[i] + alpha * y[i] : alpha * y[i];
   }
 }
 

@@ -1,9 +1,10 @@
 """Writes tests/golden/paper_tables_oracle.json: the oracle's FGMRES
-iteration counts at the settings of the paper's Q2 iteration tables
+iteration counts at the settings of the paper's iteration tables
 (workloads.PAPER_VANKA_AL: table "vanka", AL column; workloads.PAPER_K2_SMALL:
-table "k", k = 2, on a 12^3 mesh). Calls only the oracle.
+table "k", k = 2, on a 12^3 mesh; workloads.PAPER_LINEAR_Q3: table "linear",
+2D, [Q3]^2 x P2disc, robust rows). Calls only the oracle.
 
-    python tests/golden/make_paper_tables.py [--only vanka|k2]
+    python tests/golden/make_paper_tables.py [--only vanka|k2|linear_q3]
 """
 import json
 import os
@@ -14,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle.krylov import StokesSolver  # noqa: E402
-from workloads import PAPER_VANKA_AL, PAPER_K2_SMALL  # noqa: E402
+from workloads import PAPER_VANKA_AL, PAPER_K2_SMALL, PAPER_LINEAR_Q3  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_tables_oracle.json")
 
@@ -36,6 +37,10 @@ def main():
             json.dump(out, open(OUT, "w"), indent=1, sort_keys=True)
     if only in (None, "k2"):
         for wl in PAPER_K2_SMALL.values():
+            out[wl.name] = run(wl)
+            json.dump(out, open(OUT, "w"), indent=1, sort_keys=True)
+    if only in (None, "linear_q3"):
+        for wl in PAPER_LINEAR_Q3.values():
             out[wl.name] = run(wl)
             json.dump(out, open(OUT, "w"), indent=1, sort_keys=True)
 

@@ -124,6 +124,16 @@ PAPER_K2_SMALL = {g: Workload(f"k2_12cu_g{g:g}", 3, 12, 2, 24, 1e6, g, 700, nu_p
                               schur=2, cycle="F") for g in (0.0, 10.0, 1000.0)}
 
 
+# table "linear", 2D (robust smoother and transfer): [Q3]^2 x P2disc on the
+# 2D 128^2 mesh with 4 levels, 24 sinkers, F-cycles with 5 pre- and 5
+# post-relaxation steps, FGMRES(30) to a 1e6 residual reduction, P1 and P2
+PAPER_LINEAR_Q3 = {(schur, g, dr): Workload(f"linear_q3_p{schur}_g{g:g}_dr{dr:g}", 2, 128, 4, 24, dr, g, 800,
+                                            nu_pre=5, nu_post=5, rtol=1e-6, schur=schur, cycle="F", degree=3)
+                   for schur in (1, 2) for g in (10.0, 1000.0) for dr in (1e6, 1e10)}
+PAPER_LINEAR_Q3_PRINTED = {(1, 10.0, 1e6): 11, (1, 10.0, 1e10): 22, (1, 1000.0, 1e6): 13, (1, 1000.0, 1e10): 15,
+                           (2, 10.0, 1e6): 19, (2, 10.0, 1e10): 27, (2, 1000.0, 1e6): 12, (2, 1000.0, 1e10): 16}
+
+
 # Viscoplastic Newton problems (capped law over a multi-sinker base field,
 # solved from rest): 8 sinkers, contrast 1e4; tau_y is about the 90th
 # percentile of 2 mu0 eps_II of the first (Newtonian) iterate, so roughly a
