@@ -23,7 +23,10 @@
 // the factored form keeps the inverse as accurate as one formed from the
 // Cholesky factor of the whole matrix. The rank-64 updates are 64 x 64 x 64
 // tile products on the FP64 matrix cores (v_mfma_f64_16x16x4f64); the pivot
-// factorisation and inversion run in LDS.
+// factorisation and inversion run in LDS. Pivots are taken in pairs with a
+// look-ahead on the second one's block column, so that one pass over the
+// matrix applies both updates (half the passes; the same products, summed
+// in one accumulator per tile).
 #include "stk_q3.h"
 #include "stk_spd.h"
 
@@ -228,23 +231,14 @@ __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ 
       }
 }
 
-// A_IJ -= V_I V_J^T for every lower tile with I, J != K. The MFMA operands
-// are read straight from global memory (V_I and V_J are shared by a whole
-// block row / column and stay in L2), so there is no LDS staging or barrier.
-__global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
-  int I, J;
-  tile_ij(blockIdx.x, I, J);
-  if (I == K || J == K) return;
+// acc += X Y^T over k = 0..63 for panel blocks stored transposed (X[r][k]
+// at k*64 + r). The MFMA operands are read straight from global memory (the
+// panel blocks are shared by a whole block row / column and stay in L2), so
+// there is no LDS staging or barrier.
+__device__ inline void panel_gemm_acc(const double* __restrict__ X, const double* __restrict__ Y, d4 acc[2][2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
   const int li = lane & 15, lk = lane >> 4;
-  const double* X = W + (int64_t)I * kTT;                  // V_I[r][k] at k*64 + r
-  const double* Y = W + (int64_t)J * kTT;                  // V_J[c][k] at k*64 + c
-  d4 acc[2][2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < kT; k0 += 4) {
     const int k = k0 + lk;
@@ -255,7 +249,9 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
     acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
-  double* T = tile_ptr(A, I, J);
+}
+
+__device__ inline void tile_sub(double* __restrict__ T, const d4 acc[2][2]) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -266,6 +262,58 @@ __global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, in
         acc_rc(a, b, r, row, col);
         T[row * kT + col] -= acc[a][b][r];
       }
+}
+
+// A_IJ -= V_I V_J^T for every lower tile with I, J != K.
+__global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  if (I == K || J == K) return;
+  d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+  panel_gemm_acc(W + (int64_t)I * kTT, W + (int64_t)J * kTT, acc);
+  tile_sub(tile_ptr(A, I, J), acc);
+}
+
+// Two pivot blocks per pass over the matrix (look-ahead): after the panel of
+// pivot K, only block column K+1 is brought up to date (this kernel: tile of
+// (I, K+1) for every I != K, including the pivot tile (K+1, K+1)), so that
+// pivot K+1 can be factored and its panel formed before the one pass that
+// applies both rank-64 updates (k_sweep_update2).
+__global__ void __launch_bounds__(256) k_sweep_colupdate(double* __restrict__ A, int K, const double* __restrict__ W) {
+  const int I = blockIdx.x;
+  if (I == K) return;
+  const int Kn = K + 1;
+  const int a = I > Kn ? I : Kn, b = I > Kn ? Kn : I;   // lower tile (a, b), a >= b
+  d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+  panel_gemm_acc(W + (int64_t)a * kTT, W + (int64_t)b * kTT, acc);
+  tile_sub(tile_ptr(A, a, b), acc);
+}
+
+// The combined update of pivots K (panel V) and K+1 (panel V2): every lower
+// tile outside block row and column K+1 loses V2_I V2_J^T, and those outside
+// block row and column K as well V_I V_J^T (block row and column K already
+// hold their step-K values, written by k_sweep_write).
+__global__ void __launch_bounds__(256) k_sweep_update2(double* __restrict__ A, int K, const double* __restrict__ V,
+                                                        const double* __restrict__ V2) {
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  if (I == K + 1 || J == K + 1) return;
+  d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+  if (I != K && J != K) panel_gemm_acc(V + (int64_t)I * kTT, V + (int64_t)J * kTT, acc);
+  panel_gemm_acc(V2 + (int64_t)I * kTT, V2 + (int64_t)J * kTT, acc);
+  tile_sub(tile_ptr(A, I, J), acc);
 }
 
 // A_IK <- V_I L^{-1} (tile (I,K) for I > K, its transpose in tile (K,I) for
@@ -431,14 +479,34 @@ void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_
     hipLaunchKernelGGL(k_coarse_assemble<3>, grid, dim3(256), 0, s, l.g, l.mu, l.cw, l.winv, H.gamma, H.n0, ntiles, A);
 }
 
-// work: P^{-1} (kTT) + V (nb * kTT) doubles; the pivot's L^{-1} sits in the
-// block-row slot K of V, which the panel leaves unused.
+// work: P^{-1} (kTT) + two panels V, V2 (nb * kTT each) doubles; a pivot's
+// L^{-1} sits in the block-row slot of its own panel, which the panel leaves
+// unused. Pivots go in pairs (one pass over the matrix per pair; the pivot
+// of a pair's second block is factored after the first block's panel has
+// updated its block column), the last one alone if nb is odd.
 int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipStream_t s) {
   const int nb = coarse_tiles(n);
   const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
   double* Pinv = work;
   double* V = work + kTT;
-  for (int K = 0; K < nb; ++K) {
+  double* V2 = V + (int64_t)nb * kTT;
+  int K = 0;
+  for (; K + 1 < nb; K += 2) {
+    double* Linv = V + (int64_t)K * kTT;
+    double* Linv2 = V2 + (int64_t)(K + 1) * kTT;
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, Linv, H.flag);
+    hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, (const double*)Linv, V);
+    hipLaunchKernelGGL(k_sweep_colupdate, dim3(nb), dim3(256), 0, s, A, K, (const double*)V);
+    hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K, (const double*)Pinv, (const double*)Linv,
+                       (const double*)V);
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K + 1, Pinv, Linv2, H.flag);
+    hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K + 1, (const double*)Linv2, V2);
+    hipLaunchKernelGGL(k_sweep_update2, dim3((unsigned)ntiles), dim3(256), 0, s, A, K, (const double*)V,
+                       (const double*)V2);
+    hipLaunchKernelGGL(k_sweep_write, dim3(nb), dim3(256), 0, s, A, K + 1, (const double*)Pinv,
+                       (const double*)Linv2, (const double*)V2);
+  }
+  if (K < nb) {
     double* Linv = V + (int64_t)K * kTT;
     hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, s, A, K, Pinv, Linv, H.flag);
     hipLaunchKernelGGL(k_sweep_panel, dim3(nb), dim3(256), 0, s, A, K, (const double*)Linv, V);

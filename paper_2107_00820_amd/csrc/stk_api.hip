@@ -239,7 +239,7 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   {
     const size_t nb = (size_t)coarse_tiles(H.n0);
     STKCHK(alloc(nb * (nb + 1) / 2 * 4096 * 8, (void**)&H.Ainv0));
-    STKCHK(alloc((nb + 1) * 4096 * 8, (void**)&H.cwork));
+    STKCHK(alloc((2 * nb + 1) * 4096 * 8, (void**)&H.cwork));
     STKCHK(alloc(nb * 64 * 8, (void**)&H.cvec));
     STKCHK(alloc(nb * nb * 64 * 8, (void**)&H.cpart));
   }

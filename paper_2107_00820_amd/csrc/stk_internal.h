@@ -112,7 +112,7 @@ struct Hier {
   // coarse level
   int64_t n0 = 0;
   double* Ainv0 = nullptr;           // -A_0^{-1}, lower triangle in 64 x 64 tiles
-  double* cwork = nullptr;           // sweep work: pivot inverse + panel
+  double* cwork = nullptr;           // sweep work: pivot inverse + two panels
   double* cvec = nullptr;            // gathered coarse right-hand side (64 * tiles)
   double* cpart = nullptr;           // tile GEMV partials (tiles^2 * 64)
   // finest-level Schur blocks and pressure work
