@@ -26,94 +26,104 @@ __device__ inline bool bnd_node(const LevelGeo& g, int i0, int i1) {
 
 // ---------------------------------------------------------------------------
 // Cell kernel: element vectors E[cell][comp * 16 + n] of the terms in MODE
-// (EL_VISC, EL_AUG, EL_BT) and, with EL_BOUT, (B u)_K into pout.
+// (EL_VISC, EL_AUG, EL_BT) and, with EL_BOUT, (B u)_K into pout. Four cells
+// per 64-lane workgroup, 16 lanes per cell: lane t loads node t, then forms
+// the stress at Gauss point t, then the outputs of node t; the six pressure
+// moments are formed by lanes 0..5 of the cell. Exchanges through LDS.
 template <int MODE>
 __global__ void __launch_bounds__(64) k3_elem(LevelGeo g, const double* __restrict__ mu,
                                               const double* __restrict__ winv, double gamma,
                                               const double* __restrict__ u, const double* __restrict__ p,
                                               double* __restrict__ E, double* __restrict__ pout) {
-  constexpr const Tab& T = RefQ3::T;
-  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (cell >= g.ncell) return;
+  const Tab& T = cQ3;
+  __shared__ double su[4][NL];
+  __shared__ double ss[4][NQ][3];
+  __shared__ double sp[4][NP];
+  const int c = threadIdx.x >> 4, t = threadIdx.x & 15;
+  const int64_t cell0 = (int64_t)blockIdx.x * 4 + c;
+  const bool valid = cell0 < g.ncell;
+  const int64_t cell = valid ? cell0 : g.ncell - 1;   // lanes past the end take part in the barriers
   const int c0 = (int)(cell % g.N), c1 = (int)(cell / g.N);
-  double ue[NL], e[NL];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) e[j] = 0.0;
-  if (MODE & (EL_VISC | EL_AUG | EL_BOUT)) {
+  constexpr bool NEED_U = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  if (NEED_U) {
+    const int i0 = 3 * c0 + t % NA, i1 = 3 * c1 + t / NA;
+    const bool b = bnd_node(g, i0, i1);
+    const int64_t nd = (int64_t)i0 + (int64_t)g.n1 * i1;
+    su[c][t] = b ? 0.0 : u[nd];
+    su[c][NN + t] = b ? 0.0 : u[g.nnodes + nd];
+  }
+  __syncthreads();
+  double e0 = 0.0, e1 = 0.0;   // outputs of node t, components 0 and 1
+  if (MODE & EL_VISC) {
+    const int q = t;
+    double G00 = 0.0, G01 = 0.0, G10 = 0.0, G11 = 0.0;
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      const int i0 = 3 * c0 + n % NA, i1 = 3 * c1 + n / NA;
-      const bool b = bnd_node(g, i0, i1);
-      const int64_t nd = (int64_t)i0 + (int64_t)g.n1 * i1;
-      ue[n] = b ? 0.0 : u[nd];
-      ue[NN + n] = b ? 0.0 : u[g.nnodes + nd];
+      const double d0 = T.dphi[q][n][0], d1 = T.dphi[q][n][1];
+      G00 += d0 * su[c][n];
+      G01 += d1 * su[c][n];
+      G10 += d0 * su[c][NN + n];
+      G11 += d1 * su[c][NN + n];
+    }
+    const double wm = T.w[q] * mu[cell * NQ + q];
+    ss[c][q][0] = wm * 2.0 * G00;
+    ss[c][q][1] = wm * 2.0 * G11;
+    ss[c][q][2] = wm * (G01 + G10);
+  }
+  if (MODE & (EL_AUG | EL_BOUT | EL_BT)) {
+    if (t < NP) {
+      const int m = t;
+      double v = 0.0;
+      if (MODE & (EL_AUG | EL_BOUT)) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) v += T.bhat[m][j] * su[c][j];
+      }
+      if ((MODE & EL_BOUT) && valid) pout[cell * NP + m] = -g.h * v;
+      sp[c][m] = v;
     }
   }
+  __syncthreads();
   if (MODE & EL_VISC) {
+    const int n = t;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      double G[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-#pragma unroll
-      for (int n = 0; n < NN; ++n)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          G[0][k] += T.dphi[q][n][k] * ue[n];
-          G[1][k] += T.dphi[q][n][k] * ue[NN + n];
-        }
-      const double wm = T.w[q] * mu[cell * NQ + q];
-      const double s00 = wm * 2.0 * G[0][0], s11 = wm * 2.0 * G[1][1], s01 = wm * (G[0][1] + G[1][0]);
-#pragma unroll
-      for (int n = 0; n < NN; ++n) {
-        e[n] += s00 * T.dphi[q][n][0] + s01 * T.dphi[q][n][1];
-        e[NN + n] += s01 * T.dphi[q][n][0] + s11 * T.dphi[q][n][1];
-      }
+      const double d0 = T.dphi[q][n][0], d1 = T.dphi[q][n][1];
+      e0 += ss[c][q][0] * d0 + ss[c][q][2] * d1;
+      e1 += ss[c][q][2] * d0 + ss[c][q][1] * d1;
     }
   }
-  if (MODE & (EL_AUG | EL_BOUT)) {
-    double bu[NP];
+  if (MODE & (EL_AUG | EL_BT)) {
+    // pressure-side coefficients per cell: gamma W^{-1} (B u)-moments and/or -h p
+    double tm[NP];
 #pragma unroll
-    for (int m = 0; m < NP; ++m) {
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) s += T.bhat[m][j] * ue[j];
-      bu[m] = s;
-    }
+    for (int m = 0; m < NP; ++m) tm[m] = 0.0;
     if (MODE & EL_AUG) {
-      double t[NP];
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * bu[k];
-        t[m] = gamma * s;
-      }
-#pragma unroll
-      for (int j = 0; j < NL; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < NP; ++m) s += T.bhat[m][j] * t[m];
-        e[j] += s;
+        for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[c][k];
+        tm[m] = gamma * s;
       }
     }
-    if (MODE & EL_BOUT) {
+    if (MODE & EL_BT) {
 #pragma unroll
-      for (int m = 0; m < NP; ++m) pout[cell * NP + m] = -g.h * bu[m];
+      for (int m = 0; m < NP; ++m) tm[m] -= g.h * p[cell * NP + m];
     }
-  }
-  if (MODE & EL_BT) {
-    double pc[NP];
+    const int n = t;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int m = 0; m < NP; ++m) pc[m] = p[cell * NP + m];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < NP; ++m) s += T.bhat[m][j] * pc[m];
-      e[j] -= g.h * s;
+    for (int m = 0; m < NP; ++m) {
+      a0 += T.bhat[m][n] * tm[m];
+      a1 += T.bhat[m][NN + n] * tm[m];
     }
+    e0 += a0;
+    e1 += a1;
   }
-#pragma unroll
-  for (int j = 0; j < NL; ++j) E[cell * NL + j] = e[j];
+  if (valid) {
+    E[cell * NL + t] = e0;
+    E[cell * NL + NN + t] = e1;
+  }
 }
 
 // out[idx] = base[idx] + alpha * sum of the element outputs of the cells
@@ -513,7 +523,7 @@ using namespace q3;
 
 void q3_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
              hipStream_t s) {
-  const dim3 grid(nblk(l.g.ncell, 64)), blk(64);
+  const dim3 grid(nblk(l.g.ncell, 4)), blk(64);
   switch (mode) {
     case EL_VISC | EL_AUG:
       hipLaunchKernelGGL(k3_elem<EL_VISC | EL_AUG>, grid, blk, 0, s, l.g, l.mu, l.winv, H.gamma, u, p, l.E, pout);
