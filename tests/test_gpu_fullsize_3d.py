@@ -73,3 +73,40 @@ def test_fullsize_sampled(name):
     assert np.max(np.abs(r_v)) <= wl.rtol * bnorm and np.max(np.abs(r_p)) <= wl.rtol * bnorm
     gpu.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3"])
+def test_fullsize_solve_against_recorded_oracle_solve(name):
+    """The full-size solve against the oracle's own solve of the same
+    workload, recorded once (tests/golden/fullsize_oracle.json, written by
+    make_fullsize_golden.py from the oracle alone; minutes of CPU and tens
+    of GB): the same FGMRES iteration count, residual histories within 1e-6
+    (relative) over the first restart cycle, solution norms within 1e-8 and
+    2,000 seeded solution entries within 1e-8 of the solution norm."""
+    import json
+    import os
+    from oracle.fem import Level
+    from paper_2107_00820_amd import Hierarchy
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_oracle.json")
+    rec = json.load(open(golden)).get(name)
+    if rec is None:
+        pytest.skip(f"no recorded oracle solve of {name}")
+    wl = CONFIGS[name]
+    lv = Level(wl.dim, wl.n_fine)
+    gpu = Hierarchy.from_workload(wl)
+    bu, bp = gpu.stk_rhs()
+    xu, xp, info = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+    x = np.concatenate([lv.from_stored(to_host(xu)), to_host(xp)])
+    log(f"[fullsize solve] {name}: GPU {info['iters']} iterations, oracle {rec['iters']}")
+    assert info["converged"] and info["iters"] == rec["iters"]
+    m = min(len(rec["hist"]), wl.restart + 1)
+    assert np.allclose(np.array(info["hist"][:m]), np.array(rec["hist"][:m]), rtol=1e-6, atol=1e-14)
+    nu = rec["n_u"]
+    nx = np.hypot(rec["norm_u"], rec["norm_p"])
+    assert abs(np.linalg.norm(x[:nu]) - rec["norm_u"]) <= 1e-8 * nx
+    assert abs(np.linalg.norm(x[nu:]) - rec["norm_p"]) <= 1e-8 * nx
+    idx = np.array(rec["sample_index"])
+    err = np.max(np.abs(x[idx] - np.array(rec["sample_value"])))
+    log(f"  sampled solution: max err {err:.2e} (of the solution norm {nx:.2e})")
+    assert err <= 1e-8 * nx
+    gpu.close()
