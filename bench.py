@@ -146,7 +146,7 @@ def time_form(h, wl, bu, bp, xu, xp, form, steps, warmup, profile_pass):
     import torch
     mixed = form.startswith("mixed")
     pc = "upper" if "_upper" in form else "full"
-    cycle = "F" if form.endswith("_F") else "V"
+    cycle = "F" if form.endswith("_F") else getattr(wl, "cycle", "V")
     kw = dict(rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, xu=xu, xp=xp, mixed=mixed, pc=pc, cycle=cycle)
     ok = True
     info = None
@@ -370,10 +370,12 @@ def main():
         args.no_extra = args.no_serving = args.no_cpu_baseline = True
 
     import torch
-    from workloads import CONFIGS
+    from workloads import CONFIGS, PAPER_LINEAR_Q3
     from paper_2107_00820_amd import Hierarchy
 
-    wl = CONFIGS[args.config]
+    # the named configurations, and (for profiling) the degree-3 table settings by name
+    named = dict(CONFIGS, **{w.name: w for w in PAPER_LINEAR_Q3.values()})
+    wl = named[args.config]
     n_u, n_p = wl.unknowns()
     dof = n_u + n_p
     log(f"[bench] workload {wl.name}: {dof} unknowns")
@@ -392,7 +394,7 @@ def main():
     t0 = time.perf_counter()
     tune = h.apply_asm_tuning(load_asm_tuning())
     tune_src = "paper_2107_00820_amd/asm_tuning.json"
-    if len(tune) < (h.L - 1) * (2 if h.desc.mixed else 1):
+    if getattr(wl, "degree", 2) == 2 and len(tune) < (h.L - 1) * (2 if h.desc.mixed else 1):
         tune, tune_src = h.stk_autotune(reps=5), "live (stk_autotune)"
     t_tune = time.perf_counter() - t0
     log(f"[bench] patch-solve variants ({tune_src}, {t_tune:.3f} s): {tune}")
