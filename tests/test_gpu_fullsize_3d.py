@@ -75,14 +75,16 @@ def test_fullsize_sampled(name):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3"])
+@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3"])
 def test_fullsize_solve_against_recorded_oracle_solve(name):
     """The full-size solve against the oracle's own solve of the same
     workload, recorded once (tests/golden/fullsize_oracle.json, written by
-    make_fullsize_golden.py from the oracle alone; minutes of CPU and tens
-    of GB): the same FGMRES iteration count, residual histories within 1e-6
-    (relative) over the first restart cycle, solution norms within 1e-8 and
-    2,000 seeded solution entries within 1e-8 of the solution norm."""
+    make_fullsize_golden.py from the oracle alone; minutes of CPU and 12 GB;
+    the 48^3 workload's assembled operators do not fit the oracle's 52 GB
+    memory limit): the same FGMRES iteration count, residual histories
+    within 1e-6 (relative) over the first restart cycle, solution norms
+    within 1e-8 and 2,000 seeded solution entries within 1e-8 of the
+    solution norm."""
     import json
     import os
     from oracle.fem import Level
