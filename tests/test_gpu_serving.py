@@ -103,3 +103,33 @@ def test_same_shape_requests_step_together_and_equal_alone(dim, cross, monkeypat
         assert np.array_equal(xu.cpu().numpy(), outs[k][0].cpu().numpy())
         assert np.array_equal(xp.cpu().numpy(), outs[k][1].cpu().numpy())
         h.close()
+
+
+def test_degree_three_requests_in_the_mix():
+    """[Q3]^2 x P2disc requests served beside Q2 ones (same-size meshes, so
+    the cross-request cohorts must keep the degrees apart): results
+    bit-identical to each request solved alone."""
+    import os
+    import torch
+    from paper_2107_00820_amd import Hierarchy
+    from paper_2107_00820_amd.serve import Server
+    reqs = [(0.002 * k, small(2, 32, 2, gamma=1e3, dr=1e4, n_sinkers=24, seed=3 * 10 ** 6 + k, degree=d))
+            for k, d in enumerate((3, 2, 3, 2, 3))]
+    for cross in ("0", "1"):
+        os.environ["STK_CROSS_BATCH"] = cross
+        try:
+            out = Server(hbm_budget=8 << 30, max_active=5, keep_solutions=True).run(reqs)
+        finally:
+            del os.environ["STK_CROSS_BATCH"]
+        assert out["completed"] == len(reqs), [r.error for r in out["results"]]
+        for r in out["results"]:
+            wl = reqs[r.index][1]
+            h = Hierarchy.from_workload(wl)
+            bu, bp = h.stk_rhs()
+            xu, xp, info = h.stk_solve(bu, bp, eager=True)
+            torch.cuda.synchronize()
+            log(f"  [q3 mix, cross {cross}] {wl.name} (degree {wl.degree}): {r.iters} it, alone {info['iters']}")
+            assert info["iters"] == r.iters
+            assert np.array_equal(xu.cpu().numpy(), r.solution[0])
+            assert np.array_equal(xp.cpu().numpy(), r.solution[1])
+            h.close()
