@@ -20,7 +20,8 @@
  *  - Pressure layout: p[cell*(d+1) + m], cell lexicographic with x fastest,
  *    basis psi_0 = 1, psi_j = (x_j - c_j)/h on each cell (c the cell centre).
  *    For degree 3: p[cell*6 + m] with the monomials 1, x, y, x^2, xy, y^2 of
- *    (x - c)/h (total degree <= 2).
+ *    (x - c)/h (total degree <= 2); in 3D p[cell*10 + m] with 1, x, y, z, x^2,
+ *    xy, xz, y^2, yz, z^2.
  *  - Level 0 is the coarsest level, level n_levels-1 the finest.
  *  - Every call is asynchronous on the HIP stream passed (hipStream_t as
  *    void*, NULL = default stream) except stk_setup_hierarchy and stk_solve,
@@ -120,9 +121,11 @@ typedef struct {
   size_t hbm_budget;  /* bytes; 0 = unlimited. Setup fails with STK_ENOMEM above it */
   int degree;         /* velocity degree k of [Q_k]^d x P_{k-1}^disc (Section 4,
                          definition of V_h^k and Q_h^{k-1}): 0 or 2 = Q2 x P1disc;
-                         3 = [Q3]^2 x P2disc (2D only, coef_kind 0, mixed 0;
-                         cubic Lagrange basis on equispaced nodes, 4-point Gauss
-                         rule: qpts_1d 0 or 4), with every operation below */
+                         3 = [Q3]^d x P2disc (coef_kind 0, mixed 0; cubic Lagrange
+                         basis on equispaced nodes, 4-point Gauss rule: qpts_1d 0
+                         or 4; in 3D up to n_fine = 32, its 375-unknown star
+                         patches held as explicit inverses in 64 x 64 tiles), with
+                         every operation below */
 } stk_desc;
 
 /* Device bytes that stk_setup_hierarchy will allocate for `desc` (host-only

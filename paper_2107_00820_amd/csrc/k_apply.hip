@@ -16,7 +16,7 @@
 #include <type_traits>
 
 #include "stk_asm_sum.h"
-#include "stk_q3.h"
+#include "stk_q3d.h"
 #include "stk_reduce.h"
 
 namespace stk {
@@ -1240,13 +1240,62 @@ __global__ void k_p0_subtract(int64_t ncell, const double* __restrict__ part, in
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// [Q3]^3 x P2disc: the sinker viscosity at a cell's 4^3 Gauss points and the
+// element loads of the tricubic basis.
+__global__ void k3d_mu_sinker(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta,
+                              double mu_min, double mu_max, double* __restrict__ mu) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)q3d::NQ * g.ncell) return;
+  const int64_t cell = idx / q3d::NQ;
+  const int q = (int)(idx - cell * q3d::NQ);
+  const int64_t c0 = cell % g.N, c1 = (cell / g.N) % g.N, c2 = cell / ((int64_t)g.N * g.N);
+  const double x[3] = {g.h * ((double)c0 + q3::kGx[q & 3]), g.h * ((double)c1 + q3::kGx[(q >> 2) & 3]),
+                       g.h * ((double)c2 + q3::kGx[q >> 4])};
+  const double chi = sinker_chi<3>(ctr, ns, omega, delta, x);
+  mu[idx] = (mu_max - mu_min) * (1.0 - chi) + mu_min;
+}
+
+__global__ void k3d_rhs_elem(LevelGeo g, const double* __restrict__ ctr, int ns, double omega, double delta,
+                             double beta, double* __restrict__ E) {
+  const int64_t cell = blockIdx.x;
+  const int n = threadIdx.x;   // 64 lanes: lane n owns basis n
+  __shared__ double fq[q3d::NQ];
+  const int64_t c0 = cell % g.N, c1 = (cell / g.N) % g.N, c2 = cell / ((int64_t)g.N * g.N);
+  {
+    const int q = n;
+    const double x[3] = {g.h * ((double)c0 + q3::kGx[q & 3]), g.h * ((double)c1 + q3::kGx[(q >> 2) & 3]),
+                         g.h * ((double)c2 + q3::kGx[q >> 4])};
+    fq[q] = q3d::gauss_w(q) * beta * (sinker_chi<3>(ctr, ns, omega, delta, x) - 1.0);
+  }
+  __syncthreads();
+  double be = 0.0;
+  for (int q = 0; q < q3d::NQ; ++q) be += fq[q] * q3d::phi(q, n);
+  const double vol = g.h * g.h * g.h;
+  E[cell * q3d::NL + n] = 0.0;
+  E[cell * q3d::NL + q3d::NN + n] = 0.0;
+  E[cell * q3d::NL + 2 * q3d::NN + n] = vol * be;
+}
+
+void q3d_mu_sinker(const Hier& H, const Level& l, double* out, hipStream_t s) {
+  const int64_t n = (int64_t)q3d::NQ * l.g.ncell;
+  hipLaunchKernelGGL(k3d_mu_sinker, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
+                     H.delta, H.mu_min, H.mu_max, out);
+}
+
+void q3d_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
+  hipLaunchKernelGGL(k3d_rhs_elem, dim3((unsigned)l.g.ncell), dim3(64), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
+                     H.delta, H.beta, l.E);
+}
+
 void q3_mu_sinker(const Hier& H, const Level& l, double* out, hipStream_t s) {
+  if (H.dim == 3) return q3d_mu_sinker(H, l, out, s);
   const int64_t n = (int64_t)q3::NQ * l.g.ncell;
   hipLaunchKernelGGL(k3_mu_sinker, dim3(nblk(n, 256)), dim3(256), 0, s, l.g, H.centers, H.n_sinkers, H.omega, H.delta,
                      H.mu_min, H.mu_max, out);
 }
 
 void q3_rhs_elem(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 3) return q3d_rhs_elem(H, l, s);
   hipLaunchKernelGGL(k3_rhs_elem, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, H.centers, H.n_sinkers, H.omega,
                      H.delta, H.beta, l.E);
 }

@@ -27,7 +27,7 @@
 // look-ahead on the second one's block column, so that one pass over the
 // matrix applies both updates (half the passes; the same products, summed
 // in one accumulator per tile).
-#include "stk_q3.h"
+#include "stk_q3d.h"
 #include "stk_spd.h"
 
 namespace stk {
@@ -123,12 +123,59 @@ __global__ void __launch_bounds__(256) k3_coarse_assemble(LevelGeo g, const doub
   A[idx] = v;
 }
 
+// [Q3]^3 x P2disc: the same tiles from the cell matrices CM[cell][192][192]
+// of the level (sum over the cells that contain both nodes, ascending z, y, x).
+__global__ void __launch_bounds__(256) k3d_coarse_assemble(LevelGeo g, const double* __restrict__ CM, int64_t n,
+                                                            int64_t ntiles, double* __restrict__ A) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= ntiles * kTT) return;
+  const int64_t t = idx / kTT;
+  const int e = (int)(idx - t * kTT);
+  int I, J;
+  tile_ij(t, I, J);
+  const int64_t i = (int64_t)I * kT + e / kT, j = (int64_t)J * kT + e % kT;
+  double v = i == j ? 1.0 : 0.0;
+  if (i < n && j < n) {
+    int ni[3], nj[3];
+    const int ci = interior_dof<3>(g, i, ni);
+    const int cj = interior_dof<3>(g, j, nj);
+    int ca[3][2], la[3][2], cb[3][2], lb[3][2], na[3], nb[3];
+    for (int k = 0; k < 3; ++k) {
+      na[k] = q3::node_cells(ni[k], g.N, ca[k], la[k]);
+      nb[k] = q3::node_cells(nj[k], g.N, cb[k], lb[k]);
+    }
+    v = 0.0;
+    for (int t2 = 0; t2 < na[2]; ++t2)
+      for (int u2 = 0; u2 < nb[2]; ++u2) {
+        if (ca[2][t2] != cb[2][u2]) continue;
+        for (int t1 = 0; t1 < na[1]; ++t1)
+          for (int u1 = 0; u1 < nb[1]; ++u1) {
+            if (ca[1][t1] != cb[1][u1]) continue;
+            for (int t0 = 0; t0 < na[0]; ++t0)
+              for (int u0 = 0; u0 < nb[0]; ++u0) {
+                if (ca[0][t0] != cb[0][u0]) continue;
+                const int64_t cell = (int64_t)ca[0][t0] + (int64_t)g.N * ((int64_t)ca[1][t1] + (int64_t)g.N * ca[2][t2]);
+                const int a = la[0][t0] + 4 * la[1][t1] + 16 * la[2][t2];
+                const int b = lb[0][u0] + 4 * lb[1][u1] + 16 * lb[2][u2];
+                v += CM[cell * (192 * 192) + (int64_t)(ci * 64 + a) * 192 + cj * 64 + b];
+              }
+          }
+      }
+  }
+  A[idx] = v;
+}
+
 // Pivot: with A_KK = L L^T, Linv = L^{-1} (64 x 64 row-major, zeros above
 // the diagonal) and Pinv = A_KK^{-1} = L^{-T} L^{-1} (full symmetric), by the
 // blocked Cholesky inversion in 16 x 16 tiles on the FP64 matrix cores.
+// Batched use (degree-3 3D star patches): blockIdx.y selects a matrix at
+// A + y * as with its work at + y * ws; the coarse level runs one matrix.
 __global__ void __launch_bounds__(256) k_sweep_pivot(const double* __restrict__ A, int K,
                                                       double* __restrict__ Pinv, double* __restrict__ Linv,
-                                                      int* __restrict__ flag) {
+                                                      int* __restrict__ flag, int64_t as = 0, int64_t ws = 0) {
+  A += blockIdx.y * as;
+  Pinv += blockIdx.y * ws;
+  Linv += blockIdx.y * ws;
   constexpr int NB = kT / 16, NT = NB * (NB + 1) / 2;
   __shared__ double L[NT * kTile17];
   __shared__ double W[NB * kTile17];
@@ -206,7 +253,11 @@ __device__ inline void acc_rc(int a, int b, int r, int& row, int& col) {
 
 // V_I = C_I L^{-T} for every I != K (grid: one workgroup per block row).
 __global__ void __launch_bounds__(256) k_sweep_panel(const double* __restrict__ A, int K,
-                                                      const double* __restrict__ Linv, double* __restrict__ W) {
+                                                      const double* __restrict__ Linv, double* __restrict__ W,
+                                                      int64_t as = 0, int64_t ws = 0) {
+  A += blockIdx.y * as;
+  Linv += blockIdx.y * ws;
+  W += blockIdx.y * ws;
   __shared__ double X[kT * kLd];
   __shared__ double Y[kT * kLd];
   const int I = blockIdx.x;
@@ -265,7 +316,10 @@ __device__ inline void tile_sub(double* __restrict__ T, const d4 acc[2][2]) {
 }
 
 // A_IJ -= V_I V_J^T for every lower tile with I, J != K.
-__global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W) {
+__global__ void __launch_bounds__(256) k_sweep_update(double* __restrict__ A, int K, const double* __restrict__ W,
+                                                       int64_t as = 0, int64_t ws = 0) {
+  A += blockIdx.y * as;
+  W += blockIdx.y * ws;
   int I, J;
   tile_ij(blockIdx.x, I, J);
   if (I == K || J == K) return;
@@ -320,7 +374,12 @@ __global__ void __launch_bounds__(256) k_sweep_update2(double* __restrict__ A, i
 // I < K); A_KK <- -P^{-1}. Operands straight from global memory as in the
 // update.
 __global__ void __launch_bounds__(256) k_sweep_write(double* __restrict__ A, int K, const double* __restrict__ Pinv,
-                                                      const double* __restrict__ Linv, const double* __restrict__ W) {
+                                                      const double* __restrict__ Linv, const double* __restrict__ W,
+                                                      int64_t as = 0, int64_t ws = 0) {
+  A += blockIdx.y * as;
+  Pinv += blockIdx.y * ws;
+  Linv += blockIdx.y * ws;
+  W += blockIdx.y * ws;
   const int I = blockIdx.x;
   if (I == K) {
     double* T = tile_ptr(A, K, K);
@@ -470,7 +529,10 @@ void launch_coarse_assemble(const Hier& H, const Level& l, double* A, hipStream_
   const int64_t nb = coarse_tiles(H.n0);
   const int64_t ntiles = nb * (nb + 1) / 2;
   const dim3 grid(nblk(ntiles * kTT, 256));
-  if (H.deg == 3)
+  if (H.deg == 3 && H.dim == 3) {
+    q3d_cell_matrices(H, l, H.q3cm, s);
+    hipLaunchKernelGGL(k3d_coarse_assemble, grid, dim3(256), 0, s, l.g, (const double*)H.q3cm, H.n0, ntiles, A);
+  } else if (H.deg == 3)
     hipLaunchKernelGGL(k3_coarse_assemble, grid, dim3(256), 0, s, l.g, (const double*)l.mu, (const double*)l.winv,
                        H.gamma, H.n0, ntiles, A);
   else if (H.dim == 2)
@@ -519,6 +581,26 @@ int launch_coarse_invert(const Hier& H, double* A, int64_t n, double* work, hipS
 
 // The coarse solve is FP64 in both forms; R only selects the vector storage.
 // H.cvec holds bc (nb*64 doubles), H.cpart the tile partials (nb*nb*64).
+// In-place -A^{-1} of `count` SPD matrices of nb x nb tiles (coarse-matrix
+// tile layout; matrix k at A + k * as, its work of (nb + 1) * 4096 doubles at
+// work + k * ws): the single-pivot sweep, every launch over the whole batch.
+void launch_tile_invert_batched(const Hier& H, double* A, int nb, int64_t count, int64_t as, double* work,
+                                int64_t ws, hipStream_t s) {
+  const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
+  const unsigned cy = (unsigned)count;
+  double* Pinv = work;
+  double* V = work + kTT;
+  for (int K = 0; K < nb; ++K) {
+    double* Linv = V + (int64_t)K * kTT;
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1, cy), dim3(256), 0, s, (const double*)A, K, Pinv, Linv, H.flag, as, ws);
+    hipLaunchKernelGGL(k_sweep_panel, dim3(nb, cy), dim3(256), 0, s, (const double*)A, K, (const double*)Linv, V, as,
+                       ws);
+    hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles, cy), dim3(256), 0, s, A, K, (const double*)V, as, ws);
+    hipLaunchKernelGGL(k_sweep_write, dim3(nb, cy), dim3(256), 0, s, A, K, (const double*)Pinv, (const double*)Linv,
+                       (const double*)V, as, ws);
+  }
+}
+
 template <class R>
 void launch_coarse_apply(const Hier& H, const Level& l, const R* b, R* x, hipStream_t s) {
   const int nb = coarse_tiles(H.n0);

@@ -12,7 +12,7 @@
 // bit-identical results. These kernels favour plain structure over speed:
 // one lane per cell, patch or node.
 #include "stk_dev.h"
-#include "stk_q3.h"
+#include "stk_q3d.h"
 #include "stk_reduce.h"
 
 namespace stk {
@@ -523,6 +523,7 @@ using namespace q3;
 
 void q3_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
              hipStream_t s) {
+  if (H.dim == 3) return q3d_elem(H, l, mode, u, p, pout, s);
   const dim3 grid(nblk(l.g.ncell, 4)), blk(64);
   switch (mode) {
     case EL_VISC | EL_AUG:
@@ -544,27 +545,32 @@ void q3_elem(const Hier& H, const Level& l, int mode, const double* u, const dou
 }
 
 void q3_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out, hipStream_t s) {
+  if (H.dim == 3) return q3d_gather(H, l, base, alpha, out, s);
   (void)H;
   hipLaunchKernelGGL(k3_gather, dim3(nblk(2 * l.g.nnodes, 256)), dim3(256), 0, s, l.g, (const double*)l.E, base,
                      alpha, out);
 }
 
 void q3_winv_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 3) return q3d_winv_setup(H, l, s);
   (void)H;
   hipLaunchKernelGGL(k3_winv_setup, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, (const double*)l.mu, l.winv);
 }
 
 void q3_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
+  if (H.dim == 3) return q3d_schur_setup(H, l, s);
   hipLaunchKernelGGL(k3_schur_setup, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, (const double*)l.mu, H.gamma,
                      H.schur == 2 ? 1 : 0, H.Sinv);
 }
 
 void q3_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp, hipStream_t s) {
+  if (H.dim == 3) return q3d_schur_apply(H, l, y, vp, zp, s);
   hipLaunchKernelGGL(k3_schur_apply, dim3(nblk(l.g.ncell, 128)), dim3(128), 0, s, l.g, (const double*)H.Sinv, y, vp,
                      zp);
 }
 
 void q3_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
+  if (H.dim == 3) return q3d_project_mean(H, l, p, s);
   const int np = red_parts(l.g.ncell);
   hipLaunchKernelGGL(k3_pmean_partials, dim3(np), dim3(red_threads(l.g.ncell)), 0, s, l.g.ncell, (const double*)p,
                      H.partials);
@@ -573,12 +579,14 @@ void q3_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
 }
 
 void q3_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
+  if (H.dim == 3) return q3d_patch_setup(H, l, pc, s);
   if (pc.count == 0) return;
   hipLaunchKernelGGL(k3_patch_setup, dim3(pc.count), dim3(64), 0, s, l.g, (const double*)l.mu,
                      (const double*)l.winv, H.gamma, (const int*)pc.verts, pc.count, pc.inv, H.flag);
 }
 
 void q3_asm_solves(const Hier& H, const Level& l, const double* r, double* zbuf, hipStream_t s) {
+  if (H.dim == 3) return q3d_asm_solves(H, l, r, zbuf, s);
   (void)H;
   const PatchClass& pc = l.cls[0];
   hipLaunchKernelGGL(k3_asm_solves, dim3(nblk(pc.count, 64)), dim3(64), 0, s, l.g, (const int*)pc.verts, pc.count,
@@ -586,12 +594,14 @@ void q3_asm_solves(const Hier& H, const Level& l, const double* r, double* zbuf,
 }
 
 void q3_asm_gather(const Hier& H, const Level& l, const double* zbuf, double* y, hipStream_t s) {
+  if (H.dim == 3) return q3d_asm_gather(H, l, zbuf, y, s);
   (void)H;
   hipLaunchKernelGGL(k3_asm_gather, dim3(nblk(2 * l.g.nnodes, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
 }
 
 void q3_center_solve(const Hier& H, const Level& fine, const double* in, double* out, double alpha,
                      bool accumulate, hipStream_t s) {
+  if (H.dim == 3) return q3d_center_solve(H, fine, in, out, alpha, accumulate, s);
   (void)H;
   const int nc = fine.g.N / 2;
   const dim3 grid(nblk((int64_t)nc * nc, 64)), blk(64);
@@ -602,12 +612,14 @@ void q3_center_solve(const Hier& H, const Level& fine, const double* in, double*
 
 void q3_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc, double* xf,
                     hipStream_t s) {
+  if (H.dim == 3) return q3d_prolong_std(H, coarse, fine, xc, xf, s);
   (void)H;
   hipLaunchKernelGGL(k3_prolong_std, dim3(nblk(2 * fine.g.nnodes, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
 }
 
 void q3_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf, double* rc,
                      hipStream_t s) {
+  if (H.dim == 3) return q3d_restrict_std(H, fine, coarse, rf, rc, s);
   (void)H;
   hipLaunchKernelGGL(k3_restrict_std, dim3(nblk(2 * coarse.g.nnodes, 256)), dim3(256), 0, s, fine.g, coarse.g, rf,
                      rc);

@@ -1,0 +1,710 @@
+// Kernels of [Q3]^3 x P2disc (velocity degree 3 on hexahedra), on the same
+// level layout and with the same semantics as the Q2 launchers that route
+// to them: the cell kernel of A_gamma / B / B^T and its node gather, the
+// cellwise W and Schur blocks, the cell matrices, the vertex-star patch
+// inverses (Section 4.1, eq. (viim): 375 unknowns at an interior vertex)
+// and their solves, the local solves of the robust prolongation on
+// coarse-cell interiors (Section 4.2, eq. (Ptilde)) and the standard Q3
+// prolongation and its transpose.
+//
+// A 375-unknown star does not fit a workgroup's LDS, so its matrix is
+// assembled from the cell matrices into 64 x 64 tiles in device memory and
+// inverted there by the coarse level's symmetric sweep, batched over the
+// patches; a patch solve is a tile GEMV of one workgroup. Every output is a
+// fixed-order sum (no atomics): repeated calls are bit-identical.
+#include "stk_dev.h"
+#include "stk_q3d.h"
+#include "stk_reduce.h"
+
+namespace stk {
+namespace q3d {
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+constexpr int64_t kCM = (int64_t)NL * NL;   // doubles per cell matrix
+
+__device__ inline void cell3(const LevelGeo& g, int64_t cell, int c[3]) {
+  c[0] = (int)(cell % g.N);
+  c[1] = (int)((cell / g.N) % g.N);
+  c[2] = (int)(cell / ((int64_t)g.N * g.N));
+}
+
+__device__ inline int64_t node3(const LevelGeo& g, int i0, int i1, int i2) {
+  return (int64_t)i0 + (int64_t)g.n1 * ((int64_t)i1 + (int64_t)g.n1 * i2);
+}
+
+// ---------------------------------------------------------------------------
+// Cell kernel: one 64-lane workgroup per cell; lane t loads node t, forms
+// the stress at Gauss point t, then the outputs of node t (3 components);
+// the ten pressure moments are formed by lanes 0..9.
+template <int MODE>
+__global__ void __launch_bounds__(64) k3d_elem(LevelGeo g, const double* __restrict__ mu,
+                                               const double* __restrict__ winv, double gamma,
+                                               const double* __restrict__ u, const double* __restrict__ p,
+                                               double* __restrict__ E, double* __restrict__ pout) {
+  const Tab1& T = cT1;
+  __shared__ double su[NL];
+  __shared__ double ss[NQ][6];
+  __shared__ double sp[NP];
+  const int64_t cell = blockIdx.x;
+  const int t = threadIdx.x;
+  int c[3];
+  cell3(g, cell, c);
+  constexpr bool NEED_U = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  if (NEED_U) {
+    const int i0 = 3 * c[0] + (t & 3), i1 = 3 * c[1] + ((t >> 2) & 3), i2 = 3 * c[2] + (t >> 4);
+    const bool b = bnd_node3(g, i0, i1, i2);
+    const int64_t nd = node3(g, i0, i1, i2);
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) su[comp * NN + t] = b ? 0.0 : u[comp * g.nnodes + nd];
+  }
+  __syncthreads();
+  if (MODE & EL_VISC) {
+    const int q = t;
+    double G[3][3] = {};
+    for (int n = 0; n < NN; ++n) {
+      double gr[3];
+      grad_phi(q, n, gr);
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) G[comp][k] += gr[k] * su[comp * NN + n];
+    }
+    const double wm = gauss_w(q) * mu[cell * NQ + q] * g.h;
+    ss[q][0] = 2.0 * wm * G[0][0];
+    ss[q][1] = 2.0 * wm * G[1][1];
+    ss[q][2] = 2.0 * wm * G[2][2];
+    ss[q][3] = wm * (G[0][1] + G[1][0]);
+    ss[q][4] = wm * (G[0][2] + G[2][0]);
+    ss[q][5] = wm * (G[1][2] + G[2][1]);
+  }
+  if (MODE & (EL_AUG | EL_BOUT)) {
+    if (t < NP) {
+      double v = 0.0;
+      for (int comp = 0; comp < 3; ++comp)
+        for (int n = 0; n < NN; ++n) v += bhat(t, comp, n) * su[comp * NN + n];
+      sp[t] = v;
+      if (MODE & EL_BOUT) pout[cell * NP + t] = -g.h * g.h * v;
+    }
+  }
+  __syncthreads();
+  double e[3] = {0.0, 0.0, 0.0};
+  const int n = t;
+  if (MODE & EL_VISC) {
+    for (int q = 0; q < NQ; ++q) {
+      double gr[3];
+      grad_phi(q, n, gr);
+      const double* S = ss[q];
+      e[0] += S[0] * gr[0] + S[3] * gr[1] + S[4] * gr[2];
+      e[1] += S[3] * gr[0] + S[1] * gr[1] + S[5] * gr[2];
+      e[2] += S[4] * gr[0] + S[5] * gr[1] + S[2] * gr[2];
+    }
+  }
+  if (MODE & (EL_AUG | EL_BT)) {
+    double tm[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) tm[m] = 0.0;
+    if (MODE & EL_AUG) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[k];
+        tm[m] = gamma * g.h * s;
+      }
+    }
+    if (MODE & EL_BT) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) tm[m] -= g.h * g.h * p[cell * NP + m];
+    }
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += bhat(m, comp, n) * tm[m];
+      e[comp] += s;
+    }
+  }
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) E[cell * NL + comp * NN + n] = e[comp];
+}
+
+// out[idx] = base[idx] + alpha * sum over the cells containing the node
+// (ascending z, y, x); 0 on Dirichlet nodes.
+__global__ void k3d_gather(LevelGeo g, const double* __restrict__ E, const double* __restrict__ base, double alpha,
+                           double* __restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= 3 * g.nnodes) return;
+  const int comp = (int)(idx / g.nnodes);
+  const int64_t nd = idx - (int64_t)comp * g.nnodes;
+  const int i0 = (int)(nd % g.n1), i1 = (int)((nd / g.n1) % g.n1), i2 = (int)(nd / ((int64_t)g.n1 * g.n1));
+  if (bnd_node3(g, i0, i1, i2)) {
+    out[idx] = 0.0;
+    return;
+  }
+  int ca[3][2], la[3][2], na[3];
+  na[0] = q3::node_cells(i0, g.N, ca[0], la[0]);
+  na[1] = q3::node_cells(i1, g.N, ca[1], la[1]);
+  na[2] = q3::node_cells(i2, g.N, ca[2], la[2]);
+  double s = 0.0;
+  for (int t2 = 0; t2 < na[2]; ++t2)
+    for (int t1 = 0; t1 < na[1]; ++t1)
+      for (int t0 = 0; t0 < na[0]; ++t0) {
+        const int64_t cell = (int64_t)ca[0][t0] + (int64_t)g.N * ((int64_t)ca[1][t1] + (int64_t)g.N * ca[2][t2]);
+        s += E[cell * NL + comp * NN + la[0][t0] + 4 * la[1][t1] + 16 * la[2][t2]];
+      }
+  out[idx] = (base ? base[idx] : 0.0) + alpha * s;
+}
+
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ inline void small_inverse_n(double (&M)[N][N], double (&X)[N][N]) {
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) X[a][b] = a == b ? 1.0 : 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double piv = 1.0 / M[k][k];
+    for (int b = 0; b < N; ++b) {
+      M[k][b] *= piv;
+      X[k][b] *= piv;
+    }
+    for (int a = 0; a < N; ++a) {
+      if (a == k) continue;
+      const double f = M[a][k];
+      for (int b = 0; b < N; ++b) {
+        M[a][b] -= f * M[k][b];
+        X[a][b] -= f * X[k][b];
+      }
+    }
+  }
+}
+
+__device__ inline void weighted_mass3(const double* __restrict__ mu, int64_t cell, double (&M)[NP][NP]) {
+  for (int a = 0; a < NP; ++a)
+    for (int b = 0; b < NP; ++b) M[a][b] = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    const double wq = gauss_w(q) / mu[cell * NQ + q];
+    double ps[NP];
+    for (int m = 0; m < NP; ++m) ps[m] = psi(m, q);
+    for (int a = 0; a < NP; ++a)
+      for (int b = 0; b < NP; ++b) M[a][b] += wq * ps[a] * ps[b];
+  }
+}
+
+__global__ void k3d_winv_setup(LevelGeo g, const double* __restrict__ mu, double* __restrict__ winv) {
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  double M[NP][NP], X[NP][NP];
+  weighted_mass3(mu, cell, M);
+  small_inverse_n<NP>(M, X);
+  for (int a = 0; a < NP; ++a)
+    for (int b = 0; b < NP; ++b) winv[cell * NP * NP + a * NP + b] = X[a][b];
+}
+
+__global__ void k3d_schur_setup(LevelGeo g, const double* __restrict__ mu, double gamma, int p2,
+                                double* __restrict__ Sinv) {
+  const Tab1& T = cT1;
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  double M[NP][NP], X[NP][NP];
+  weighted_mass3(mu, cell, M);
+  small_inverse_n<NP>(M, X);
+  const double ivol = 1.0 / (g.h * g.h * g.h);
+  for (int a = 0; a < NP; ++a)
+    for (int b = 0; b < NP; ++b) {
+      double v = ivol * X[a][b];
+      if (p2) v *= 1.0 + gamma;
+      else v += gamma * ivol * T.mhinv[a][b];
+      Sinv[cell * NP * NP + a * NP + b] = v;
+    }
+}
+
+// z_p = -Sinv (v_p - B y) per cell (y == NULL: z_p = -Sinv v_p).
+__global__ void k3d_schur_apply(LevelGeo g, const double* __restrict__ Sinv, const double* __restrict__ y,
+                                const double* __restrict__ vp, double* __restrict__ zp) {
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int c[3];
+  cell3(g, cell, c);
+  double bu[NP];
+  for (int m = 0; m < NP; ++m) bu[m] = 0.0;
+  if (y) {
+    for (int n = 0; n < NN; ++n) {
+      const int i0 = 3 * c[0] + (n & 3), i1 = 3 * c[1] + ((n >> 2) & 3), i2 = 3 * c[2] + (n >> 4);
+      if (bnd_node3(g, i0, i1, i2)) continue;
+      const int64_t nd = node3(g, i0, i1, i2);
+      const double v0 = y[nd], v1 = y[g.nnodes + nd], v2 = y[2 * g.nnodes + nd];
+      for (int m = 0; m < NP; ++m) bu[m] += bhat(m, 0, n) * v0 + bhat(m, 1, n) * v1 + bhat(m, 2, n) * v2;
+    }
+  }
+  double t[NP];
+  for (int m = 0; m < NP; ++m) t[m] = vp[cell * NP + m] + g.h * g.h * bu[m];
+  for (int a = 0; a < NP; ++a) {
+    double s = 0.0;
+    for (int b = 0; b < NP; ++b) s += Sinv[cell * NP * NP + a * NP + b] * t[b];
+    zp[cell * NP + a] = -s;
+  }
+}
+
+// Zero mean: int_K p = h^3 (p_0 + (p_x2 + p_y2 + p_z2) / 12).
+__global__ void k3d_pmean_partials(int64_t ncell, const double* __restrict__ p, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x)
+    s += p[c * NP] + (p[c * NP + 4] + p[c * NP + 7] + p[c * NP + 9]) * (1.0 / 12.0);
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k3d_pmean_subtract(int64_t ncell, const double* __restrict__ part, int nparts,
+                                   double* __restrict__ p) {
+  __shared__ double mean;
+  if (threadIdx.x < 64) {
+    const double s = wave_reduce_parts(part, nparts, 1, 0);
+    if (threadIdx.x == 0) mean = s / (double)ncell;
+  }
+  __syncthreads();
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x)
+    p[c * NP] -= mean;
+}
+
+// ---------------------------------------------------------------------------
+// Cell matrices CM[cell][i][j] of A_gamma (i, j = comp * 64 + node): h sum_q
+// w_q mu_q [delta_{ci,cj} grad phi_a . grad phi_b + d_cj phi_a d_ci phi_b] +
+// gamma h sum_m Bhat[m][i] (W^{-1} Bhat)[m][j]. One workgroup per cell; the
+// Gauss points go in four groups of 16 whose basis gradients are staged in
+// LDS, each group's terms added to the entries in place (fixed order).
+__global__ void __launch_bounds__(256) k3d_cellmat(LevelGeo g, const double* __restrict__ mu,
+                                                   const double* __restrict__ winv, double gamma,
+                                                   double* __restrict__ CM) {
+  const Tab1& T = cT1;
+  constexpr int QG = 16;
+  __shared__ double gr[QG][NN][3];
+  __shared__ double wmu[NQ];
+  __shared__ double Bh[NP][NL];
+  __shared__ double WB[NP][NL];
+  const int64_t cell = blockIdx.x;
+  for (int q = threadIdx.x; q < NQ; q += blockDim.x) wmu[q] = gauss_w(q) * mu[cell * NQ + q] * g.h;
+  for (int e = threadIdx.x; e < NP * NL; e += blockDim.x) {
+    const int m = e / NL, j = e % NL;
+    Bh[m][j] = bhat(m, j / NN, j % NN);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NP * NL; e += blockDim.x) {
+    const int m = e / NL, j = e % NL;
+    double t = 0.0;
+    for (int k = 0; k < NP; ++k) t += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * Bh[k][j];
+    WB[m][j] = t;
+  }
+  double* out = CM + cell * kCM;
+  for (int qg = 0; qg < NQ / QG; ++qg) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < QG * NN; e += blockDim.x) {
+      const int q = e / NN, n = e % NN;
+      double v[3];
+      grad_phi(QG * qg + q, n, v);
+      gr[q][n][0] = v[0];
+      gr[q][n][1] = v[1];
+      gr[q][n][2] = v[2];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NL * NL; e += blockDim.x) {
+      const int i = e / NL, j = e % NL;
+      const int ci = i / NN, a = i % NN, cj = j / NN, b = j % NN;
+      double s;
+      if (qg == 0) {
+        double al = 0.0;
+        for (int m = 0; m < NP; ++m) al += Bh[m][i] * WB[m][j];
+        s = gamma * g.h * al;
+      } else {
+        s = out[(int64_t)i * NL + j];
+      }
+      for (int q = 0; q < QG; ++q) {
+        double gg = gr[q][a][cj] * gr[q][b][ci];
+        if (ci == cj) gg += gr[q][a][0] * gr[q][b][0] + gr[q][a][1] * gr[q][b][1] + gr[q][a][2] * gr[q][b][2];
+        s += wmu[QG * qg + q] * gg;
+      }
+      out[(int64_t)i * NL + j] = s;
+    }
+  }
+}
+
+// Star patches: the patch of vertex v holds the 5^3 nodes 3v - 2 .. 3v + 2
+// per axis, three components (unknown i = comp * 125 + a0 + 5 a1 + 25 a2),
+// padded to 384 unknowns; nodes outside the domain interior and the padding
+// keep an identity row.
+__device__ inline bool patch_node3(const LevelGeo& g, int vert, int i, int& comp, int nd[3]) {
+  if (i >= PU) return false;
+  const int nv = g.N + 1;
+  const int v0 = vert % nv, v1 = (vert / nv) % nv, v2 = vert / (nv * nv);
+  comp = i / PN;
+  const int a = i - comp * PN;
+  nd[0] = 3 * v0 - 2 + a % PA;
+  nd[1] = 3 * v1 - 2 + (a / PA) % PA;
+  nd[2] = 3 * v2 - 2 + a / (PA * PA);
+  const int e = 3 * g.N - 1;
+  return nd[0] >= 1 && nd[1] >= 1 && nd[2] >= 1 && nd[0] <= e && nd[1] <= e && nd[2] <= e;
+}
+
+__device__ inline void tile_of(int t, int& I, int& J) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+// Patch matrices in the tile layout of the coarse inverse (lower tiles,
+// diagonal tiles full): grid (21 tiles, patches); entries are sums of the
+// cell-matrix entries of the cells that contain both nodes.
+__global__ void __launch_bounds__(256) k3d_patch_assemble(LevelGeo g, const double* __restrict__ CM,
+                                                          const int* __restrict__ verts, double* __restrict__ A) {
+  const int t = blockIdx.x, s = blockIdx.y;
+  int I, J;
+  tile_of(t, I, J);
+  const int vert = verts[s];
+  double* T = A + (int64_t)s * TS + (int64_t)t * 4096;
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int i = 64 * I + e / 64, j = 64 * J + e % 64;
+    int ci = 0, cj = 0, ni[3], nj[3];
+    const bool vi = patch_node3(g, vert, i, ci, ni);
+    const bool vj = patch_node3(g, vert, j, cj, nj);
+    double v = i == j ? 1.0 : 0.0;
+    if (vi && vj) {
+      int ca[3][2], la[3][2], cb[3][2], lb[3][2], na[3], nb[3];
+      for (int k = 0; k < 3; ++k) {
+        na[k] = q3::node_cells(ni[k], g.N, ca[k], la[k]);
+        nb[k] = q3::node_cells(nj[k], g.N, cb[k], lb[k]);
+      }
+      v = 0.0;
+      for (int t2 = 0; t2 < na[2]; ++t2)
+        for (int u2 = 0; u2 < nb[2]; ++u2) {
+          if (ca[2][t2] != cb[2][u2]) continue;
+          for (int t1 = 0; t1 < na[1]; ++t1)
+            for (int u1 = 0; u1 < nb[1]; ++u1) {
+              if (ca[1][t1] != cb[1][u1]) continue;
+              for (int t0 = 0; t0 < na[0]; ++t0)
+                for (int u0 = 0; u0 < nb[0]; ++u0) {
+                  if (ca[0][t0] != cb[0][u0]) continue;
+                  const int64_t cell =
+                      (int64_t)ca[0][t0] + (int64_t)g.N * ((int64_t)ca[1][t1] + (int64_t)g.N * ca[2][t2]);
+                  const int a = la[0][t0] + 4 * la[1][t1] + 16 * la[2][t2];
+                  const int b = lb[0][u0] + 4 * lb[1][u1] + 16 * lb[2][u2];
+                  v += CM[cell * kCM + (int64_t)(ci * NN + a) * NL + cj * NN + b];
+                }
+            }
+        }
+    }
+    T[e] = v;
+  }
+}
+
+// y = A_s^{-1} x for the patch's stored -A_s^{-1} (21 tiles), one 256-lane
+// workgroup: tile by tile in a fixed order, thread (tr, tc) = (t / 16, t % 16)
+// multiplies its 4 x 4 block; row sums meet over the 16 lanes of a row band
+// (shuffles), column sums (the transposed use of a lower tile) over the 16
+// bands (shuffles, then the four wavefronts through LDS in order), and one
+// thread per row adds them to y.
+__device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const double* x, double* y, double* part) {
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15, wave = t >> 6, lane = t & 63;
+  for (int tt = 0; tt < TT; ++tt) {
+    int I, J;
+    tile_of(tt, I, J);
+    const double* T = Ainv + (int64_t)tt * 4096;
+    double m[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m[r][c] = T[(4 * tr + r) * 64 + 4 * tc + c];
+    double rs[4], cs[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v += m[r][c] * x[64 * J + 4 * tc + c];
+      rs[r] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v += m[r][c] * x[64 * I + 4 * tr + r];
+      cs[c] = v;
+    }
+    // row sums over the 16 lanes of the band
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int off = 8; off >= 1; off >>= 1) rs[r] += __shfl_xor(rs[r], off, 64);
+    // column sums over the 4 bands of the wavefront
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int off = 32; off >= 16; off >>= 1) cs[c] += __shfl_xor(cs[c], off, 64);
+    if (lane < 16) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) part[wave * 64 + 4 * lane + c] = cs[c];
+    }
+    __syncthreads();
+    if (tc == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[64 * I + 4 * tr + r] -= rs[r];
+    }
+    __syncthreads();
+    if (I != J && t < 64) {
+      const double v = part[t] + part[64 + t] + part[128 + t] + part[192 + t];
+      y[64 * J + t] -= v;
+    }
+    __syncthreads();
+  }
+}
+
+// MODE 0: patch solves of an ASM application (residual r, outputs
+// zbuf[i * nvert + vert]); MODE 1 / 2: local solves of the robust transfer
+// on coarse cell s (the star of its centre vertex, patch slot s), out|_K =
+// alpha z (1) or out|_K + alpha z (2).
+template <int MODE>
+__global__ void __launch_bounds__(256) k3d_patch_solve(LevelGeo g, const int* __restrict__ verts,
+                                                       const double* __restrict__ inv, const double* __restrict__ in,
+                                                       double* __restrict__ out, int nvert, double alpha) {
+  __shared__ double x[64 * TB];
+  __shared__ double y[64 * TB];
+  __shared__ double part[256];
+  const int s = blockIdx.x;
+  const int vert = verts[s];
+  for (int i = threadIdx.x; i < 64 * TB; i += blockDim.x) {
+    int c, nd[3];
+    const bool v = patch_node3(g, vert, i, c, nd);
+    x[i] = v ? in[c * g.nnodes + node3(g, nd[0], nd[1], nd[2])] : 0.0;
+    y[i] = 0.0;
+  }
+  __syncthreads();
+  patch_tile_gemv(inv + (int64_t)s * TS, x, y, part);
+  for (int i = threadIdx.x; i < PU; i += blockDim.x) {
+    int c, nd[3];
+    const bool v = patch_node3(g, vert, i, c, nd);
+    if (MODE == 0) {
+      out[(int64_t)i * nvert + vert] = v ? y[i] : 0.0;
+    } else if (v) {
+      const int64_t idx = c * g.nnodes + node3(g, nd[0], nd[1], nd[2]);
+      out[idx] = MODE == 2 ? out[idx] + alpha * y[i] : alpha * y[i];
+    }
+  }
+}
+
+// y[idx] = sum over the patches containing the node of their results
+// (ascending vertex z, y, x); 0 on Dirichlet nodes.
+__global__ void k3d_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int nvert, double* __restrict__ y) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= 3 * g.nnodes) return;
+  const int comp = (int)(idx / g.nnodes);
+  const int64_t nd = idx - (int64_t)comp * g.nnodes;
+  const int i[3] = {(int)(nd % g.n1), (int)((nd / g.n1) % g.n1), (int)(nd / ((int64_t)g.n1 * g.n1))};
+  if (bnd_node3(g, i[0], i[1], i[2])) {
+    y[idx] = 0.0;
+    return;
+  }
+  const int nv = g.N + 1;
+  int lo[3], cnt[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = i[k] / 3;
+    cnt[k] = i[k] % 3 ? 2 : 1;
+  }
+  double s = 0.0;
+  for (int t2 = 0; t2 < cnt[2]; ++t2)
+    for (int t1 = 0; t1 < cnt[1]; ++t1)
+      for (int t0 = 0; t0 < cnt[0]; ++t0) {
+        const int v0 = lo[0] + t0, v1 = lo[1] + t1, v2 = lo[2] + t2;
+        const int a = (i[0] - (3 * v0 - 2)) + PA * (i[1] - (3 * v1 - 2)) + PA * PA * (i[2] - (3 * v2 - 2));
+        s += zbuf[(int64_t)(comp * PN + a) * nvert + v0 + nv * (v1 + nv * v2)];
+      }
+  y[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k3d_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict__ xc, double* __restrict__ xf) {
+  constexpr const q3::Tab& T = q3::RefQ3::T;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= 3 * gf.nnodes) return;
+  const int comp = (int)(idx / gf.nnodes);
+  const int64_t nd = idx - (int64_t)comp * gf.nnodes;
+  const int i[3] = {(int)(nd % gf.n1), (int)((nd / gf.n1) % gf.n1), (int)(nd / ((int64_t)gf.n1 * gf.n1))};
+  if (bnd_node3(gf, i[0], i[1], i[2])) {
+    xf[idx] = 0.0;
+    return;
+  }
+  int C[3], r[3];
+  for (int k = 0; k < 3; ++k) {
+    C[k] = i[k] / 6;
+    r[k] = i[k] % 6;
+    if (C[k] == gc.N) { C[k] = gc.N - 1; r[k] = 6; }
+  }
+  double s = 0.0;
+  for (int a2 = 0; a2 < NA; ++a2)
+    for (int a1 = 0; a1 < NA; ++a1)
+      for (int a0 = 0; a0 < NA; ++a0) {
+        const double w = T.prol[r[0]][a0] * T.prol[r[1]][a1] * T.prol[r[2]][a2];
+        const int j0 = 3 * C[0] + a0, j1 = 3 * C[1] + a1, j2 = 3 * C[2] + a2;
+        if (w == 0.0 || bnd_node3(gc, j0, j1, j2)) continue;
+        s += w * xc[comp * gc.nnodes + node3(gc, j0, j1, j2)];
+      }
+  xf[idx] = s;
+}
+
+__device__ inline int fine_support3(int j, int Nc, int nodes[11], double w[11]) {
+  constexpr const q3::Tab& T = q3::RefQ3::T;
+  int n = 0;
+  const int C = j / 3, a = j % 3;
+  if (a == 0) {
+    for (int t = -5; t <= 5; ++t) {
+      if (t < 0 && C == 0) continue;
+      if (t > 0 && C == Nc) continue;
+      const double wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
+      if (wt == 0.0) continue;
+      nodes[n] = 6 * C + t;
+      w[n] = wt;
+      ++n;
+    }
+  } else {
+    for (int t = 1; t <= 5; ++t) {
+      const double wt = T.prol[t][a];
+      if (wt == 0.0) continue;
+      nodes[n] = 6 * C + t;
+      w[n] = wt;
+      ++n;
+    }
+  }
+  return n;
+}
+
+__global__ void k3d_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restrict__ rf, double* __restrict__ rc) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= 3 * gc.nnodes) return;
+  const int comp = (int)(idx / gc.nnodes);
+  const int64_t nd = idx - (int64_t)comp * gc.nnodes;
+  const int j[3] = {(int)(nd % gc.n1), (int)((nd / gc.n1) % gc.n1), (int)(nd / ((int64_t)gc.n1 * gc.n1))};
+  if (bnd_node3(gc, j[0], j[1], j[2])) {
+    rc[idx] = 0.0;
+    return;
+  }
+  int f[3][11], nn[3];
+  double w[3][11];
+  for (int k = 0; k < 3; ++k) nn[k] = fine_support3(j[k], gc.N, f[k], w[k]);
+  double s = 0.0;
+  for (int t2 = 0; t2 < nn[2]; ++t2)
+    for (int t1 = 0; t1 < nn[1]; ++t1)
+      for (int t0 = 0; t0 < nn[0]; ++t0) {
+        if (bnd_node3(gf, f[0][t0], f[1][t1], f[2][t2])) continue;
+        s += w[0][t0] * w[1][t1] * w[2][t2] * rf[comp * gf.nnodes + node3(gf, f[0][t0], f[1][t1], f[2][t2])];
+      }
+  rc[idx] = s;
+}
+
+}  // namespace q3d
+
+// ---------------------------------------------------------------------------
+using namespace q3d;
+
+void q3d_elem(const Hier& H, const Level& l, int mode, const double* u, const double* p, double* pout,
+              hipStream_t s) {
+  const dim3 grid((unsigned)l.g.ncell), blk(64);
+  switch (mode) {
+    case EL_VISC | EL_AUG:
+      hipLaunchKernelGGL(k3d_elem<EL_VISC | EL_AUG>, grid, blk, 0, s, l.g, l.mu, l.winv, H.gamma, u, p, l.E, pout);
+      break;
+    case EL_AUG:
+      hipLaunchKernelGGL(k3d_elem<EL_AUG>, grid, blk, 0, s, l.g, l.mu, l.winv, H.gamma, u, p, l.E, pout);
+      break;
+    case EL_BT:
+      hipLaunchKernelGGL(k3d_elem<EL_BT>, grid, blk, 0, s, l.g, l.mu, l.winv, H.gamma, u, p, l.E, pout);
+      break;
+    case EL_VISC | EL_AUG | EL_BT | EL_BOUT:
+      hipLaunchKernelGGL(k3d_elem<EL_VISC | EL_AUG | EL_BT | EL_BOUT>, grid, blk, 0, s, l.g, l.mu, l.winv, H.gamma,
+                         u, p, l.E, pout);
+      break;
+    default:
+      break;
+  }
+}
+
+void q3d_gather(const Hier& H, const Level& l, const double* base, double alpha, double* out, hipStream_t s) {
+  (void)H;
+  hipLaunchKernelGGL(k3d_gather, dim3(nblk(3 * l.g.nnodes, 256)), dim3(256), 0, s, l.g, (const double*)l.E, base,
+                     alpha, out);
+}
+
+void q3d_winv_setup(const Hier& H, const Level& l, hipStream_t s) {
+  (void)H;
+  hipLaunchKernelGGL(k3d_winv_setup, dim3(nblk(l.g.ncell, 64)), dim3(64), 0, s, l.g, (const double*)l.mu, l.winv);
+}
+
+void q3d_schur_setup(const Hier& H, const Level& l, hipStream_t s) {
+  hipLaunchKernelGGL(k3d_schur_setup, dim3(nblk(l.g.ncell, 64)), dim3(64), 0, s, l.g, (const double*)l.mu, H.gamma,
+                     H.schur == 2 ? 1 : 0, H.Sinv);
+}
+
+void q3d_schur_apply(const Hier& H, const Level& l, const double* y, const double* vp, double* zp, hipStream_t s) {
+  hipLaunchKernelGGL(k3d_schur_apply, dim3(nblk(l.g.ncell, 64)), dim3(64), 0, s, l.g, (const double*)H.Sinv, y, vp,
+                     zp);
+}
+
+void q3d_project_mean(const Hier& H, const Level& l, double* p, hipStream_t s) {
+  const int np = red_parts(l.g.ncell);
+  hipLaunchKernelGGL(k3d_pmean_partials, dim3(np), dim3(red_threads(l.g.ncell)), 0, s, l.g.ncell, (const double*)p,
+                     H.partials);
+  hipLaunchKernelGGL(k3d_pmean_subtract, dim3(nblk(l.g.ncell, 256)), dim3(256), 0, s, l.g.ncell,
+                     (const double*)H.partials, np, p);
+}
+
+void q3d_cell_matrices(const Hier& H, const Level& l, double* CM, hipStream_t s) {
+  hipLaunchKernelGGL(k3d_cellmat, dim3((unsigned)l.g.ncell), dim3(256), 0, s, l.g, (const double*)l.mu,
+                     (const double*)l.winv, H.gamma, CM);
+}
+
+void q3d_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
+  if (pc.count == 0) return;
+  q3d_cell_matrices(H, l, H.q3cm, s);
+  hipLaunchKernelGGL(k3d_patch_assemble, dim3(TT, (unsigned)pc.count), dim3(256), 0, s, l.g,
+                     (const double*)H.q3cm, (const int*)pc.verts, pc.inv);
+  // the sweep works on the stored tiles in place; its work, 7 tiles per
+  // patch, takes the cell-matrix buffer (no longer needed)
+  launch_tile_invert_batched(H, pc.inv, TB, pc.count, TS, H.q3cm, 7 * 4096, s);
+}
+
+void q3d_asm_solves(const Hier& H, const Level& l, const double* r, double* zbuf, hipStream_t s) {
+  (void)H;
+  const PatchClass& pc = l.cls[0];
+  hipLaunchKernelGGL(k3d_patch_solve<0>, dim3((unsigned)pc.count), dim3(256), 0, s, l.g, (const int*)pc.verts,
+                     (const double*)pc.inv, r, zbuf, l.nvert, 1.0);
+}
+
+void q3d_asm_gather(const Hier& H, const Level& l, const double* zbuf, double* y, hipStream_t s) {
+  (void)H;
+  hipLaunchKernelGGL(k3d_asm_gather, dim3(nblk(3 * l.g.nnodes, 256)), dim3(256), 0, s, l.g, zbuf, l.nvert, y);
+}
+
+void q3d_center_solve(const Hier& H, const Level& fine, const double* in, double* out, double alpha,
+                      bool accumulate, hipStream_t s) {
+  (void)H;
+  const int nc = fine.g.N / 2;
+  const unsigned ncc = (unsigned)(nc * nc * nc);
+  const PatchClass& pc = fine.cls[0];
+  if (accumulate)
+    hipLaunchKernelGGL(k3d_patch_solve<2>, dim3(ncc), dim3(256), 0, s, fine.g, (const int*)pc.verts,
+                       (const double*)pc.inv, in, out, fine.nvert, alpha);
+  else
+    hipLaunchKernelGGL(k3d_patch_solve<1>, dim3(ncc), dim3(256), 0, s, fine.g, (const int*)pc.verts,
+                       (const double*)pc.inv, in, out, fine.nvert, alpha);
+}
+
+void q3d_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc, double* xf,
+                     hipStream_t s) {
+  (void)H;
+  hipLaunchKernelGGL(k3d_prolong_std, dim3(nblk(3 * fine.g.nnodes, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
+}
+
+void q3d_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf, double* rc,
+                      hipStream_t s) {
+  (void)H;
+  hipLaunchKernelGGL(k3d_restrict_std, dim3(nblk(3 * coarse.g.nnodes, 256)), dim3(256), 0, s, fine.g, coarse.g, rf,
+                     rc);
+}
+
+}  // namespace stk

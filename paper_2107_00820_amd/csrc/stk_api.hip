@@ -69,7 +69,8 @@ stk_status validate(const stk_desc* d) {
   if (d->degree != 0 && d->degree != 2 && d->degree != 3) return fail(STK_EINVAL, "degree must be 0, 2 or 3");
   const int deg = d->degree == 3 ? 3 : 2;
   if (deg == 3) {
-    if (d->dim != 2) return fail(STK_EINVAL, "degree 3 ([Q3]^2 x P2disc) is built in 2D only");
+    if (d->dim == 3 && d->n_fine > 32)
+      return fail(STK_EINVAL, "degree 3 in 3D is built up to 32^3 cells (explicit 375-unknown patch inverses)");
     if (d->coef_kind != 0) return fail(STK_EINVAL, "degree 3 takes the scalar sinker viscosity (coef_kind 0)");
     if (d->mixed != 0) return fail(STK_EINVAL, "degree 3 has the FP64 form only (mixed 0)");
     if (d->qpts_1d != 0 && d->qpts_1d != 4)
@@ -119,14 +120,26 @@ struct ClassPlan {
 // Degree 3: one class of 50-unknown patches (boundary patches padded), the
 // coarse-cell centre vertices first in lexicographic order of the coarse
 // cell, then the other vertices in lexicographic order.
-std::vector<ClassPlan> plan_patches_q3(int N) {
+std::vector<ClassPlan> plan_patches_q3(int D, int N) {
   const int nv = N + 1, nc = N / 2;
-  ClassPlan all{50, {}};
-  for (int s = 0; s < nc * nc; ++s) all.verts.push_back((2 * (s % nc) + 1) + nv * (2 * (s / nc) + 1));
-  for (int vert = 0; vert < nv * nv; ++vert) {
-    const int v0 = vert % nv, v1 = vert / nv;
-    if ((v0 & 1) && (v1 & 1)) continue;
-    all.verts.push_back(vert);
+  ClassPlan all{D == 2 ? 50 : 375, {}};
+  if (D == 2) {
+    for (int s = 0; s < nc * nc; ++s) all.verts.push_back((2 * (s % nc) + 1) + nv * (2 * (s / nc) + 1));
+    for (int vert = 0; vert < nv * nv; ++vert) {
+      const int v0 = vert % nv, v1 = vert / nv;
+      if ((v0 & 1) && (v1 & 1)) continue;
+      all.verts.push_back(vert);
+    }
+  } else {
+    for (int s = 0; s < nc * nc * nc; ++s) {
+      const int k0 = s % nc, k1 = (s / nc) % nc, k2 = s / (nc * nc);
+      all.verts.push_back((2 * k0 + 1) + nv * ((2 * k1 + 1) + nv * (2 * k2 + 1)));
+    }
+    for (int vert = 0; vert < nv * nv * nv; ++vert) {
+      const int v0 = vert % nv, v1 = (vert / nv) % nv, v2 = vert / (nv * nv);
+      if ((v0 & 1) && (v1 & 1) && (v2 & 1)) continue;
+      all.verts.push_back(vert);
+    }
   }
   return {all};
 }
@@ -181,7 +194,9 @@ template <class F>
 stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes) {
   const int D = d->dim;
   const int deg = d->degree == 3 ? 3 : 2;
-  const int NN = ipow(deg + 1, D), NL = D * NN, NP = deg == 3 ? 6 : D + 1;
+  const int NN = ipow(deg + 1, D), NL = D * NN, NP = deg == 3 ? (D == 2 ? 6 : 10) : D + 1;
+  const bool q3d = deg == 3 && D == 3;   // 375-unknown patches: tile-layout inverses
+  int64_t q3ws = 0;                      // doubles of the 3D degree-3 setup workspace
   const int PU = D * ipow(2 * deg - 1, D);   // unknowns of an interior star patch
   H.dim = D;
   H.deg = deg;
@@ -222,12 +237,18 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
       STKCHK(alloc((size_t)(kMaxNu + 1) * L.nvel * 8, (void**)&L.V));
       STKCHK(alloc((size_t)kMaxNu * L.nvel * 8, (void**)&L.Z));
       STKCHK(alloc((size_t)PU * L.nvert * 8, (void**)&L.zbuf));
-      std::vector<ClassPlan> plan = deg == 3 ? plan_patches_q3(N) : plan_patches(D, N);
+      std::vector<ClassPlan> plan = deg == 3 ? plan_patches_q3(D, N) : plan_patches(D, N);
       L.cls.assign(plan.size(), PatchClass{});
       for (size_t c = 0; c < plan.size(); ++c) {
         L.cls[c].n = plan[c].n;
         L.cls[c].count = (int)plan[c].verts.size();
         STKCHK(alloc(plan[c].verts.size() * 4, (void**)&L.cls[c].verts));
+        if (q3d) {
+          // 21 tiles of 64 x 64 per patch (384 padded unknowns)
+          STKCHK(alloc((size_t)L.cls[c].count * 21 * 4096 * 8, (void**)&L.cls[c].inv));
+          q3ws = std::max(q3ws, std::max((int64_t)L.g.ncell * NL * NL, (int64_t)L.cls[c].count * 7 * 4096));
+          continue;
+        }
         STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 8, (void**)&L.cls[c].inv));
         if (d->mixed)
           STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 4, (void**)&L.cls[c].inv32));
@@ -236,6 +257,10 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
   }
   const Level& L0 = H.lv[0];
   H.n0 = (int64_t)D * ipow(deg * L0.g.N - 1, D);
+  if (q3d) {
+    q3ws = std::max(q3ws, (int64_t)L0.g.ncell * NL * NL);
+    STKCHK(alloc((size_t)q3ws * 8, (void**)&H.q3cm));
+  }
   {
     const size_t nb = (size_t)coarse_tiles(H.n0);
     STKCHK(alloc(nb * (nb + 1) / 2 * 4096 * 8, (void**)&H.Ainv0));
@@ -889,7 +914,7 @@ stk_status stk_setup_hierarchy(const stk_desc* desc, void* stream, stk_hier** ou
     if (L.S32) launch_fill<float>(L.S32, 0.0, L.nvel, s);
     launch_fill<double>(L.x, 0.0, L.nvel, s);
     if (l >= 1) {
-      std::vector<ClassPlan> plan = H.deg == 3 ? plan_patches_q3(L.g.N) : plan_patches(D, L.g.N);
+      std::vector<ClassPlan> plan = H.deg == 3 ? plan_patches_q3(D, L.g.N) : plan_patches(D, L.g.N);
       for (size_t c = 0; c < plan.size(); ++c) {
         if (hipMemcpyAsync(L.cls[c].verts, plan[c].verts.data(), plan[c].verts.size() * 4, hipMemcpyHostToDevice,
                            s) != hipSuccess)

@@ -163,6 +163,9 @@ struct Hier {
   // side, residual, step, trial iterate)
   double* mu0 = nullptr;
   double *nl_b = nullptr, *nl_F = nullptr, *nl_d = nullptr, *nl_x = nullptr, *nl_t = nullptr;
+  // degree 3 in 3D: setup workspace (cell matrices of one level, then the
+  // batched sweep's work)
+  double* q3cm = nullptr;
 };
 
 // Sets the thread-local message returned by stk_last_error().

@@ -46,8 +46,10 @@ CASES = {
     "q3_2d_8_L2": small(2, 8, 2, gamma=1e3, dr=1e4, n_sinkers=4, seed=471, degree=3),
     "q3_2d_16_L3": small(2, 16, 3, gamma=1e3, dr=1e6, n_sinkers=8, seed=481, degree=3),
     "q3_2d_16_L2_p2": small(2, 16, 2, gamma=1e2, dr=1e4, n_sinkers=6, seed=491, schur=2, degree=3),
+    # [Q3]^3 x P2disc: 4^3 fine cells over 2^3 (27 interior 375-unknown stars)
+    "q3_3d_4_L2": small(3, 4, 2, gamma=1e3, dr=1e4, n_sinkers=4, seed=521, degree=3),
 }
-Q3_CASES = ["q3_2d_8_L2", "q3_2d_16_L3", "q3_2d_16_L2_p2"]
+Q3_CASES = ["q3_2d_8_L2", "q3_2d_16_L3", "q3_2d_16_L2_p2", "q3_3d_4_L2"]
 SCALAR_CASES = ["sinker_2d_16sq_L2", "2d_32_L3", "3d_8_L2"]
 # the slow oracle cases (about a minute of oracle setup and solve each)
 BIG_CASES = ["3d_16_L3", "3d_16_L3_tensor"]

@@ -112,10 +112,10 @@ def test_descriptor_fields_of_the_boundary():
 
 
 def test_degree_three_descriptor():
-    """degree 3 ([Q3]^2 x P2disc) is accepted in 2D with the scalar law and
-    the FP64 form; its footprint holds 16 Gauss points per cell, 6 pressure
-    unknowns per cell and 50-unknown patch inverses; other combinations are
-    rejected on the host."""
+    """degree 3 ([Q3]^d x P2disc) is accepted with the scalar law and the
+    FP64 form (3D up to 32^3 cells); its footprint holds 16 Gauss points per
+    cell, 6 pressure unknowns per cell and 50-unknown patch inverses in 2D;
+    other combinations (here a 3D 64^3 mesh) are rejected on the host."""
     from paper_2107_00820_amd import stk
     from workloads import small
     wl3 = small(2, 64, 3, gamma=1e3, dr=1e4, degree=3)
@@ -131,6 +131,8 @@ def test_degree_three_descriptor():
         else:
             with pytest.raises(stk.StkError):
                 stk.stk_footprint(d)
+    # 3D degree 3 up to 32^3 (explicit 375-unknown patch inverses)
+    assert stk.stk_footprint(stk.desc_from_workload(small(3, 16, 2, gamma=1e3, dr=1e4, degree=3))) > 0
     for field, value in (("mixed", 1), ("dim", 3), ("coef_kind", 1), ("degree", 4)):
         d = stk.desc_from_workload(wl3)
         setattr(d, field, value)
