@@ -132,6 +132,19 @@ PAPER_LINEAR_Q3 = {(schur, g, dr): Workload(f"linear_q3_p{schur}_g{g:g}_dr{dr:g}
                    for schur in (1, 2) for g in (10.0, 1000.0) for dr in (1e6, 1e10)}
 PAPER_LINEAR_Q3_PRINTED = {(1, 10.0, 1e6): 11, (1, 10.0, 1e10): 22, (1, 1000.0, 1e6): 13, (1, 1000.0, 1e10): 15,
                            (2, 10.0, 1e6): 19, (2, 10.0, 1e10): 27, (2, 1000.0, 1e6): 12, (2, 1000.0, 1e10): 16}
+# the same table's 3D settings (contrast 1e8, P1 and P2, gamma 10 / 1000) on
+# 8^3 cells with 2 levels: the paper's 80^3 with 3 levels is beyond the
+# explicit 375-unknown patch inverses (its finest level alone would take
+# about 370 GB)
+PAPER_LINEAR_Q3_3D = {(schur, g): Workload(f"linear_q3_3d_p{schur}_g{g:g}", 3, 8, 2, 24, 1e8, g, 810, nu_pre=5,
+                                           nu_post=5, rtol=1e-6, schur=schur, cycle="F", degree=3)
+                      for schur in (1, 2) for g in (10.0, 1000.0)}
+PAPER_LINEAR_Q3_3D_PRINTED = {(1, 10.0): 15, (1, 1000.0): 14, (2, 10.0): 15, (2, 1000.0): 14}
+# the 3D degree-3 benchmark setting: the same solver options on 16^3 cells
+# with 3 levels (P1, gamma 1000), the largest mesh whose setup stays well
+# under a second
+Q3_3D_BENCH = Workload("q3_3d_16cu_L3", 3, 16, 3, 24, 1e8, 1000.0, 810, nu_pre=5, nu_post=5, rtol=1e-6, schur=1,
+                       cycle="F", degree=3)
 
 
 # Viscoplastic Newton problems (capped law over a multi-sinker base field,
