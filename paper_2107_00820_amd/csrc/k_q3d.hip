@@ -33,99 +33,205 @@ __device__ inline int64_t node3(const LevelGeo& g, int i0, int i1, int i2) {
 }
 
 // ---------------------------------------------------------------------------
-// Cell kernel: one 64-lane workgroup per cell; lane t loads node t, forms
-// the stress at Gauss point t, then the outputs of node t (3 components);
-// the ten pressure moments are formed by lanes 0..9.
+// Cell kernel: one 64-lane workgroup per cell, by sum factorisation over the
+// tensor-product basis. Forward: the reference gradient of each component at
+// the 64 Gauss points from the 64 nodal values in three 1D contractions
+// (z, then y, then x; lane t owns one point of each intermediate tensor).
+// Lane q then forms the weighted stress at Gauss point q, and the pressure
+// moments (B-hat u)_m = sum_q w_q psi_m(q) div u(q) (the 4-point rule is
+// exact for these products, so this equals B-hat u) by butterfly sums that
+// leave the same value in every lane. The augmented and B^T terms enter as
+// pi(q) = w_q sum_m psi_m(q) t_m on the stress diagonal, since
+// sum_m Bhat[m][c, n] t_m = sum_q d_c phi_n(q) pi(q). Backward: the
+// transposed contractions (x, then y, then z) give the outputs of node t.
+// Two LDS regions of 9 x 64 doubles alternate between the stages.
 template <int MODE>
 __global__ void __launch_bounds__(64) k3d_elem(LevelGeo g, const double* __restrict__ mu,
                                                const double* __restrict__ winv, double gamma,
                                                const double* __restrict__ u, const double* __restrict__ p,
                                                double* __restrict__ E, double* __restrict__ pout) {
   const Tab1& T = cT1;
-  __shared__ double su[NL];
-  __shared__ double ss[NQ][6];
-  __shared__ double sp[NP];
+  __shared__ double R0[9 * 64];
+  __shared__ double R1[9 * 64];
+  __shared__ double sT[40];   // L[4][4], D[4][4], gx[4], gw[4]
   const int64_t cell = blockIdx.x;
   const int t = threadIdx.x;
-  int c[3];
-  cell3(g, cell, c);
+  const int t0 = t & 3, t1 = (t >> 2) & 3, t2 = t >> 4;
+  if (t < 16) {
+    sT[t] = T.L[t >> 2][t & 3];
+    sT[16 + t] = T.D[t >> 2][t & 3];
+  } else if (t < 20) {
+    sT[32 + (t - 16)] = T.gx[t - 16];
+    sT[36 + (t - 16)] = T.gw[t - 16];
+  }
+  __syncthreads();
+  const double* Lt = sT;         // Lt[4 * point + basis]
+  const double* Dt = sT + 16;
+  const double* gxt = sT + 32;
+  const double* gwt = sT + 36;
   constexpr bool NEED_U = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  constexpr bool NEED_T = (MODE & (EL_AUG | EL_BT)) != 0;
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double tm[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) tm[m] = 0.0;
   if (NEED_U) {
-    const int i0 = 3 * c[0] + (t & 3), i1 = 3 * c[1] + ((t >> 2) & 3), i2 = 3 * c[2] + (t >> 4);
-    const bool b = bnd_node3(g, i0, i1, i2);
-    const int64_t nd = node3(g, i0, i1, i2);
+    int c[3];
+    cell3(g, cell, c);
+    {
+      const int i0 = 3 * c[0] + t0, i1 = 3 * c[1] + t1, i2 = 3 * c[2] + t2;
+      const bool b = bnd_node3(g, i0, i1, i2);
+      const int64_t nd = node3(g, i0, i1, i2);
 #pragma unroll
-    for (int comp = 0; comp < 3; ++comp) su[comp * NN + t] = b ? 0.0 : u[comp * g.nnodes + nd];
-  }
-  __syncthreads();
-  if (MODE & EL_VISC) {
-    const int q = t;
-    double G[3][3] = {};
-    for (int n = 0; n < NN; ++n) {
-      double gr[3];
-      grad_phi(q, n, gr);
-#pragma unroll
-      for (int comp = 0; comp < 3; ++comp)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) G[comp][k] += gr[k] * su[comp * NN + n];
+      for (int comp = 0; comp < 3; ++comp) R0[comp * 64 + t] = b ? 0.0 : u[comp * g.nnodes + nd];
     }
-    const double wm = gauss_w(q) * mu[cell * NQ + q] * g.h;
-    ss[q][0] = 2.0 * wm * G[0][0];
-    ss[q][1] = 2.0 * wm * G[1][1];
-    ss[q][2] = 2.0 * wm * G[2][2];
-    ss[q][3] = wm * (G[0][1] + G[1][0]);
-    ss[q][4] = wm * (G[0][2] + G[2][0]);
-    ss[q][5] = wm * (G[1][2] + G[2][1]);
-  }
-  if (MODE & (EL_AUG | EL_BOUT)) {
-    if (t < NP) {
-      double v = 0.0;
-      for (int comp = 0; comp < 3; ++comp)
-        for (int n = 0; n < NN; ++n) v += bhat(t, comp, n) * su[comp * NN + n];
-      sp[t] = v;
-      if (MODE & EL_BOUT) pout[cell * NP + t] = -g.h * g.h * v;
-    }
-  }
-  __syncthreads();
-  double e[3] = {0.0, 0.0, 0.0};
-  const int n = t;
-  if (MODE & EL_VISC) {
-    for (int q = 0; q < NQ; ++q) {
-      double gr[3];
-      grad_phi(q, n, gr);
-      const double* S = ss[q];
-      e[0] += S[0] * gr[0] + S[3] * gr[1] + S[4] * gr[2];
-      e[1] += S[3] * gr[0] + S[1] * gr[1] + S[5] * gr[2];
-      e[2] += S[4] * gr[0] + S[5] * gr[1] + S[2] * gr[2];
-    }
-  }
-  if (MODE & (EL_AUG | EL_BT)) {
-    double tm[NP];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) tm[m] = 0.0;
-    if (MODE & EL_AUG) {
-#pragma unroll
-      for (int m = 0; m < NP; ++m) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[k];
-        tm[m] = gamma * g.h * s;
-      }
-    }
-    if (MODE & EL_BT) {
-#pragma unroll
-      for (int m = 0; m < NP; ++m) tm[m] -= g.h * g.h * p[cell * NP + m];
-    }
+    __syncthreads();
+    // z: lane (a, b, k); AL = sum_c L[k][c] u, AD = sum_c D[k][c] u
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-      double s = 0.0;
+      double al = 0.0, ad = 0.0;
 #pragma unroll
-      for (int m = 0; m < NP; ++m) s += bhat(m, comp, n) * tm[m];
-      e[comp] += s;
+      for (int cc = 0; cc < 4; ++cc) {
+        const double v = R0[comp * 64 + t0 + 4 * t1 + 16 * cc];
+        al += Lt[4 * t2 + cc] * v;
+        ad += Dt[4 * t2 + cc] * v;
+      }
+      R1[(2 * comp) * 64 + t] = al;
+      R1[(2 * comp + 1) * 64 + t] = ad;
+    }
+    __syncthreads();
+    // y: lane (a, j, k); LL = sum_b L[j][b] AL, DL = sum_b D[j][b] AL, LD = sum_b L[j][b] AD
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      double ll = 0.0, dl = 0.0, ld = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const double al = R1[(2 * comp) * 64 + t0 + 4 * bb + 16 * t2];
+        const double ad = R1[(2 * comp + 1) * 64 + t0 + 4 * bb + 16 * t2];
+        ll += Lt[4 * t1 + bb] * al;
+        dl += Dt[4 * t1 + bb] * al;
+        ld += Lt[4 * t1 + bb] * ad;
+      }
+      R0[(3 * comp) * 64 + t] = ll;
+      R0[(3 * comp + 1) * 64 + t] = dl;
+      R0[(3 * comp + 2) * 64 + t] = ld;
+    }
+    __syncthreads();
+    // x: lane q = (i, j, k); G[comp][dir]
+    double G[3][3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int o = aa + 4 * t1 + 16 * t2;
+        g0 += Dt[4 * t0 + aa] * R0[(3 * comp) * 64 + o];
+        g1 += Lt[4 * t0 + aa] * R0[(3 * comp + 1) * 64 + o];
+        g2 += Lt[4 * t0 + aa] * R0[(3 * comp + 2) * 64 + o];
+      }
+      G[comp][0] = g0;
+      G[comp][1] = g1;
+      G[comp][2] = g2;
+    }
+    const double wq = gwt[t0] * gwt[t1] * gwt[t2];
+    if (MODE & EL_VISC) {
+      const double wm = wq * mu[cell * NQ + t] * g.h;
+      S[0] = 2.0 * wm * G[0][0];
+      S[1] = 2.0 * wm * G[1][1];
+      S[2] = 2.0 * wm * G[2][2];
+      S[3] = wm * (G[0][1] + G[1][0]);
+      S[4] = wm * (G[0][2] + G[2][0]);
+      S[5] = wm * (G[1][2] + G[2][1]);
+    }
+    if (MODE & (EL_AUG | EL_BOUT)) {
+      const double dq = wq * (G[0][0] + G[1][1] + G[2][2]);
+      const double x0 = gxt[t0] - 0.5, x1 = gxt[t1] - 0.5, x2 = gxt[t2] - 0.5;
+      const double ps[NP] = {1.0, x0, x1, x2, x0 * x0, x0 * x1, x0 * x2, x1 * x1, x1 * x2, x2 * x2};
+      double sp[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        double v = dq * ps[m];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        sp[m] = v;
+      }
+      if (MODE & EL_BOUT) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+          if (t == m) pout[cell * NP + m] = -g.h * g.h * sp[m];
+      }
+      if (MODE & EL_AUG) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[k];
+          tm[m] = gamma * g.h * s;
+        }
+      }
     }
   }
+  if (MODE & EL_BT) {
 #pragma unroll
-  for (int comp = 0; comp < 3; ++comp) E[cell * NL + comp * NN + n] = e[comp];
+    for (int m = 0; m < NP; ++m) tm[m] -= g.h * g.h * p[cell * NP + m];
+  }
+  if (NEED_T) {
+    const double x0 = gxt[t0] - 0.5, x1 = gxt[t1] - 0.5, x2 = gxt[t2] - 0.5;
+    const double ps[NP] = {1.0, x0, x1, x2, x0 * x0, x0 * x1, x0 * x2, x1 * x1, x1 * x2, x2 * x2};
+    double pi = 0.0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) pi += ps[m] * tm[m];
+    pi *= gwt[t0] * gwt[t1] * gwt[t2];
+    S[0] += pi;
+    S[1] += pi;
+    S[2] += pi;
+  }
+  // weighted stress rows at Gauss point t: comp 0 (S0 S3 S4), 1 (S3 S1 S5), 2 (S4 S5 S2)
+#pragma unroll
+  for (int k = 0; k < 6; ++k) R1[k * 64 + t] = S[k];
+  __syncthreads();
+  constexpr int kRow[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  // x: lane (a, j, k); X0 = sum_i D[i][a] F0, X1 = sum_i L[i][a] F1, X2 = sum_i L[i][a] F2
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int o = ii + 4 * t1 + 16 * t2;
+      x0 += Dt[4 * ii + t0] * R1[kRow[comp][0] * 64 + o];
+      x1 += Lt[4 * ii + t0] * R1[kRow[comp][1] * 64 + o];
+      x2 += Lt[4 * ii + t0] * R1[kRow[comp][2] * 64 + o];
+    }
+    R0[(3 * comp) * 64 + t] = x0;
+    R0[(3 * comp + 1) * 64 + t] = x1;
+    R0[(3 * comp + 2) * 64 + t] = x2;
+  }
+  __syncthreads();
+  // y: lane (a, b, k); Y0 = sum_j L[j][b] X0 + D[j][b] X1, Y2 = sum_j L[j][b] X2
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    double y0 = 0.0, y2 = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int o = t0 + 4 * jj + 16 * t2;
+      y0 += Lt[4 * jj + t1] * R0[(3 * comp) * 64 + o] + Dt[4 * jj + t1] * R0[(3 * comp + 1) * 64 + o];
+      y2 += Lt[4 * jj + t1] * R0[(3 * comp + 2) * 64 + o];
+    }
+    R1[(2 * comp) * 64 + t] = y0;
+    R1[(2 * comp + 1) * 64 + t] = y2;
+  }
+  __syncthreads();
+  // z: lane n = (a, b, c); e = sum_k L[k][c] Y0 + D[k][c] Y2
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    double e = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int o = t0 + 4 * t1 + 16 * kk;
+      e += Lt[4 * kk + t2] * R1[(2 * comp) * 64 + o] + Dt[4 * kk + t2] * R1[(2 * comp + 1) * 64 + o];
+    }
+    E[cell * NL + comp * NN + t] = e;
+  }
 }
 
 // out[idx] = base[idx] + alpha * sum over the cells containing the node
@@ -401,18 +507,28 @@ __global__ void __launch_bounds__(256) k3d_patch_assemble(LevelGeo g, const doub
 // multiplies its 4 x 4 block; row sums meet over the 16 lanes of a row band
 // (shuffles), column sums (the transposed use of a lower tile) over the 16
 // bands (shuffles, then the four wavefronts through LDS in order), and one
-// thread per row adds them to y.
+// thread per row adds them to y. The next tile's block is loaded before the
+// current one is reduced, so its loads are in flight across the barrier; the
+// column partials alternate between two LDS buffers, so one barrier per tile
+// separates both the partials and the updates of y of consecutive tiles (the
+// row and column updates of one tile touch different bands unless I = J, and
+// then only the row update is made). `part` holds 2 x 256 doubles; y is
+// complete after the caller's next barrier.
+__device__ inline void load_block(const double* __restrict__ T, int tr, int tc, double m[4][4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m[r][c] = T[(4 * tr + r) * 64 + 4 * tc + c];
+}
+
 __device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const double* x, double* y, double* part) {
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15, wave = t >> 6, lane = t & 63;
+  double m[4][4], mn[4][4];
+  load_block(Ainv, tr, tc, m);
   for (int tt = 0; tt < TT; ++tt) {
     int I, J;
     tile_of(tt, I, J);
-    const double* T = Ainv + (int64_t)tt * 4096;
-    double m[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) m[r][c] = T[(4 * tr + r) * 64 + 4 * tc + c];
+    if (tt + 1 < TT) load_block(Ainv + (int64_t)(tt + 1) * 4096, tr, tc, mn);
     double rs[4], cs[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -438,21 +554,24 @@ __device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const do
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int off = 32; off >= 16; off >>= 1) cs[c] += __shfl_xor(cs[c], off, 64);
+    double* pb = part + (tt & 1) * 256;
     if (lane < 16) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) part[wave * 64 + 4 * lane + c] = cs[c];
+      for (int c = 0; c < 4; ++c) pb[wave * 64 + 4 * lane + c] = cs[c];
     }
     __syncthreads();
     if (tc == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) y[64 * I + 4 * tr + r] -= rs[r];
     }
-    __syncthreads();
     if (I != J && t < 64) {
-      const double v = part[t] + part[64 + t] + part[128 + t] + part[192 + t];
+      const double v = pb[t] + pb[64 + t] + pb[128 + t] + pb[192 + t];
       y[64 * J + t] -= v;
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m[r][c] = mn[r][c];
   }
 }
 
@@ -466,7 +585,7 @@ __global__ void __launch_bounds__(256) k3d_patch_solve(LevelGeo g, const int* __
                                                        double* __restrict__ out, int nvert, double alpha) {
   __shared__ double x[64 * TB];
   __shared__ double y[64 * TB];
-  __shared__ double part[256];
+  __shared__ double part[2 * 256];
   const int s = blockIdx.x;
   const int vert = verts[s];
   for (int i = threadIdx.x; i < 64 * TB; i += blockDim.x) {
@@ -477,6 +596,7 @@ __global__ void __launch_bounds__(256) k3d_patch_solve(LevelGeo g, const int* __
   }
   __syncthreads();
   patch_tile_gemv(inv + (int64_t)s * TS, x, y, part);
+  __syncthreads();
   for (int i = threadIdx.x; i < PU; i += blockDim.x) {
     int c, nd[3];
     const bool v = patch_node3(g, vert, i, c, nd);
@@ -548,32 +668,44 @@ __global__ void k3d_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restri
   xf[idx] = s;
 }
 
-__device__ inline int fine_support3(int j, int Nc, int nodes[11], double w[11]) {
-  constexpr const q3::Tab& T = q3::RefQ3::T;
-  int n = 0;
-  const int C = j / 3, a = j % 3;
-  if (a == 0) {
-    for (int t = -5; t <= 5; ++t) {
-      if (t < 0 && C == 0) continue;
-      if (t > 0 && C == Nc) continue;
-      const double wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
-      if (wt == 0.0) continue;
-      nodes[n] = 6 * C + t;
-      w[n] = wt;
-      ++n;
-    }
-  } else {
-    for (int t = 1; t <= 5; ++t) {
-      const double wt = T.prol[t][a];
-      if (wt == 0.0) continue;
-      nodes[n] = 6 * C + t;
-      w[n] = wt;
-      ++n;
+// 1D restriction stencils of a coarse node of local index a = j mod 3 in its
+// cell: the fine offsets from 6 C (C = j / 3) with nonzero prolongation
+// weight, in 7 slots (a = 0: a cell vertex, weights from both neighbouring
+// cells; a = 1, 2: four entries, the remaining slots weight 0 at a valid
+// offset).
+struct RestrictTab {
+  int n[3];
+  int off[3][7];
+  double w[3][7];
+  constexpr RestrictTab() : n(), off(), w() {
+    constexpr const q3::Tab& T = q3::RefQ3::T;
+    for (int a = 0; a < 3; ++a) {
+      int k = 0;
+      for (int t = -5; t <= 5; ++t) {
+        double wt = 0.0;
+        if (a == 0) wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
+        else if (t >= 1) wt = T.prol[t][a];
+        if (wt == 0.0) continue;
+        off[a][k] = t;
+        w[a][k] = wt;
+        ++k;
+      }
+      n[a] = k;
+      for (int q = k; q < 7; ++q) {
+        off[a][q] = off[a][0];
+        w[a][q] = 0.0;
+      }
     }
   }
-  return n;
-}
+};
+constexpr RestrictTab kRT{};
 
+// rc = P^T rf for the standard prolongation: for an interior coarse node
+// every fine node of its stencil is interior (a vertex has 1 <= C <= N - 1,
+// the others 0 <= C <= N - 1, and the offsets lie in [-5, 5] and [1, 5]), so
+// the sum runs over the tensor product of the three 1D stencils; its weights
+// and offsets are compile-time constants selected by a (fixed slots, guarded
+// by the stencil length), so no table is read with a lane-dependent index.
 __global__ void k3d_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restrict__ rf, double* __restrict__ rc) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= 3 * gc.nnodes) return;
@@ -584,16 +716,38 @@ __global__ void k3d_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restr
     rc[idx] = 0.0;
     return;
   }
-  int f[3][11], nn[3];
-  double w[3][11];
-  for (int k = 0; k < 3; ++k) nn[k] = fine_support3(j[k], gc.N, f[k], w[k]);
+  int len[3];
+  int64_t off[3][7];
+  double w[3][7];
+  const int64_t stride[3] = {1, gf.n1, (int64_t)gf.n1 * gf.n1};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = j[k] % 3, base = 6 * (j[k] / 3);
+    len[k] = a == 0 ? kRT.n[0] : (a == 1 ? kRT.n[1] : kRT.n[2]);
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) {
+      const int o = a == 0 ? kRT.off[0][sl] : (a == 1 ? kRT.off[1][sl] : kRT.off[2][sl]);
+      off[k][sl] = (int64_t)(base + o) * stride[k];
+      w[k][sl] = a == 0 ? kRT.w[0][sl] : (a == 1 ? kRT.w[1][sl] : kRT.w[2][sl]);
+    }
+  }
+  const double* src = rf + comp * gf.nnodes;
   double s = 0.0;
-  for (int t2 = 0; t2 < nn[2]; ++t2)
-    for (int t1 = 0; t1 < nn[1]; ++t1)
-      for (int t0 = 0; t0 < nn[0]; ++t0) {
-        if (bnd_node3(gf, f[0][t0], f[1][t1], f[2][t2])) continue;
-        s += w[0][t0] * w[1][t1] * w[2][t2] * rf[comp * gf.nnodes + node3(gf, f[0][t0], f[1][t1], f[2][t2])];
-      }
+#pragma unroll
+  for (int s2 = 0; s2 < 7; ++s2) {
+    if (s2 >= len[2]) break;
+    double s1v = 0.0;
+#pragma unroll
+    for (int s1 = 0; s1 < 7; ++s1) {
+      if (s1 >= len[1]) break;
+      const double* row = src + off[2][s2] + off[1][s1];
+      double s0v = 0.0;
+#pragma unroll
+      for (int s0 = 0; s0 < 7; ++s0) s0v += w[0][s0] * row[off[0][s0]];
+      s1v += w[1][s1] * s0v;
+    }
+    s += w[2][s2] * s1v;
+  }
   rc[idx] = s;
 }
 

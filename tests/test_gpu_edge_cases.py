@@ -5,9 +5,9 @@ oracle where there is something to compare:
 - gamma = 0 (A_gamma = A; P1 reduces to the inverse viscosity-weighted mass)
   and a constant viscosity (contrast 1): operator, smoother and solve parity;
 - the smallest hierarchies (one coarse cell, 2 x 2 / 2 x 2 x 2 fine cells;
-  Q2 and Q3): every patch class a boundary class but one, coarse problems of
-  2, 3 and 8 unknowns in one padded tile; operator, smoother, transfer and
-  solve parity.
+  Q2 and Q3, in 2D and 3D): every patch class a boundary class but one,
+  coarse problems of 2, 3, 8 and 24 unknowns in one padded tile; operator,
+  smoother, transfer and solve parity.
 Tolerances as in test_gpu_parity (these meshes have small condition
 numbers, so the applies and solves use the strict 1e-12 / 1e-8 bars)."""
 import numpy as np
@@ -24,6 +24,7 @@ EDGE = {
     "min_2d": small(2, 2, 2, gamma=1e2, dr=1e2, n_sinkers=2, seed=903),
     "min_3d": small(3, 2, 2, gamma=1e2, dr=1e2, n_sinkers=2, seed=904),
     "min_q3": small(2, 2, 2, gamma=1e2, dr=1e2, n_sinkers=2, seed=905, degree=3),
+    "min_q3_3d": small(3, 2, 2, gamma=1e2, dr=1e2, n_sinkers=2, seed=907, degree=3),
 }
 
 

@@ -17,7 +17,13 @@ reduction; preconditioner P2 unless stated):
   P2, gamma 10 / 1000, contrast 1e6 / 1e10, robust smoother and transfer):
   GPU = oracle, the printed count logged beside them, and every count within
   the paper's observation of convergence in at most 30 iterations for gamma
-  from 10 to 1000.
+  from 10 to 1000; its 3D settings ([Q3]^3 x P2disc, contrast 1e8, P1 and P2,
+  gamma 10 / 1000) on 8^3 cells with 2 levels (the paper's 80^3 is beyond the
+  explicit patch inverses): GPU = oracle, printed counts logged. On this
+  mesh a cell is wider than a sinker, and P2 at gamma 10 stalls above the
+  1e6 reduction within 300 iterations in the oracle too: there the GPU must
+  stop at the same count with a true residual within 10% of the oracle's.
+  At gamma 1000 both preconditioners converge.
 """
 import json
 import os
@@ -86,3 +92,20 @@ def test_table_linear_q3_2d():
         assert info["converged"] and o["converged"]
         assert info["iters"] == o["iters"]
         assert info["iters"] <= 30
+
+
+def test_table_linear_q3_3d():
+    from workloads import PAPER_LINEAR_Q3_3D, PAPER_LINEAR_Q3_3D_PRINTED
+    orc = json.load(open(GOLDEN))
+    for key, wl in PAPER_LINEAR_Q3_3D.items():
+        info = gpu_count(wl)
+        o = orc[wl.name]
+        log(f"[linear Q3 3D, 8^3] P{key[0]} gamma {key[1]:g}: GPU {info['iters']} (residual "
+            f"{info['rel_res']:.3e}), oracle {o['iters']} ({o['rel_res']:.3e}), "
+            f"paper (80^3) {PAPER_LINEAR_Q3_3D_PRINTED[key]}")
+        assert info["converged"] == o["converged"]
+        assert info["iters"] == o["iters"]
+        if not o["converged"]:
+            assert abs(info["rel_res"] - o["rel_res"]) <= 0.1 * o["rel_res"]
+        if key[1] >= 1000.0:
+            assert info["converged"]
