@@ -328,7 +328,7 @@ def q3_3d_leg(steps):
     P1, gamma 1000, F-cycles, 5 + 5 relaxation steps, 1e6 reduction): setup
     (cell matrices, batched 375-unknown patch inversions) and timed solves,
     and the patch solves' rate on the finest level (packed-equivalent bytes
-    of the symmetric inverses: the stored 64 x 64 tiles read 22% more)."""
+    of the symmetric inverses: the stored tiles read 5.7% more)."""
     import torch
     from workloads import Q3_3D_BENCH as wl
     from paper_2107_00820_amd import Hierarchy

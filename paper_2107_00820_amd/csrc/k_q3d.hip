@@ -502,33 +502,70 @@ __global__ void __launch_bounds__(256) k3d_patch_assemble(LevelGeo g, const doub
   }
 }
 
-// y = A_s^{-1} x for the patch's stored -A_s^{-1} (21 tiles), one 256-lane
-// workgroup: tile by tile in a fixed order, thread (tr, tc) = (t / 16, t % 16)
-// multiplies its 4 x 4 block; row sums meet over the 16 lanes of a row band
-// (shuffles), column sums (the transposed use of a lower tile) over the 16
+// The full-tile inverses of `n` patches (A, TS apart; grid (21 tiles, n))
+// into the stored layout of patches s0, s0 + 1, ..: off-diagonal tiles as
+// they are, diagonal tiles as their lower 4 x 4 blocks in row bands.
+__global__ void __launch_bounds__(256) k3d_patch_pack(const double* __restrict__ A, int64_t s0,
+                                                      double* __restrict__ inv) {
+  const int tt = blockIdx.x, s = blockIdx.y;
+  int I, J;
+  tile_of(tt, I, J);
+  const double* src = A + (int64_t)s * TS + (int64_t)tt * 4096;
+  double* dst = inv + (s0 + s) * PS + tile_off(tt, I);
+  if (I != J) {
+    for (int e = threadIdx.x; e < 4096; e += blockDim.x) dst[e] = src[e];
+    return;
+  }
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int row = e >> 6, col = e & 63, b = row >> 2, r = row & 3;
+    if (col < 4 * b + 4) dst[8 * b * (b + 1) + r * 4 * (b + 1) + col] = src[e];
+  }
+}
+
+// y = A_s^{-1} x for the patch's stored -A_s^{-1} (21 tiles, the diagonal
+// ones as lower 4 x 4 blocks), one 256-lane workgroup: tile by tile in a
+// fixed order, thread (tr, tc) = (t / 16, t % 16) multiplies its 4 x 4 block
+// (in a diagonal tile only tc <= tr, whose diagonal block is stored whole and
+// used by rows only); row sums meet over the 16 lanes of a row band
+// (shuffles), column sums (the transposed use of a lower block) over the 16
 // bands (shuffles, then the four wavefronts through LDS in order), and one
-// thread per row adds them to y. The next tile's block is loaded before the
-// current one is reduced, so its loads are in flight across the barrier; the
-// column partials alternate between two LDS buffers, so one barrier per tile
-// separates both the partials and the updates of y of consecutive tiles (the
-// row and column updates of one tile touch different bands unless I = J, and
-// then only the row update is made). `part` holds 2 x 256 doubles; y is
-// complete after the caller's next barrier.
-__device__ inline void load_block(const double* __restrict__ T, int tr, int tc, double m[4][4]) {
+// thread per row adds them to y: in an off-diagonal tile the row sums go to
+// band I and the column sums to band J, in a diagonal tile both to band I,
+// added together by one thread per row. The next tile's block is loaded
+// before the current one is reduced, so its loads are in flight across the
+// barrier; the partials alternate between two LDS buffers, so one barrier
+// per tile separates both the partials and the updates of y of consecutive
+// tiles. `part` holds 2 x 320 doubles; y is complete after the caller's next
+// barrier.
+__device__ inline void load_block(const double* __restrict__ T, bool diag, int tr, int tc, double m[4][4]) {
+  if (diag && tc > tr) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m[r][c] = 0.0;
+    return;
+  }
+  const int base = diag ? 8 * tr * (tr + 1) + 4 * tc : 256 * tr + 4 * tc;
+  const int stride = diag ? 4 * (tr + 1) : 64;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) m[r][c] = T[(4 * tr + r) * 64 + 4 * tc + c];
+    for (int c = 0; c < 4; ++c) m[r][c] = T[base + r * stride + c];
 }
 
 __device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const double* x, double* y, double* part) {
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15, wave = t >> 6, lane = t & 63;
   double m[4][4], mn[4][4];
-  load_block(Ainv, tr, tc, m);
+  load_block(Ainv, true, tr, tc, m);
   for (int tt = 0; tt < TT; ++tt) {
     int I, J;
     tile_of(tt, I, J);
-    if (tt + 1 < TT) load_block(Ainv + (int64_t)(tt + 1) * 4096, tr, tc, mn);
+    const bool diag = I == J;
+    if (tt + 1 < TT) {
+      int In, Jn;
+      tile_of(tt + 1, In, Jn);
+      load_block(Ainv + tile_off(tt + 1, In), In == Jn, tr, tc, mn);
+    }
     double rs[4], cs[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -537,12 +574,14 @@ __device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const do
       for (int c = 0; c < 4; ++c) v += m[r][c] * x[64 * J + 4 * tc + c];
       rs[r] = v;
     }
+    // the column use of a diagonal tile's blocks: strictly below the diagonal only
+    const bool cuse = !diag || tc < tr;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       double v = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) v += m[r][c] * x[64 * I + 4 * tr + r];
-      cs[c] = v;
+      cs[c] = cuse ? v : 0.0;
     }
     // row sums over the 16 lanes of the band
 #pragma unroll
@@ -554,19 +593,24 @@ __device__ inline void patch_tile_gemv(const double* __restrict__ Ainv, const do
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int off = 32; off >= 16; off >>= 1) cs[c] += __shfl_xor(cs[c], off, 64);
-    double* pb = part + (tt & 1) * 256;
+    double* pb = part + (tt & 1) * 320;
     if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) pb[wave * 64 + 4 * lane + c] = cs[c];
     }
-    __syncthreads();
-    if (tc == 0) {
+    if (diag && tc == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) y[64 * I + 4 * tr + r] -= rs[r];
+      for (int r = 0; r < 4; ++r) pb[256 + 4 * tr + r] = rs[r];
     }
-    if (I != J && t < 64) {
-      const double v = pb[t] + pb[64 + t] + pb[128 + t] + pb[192 + t];
-      y[64 * J + t] -= v;
+    __syncthreads();
+    if (diag) {
+      if (t < 64) y[64 * I + t] -= pb[256 + t] + (pb[t] + pb[64 + t] + pb[128 + t] + pb[192 + t]);
+    } else {
+      if (tc == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[64 * I + 4 * tr + r] -= rs[r];
+      }
+      if (t < 64) y[64 * J + t] -= pb[t] + pb[64 + t] + pb[128 + t] + pb[192 + t];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -585,7 +629,7 @@ __global__ void __launch_bounds__(256) k3d_patch_solve(LevelGeo g, const int* __
                                                        double* __restrict__ out, int nvert, double alpha) {
   __shared__ double x[64 * TB];
   __shared__ double y[64 * TB];
-  __shared__ double part[2 * 256];
+  __shared__ double part[2 * 320];
   const int s = blockIdx.x;
   const int vert = verts[s];
   for (int i = threadIdx.x; i < 64 * TB; i += blockDim.x) {
@@ -595,7 +639,7 @@ __global__ void __launch_bounds__(256) k3d_patch_solve(LevelGeo g, const int* __
     y[i] = 0.0;
   }
   __syncthreads();
-  patch_tile_gemv(inv + (int64_t)s * TS, x, y, part);
+  patch_tile_gemv(inv + (int64_t)s * PS, x, y, part);
   __syncthreads();
   for (int i = threadIdx.x; i < PU; i += blockDim.x) {
     int c, nd[3];
@@ -812,14 +856,23 @@ void q3d_cell_matrices(const Hier& H, const Level& l, double* CM, hipStream_t s)
                      (const double*)l.winv, H.gamma, CM);
 }
 
+// Patch inverses of a level in passes of up to kPatchBatch patches: each
+// pass assembles full tiles into the staging area behind the level's cell
+// matrices, inverts them in place by the batched sweep (its work, 7 tiles per
+// patch, behind the staging) and packs them into the stored layout.
 void q3d_patch_setup(const Hier& H, const Level& l, const PatchClass& pc, hipStream_t s) {
   if (pc.count == 0) return;
   q3d_cell_matrices(H, l, H.q3cm, s);
-  hipLaunchKernelGGL(k3d_patch_assemble, dim3(TT, (unsigned)pc.count), dim3(256), 0, s, l.g,
-                     (const double*)H.q3cm, (const int*)pc.verts, pc.inv);
-  // the sweep works on the stored tiles in place; its work, 7 tiles per
-  // patch, takes the cell-matrix buffer (no longer needed)
-  launch_tile_invert_batched(H, pc.inv, TB, pc.count, TS, H.q3cm, 7 * 4096, s);
+  const int64_t pass = std::min<int64_t>(pc.count, kPatchBatch);
+  double* stage = H.q3cm + l.g.ncell * kCM;
+  double* work = stage + pass * TS;
+  for (int64_t s0 = 0; s0 < pc.count; s0 += pass) {
+    const int n = (int)std::min<int64_t>(pass, pc.count - s0);
+    hipLaunchKernelGGL(k3d_patch_assemble, dim3(TT, (unsigned)n), dim3(256), 0, s, l.g, (const double*)H.q3cm,
+                       (const int*)pc.verts + s0, stage);
+    launch_tile_invert_batched(H, stage, TB, n, TS, work, 7 * 4096, s);
+    hipLaunchKernelGGL(k3d_patch_pack, dim3(TT, (unsigned)n), dim3(256), 0, s, (const double*)stage, s0, pc.inv);
+  }
 }
 
 void q3d_asm_solves(const Hier& H, const Level& l, const double* r, double* zbuf, hipStream_t s) {

@@ -22,6 +22,7 @@
 
 #include "../../include/stk.h"
 #include "stk_reduce.h"
+#include "stk_q3d.h"
 
 using namespace stk;
 
@@ -244,9 +245,12 @@ stk_status plan_allocs(const stk_desc* d, Hier& H, F&& alloc, bool build_classes
         L.cls[c].count = (int)plan[c].verts.size();
         STKCHK(alloc(plan[c].verts.size() * 4, (void**)&L.cls[c].verts));
         if (q3d) {
-          // 21 tiles of 64 x 64 per patch (384 padded unknowns)
-          STKCHK(alloc((size_t)L.cls[c].count * 21 * 4096 * 8, (void**)&L.cls[c].inv));
-          q3ws = std::max(q3ws, std::max((int64_t)L.g.ncell * NL * NL, (int64_t)L.cls[c].count * 7 * 4096));
+          // 21 tiles of 64 x 64 per patch (384 padded unknowns), the 6
+          // diagonal ones stored as their lower 4 x 4 blocks
+          STKCHK(alloc((size_t)L.cls[c].count * stk::q3d::PS * 8, (void**)&L.cls[c].inv));
+          // setup: the level's cell matrices, then one pass of full tiles and the sweep's work
+          const int64_t pass = std::min<int64_t>(L.cls[c].count, stk::q3d::kPatchBatch);
+          q3ws = std::max(q3ws, (int64_t)L.g.ncell * NL * NL + pass * (stk::q3d::TS + 7 * 4096));
           continue;
         }
         STKCHK(alloc((size_t)packed_doubles(plan[c].n, L.cls[c].count) * 8, (void**)&L.cls[c].inv));

@@ -28,8 +28,19 @@ constexpr int PA = 5;                  // star-interior nodes per axis
 constexpr int PN = 125;
 constexpr int PU = 375;                // unknowns of a star patch (padded at the boundary)
 constexpr int TB = 6;                  // 64-wide tile rows of a patch (384 padded)
-constexpr int TT = 21;                 // stored lower tiles of a patch
-constexpr int64_t TS = (int64_t)TT * 4096;   // doubles per patch inverse
+constexpr int TT = 21;                 // lower tiles of a patch
+constexpr int64_t TS = (int64_t)TT * 4096;   // doubles per patch in the full-tile layout (setup)
+// Stored inverses: the 15 off-diagonal tiles full, the 6 diagonal tiles as
+// their lower 4 x 4 blocks in row bands (band b = rows 4b..4b+3, columns
+// 0..4b+3, row-major; band b starts at 8 b (b + 1)), so a tile takes 2,176
+// doubles instead of 4,096.
+constexpr int DS = 2176;
+constexpr int64_t PS = (int64_t)(TT - TB) * 4096 + (int64_t)TB * DS;   // doubles per stored patch inverse
+// offset of tile tt = I (I + 1) / 2 + J (J <= I) in a stored inverse: the
+// I diagonal tiles of the rows above are the short ones
+__host__ __device__ constexpr int64_t tile_off(int tt, int I) { return (int64_t)tt * 4096 - (int64_t)I * (4096 - DS); }
+// patches assembled and inverted per setup pass (the full-tile staging)
+constexpr int kPatchBatch = 2048;
 
 constexpr int kPe[NP][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
                             {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};

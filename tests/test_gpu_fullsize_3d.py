@@ -1,6 +1,8 @@
-"""GPU parity at the full 3D sizes (32^3 sinker workload, 881,213 unknowns;
-48^3 viscoplastic tensor workload, 3,014,493 unknowns), too large for the
-oracle to assemble or solve in a test. Checked on sampled outputs, each
+"""GPU parity at the full sizes (32^3 sinker workload, 881,213 unknowns;
+48^3 viscoplastic tensor workload, 3,014,493 unknowns; the degree-3
+benchmark settings: [Q3]^3 x P2disc on 16^3 cells, 352,429 unknowns, and
+[Q3]^2 x P2disc on the 2D 128^2 mesh, 391,682 unknowns, both with F-cycles to
+a 1e6 reduction), too large for the oracle to assemble or solve in a test. Checked on sampled outputs, each
 computed by the oracle from the element matrices of only the cells it
 touches (oracle.assembly.stokes_rows / rhs_rows, pinned against the
 assembled operators on small meshes):
@@ -14,10 +16,12 @@ assembled operators on small meshes):
 import numpy as np
 import pytest
 
-from workloads import CONFIGS
+from workloads import CONFIGS, PAPER_LINEAR_Q3, Q3_3D_BENCH
 from gpu_common import to_dev, to_host, log
 
 pytestmark = pytest.mark.gpu
+
+NAMED = dict(CONFIGS, **{w.name: w for w in PAPER_LINEAR_Q3.values()}, **{Q3_3D_BENCH.name: Q3_3D_BENCH})
 
 
 def _coef(wl, lv):
@@ -27,14 +31,15 @@ def _coef(wl, lv):
     return ViscoplasticNewton.from_workload(wl, lv.quad_points())
 
 
-@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3"])
+@pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3", "q3_3d_16cu_L3",
+                                  "linear_q3_p1_g1000_dr1e+10"])
 def test_fullsize_sampled(name):
     import torch
     from oracle.fem import Level
     from oracle.assembly import stokes_rows, rhs_rows
     from paper_2107_00820_amd import Hierarchy
-    wl = CONFIGS[name]
-    lv = Level(wl.dim, wl.n_fine)
+    wl = NAMED[name]
+    lv = Level(wl.dim, wl.n_fine, wl.degree)
     log(f"[fullsize3d] {wl.name}: oracle coefficient")
     coef = _coef(wl, lv)
     log(f"[fullsize3d] {wl.name}: gpu setup")
@@ -42,7 +47,7 @@ def test_fullsize_sampled(name):
     rng = np.random.default_rng(7)
     rows = rng.choice(lv.n_u, 400, replace=False)
     cells = rng.choice(lv.n_cells, 64, replace=False)
-    pidx = (cells[:, None] * (wl.dim + 1) + np.arange(wl.dim + 1)).ravel()
+    pidx = (cells[:, None] * lv.n_pb + np.arange(lv.n_pb)).ravel()
     sidx = lv.stored_index()
     # operator apply
     u = rng.standard_normal(lv.n_u)
@@ -60,7 +65,7 @@ def test_fullsize_sampled(name):
     b_rows = rhs_rows(lv, coef, rows)
     assert np.max(np.abs(to_host(bu)[sidx[rows]] - b_rows)) <= 1e-12 * np.max(np.abs(b_rows))
     # solve (graph replays, as timed by the benchmark)
-    xu, xp, info = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit)
+    xu, xp, info = gpu.stk_solve(bu, bp, rtol=wl.rtol, restart=wl.restart, maxit=wl.maxit, cycle=wl.cycle)
     log(f"  solve: {info['iters']} iterations, rel res {info['rel_res']:.2e}")
     assert info["converged"] and info["rel_res"] <= wl.rtol
     x_u = lv.from_stored(to_host(xu))

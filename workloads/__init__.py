@@ -135,7 +135,7 @@ PAPER_LINEAR_Q3_PRINTED = {(1, 10.0, 1e6): 11, (1, 10.0, 1e10): 22, (1, 1000.0, 
 # the same table's 3D settings (contrast 1e8, P1 and P2, gamma 10 / 1000) on
 # 8^3 cells with 2 levels: the paper's 80^3 with 3 levels is beyond the
 # explicit 375-unknown patch inverses (its finest level alone would take
-# about 370 GB)
+# about 320 GB)
 PAPER_LINEAR_Q3_3D = {(schur, g): Workload(f"linear_q3_3d_p{schur}_g{g:g}", 3, 8, 2, 24, 1e8, g, 810, nu_pre=5,
                                            nu_post=5, rtol=1e-6, schur=schur, cycle="F", degree=3)
                       for schur in (1, 2) for g in (10.0, 1000.0)}
