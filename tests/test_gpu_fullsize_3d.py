@@ -2,7 +2,9 @@
 48^3 viscoplastic tensor workload, 3,014,493 unknowns; the degree-3
 benchmark settings: [Q3]^3 x P2disc on 16^3 cells, 352,429 unknowns, and
 [Q3]^2 x P2disc on the 2D 128^2 mesh, 391,682 unknowns, both with F-cycles to
-a 1e6 reduction), too large for the oracle to assemble or solve in a test. Checked on sampled outputs, each
+a 1e6 reduction; and the largest 3D degree-3 mesh the library accepts, 32^3
+cells over 4 levels, 2,899,805 unknowns), too large for the oracle to
+assemble or solve in a test. Checked on sampled outputs, each
 computed by the oracle from the element matrices of only the cells it
 touches (oracle.assembly.stokes_rows / rhs_rows, pinned against the
 assembled operators on small meshes):
@@ -16,12 +18,16 @@ assembled operators on small meshes):
 import numpy as np
 import pytest
 
-from workloads import CONFIGS, PAPER_LINEAR_Q3, Q3_3D_BENCH
+from workloads import CONFIGS, PAPER_LINEAR_Q3, Q3_3D_BENCH, Workload
 from gpu_common import to_dev, to_host, log
 
 pytestmark = pytest.mark.gpu
 
-NAMED = dict(CONFIGS, **{w.name: w for w in PAPER_LINEAR_Q3.values()}, **{Q3_3D_BENCH.name: Q3_3D_BENCH})
+# the largest 3D degree-3 hierarchy (n_fine <= 32 for degree 3 in 3D)
+Q3_3D_MAX = Workload("q3_3d_32cu_L4", 3, 32, 4, 24, 1e8, 1000.0, 811, nu_pre=5, nu_post=5, rtol=1e-6, schur=1,
+                     cycle="F", degree=3)
+NAMED = dict(CONFIGS, **{w.name: w for w in PAPER_LINEAR_Q3.values()}, **{Q3_3D_BENCH.name: Q3_3D_BENCH},
+             **{Q3_3D_MAX.name: Q3_3D_MAX})
 
 
 def _coef(wl, lv):
@@ -32,7 +38,7 @@ def _coef(wl, lv):
 
 
 @pytest.mark.parametrize("name", ["sinker_3d_32cu_L3", "viscoplastic_3d_48cu_L3", "q3_3d_16cu_L3",
-                                  "linear_q3_p1_g1000_dr1e+10"])
+                                  "linear_q3_p1_g1000_dr1e+10", "q3_3d_32cu_L4"])
 def test_fullsize_sampled(name):
     import torch
     from oracle.fem import Level

@@ -35,6 +35,23 @@ def test_noalloc_asm_equals_asm_twice(name):
         assert np.array_equal(to_host(y), y_ref), l
 
 
+def test_noalloc_asm_equals_asm_twice_q3_3d():
+    """[Q3]^3: 375 patch outputs per vertex; the fine level of 4^3 cells, then
+    the 2^3 level of the same hierarchy."""
+    from paper_2107_00820_amd import Hierarchy
+    from workloads import small
+    log("[noalloc] q3 3d 4^3 L3")
+    h = Hierarchy.from_workload(small(3, 4, 3, gamma=1e3, dr=1e4, n_sinkers=4, seed=523, degree=3))
+    rng = np.random.default_rng(90)
+    for l in (2, 1):
+        r = to_dev(rng.standard_normal(h.zeros_u(l).numel()))
+        y_ref = to_host(h.stk_asm(l, r))
+        y = h.zeros_u(l)
+        assert noalloc(h, l, r, y) == 0
+        assert np.array_equal(to_host(y), y_ref), l
+    h.close()
+
+
 def test_noalloc_asm_fp32():
     name = "2d_32_L3"
     log(f"[noalloc f32] {name}")
