@@ -187,6 +187,39 @@ def time_form(h, wl, bu, bp, xu, xp, form, steps, warmup, profile_pass):
     return out
 
 
+def roofline_of(h, wl, r, t_solve):
+    """The patch-solve roofline of a timed form (r from time_form with its
+    profiling pass): event-timed algorithmic bytes of every k_asm_gemv launch
+    (all smoothed levels, then the finest), the cell kernel's rate, the
+    solve-level byte model and the counter traffic recorded for the workload."""
+    n_gemv, ms_gemv, by_gemv = r["prof"][0]
+    n_elem, ms_elem, by_elem = r["prof"][1]
+    n_fine, ms_fine, by_fine = r["prof"][2]
+    ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
+    ach_fine = by_fine / (ms_fine * 1e-3) / 1e9 if ms_fine > 0 else 0.0
+    traffic, traffic_src = measured_traffic(wl, "fp64")
+    sb = solve_bytes_model(h, wl, r["iterations"], r["prof"], wl.restart)
+    return {
+        "bound": "hbm", "kernel": "k_asm_gemv (batched star-patch solves, all smoothed levels)",
+        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+        "traffic": traffic, "traffic_source": traffic_src, "form": "fp64",
+        "launches_per_solve": n_gemv, "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
+        "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
+        "time_share_of_solve": (ms_gemv * 1e-3) / t_solve,
+        "fine_level": {"achieved": ach_fine, "frac": ach_fine / HBM_PEAK_GBS, "launches_per_solve": n_fine,
+                       "avg_launch_us": 1e3 * ms_fine / max(n_fine, 1),
+                       "algorithmic_bytes_per_launch": by_fine / max(n_fine, 1)},
+        "cell_kernel": {"avg_launch_us": 1e3 * ms_elem / max(n_elem, 1),
+                        "GBs": (by_elem / (ms_elem * 1e-3) / 1e9) if ms_elem > 0 else 0.0,
+                        "time_share_of_solve": (ms_elem * 1e-3) / t_solve},
+        "solve_level": {"algorithmic_bytes": sb, "achieved": sb / t_solve / 1e9,
+                        "frac": sb / t_solve / 1e9 / HBM_PEAK_GBS,
+                        "model": "patch solves + cell kernels (counted by the library) + coarse solves "
+                                 "+ outer Gram-Schmidt; transfers, gathers and relaxation vectors left out"},
+        "timing": "HIP events on the library's launch stream around every launch of the kernel "
+                  "in one extra plain-launch solve"}
+
+
 def other_workload(name, steps):
     """FP64 (and, for the 2D workload, mixed) solves of another configuration."""
     import torch
@@ -205,7 +238,10 @@ def other_workload(name, steps):
     xu, xp = h.zeros_u(), h.zeros_p()
     res = {"setup_s": t_setup, "unknowns": sum(wl.unknowns())}
     for f in forms:
-        r = time_form(h, wl, bu, bp, xu, xp, f, steps, 1, False)
+        r = time_form(h, wl, bu, bp, xu, xp, f, steps, 1, f == "fp64")
+        if "prof" in r:
+            res["roofline"] = roofline_of(h, wl, r, r["t_total"] / steps)
+            r.pop("prof")
         r.pop("t_total", None)
         res[f] = r
     h.close()
@@ -469,33 +505,7 @@ def main():
            "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
            "forms": {f: {k: v for k, v in res[f].items() if k not in ("prof", "t_total")} for f in res}}
     if "prof" in r:
-        n_gemv, ms_gemv, by_gemv = r["prof"][0]
-        n_elem, ms_elem, by_elem = r["prof"][1]
-        n_fine, ms_fine, by_fine = r["prof"][2]
-        ach = by_gemv / (ms_gemv * 1e-3) / 1e9 if ms_gemv > 0 else 0.0
-        ach_fine = by_fine / (ms_fine * 1e-3) / 1e9 if ms_fine > 0 else 0.0
-        traffic, traffic_src = measured_traffic(wl, "fp64")
-        t_solve = r["t_total"] / args.steps
-        sb = solve_bytes_model(h, wl, r["iterations"], r["prof"], wl.restart)
-        out["roofline"] = {
-            "bound": "hbm", "kernel": "k_asm_gemv (batched star-patch solves, all smoothed levels)",
-            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": traffic, "traffic_source": traffic_src, "form": "fp64",
-            "launches_per_solve": n_gemv, "avg_launch_us": 1e3 * ms_gemv / max(n_gemv, 1),
-            "algorithmic_bytes_per_launch": by_gemv / max(n_gemv, 1),
-            "time_share_of_solve": (ms_gemv * 1e-3) / t_solve,
-            "fine_level": {"achieved": ach_fine, "frac": ach_fine / HBM_PEAK_GBS, "launches_per_solve": n_fine,
-                           "avg_launch_us": 1e3 * ms_fine / max(n_fine, 1),
-                           "algorithmic_bytes_per_launch": by_fine / max(n_fine, 1)},
-            "cell_kernel": {"avg_launch_us": 1e3 * ms_elem / max(n_elem, 1),
-                            "GBs": (by_elem / (ms_elem * 1e-3) / 1e9) if ms_elem > 0 else 0.0,
-                            "time_share_of_solve": (ms_elem * 1e-3) / t_solve},
-            "solve_level": {"algorithmic_bytes": sb, "achieved": sb / t_solve / 1e9,
-                            "frac": sb / t_solve / 1e9 / HBM_PEAK_GBS,
-                            "model": "patch solves + cell kernels (counted by the library) + coarse solves "
-                                     "+ outer Gram-Schmidt; transfers, gathers and relaxation vectors left out"},
-            "timing": "HIP events on the library's launch stream around every launch of the kernel "
-                      "in one extra plain-launch solve"}
+        out["roofline"] = roofline_of(h, wl, r, r["t_total"] / args.steps)
     out["autotune"] = {"asm_variant": {f"level{l}_{p}": v for (l, p), v in sorted(tune.items())},
                        "source": tune_src, "seconds": t_tune}
     h.close()
