@@ -124,7 +124,8 @@ typedef struct {
                          3 = [Q3]^d x P2disc (coef_kind 0, mixed 0; cubic Lagrange
                          basis on equispaced nodes, 4-point Gauss rule: qpts_1d 0
                          or 4; in 3D up to n_fine = 32, its 375-unknown star
-                         patches held as explicit inverses in 64 x 64 tiles), with
+                         patches held as explicit inverses in 64 x 64 tiles, the
+                         diagonal tiles as their lower 4 x 4 blocks), with
                          every operation below */
 } stk_desc;
 
