@@ -3,60 +3,83 @@
 // the fine nodes). Per axis a fine node i lies in coarse cell floor(i/4) at
 // offset r = i mod 4 quarters; the 1D weights l_a(r/4) are exact binary
 // fractions (1, 3/8, 3/4, -1/8, ...), so P_H itself introduces no rounding
-// beyond the sums. Both are node-parallel gathers (no atomics); the transpose
-// runs one axis at a time.
+// beyond the sums. Both are gathers (no atomics): the prolongation writes
+// four fine nodes of a row per thread, the transpose runs one axis at a time.
 #include <type_traits>
 
 #include "stk_internal.h"
 
 namespace stk {
 
+// 1D weight l_a(r/4) for a lane-dependent quarter offset r and a compile-time
+// a, chosen among constants (no table read with a lane-dependent index).
+template <int A>
+__device__ inline double prol_w(int r) {
+  return r == 0 ? kProlW[0][A] : (r == 1 ? kProlW[1][A] : (r == 2 ? kProlW[2][A] : (r == 3 ? kProlW[3][A] : kProlW[4][A])));
+}
+
+// P_H x_c, four fine nodes per thread: the nodes 4c .. 4c+3 of one fine row
+// (i1, i2) along x, which lie in coarse cell c at the quarter offsets 0..3
+// (thread c = N_c owns the last node 4 N_c, a Dirichlet node). The coarse
+// values of the row's (y, z) stencil (at most 3 x 3 entries, the same for all
+// four nodes) are summed per coarse x-node first, then each output takes its
+// x weights, compile-time constants. Coarse Dirichlet nodes contribute
+// nothing; fine Dirichlet nodes are written as 0.
 template <int D, class R>
 __global__ void k_prolong_std(LevelGeo gc, LevelGeo gf, const R* __restrict__ xc, R* __restrict__ xf) {
+  const int Nc = gc.N, nf1 = gf.n1;
+  const int64_t nc1 = gc.n1;
+  const int64_t nrow = D == 3 ? (int64_t)nf1 * nf1 : (int64_t)nf1;
+  const int64_t per = nrow * (Nc + 1);
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)D * gf.nnodes) return;
-  const int comp = (int)(idx / gf.nnodes);
-  const int64_t nd = idx - (int64_t)comp * gf.nnodes;
-  int i[3];
-  i[0] = (int)(nd % gf.n1);
-  i[1] = (int)((nd / gf.n1) % gf.n1);
-  i[2] = D == 3 ? (int)(nd / ((int64_t)gf.n1 * gf.n1)) : 0;
-  bool bnd = false;
-#pragma unroll
-  for (int k = 0; k < D; ++k) bnd = bnd || i[k] == 0 || i[k] == 2 * gf.N;
-  if (bnd) {
-    xf[idx] = (R)0;
+  if (idx >= (int64_t)D * per) return;
+  const int comp = (int)(idx / per);
+  const int64_t rem = idx - (int64_t)comp * per;
+  const int c = (int)(rem % (Nc + 1));
+  const int64_t row = rem / (Nc + 1);
+  const int i1 = (int)(row % nf1), i2 = D == 3 ? (int)(row / nf1) : 0;
+  R* out = xf + (int64_t)comp * gf.nnodes + (int64_t)nf1 * (i1 + (int64_t)nf1 * i2) + 4 * c;
+  const bool bndrow = i1 == 0 || i1 == 2 * gf.N || (D == 3 && (i2 == 0 || i2 == 2 * gf.N));
+  if (c == Nc || bndrow) {
+    const int nout = c == Nc ? 1 : 4;
+    for (int k = 0; k < nout; ++k) out[k] = (R)0;
     return;
   }
-  int cell[3], r[3];
+  int cl1 = i1 >> 2, r1 = i1 & 3;
+  if (cl1 == Nc) { cl1 = Nc - 1; r1 = 4; }
+  int cl2 = D == 3 ? i2 >> 2 : 0, r2 = D == 3 ? i2 & 3 : 0;
+  if (D == 3 && cl2 == Nc) { cl2 = Nc - 1; r2 = 4; }
+  const double w1[3] = {prol_w<0>(r1), prol_w<1>(r1), prol_w<2>(r1)};
+  const double w2[3] = {D == 3 ? prol_w<0>(r2) : 1.0, prol_w<1>(r2), prol_w<2>(r2)};
+  // (y, z)-weighted coarse values at the cell's x-nodes 2c, 2c+1, 2c+2
+  R t[3] = {(R)0, (R)0, (R)0};
+  const R* src0 = xc + (int64_t)comp * gc.nnodes + 2 * c;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (k >= D) { cell[k] = 0; r[k] = 0; continue; }
-    cell[k] = i[k] >> 2;
-    r[k] = i[k] & 3;
-    if (cell[k] == gc.N) { cell[k] = gc.N - 1; r[k] = 4; }
+  for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2) {
+    const int j2 = 2 * cl2 + a2;
+    if (D == 3 && (w2[a2] == 0.0 || j2 == 0 || j2 == 2 * Nc)) continue;
+#pragma unroll
+    for (int a1 = 0; a1 < 3; ++a1) {
+      const int j1 = 2 * cl1 + a1;
+      if (w1[a1] == 0.0 || j1 == 0 || j1 == 2 * Nc) continue;
+      const R w = (R)(w1[a1] * w2[a2]);
+      const R* src = src0 + nc1 * (j1 + nc1 * j2);
+      const R v0 = c > 0 ? src[0] : (R)0;             // x-node 2c is Dirichlet for c = 0
+      const R v1 = src[1];
+      const R v2 = c < Nc - 1 ? src[2] : (R)0;        // x-node 2c+2 is Dirichlet for c = Nc - 1
+      t[0] += w * v0;
+      t[1] += w * v1;
+      t[2] += w * v2;
+    }
   }
-  // all (up to 3^d) loads issued together, then summed in the fixed order
-  // (a2, a1, a0 ascending, zero weights and coarse Dirichlet nodes skipped)
-  constexpr int NA2 = D == 3 ? 3 : 1, NT = NA2 * 9;
-  R v[NT];
-  double wt[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int a0 = t % 3, a1 = (t / 3) % 3, a2 = t / 9;
-    const double w2 = D == 3 ? kProlW[r[2]][a2] : 1.0;
-    const double w1 = kProlW[r[1]][a1], w0 = kProlW[r[0]][a0];
-    const int j0 = 2 * cell[0] + a0, j1 = 2 * cell[1] + a1, j2 = D == 3 ? 2 * cell[2] + a2 : 0;
-    bool ok = w0 != 0.0 && w1 != 0.0 && w2 != 0.0 && j0 != 0 && j0 != 2 * gc.N && j1 != 0 && j1 != 2 * gc.N;
-    if (D == 3) ok = ok && j2 != 0 && j2 != 2 * gc.N;
-    wt[t] = ok ? w0 * w1 * w2 : 0.0;
-    v[t] = ok ? xc[comp * gc.nnodes + node_index<D>(gc, j0, j1, j2)] : (R)0;
+  for (int r0 = 0; r0 < 4; ++r0) {
+    R y = (R)0;
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0)
+      if (kProlW[r0][a0] != 0.0) y += (R)kProlW[r0][a0] * t[a0];
+    out[r0] = (c == 0 && r0 == 0) ? (R)0 : y;          // fine node 0 is Dirichlet
   }
-  R s = 0;
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (wt[t] != 0.0) s += (R)wt[t] * v[t];
-  xf[idx] = s;
 }
 
 // Transpose: coarse node j collects from the fine nodes where its basis
@@ -152,11 +175,15 @@ void launch_prolong_std(const Hier& H, const Level& coarse, const Level& fine, c
   if constexpr (std::is_same<R, double>::value) {
     if (H.deg == 3) return q3_prolong_std(H, coarse, fine, xc, xf, s);
   }
-  const int64_t n = (int64_t)H.dim * fine.g.nnodes;
-  if (H.dim == 2)
+  // threads: components x fine rows x (coarse cells along x + 1)
+  const int64_t nf1 = fine.g.n1, per_row = coarse.g.N + 1;
+  if (H.dim == 2) {
+    const int64_t n = 2 * nf1 * per_row;
     hipLaunchKernelGGL((k_prolong_std<2, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
-  else
+  } else {
+    const int64_t n = 3 * nf1 * nf1 * per_row;
     hipLaunchKernelGGL((k_prolong_std<3, R>), dim3(nblk(n, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
+  }
 }
 
 // The intermediate passes go through the fine level's T buffer (nvel
