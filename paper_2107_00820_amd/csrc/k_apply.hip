@@ -646,6 +646,11 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
   constexpr int NQ = 27, NL = 81, NP = 4, NS = 6;
   constexpr bool need_u = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
   constexpr bool need_c = (MODE & (EL_AUG | EL_BT | EL_BOUT)) != 0;
+  // without the viscous term the stress is diagonal (pi I): the forward
+  // stages need only the divergence, d_c u_c, and the transposed stages only
+  // the diagonal entries, so each component runs one contraction chain
+  // (the same arithmetic as the full chains on the entries that are used)
+  constexpr bool DIAG = (MODE & EL_VISC) == 0;
   __shared__ E3Smem<R> sm;
   const R gamma = (R)gamma_d;
   const int lane = threadIdx.x;
@@ -692,41 +697,49 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
         const R u0 = upen[comp][0], u1 = upen[comp][1], u2 = upen[comp][2];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          sm.x[lc][0][i3(q, p0, p1)] = u0 * (R)kB1[q][0] + u1 * (R)kB1[q][1] + u2 * (R)kB1[q][2];
-          sm.x[lc][1][i3(q, p0, p1)] = u0 * (R)kD1[q][0] + u1 * (R)kD1[q][1] + u2 * (R)kD1[q][2];
+          if (!DIAG || comp != 0)
+            sm.x[lc][0][i3(q, p0, p1)] = u0 * (R)kB1[q][0] + u1 * (R)kB1[q][1] + u2 * (R)kB1[q][2];
+          if (!DIAG || comp == 0)
+            sm.x[lc][1][i3(q, p0, p1)] = u0 * (R)kD1[q][0] + u1 * (R)kD1[q][1] + u2 * (R)kD1[q][2];
         }
       }
       __syncthreads();
       // y: lane (qx,z) = (p0,p1); outputs B_y B_x u, D_y B_x u, B_y D_x u
       {
-        R xb[3], xd[3];
+        R xb[3] = {}, xd[3] = {};
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          xb[b] = sm.x[lc][0][i3(p0, b, p1)];
-          xd[b] = sm.x[lc][1][i3(p0, b, p1)];
+          if (!DIAG || comp != 0) xb[b] = sm.x[lc][0][i3(p0, b, p1)];
+          if (!DIAG || comp == 0) xd[b] = sm.x[lc][1][i3(p0, b, p1)];
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          sm.y[lc][0][i3(p0, q, p1)] = xb[0] * (R)kB1[q][0] + xb[1] * (R)kB1[q][1] + xb[2] * (R)kB1[q][2];
-          sm.y[lc][1][i3(p0, q, p1)] = xb[0] * (R)kD1[q][0] + xb[1] * (R)kD1[q][1] + xb[2] * (R)kD1[q][2];
-          sm.y[lc][2][i3(p0, q, p1)] = xd[0] * (R)kB1[q][0] + xd[1] * (R)kB1[q][1] + xd[2] * (R)kB1[q][2];
+          if (!DIAG || comp == 2)
+            sm.y[lc][0][i3(p0, q, p1)] = xb[0] * (R)kB1[q][0] + xb[1] * (R)kB1[q][1] + xb[2] * (R)kB1[q][2];
+          if (!DIAG || comp == 1)
+            sm.y[lc][1][i3(p0, q, p1)] = xb[0] * (R)kD1[q][0] + xb[1] * (R)kD1[q][1] + xb[2] * (R)kD1[q][2];
+          if (!DIAG || comp == 0)
+            sm.y[lc][2][i3(p0, q, p1)] = xd[0] * (R)kB1[q][0] + xd[1] * (R)kB1[q][1] + xd[2] * (R)kB1[q][2];
         }
       }
       __syncthreads();
       // z: lane (qx,qy) = (p0,p1)
       {
-        R ybb[3], ybd[3], ydb[3];
+        R ybb[3] = {}, ybd[3] = {}, ydb[3] = {};
 #pragma unroll
         for (int z = 0; z < 3; ++z) {
-          ybb[z] = sm.y[lc][0][i3(p0, p1, z)];
-          ybd[z] = sm.y[lc][1][i3(p0, p1, z)];
-          ydb[z] = sm.y[lc][2][i3(p0, p1, z)];
+          if (!DIAG || comp == 2) ybb[z] = sm.y[lc][0][i3(p0, p1, z)];
+          if (!DIAG || comp == 1) ybd[z] = sm.y[lc][1][i3(p0, p1, z)];
+          if (!DIAG || comp == 0) ydb[z] = sm.y[lc][2][i3(p0, p1, z)];
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          G[q][comp][0] = ydb[0] * (R)kB1[q][0] + ydb[1] * (R)kB1[q][1] + ydb[2] * (R)kB1[q][2];
-          G[q][comp][1] = ybd[0] * (R)kB1[q][0] + ybd[1] * (R)kB1[q][1] + ybd[2] * (R)kB1[q][2];
-          G[q][comp][2] = ybb[0] * (R)kD1[q][0] + ybb[1] * (R)kD1[q][1] + ybb[2] * (R)kD1[q][2];
+          if (!DIAG || comp == 0)
+            G[q][comp][0] = ydb[0] * (R)kB1[q][0] + ydb[1] * (R)kB1[q][1] + ydb[2] * (R)kB1[q][2];
+          if (!DIAG || comp == 1)
+            G[q][comp][1] = ybd[0] * (R)kB1[q][0] + ybd[1] * (R)kB1[q][1] + ybd[2] * (R)kB1[q][2];
+          if (!DIAG || comp == 2)
+            G[q][comp][2] = ybb[0] * (R)kD1[q][0] + ybb[1] * (R)kD1[q][1] + ybb[2] * (R)kD1[q][2];
         }
       }
       // the next component's x stage overwrites sm.x only after this
@@ -833,50 +846,62 @@ k_elem3(LevelGeo g, const R* __restrict__ mu, const R* __restrict__ cw, const R*
       R t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        t0 += S[q][SymIdx<3>::at(comp, 0)] * (R)kB1[q][n];
-        t1 += S[q][SymIdx<3>::at(comp, 1)] * (R)kB1[q][n];
-        t2 += S[q][SymIdx<3>::at(comp, 2)] * (R)kD1[q][n];
+        if (!DIAG || comp == 0) t0 += S[q][SymIdx<3>::at(comp, 0)] * (R)kB1[q][n];
+        if (!DIAG || comp == 1) t1 += S[q][SymIdx<3>::at(comp, 1)] * (R)kB1[q][n];
+        if (!DIAG || comp == 2) t2 += S[q][SymIdx<3>::at(comp, 2)] * (R)kD1[q][n];
       }
-      sm.y[lc][0][i3(p0, p1, n)] = t0;
-      sm.y[lc][1][i3(p0, p1, n)] = t1;
-      sm.y[lc][2][i3(p0, p1, n)] = t2;
+      if (!DIAG || comp == 0) sm.y[lc][0][i3(p0, p1, n)] = t0;
+      if (!DIAG || comp == 1) sm.y[lc][1][i3(p0, p1, n)] = t1;
+      if (!DIAG || comp == 2) sm.y[lc][2][i3(p0, p1, n)] = t2;
     }
     __syncthreads();
     // y: lane (qx,nz) = (p0,p1) -> (qx,ny,nz); outputs D_x-bound and B_x-bound parts
     {
-      R t0[3], t1[3], t2[3];
+      R t0[3] = {}, t1[3] = {}, t2[3] = {};
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        t0[q] = sm.y[lc][0][i3(p0, q, p1)];
-        t1[q] = sm.y[lc][1][i3(p0, q, p1)];
-        t2[q] = sm.y[lc][2][i3(p0, q, p1)];
+        if (!DIAG || comp == 0) t0[q] = sm.y[lc][0][i3(p0, q, p1)];
+        if (!DIAG || comp == 1) t1[q] = sm.y[lc][1][i3(p0, q, p1)];
+        if (!DIAG || comp == 2) t2[q] = sm.y[lc][2][i3(p0, q, p1)];
       }
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
         R w0 = 0, w12 = 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          w0 += t0[q] * (R)kB1[q][n];
-          w12 += t1[q] * (R)kD1[q][n] + t2[q] * (R)kB1[q][n];
+          if (!DIAG) {
+            w0 += t0[q] * (R)kB1[q][n];
+            w12 += t1[q] * (R)kD1[q][n] + t2[q] * (R)kB1[q][n];
+          } else if (comp == 0) {
+            w0 += t0[q] * (R)kB1[q][n];
+          } else if (comp == 1) {
+            w12 += t1[q] * (R)kD1[q][n];
+          } else {
+            w12 += t2[q] * (R)kB1[q][n];
+          }
         }
-        sm.x[lc][0][i3(p0, n, p1)] = w0;
-        sm.x[lc][1][i3(p0, n, p1)] = w12;
+        if (!DIAG || comp == 0) sm.x[lc][0][i3(p0, n, p1)] = w0;
+        if (!DIAG || comp != 0) sm.x[lc][1][i3(p0, n, p1)] = w12;
       }
     }
     __syncthreads();
     // x: lane (ny,nz) = (p0,p1) -> nodes (0..2, ny, nz)
     {
-      R w0[3], w12[3];
+      R w0[3] = {}, w12[3] = {};
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        w0[q] = sm.x[lc][0][i3(q, p0, p1)];
-        w12[q] = sm.x[lc][1][i3(q, p0, p1)];
+        if (!DIAG || comp == 0) w0[q] = sm.x[lc][0][i3(q, p0, p1)];
+        if (!DIAG || comp != 0) w12[q] = sm.x[lc][1][i3(q, p0, p1)];
       }
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
         R yv = 0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) yv += w0[q] * (R)kD1[q][n] + w12[q] * (R)kB1[q][n];
+        for (int q = 0; q < 3; ++q) {
+          if (!DIAG) yv += w0[q] * (R)kD1[q][n] + w12[q] * (R)kB1[q][n];
+          else if (comp == 0) yv += w0[q] * (R)kD1[q][n];
+          else yv += w12[q] * (R)kB1[q][n];
+        }
         if (valid) E[cell * NL + comp * 27 + i3(n, p0, p1)] = h * yv;
       }
     }
