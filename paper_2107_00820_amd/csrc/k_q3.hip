@@ -9,8 +9,7 @@
 // prolongation and its transpose.
 //
 // Every output is a fixed-order sum with no atomics, so repeated calls give
-// bit-identical results. These kernels favour plain structure over speed:
-// one lane per cell, patch or node.
+// bit-identical results.
 #include "stk_dev.h"
 #include "stk_q3d.h"
 #include "stk_reduce.h"
@@ -27,102 +26,156 @@ __device__ inline bool bnd_node(const LevelGeo& g, int i0, int i1) {
 // ---------------------------------------------------------------------------
 // Cell kernel: element vectors E[cell][comp * 16 + n] of the terms in MODE
 // (EL_VISC, EL_AUG, EL_BT) and, with EL_BOUT, (B u)_K into pout. Four cells
-// per 64-lane workgroup, 16 lanes per cell: lane t loads node t, then forms
-// the stress at Gauss point t, then the outputs of node t; the six pressure
-// moments are formed by lanes 0..5 of the cell. Exchanges through LDS.
+// per 64-lane workgroup, 16 lanes per cell, by sum factorisation: the
+// gradients at the 16 Gauss points in two 1D contractions (y, then x; lane t
+// owns one point of each intermediate), the weighted stress at Gauss point t,
+// the pressure moments (B-hat u)_m = sum_q w_q psi_m(q) div u(q) (B-hat is
+// this Gauss sum) by butterflies over the cell's 16 lanes, the augmented and
+// B^T terms as pi(q) = w_q sum_m psi_m(q) t_m on the stress diagonal, and the
+// transposed contractions (x, then y) back to node t. The 1D tables are copied
+// to LDS first (no constant-table read with a lane-dependent row).
 template <int MODE>
 __global__ void __launch_bounds__(64) k3_elem(LevelGeo g, const double* __restrict__ mu,
                                               const double* __restrict__ winv, double gamma,
                                               const double* __restrict__ u, const double* __restrict__ p,
                                               double* __restrict__ E, double* __restrict__ pout) {
   const Tab& T = cQ3;
-  __shared__ double su[4][NL];
-  __shared__ double ss[4][NQ][3];
-  __shared__ double sp[4][NP];
-  const int c = threadIdx.x >> 4, t = threadIdx.x & 15;
+  const q3d::Tab1& T1 = q3d::cT1;
+  __shared__ double R0[4][4 * NN];
+  __shared__ double R1[4][4 * NN];
+  __shared__ double sT[40];   // L[4][4], D[4][4], gx[4], gw[4]
+  const int c = threadIdx.x >> 4, t = threadIdx.x & 15, t0 = t & 3, t1 = t >> 2;
   const int64_t cell0 = (int64_t)blockIdx.x * 4 + c;
   const bool valid = cell0 < g.ncell;
   const int64_t cell = valid ? cell0 : g.ncell - 1;   // lanes past the end take part in the barriers
   const int c0 = (int)(cell % g.N), c1 = (int)(cell / g.N);
+  if (threadIdx.x < 16) {
+    sT[threadIdx.x] = T1.L[threadIdx.x >> 2][threadIdx.x & 3];
+    sT[16 + threadIdx.x] = T1.D[threadIdx.x >> 2][threadIdx.x & 3];
+  } else if (threadIdx.x < 20) {
+    sT[32 + threadIdx.x - 16] = T1.gx[threadIdx.x - 16];
+    sT[36 + threadIdx.x - 16] = T1.gw[threadIdx.x - 16];
+  }
   constexpr bool NEED_U = (MODE & (EL_VISC | EL_AUG | EL_BOUT)) != 0;
+  constexpr bool NEED_T = (MODE & (EL_AUG | EL_BT)) != 0;
   if (NEED_U) {
-    const int i0 = 3 * c0 + t % NA, i1 = 3 * c1 + t / NA;
+    const int i0 = 3 * c0 + t0, i1 = 3 * c1 + t1;
     const bool b = bnd_node(g, i0, i1);
     const int64_t nd = (int64_t)i0 + (int64_t)g.n1 * i1;
-    su[c][t] = b ? 0.0 : u[nd];
-    su[c][NN + t] = b ? 0.0 : u[g.nnodes + nd];
+    R0[c][t] = b ? 0.0 : u[nd];
+    R0[c][NN + t] = b ? 0.0 : u[g.nnodes + nd];
   }
   __syncthreads();
-  double e0 = 0.0, e1 = 0.0;   // outputs of node t, components 0 and 1
-  if (MODE & EL_VISC) {
-    const int q = t;
-    double G00 = 0.0, G01 = 0.0, G10 = 0.0, G11 = 0.0;
+  const double* Lt = sT;         // Lt[4 * point + basis]
+  const double* Dt = sT + 16;
+  const double x0 = sT[32 + t0] - 0.5, x1 = sT[32 + t1] - 0.5;
+  const double wq = sT[36 + t0] * sT[36 + t1];
+  const double ps[NP] = {1.0, x0, x1, x0 * x0, x0 * x1, x1 * x1};
+  double S[3] = {0.0, 0.0, 0.0};   // weighted stress at Gauss point t: (0,0), (1,1), (0,1)
+  double tm[NP];
 #pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      const double d0 = T.dphi[q][n][0], d1 = T.dphi[q][n][1];
-      G00 += d0 * su[c][n];
-      G01 += d1 * su[c][n];
-      G10 += d0 * su[c][NN + n];
-      G11 += d1 * su[c][NN + n];
-    }
-    const double wm = T.w[q] * mu[cell * NQ + q];
-    ss[c][q][0] = wm * 2.0 * G00;
-    ss[c][q][1] = wm * 2.0 * G11;
-    ss[c][q][2] = wm * (G01 + G10);
-  }
-  if (MODE & (EL_AUG | EL_BOUT | EL_BT)) {
-    if (t < NP) {
-      const int m = t;
-      double v = 0.0;
-      if (MODE & (EL_AUG | EL_BOUT)) {
+  for (int m = 0; m < NP; ++m) tm[m] = 0.0;
+  if (NEED_U) {
+    // y: lane (a, j) = (t0, t1); AL = sum_b L[j][b] u(a, b), AD = sum_b D[j][b] u(a, b)
 #pragma unroll
-        for (int j = 0; j < NL; ++j) v += T.bhat[m][j] * su[c][j];
+    for (int comp = 0; comp < 2; ++comp) {
+      double al = 0.0, ad = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const double v = R0[c][comp * NN + t0 + 4 * bb];
+        al += Lt[4 * t1 + bb] * v;
+        ad += Dt[4 * t1 + bb] * v;
       }
-      if ((MODE & EL_BOUT) && valid) pout[cell * NP + m] = -g.h * v;
-      sp[c][m] = v;
+      R1[c][(2 * comp) * NN + t] = al;
+      R1[c][(2 * comp + 1) * NN + t] = ad;
     }
-  }
-  __syncthreads();
-  if (MODE & EL_VISC) {
-    const int n = t;
+    __syncthreads();
+    // x: lane (i, j) = (t0, t1); G[comp][0] = sum_a D[i][a] AL(a, j), G[comp][1] = sum_a L[i][a] AD(a, j)
+    double G[2][2];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double d0 = T.dphi[q][n][0], d1 = T.dphi[q][n][1];
-      e0 += ss[c][q][0] * d0 + ss[c][q][2] * d1;
-      e1 += ss[c][q][2] * d0 + ss[c][q][1] * d1;
+    for (int comp = 0; comp < 2; ++comp) {
+      double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        g0 += Dt[4 * t0 + aa] * R1[c][(2 * comp) * NN + aa + 4 * t1];
+        g1 += Lt[4 * t0 + aa] * R1[c][(2 * comp + 1) * NN + aa + 4 * t1];
+      }
+      G[comp][0] = g0;
+      G[comp][1] = g1;
     }
-  }
-  if (MODE & (EL_AUG | EL_BT)) {
-    // pressure-side coefficients per cell: gamma W^{-1} (B u)-moments and/or -h p
-    double tm[NP];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) tm[m] = 0.0;
-    if (MODE & EL_AUG) {
+    if (MODE & EL_VISC) {
+      const double wm = wq * mu[cell * NQ + t];
+      S[0] = wm * 2.0 * G[0][0];
+      S[1] = wm * 2.0 * G[1][1];
+      S[2] = wm * (G[0][1] + G[1][0]);
+    }
+    if (MODE & (EL_AUG | EL_BOUT)) {
+      const double dq = wq * (G[0][0] + G[1][1]);
+      double sp[NP];
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        double s = 0.0;
+        double v = dq * ps[m];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[c][k];
-        tm[m] = gamma * s;
+        for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        sp[m] = v;
+      }
+      if (MODE & EL_BOUT) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+          if (t == m && valid) pout[cell * NP + m] = -g.h * sp[m];
+      }
+      if (MODE & EL_AUG) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) s += (winv ? winv[cell * NP * NP + m * NP + k] : T.mhinv[m][k]) * sp[k];
+          tm[m] = gamma * s;
+        }
       }
     }
-    if (MODE & EL_BT) {
-#pragma unroll
-      for (int m = 0; m < NP; ++m) tm[m] -= g.h * p[cell * NP + m];
-    }
-    const int n = t;
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) {
-      a0 += T.bhat[m][n] * tm[m];
-      a1 += T.bhat[m][NN + n] * tm[m];
-    }
-    e0 += a0;
-    e1 += a1;
   }
-  if (valid) {
-    E[cell * NL + t] = e0;
-    E[cell * NL + NN + t] = e1;
+  if (MODE & EL_BT) {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) tm[m] -= g.h * p[cell * NP + m];
+  }
+  if (NEED_T) {
+    double pi = 0.0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) pi += ps[m] * tm[m];
+    pi *= wq;
+    S[0] += pi;
+    S[1] += pi;
+  }
+  // stress rows: comp 0 (S0, S2), comp 1 (S2, S1); R0 is free (the y stage read it)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R0[c][k * NN + t] = S[k];
+  __syncthreads();
+  constexpr int kRow[2][2] = {{0, 2}, {2, 1}};
+  // x: lane (a, j) = (t0, t1); X0 = sum_i D[i][a] F0(i, j), X1 = sum_i L[i][a] F1(i, j)
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int o = ii + 4 * t1;
+      v0 += Dt[4 * ii + t0] * R0[c][kRow[comp][0] * NN + o];
+      v1 += Lt[4 * ii + t0] * R0[c][kRow[comp][1] * NN + o];
+    }
+    R1[c][(2 * comp) * NN + t] = v0;
+    R1[c][(2 * comp + 1) * NN + t] = v1;
+  }
+  __syncthreads();
+  // y: lane n = (a, b) = (t0, t1); e = sum_j L[j][b] X0(a, j) + D[j][b] X1(a, j)
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+    double e = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int o = t0 + 4 * jj;
+      e += Lt[4 * jj + t1] * R1[c][(2 * comp) * NN + o] + Dt[4 * jj + t1] * R1[c][(2 * comp + 1) * NN + o];
+    }
+    if (valid) E[cell * NL + comp * NN + t] = e;
   }
 }
 
@@ -465,54 +518,45 @@ __global__ void k3_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restric
   xf[idx] = s;
 }
 
-// The fine nodes (and weights) where coarse node j's 1D basis is nonzero.
-__device__ inline int fine_support(int j, int Nc, int nodes[11], double w[11]) {
-  constexpr const Tab& T = RefQ3::T;
-  int n = 0;
-  const int C = j / 3, a = j % 3;
-  if (a == 0) {
-    for (int t = -5; t <= 5; ++t) {
-      if (t < 0 && C == 0) continue;
-      if (t > 0 && C == Nc) continue;
-      const double wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
-      if (wt == 0.0) continue;
-      nodes[n] = 6 * C + t;
-      w[n] = wt;
-      ++n;
-    }
-  } else {
-    for (int t = 1; t <= 5; ++t) {
-      const double wt = T.prol[t][a];
-      if (wt == 0.0) continue;
-      nodes[n] = 6 * C + t;
-      w[n] = wt;
-      ++n;
-    }
-  }
-  return n;
-}
-
-// P_H^T: coarse node collects from the fine nodes of its support (fine
-// Dirichlet nodes skipped; coarse Dirichlet nodes written 0).
+// rc = P^T rf: for an interior coarse node every fine node of its stencil is
+// interior, so the sum runs over the product of the two 1D stencils (kRT:
+// compile-time offsets and weights selected by j mod 3, 7 slots per axis).
 __global__ void k3_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restrict__ rf, double* __restrict__ rc) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= 2 * gc.nnodes) return;
   const int comp = (int)(idx / gc.nnodes);
   const int64_t nd = idx - (int64_t)comp * gc.nnodes;
-  const int j0 = (int)(nd % gc.n1), j1 = (int)(nd / gc.n1);
-  if (bnd_node(gc, j0, j1)) {
+  const int j[2] = {(int)(nd % gc.n1), (int)(nd / gc.n1)};
+  if (bnd_node(gc, j[0], j[1])) {
     rc[idx] = 0.0;
     return;
   }
-  int f0[11], f1[11];
-  double w0[11], w1[11];
-  const int n0 = fine_support(j0, gc.N, f0, w0), n1 = fine_support(j1, gc.N, f1, w1);
-  double s = 0.0;
-  for (int t1 = 0; t1 < n1; ++t1)
-    for (int t0 = 0; t0 < n0; ++t0) {
-      if (bnd_node(gf, f0[t0], f1[t1])) continue;
-      s += w0[t0] * w1[t1] * rf[comp * gf.nnodes + (int64_t)f0[t0] + (int64_t)gf.n1 * f1[t1]];
+  int len[2];
+  int64_t off[2][7];
+  double w[2][7];
+  const int64_t stride[2] = {1, gf.n1};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int a = j[k] % 3, base = 6 * (j[k] / 3);
+    len[k] = a == 0 ? kRT.n[0] : (a == 1 ? kRT.n[1] : kRT.n[2]);
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) {
+      const int o = a == 0 ? kRT.off[0][sl] : (a == 1 ? kRT.off[1][sl] : kRT.off[2][sl]);
+      off[k][sl] = (int64_t)(base + o) * stride[k];
+      w[k][sl] = a == 0 ? kRT.w[0][sl] : (a == 1 ? kRT.w[1][sl] : kRT.w[2][sl]);
     }
+  }
+  const double* src = rf + comp * gf.nnodes;
+  double s = 0.0;
+#pragma unroll
+  for (int s1 = 0; s1 < 7; ++s1) {
+    if (s1 >= len[1]) break;
+    const double* row = src + off[1][s1];
+    double s0v = 0.0;
+#pragma unroll
+    for (int s0 = 0; s0 < 7; ++s0) s0v += w[0][s0] * row[off[0][s0]];
+    s += w[1][s1] * s0v;
+  }
   rc[idx] = s;
 }
 

@@ -712,37 +712,6 @@ __global__ void k3d_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restri
   xf[idx] = s;
 }
 
-// 1D restriction stencils of a coarse node of local index a = j mod 3 in its
-// cell: the fine offsets from 6 C (C = j / 3) with nonzero prolongation
-// weight, in 7 slots (a = 0: a cell vertex, weights from both neighbouring
-// cells; a = 1, 2: four entries, the remaining slots weight 0 at a valid
-// offset).
-struct RestrictTab {
-  int n[3];
-  int off[3][7];
-  double w[3][7];
-  constexpr RestrictTab() : n(), off(), w() {
-    constexpr const q3::Tab& T = q3::RefQ3::T;
-    for (int a = 0; a < 3; ++a) {
-      int k = 0;
-      for (int t = -5; t <= 5; ++t) {
-        double wt = 0.0;
-        if (a == 0) wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
-        else if (t >= 1) wt = T.prol[t][a];
-        if (wt == 0.0) continue;
-        off[a][k] = t;
-        w[a][k] = wt;
-        ++k;
-      }
-      n[a] = k;
-      for (int q = k; q < 7; ++q) {
-        off[a][q] = off[a][0];
-        w[a][q] = 0.0;
-      }
-    }
-  }
-};
-constexpr RestrictTab kRT{};
 
 // rc = P^T rf for the standard prolongation: for an interior coarse node
 // every fine node of its stencil is interior (a vertex has 1 <= C <= N - 1,
@@ -767,12 +736,12 @@ __global__ void k3d_restrict_std(LevelGeo gf, LevelGeo gc, const double* __restr
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int a = j[k] % 3, base = 6 * (j[k] / 3);
-    len[k] = a == 0 ? kRT.n[0] : (a == 1 ? kRT.n[1] : kRT.n[2]);
+    len[k] = a == 0 ? q3::kRT.n[0] : (a == 1 ? q3::kRT.n[1] : q3::kRT.n[2]);
 #pragma unroll
     for (int sl = 0; sl < 7; ++sl) {
-      const int o = a == 0 ? kRT.off[0][sl] : (a == 1 ? kRT.off[1][sl] : kRT.off[2][sl]);
+      const int o = a == 0 ? q3::kRT.off[0][sl] : (a == 1 ? q3::kRT.off[1][sl] : q3::kRT.off[2][sl]);
       off[k][sl] = (int64_t)(base + o) * stride[k];
-      w[k][sl] = a == 0 ? kRT.w[0][sl] : (a == 1 ? kRT.w[1][sl] : kRT.w[2][sl]);
+      w[k][sl] = a == 0 ? q3::kRT.w[0][sl] : (a == 1 ? q3::kRT.w[1][sl] : q3::kRT.w[2][sl]);
     }
   }
   const double* src = rf + comp * gf.nnodes;

@@ -137,6 +137,38 @@ struct RefQ3 {
   static constexpr Tab T{};
 };
 
+// 1D restriction stencils of a coarse node of local index a = j mod 3 in its
+// cell: the fine offsets from 6 C (C = j / 3) with nonzero prolongation
+// weight, in 7 slots (a = 0: a cell vertex, weights from both neighbouring
+// cells; a = 1, 2: four entries, the remaining slots weight 0 at a valid
+// offset).
+struct RestrictTab {
+  int n[3];
+  int off[3][7];
+  double w[3][7];
+  constexpr RestrictTab() : n(), off(), w() {
+    constexpr const Tab& T = RefQ3::T;
+    for (int a = 0; a < 3; ++a) {
+      int k = 0;
+      for (int t = -5; t <= 5; ++t) {
+        double wt = 0.0;
+        if (a == 0) wt = t < 0 ? T.prol[6 + t][3] : T.prol[t][0];
+        else if (t >= 1) wt = T.prol[t][a];
+        if (wt == 0.0) continue;
+        off[a][k] = t;
+        w[a][k] = wt;
+        ++k;
+      }
+      n[a] = k;
+      for (int q = k; q < 7; ++q) {
+        off[a][q] = off[a][0];
+        w[a][q] = 0.0;
+      }
+    }
+  }
+};
+constexpr RestrictTab kRT{};
+
 // Runtime-indexed copy in constant memory.
 static __constant__ Tab cQ3 = Tab();
 
