@@ -114,8 +114,10 @@ def test_descriptor_fields_of_the_boundary():
 def test_degree_three_descriptor():
     """degree 3 ([Q3]^d x P2disc) is accepted with the scalar law and the
     FP64 form (3D up to 32^3 cells); its footprint holds 16 Gauss points per
-    cell, 6 pressure unknowns per cell and 50-unknown patch inverses in 2D;
-    other combinations (here a 3D 64^3 mesh) are rejected on the host."""
+    cell, 6 pressure unknowns per cell and 50-unknown patch inverses in 2D,
+    and the stored 375-unknown inverses in 3D; other combinations (a 3D mesh
+    over 32^3 cells, the mixed form, the tensor law, degree 4) are rejected
+    on the host."""
     from paper_2107_00820_amd import stk
     from workloads import small
     wl3 = small(2, 64, 3, gamma=1e3, dr=1e4, degree=3)
@@ -131,8 +133,15 @@ def test_degree_three_descriptor():
         else:
             with pytest.raises(stk.StkError):
                 stk.stk_footprint(d)
-    # 3D degree 3 up to 32^3 (explicit 375-unknown patch inverses)
-    assert stk.stk_footprint(stk.desc_from_workload(small(3, 16, 2, gamma=1e3, dr=1e4, degree=3))) > 0
+    # 3D degree 3 up to 32^3 (explicit 375-unknown patch inverses): the finest
+    # level of 16^3 alone holds 17^3 inverses of 74,496 doubles (15 full 64 x 64
+    # tiles and 6 diagonal tiles of 2,176); 32^3 is accepted, 36^3 is not
+    f16 = stk.stk_footprint(stk.desc_from_workload(small(3, 16, 2, gamma=1e3, dr=1e4, degree=3)))
+    assert f16 >= 8 * 17 ** 3 * (15 * 4096 + 6 * 2176)
+    assert stk.stk_footprint(stk.desc_from_workload(small(3, 32, 4, gamma=1e3, dr=1e4, degree=3))) > f16
+    with pytest.raises(stk.StkError) as e:
+        stk.stk_footprint(stk.desc_from_workload(small(3, 36, 3, gamma=1e3, dr=1e4, degree=3)))
+    assert e.value.status == stk.STK_EINVAL
     for field, value in (("mixed", 1), ("dim", 3), ("coef_kind", 1), ("degree", 4)):
         d = stk.desc_from_workload(wl3)
         setattr(d, field, value)
