@@ -447,8 +447,8 @@ def main():
                     help="timed solves only (no event-timing pass, no extra legs, no serving, no oracle)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
+              "decomposition over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.trace:
         args.no_extra = args.no_serving = args.no_cpu_baseline = True
