@@ -683,35 +683,74 @@ __global__ void k3d_asm_gather(LevelGeo g, const double* __restrict__ zbuf, int 
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k3d_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict__ xc, double* __restrict__ xf) {
+// 1D weight l_a(r / 6) of the coarse cubic basis a (compile-time) at a
+// lane-dependent fine offset r = 0..6, chosen among constants.
+template <int A>
+__device__ inline double prol3_w(int r) {
   constexpr const q3::Tab& T = q3::RefQ3::T;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= 3 * gf.nnodes) return;
-  const int comp = (int)(idx / gf.nnodes);
-  const int64_t nd = idx - (int64_t)comp * gf.nnodes;
-  const int i[3] = {(int)(nd % gf.n1), (int)((nd / gf.n1) % gf.n1), (int)(nd / ((int64_t)gf.n1 * gf.n1))};
-  if (bnd_node3(gf, i[0], i[1], i[2])) {
-    xf[idx] = 0.0;
-    return;
-  }
-  int C[3], r[3];
-  for (int k = 0; k < 3; ++k) {
-    C[k] = i[k] / 6;
-    r[k] = i[k] % 6;
-    if (C[k] == gc.N) { C[k] = gc.N - 1; r[k] = 6; }
-  }
-  double s = 0.0;
-  for (int a2 = 0; a2 < NA; ++a2)
-    for (int a1 = 0; a1 < NA; ++a1)
-      for (int a0 = 0; a0 < NA; ++a0) {
-        const double w = T.prol[r[0]][a0] * T.prol[r[1]][a1] * T.prol[r[2]][a2];
-        const int j0 = 3 * C[0] + a0, j1 = 3 * C[1] + a1, j2 = 3 * C[2] + a2;
-        if (w == 0.0 || bnd_node3(gc, j0, j1, j2)) continue;
-        s += w * xc[comp * gc.nnodes + node3(gc, j0, j1, j2)];
-      }
-  xf[idx] = s;
+  return r == 0 ? T.prol[0][A] : r == 1 ? T.prol[1][A] : r == 2 ? T.prol[2][A] : r == 3 ? T.prol[3][A]
+         : r == 4 ? T.prol[4][A] : r == 5 ? T.prol[5][A] : T.prol[6][A];
 }
 
+// P_H x_c, six fine nodes per thread: the nodes 6C .. 6C+5 of one fine row
+// (i1, i2) along x, at offsets r = 0..5 in coarse cell C (thread C = N_c
+// owns the last node 6 N_c, a Dirichlet node). The coarse values of the
+// row's (y, z) stencil (at most 4 x 4 entries, shared by the six nodes) are
+// summed per coarse x-node 3C .. 3C+3 first; each output then takes its
+// compile-time x weights. Coarse Dirichlet nodes contribute nothing, fine
+// Dirichlet nodes are written as 0.
+__global__ void k3d_prolong_std(LevelGeo gc, LevelGeo gf, const double* __restrict__ xc, double* __restrict__ xf) {
+  constexpr const q3::Tab& T = q3::RefQ3::T;
+  const int Nc = gc.N, nf1 = gf.n1;
+  const int64_t nc1 = gc.n1;
+  const int64_t per = (int64_t)nf1 * nf1 * (Nc + 1);
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= 3 * per) return;
+  const int comp = (int)(idx / per);
+  const int64_t rem = idx - (int64_t)comp * per;
+  const int C = (int)(rem % (Nc + 1));
+  const int64_t row = rem / (Nc + 1);
+  const int i1 = (int)(row % nf1), i2 = (int)(row / nf1);
+  double* out = xf + (int64_t)comp * gf.nnodes + (int64_t)nf1 * (i1 + (int64_t)nf1 * i2) + 6 * C;
+  const int e = 3 * gf.N;
+  if (C == Nc || i1 == 0 || i1 == e || i2 == 0 || i2 == e) {
+    const int nout = C == Nc ? 1 : 6;
+    for (int k = 0; k < nout; ++k) out[k] = 0.0;
+    return;
+  }
+  int cl1 = i1 / 6, r1 = i1 % 6, cl2 = i2 / 6, r2 = i2 % 6;
+  if (cl1 == Nc) { cl1 = Nc - 1; r1 = 6; }
+  if (cl2 == Nc) { cl2 = Nc - 1; r2 = 6; }
+  const double w1[4] = {prol3_w<0>(r1), prol3_w<1>(r1), prol3_w<2>(r1), prol3_w<3>(r1)};
+  const double w2[4] = {prol3_w<0>(r2), prol3_w<1>(r2), prol3_w<2>(r2), prol3_w<3>(r2)};
+  const int ec = 3 * Nc;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* src0 = xc + (int64_t)comp * gc.nnodes + 3 * C;
+#pragma unroll
+  for (int a2 = 0; a2 < 4; ++a2) {
+    const int j2 = 3 * cl2 + a2;
+    if (w2[a2] == 0.0 || j2 == 0 || j2 == ec) continue;
+#pragma unroll
+    for (int a1 = 0; a1 < 4; ++a1) {
+      const int j1 = 3 * cl1 + a1;
+      if (w1[a1] == 0.0 || j1 == 0 || j1 == ec) continue;
+      const double w = w1[a1] * w2[a2];
+      const double* src = src0 + nc1 * (j1 + nc1 * j2);
+      t[0] += w * (C > 0 ? src[0] : 0.0);        // x-node 3C is Dirichlet for C = 0
+      t[1] += w * src[1];
+      t[2] += w * src[2];
+      t[3] += w * (C < Nc - 1 ? src[3] : 0.0);   // x-node 3C+3 is Dirichlet for C = Nc - 1
+    }
+  }
+#pragma unroll
+  for (int r0 = 0; r0 < 6; ++r0) {
+    double y = 0.0;
+#pragma unroll
+    for (int a0 = 0; a0 < 4; ++a0)
+      if (T.prol[r0][a0] != 0.0) y += T.prol[r0][a0] * t[a0];
+    out[r0] = (C == 0 && r0 == 0) ? 0.0 : y;    // fine node 0 is Dirichlet
+  }
+}
 
 // rc = P^T rf for the standard prolongation: for an interior coarse node
 // every fine node of its stencil is interior (a vertex has 1 <= C <= N - 1,
@@ -873,7 +912,10 @@ void q3d_center_solve(const Hier& H, const Level& fine, const double* in, double
 void q3d_prolong_std(const Hier& H, const Level& coarse, const Level& fine, const double* xc, double* xf,
                      hipStream_t s) {
   (void)H;
-  hipLaunchKernelGGL(k3d_prolong_std, dim3(nblk(3 * fine.g.nnodes, 256)), dim3(256), 0, s, coarse.g, fine.g, xc, xf);
+  // threads: components x fine rows x (coarse cells along x + 1)
+  const int64_t nf1 = fine.g.n1;
+  hipLaunchKernelGGL(k3d_prolong_std, dim3(nblk(3 * nf1 * nf1 * (coarse.g.N + 1), 256)), dim3(256), 0, s, coarse.g,
+                     fine.g, xc, xf);
 }
 
 void q3d_restrict_std(const Hier& H, const Level& fine, const Level& coarse, const double* rf, double* rc,
